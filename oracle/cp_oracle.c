@@ -1,0 +1,908 @@
+/*
+ * cp_oracle.c -- plain FP64 reference for critical-point probabilities of
+ * uncertain 2-D fields (Athawale et al., "Uncertainty Visualization of
+ * Critical Points of 2D Scalar Fields for Parametric and Nonparametric
+ * Probabilistic Models", arXiv 2407.18015).
+ *
+ * TEST INFRASTRUCTURE ONLY.  The product library never includes, links or
+ * calls this file; only the test-suite, the smoke check and the CPU-baseline
+ * leg of the benchmark load it.  It shares no code, header or table with the
+ * HIP path.
+ *
+ * What it computes (Sec. 3 problem setting; Eq. 3 for the minimum, the
+ * negation argument of Sec. 4.1.2 / 4.2 for the maximum):
+ *
+ *   P_min(v) = Pr[X_v < X_n for every existing 4-neighbour n]
+ *            = integral of pdf_v(x) * prod_n S_n(x) dx,   S_n = 1 - CDF_n
+ *   P_max(v) = integral of pdf_v(x) * prod_n F_n(x) dx,   F_n = CDF_n
+ *
+ * With independent X_i (Sec. 3) every inner integral of Eq. 3 is a survival
+ * function, so the 5-fold integral is a 1-D integral.  The oracle evaluates
+ * that definition directly: it splits the vertex support at every support end
+ * and bin edge of the (up to) five distributions, writes each factor on a
+ * sub-interval as a polynomial in a piece-centred variable s in [-1, 1]
+ * (x = c + h s), multiplies the polynomials in coefficient form and integrates
+ * exactly.  No ordering of breakpoints, no templates, no quadrature.
+ *
+ * Models:
+ *   uniform       pdf 1/(b-a) on [a,b]                         (Sec. 4.3)
+ *   Epanechnikov  pdf 3/(4w) (1 - ((x-m)/w)^2) on [m-w, m+w]   (Sec. 4.3)
+ *   histogram     mixture of uniform kernels, one per bin       (Sec. 4.4.1)
+ *                 pdf = m_j / Delta on bin j; masses are taken as given
+ *                 (unconstrained), so S(x) = integral_x^inf pdf, which equals
+ *                 sum(masses) below the range; P is multilinear in the masses
+ *                 exactly as in the h^5 sum of Eq. 5.
+ *   multivariate Gaussian over the 5-point stencil, Monte Carlo (Sec. 5.2,
+ *                 5.3; prior work the paper compares against): Philox4x32-10
+ *                 counters, Box-Muller normals, hit-count and conditional
+ *                 (Rao-Blackwellised) estimators, pathwise gradient.
+ *
+ * Boundary (Sec. 3 leaves it open): a vertex uses only its existing
+ * neighbours (3 on an edge, 2 at a corner, none for a 1x1 grid).
+ *
+ * Stencil slot order used for Jacobians and gathers: 0 = v (self),
+ * 1 = e (x+1), 2 = n (y-1), 3 = w (x-1), 4 = s (y+1).
+ *
+ * Parameter planes are dense [n_param][H][W] doubles:
+ *   uniform      (lo, hi)
+ *   Epanechnikov (m, w)
+ *   histogram    (lo, hi, mass_0 .. mass_{nb-1})   -- lo/hi not differentiated
+ *   mvg          (mu, L_00, L_10, L_11, L_20, ... L_44) lower-triangular
+ *                Cholesky factor over the variable order (e, n, w, s, v)
+ */
+#include <math.h>
+#include <stdint.h>
+#include <stdlib.h>
+#include <string.h>
+
+enum { OR_UNIFORM = 0, OR_EPANECHNIKOV = 1, OR_HISTOGRAM = 2, OR_MVG = 3 };
+
+#define NSLOT 5
+#define PCOEF 16 /* degree <= 15: pdf (2) + four cubic survival factors (12) */
+#define MAXNB 64
+#define MAXBREAK (5 * (MAXNB + 1) + 4)
+
+static const int SLOT_DY[NSLOT] = {0, 0, -1, 0, 1};
+static const int SLOT_DX[NSLOT] = {0, 1, 0, -1, 0};
+
+/* ------------------------------------------------------------------------ */
+/* polynomials in s, coefficient form                                       */
+/* ------------------------------------------------------------------------ */
+typedef struct {
+  int d;
+  double c[PCOEF];
+} poly_t;
+
+static void p_set0(poly_t* p, double c0) {
+  p->d = 0;
+  p->c[0] = c0;
+}
+static void p_set1(poly_t* p, double c0, double c1) {
+  p->d = 1;
+  p->c[0] = c0;
+  p->c[1] = c1;
+}
+static void p_mul(poly_t* r, const poly_t* a, const poly_t* b) {
+  poly_t t;
+  t.d = a->d + b->d;
+  for (int k = 0; k <= t.d; ++k) t.c[k] = 0.0;
+  for (int i = 0; i <= a->d; ++i)
+    for (int j = 0; j <= b->d; ++j) t.c[i + j] += a->c[i] * b->c[j];
+  *r = t;
+}
+static void p_scale(poly_t* p, double s) {
+  for (int k = 0; k <= p->d; ++k) p->c[k] *= s;
+}
+static void p_add(poly_t* r, const poly_t* a, const poly_t* b) {
+  poly_t t;
+  t.d = a->d > b->d ? a->d : b->d;
+  for (int k = 0; k <= t.d; ++k) {
+    double va = k <= a->d ? a->c[k] : 0.0, vb = k <= b->d ? b->c[k] : 0.0;
+    t.c[k] = va + vb;
+  }
+  *r = t;
+}
+/* integral over x of a polynomial in s, x = c + h s, s in [-1, 1] */
+static double p_integrate(const poly_t* p, double h) {
+  double acc = 0.0;
+  for (int k = 0; k <= p->d; k += 2) acc += 2.0 * p->c[k] / (double)(k + 1);
+  return acc * h;
+}
+/* compose a cubic in u, q(u) = q0 + q1 u + q2 u^2 + q3 u^3, with u = al + be s */
+static void p_cubic_of_linear(poly_t* r, const double q[4], double al, double be) {
+  poly_t u, u2, u3, acc, t;
+  p_set1(&u, al, be);
+  p_mul(&u2, &u, &u);
+  p_mul(&u3, &u2, &u);
+  p_set0(&acc, q[0]);
+  t = u;
+  p_scale(&t, q[1]);
+  p_add(&acc, &acc, &t);
+  t = u2;
+  p_scale(&t, q[2]);
+  p_add(&acc, &acc, &t);
+  t = u3;
+  p_scale(&t, q[3]);
+  p_add(&acc, &acc, &t);
+  *r = acc;
+}
+
+/* ------------------------------------------------------------------------ */
+/* one distribution of the stencil                                           */
+/* ------------------------------------------------------------------------ */
+typedef struct {
+  int model;
+  double lo, hi;      /* support */
+  double m, w;        /* Epanechnikov centre, half-width */
+  int nb;             /* histogram bins */
+  double delta;       /* histogram bin width */
+  const double* mass; /* histogram masses (strided in the parameter planes) */
+  int64_t mstride;
+  double total; /* sum of masses (histogram); 1 otherwise */
+} dist_t;
+
+static double d_mass(const dist_t* d, int j) { return d->mass[(int64_t)j * d->mstride]; }
+static double d_edge(const dist_t* d, int j) {
+  if (j <= 0) return d->lo;
+  if (j >= d->nb) return d->hi;
+  return d->lo + (double)j * d->delta;
+}
+
+enum { K_PDF = 0, K_SURV = 1, K_CDF = 2 };
+
+/* Region of the piece with centre c: -1 below support, +1 above, 0 inside
+ * (histogram: *bin receives the bin index). */
+static int d_region(const dist_t* d, double c, int* bin) {
+  if (c < d->lo) return -1;
+  if (c > d->hi) return 1;
+  if (d->model == OR_HISTOGRAM) {
+    int j = 0;
+    while (j + 1 < d->nb && d_edge(d, j + 1) <= c) ++j;
+    *bin = j;
+  }
+  return 0;
+}
+
+/*
+ * Polynomial (in s, x = c + h s) of pdf / survival / CDF of distribution d on
+ * a piece that lies inside one smooth segment of d.  dp < 0: the function
+ * itself; dp >= 0: its partial derivative w.r.t. parameter dp (uniform:
+ * 0 = lo, 1 = hi; Epanechnikov: 0 = m, 1 = w; histogram: mass index).
+ */
+static void d_poly(const dist_t* d, int kind, int dp, double c, double h, poly_t* out) {
+  int bin = 0;
+  int reg = d_region(d, c, &bin);
+  if (reg != 0) {
+    /* outside the support: pdf 0; S = total below / 0 above; F = 0 / total */
+    double v = 0.0;
+    if (dp < 0) {
+      if (kind == K_SURV && reg < 0) v = d->total;
+      if (kind == K_CDF && reg > 0) v = d->total;
+    } else if (d->model == OR_HISTOGRAM) {
+      if (kind == K_SURV && reg < 0) v = 1.0;
+      if (kind == K_CDF && reg > 0) v = 1.0;
+    }
+    p_set0(out, v);
+    return;
+  }
+  if (d->model == OR_UNIFORM) {
+    double L = d->hi - d->lo, L2 = L * L;
+    double sv = (d->hi - c) / L, sh = -h / L; /* S = (hi - x)/L */
+    double fv = (c - d->lo) / L, fh = h / L;  /* F = (x - lo)/L */
+    if (kind == K_PDF) {
+      if (dp < 0) p_set0(out, 1.0 / L);
+      else p_set0(out, dp == 0 ? 1.0 / L2 : -1.0 / L2);
+    } else if (kind == K_SURV) {
+      if (dp < 0) p_set1(out, sv, sh);
+      else if (dp == 0) p_set1(out, sv / L, sh / L); /* dS/dlo = (hi-x)/L^2 */
+      else p_set1(out, fv / L, fh / L);              /* dS/dhi = (x-lo)/L^2 */
+    } else {
+      if (dp < 0) p_set1(out, fv, fh);
+      else if (dp == 0) p_set1(out, -sv / L, -sh / L); /* dF/dlo = -(hi-x)/L^2 */
+      else p_set1(out, -fv / L, -fh / L);              /* dF/dhi = -(x-lo)/L^2 */
+    }
+    return;
+  }
+  if (d->model == OR_EPANECHNIKOV) {
+    double w = d->w, al = (c - d->m) / w, be = h / w;
+    double k = 3.0 / (4.0 * w);
+    /* pdf(u) = k (1 - u^2) */
+    double q_pdf[4] = {k, 0.0, -k, 0.0};
+    if (kind == K_PDF) {
+      if (dp < 0) {
+        p_cubic_of_linear(out, q_pdf, al, be);
+      } else if (dp == 0) { /* d pdf / dm = 3/(2 w^2) u */
+        double q[4] = {0.0, 3.0 / (2.0 * w * w), 0.0, 0.0};
+        p_cubic_of_linear(out, q, al, be);
+      } else { /* d pdf / dw = 3/(4 w^2) (3u^2 - 1) */
+        double kk = 3.0 / (4.0 * w * w);
+        double q[4] = {-kk, 0.0, 3.0 * kk, 0.0};
+        p_cubic_of_linear(out, q, al, be);
+      }
+      return;
+    }
+    double sgn = (kind == K_SURV) ? 1.0 : -1.0;
+    if (dp < 0) {
+      /* S(u) = (2 - 3u + u^3)/4, F(u) = (2 + 3u - u^3)/4 */
+      double q[4] = {0.5, -0.75 * sgn, 0.0, 0.25 * sgn};
+      p_cubic_of_linear(out, q, al, be);
+    } else if (dp == 0) { /* dS/dm = pdf, dF/dm = -pdf */
+      double q[4] = {sgn * k, 0.0, -sgn * k, 0.0};
+      p_cubic_of_linear(out, q, al, be);
+    } else { /* dS/dw = u pdf, dF/dw = -u pdf */
+      double q[4] = {0.0, sgn * k, 0.0, -sgn * k};
+      p_cubic_of_linear(out, q, al, be);
+    }
+    return;
+  }
+  /* histogram: inside bin `bin` */
+  {
+    double D = d->delta;
+    double e0 = d_edge(d, bin), e1 = d_edge(d, bin + 1);
+    double mj = d_mass(d, bin);
+    if (kind == K_PDF) {
+      if (dp < 0) p_set0(out, mj / D);
+      else p_set0(out, dp == bin ? 1.0 / D : 0.0);
+      return;
+    }
+    if (kind == K_SURV) {
+      if (dp < 0) {
+        double tail = 0.0;
+        for (int i = bin + 1; i < d->nb; ++i) tail += d_mass(d, i);
+        p_set1(out, tail + mj * (e1 - c) / D, -mj * h / D);
+      } else if (dp > bin) {
+        p_set0(out, 1.0);
+      } else if (dp == bin) {
+        p_set1(out, (e1 - c) / D, -h / D);
+      } else {
+        p_set0(out, 0.0);
+      }
+      return;
+    }
+    if (dp < 0) {
+      double head = 0.0;
+      for (int i = 0; i < bin; ++i) head += d_mass(d, i);
+      p_set1(out, head + mj * (c - e0) / D, mj * h / D);
+    } else if (dp < bin) {
+      p_set0(out, 1.0);
+    } else if (dp == bin) {
+      p_set1(out, (c - e0) / D, h / D);
+    } else {
+      p_set0(out, 0.0);
+    }
+  }
+}
+
+/* value of S or F of d at a point (used for the boundary terms) */
+static double d_point(const dist_t* d, int kind, double x) {
+  poly_t p;
+  d_poly(d, kind, -1, x, 0.0, &p);
+  return p.c[0];
+}
+
+/* ------------------------------------------------------------------------ */
+/* grids                                                                      */
+/* ------------------------------------------------------------------------ */
+typedef struct {
+  int model, H, W, nb;
+  const double* par; /* [np][H][W] */
+} grid_t;
+
+static int n_param(int model, int nb) {
+  if (model == OR_HISTOGRAM) return 2 + nb;
+  if (model == OR_MVG) return 16;
+  return 2;
+}
+
+static void grid_dist(const grid_t* g, int y, int x, dist_t* d) {
+  int64_t plane = (int64_t)g->H * g->W, at = (int64_t)y * g->W + x;
+  double p0 = g->par[at], p1 = g->par[plane + at];
+  memset(d, 0, sizeof(*d));
+  d->model = g->model;
+  d->total = 1.0;
+  if (g->model == OR_UNIFORM) {
+    d->lo = p0;
+    d->hi = p1;
+  } else if (g->model == OR_EPANECHNIKOV) {
+    d->m = p0;
+    d->w = p1;
+    d->lo = p0 - p1;
+    d->hi = p0 + p1;
+  } else {
+    d->lo = p0;
+    d->hi = p1;
+    d->nb = g->nb;
+    d->delta = (p1 - p0) / (double)g->nb;
+    d->mass = g->par + 2 * plane + at;
+    d->mstride = plane;
+    d->total = 0.0;
+    for (int j = 0; j < g->nb; ++j) d->total += d_mass(d, j);
+  }
+}
+
+static int cmp_double(const void* a, const void* b) {
+  double x = *(const double*)a, y = *(const double*)b;
+  return (x > y) - (x < y);
+}
+
+/* All breakpoints of the given distributions inside [lo, hi], sorted, unique. */
+static int breakpoints(const dist_t* ds, int nd, double lo, double hi, double* out) {
+  int n = 0;
+  out[n++] = lo;
+  out[n++] = hi;
+  for (int k = 0; k < nd; ++k) {
+    const dist_t* d = &ds[k];
+    int ne = d->model == OR_HISTOGRAM ? d->nb : 1;
+    for (int j = 0; j <= ne; ++j) {
+      double e = d->model == OR_HISTOGRAM ? d_edge(d, j) : (j == 0 ? d->lo : d->hi);
+      if (e > lo && e < hi) out[n++] = e;
+    }
+  }
+  qsort(out, (size_t)n, sizeof(double), cmp_double);
+  int u = 0;
+  for (int i = 0; i < n; ++i)
+    if (u == 0 || out[i] != out[u - 1]) out[u++] = out[i];
+  return u;
+}
+
+/*
+ * Per-vertex probabilities and (optionally) the Jacobian of P_min / P_max
+ * with respect to every parameter of the five stencil members.
+ * jmin/jmax: [NSLOT][np] (slot of an absent neighbour stays 0).
+ */
+static void cf_vertex(const grid_t* g, int y, int x, double* pmin, double* pmax, double* jmin,
+                      double* jmax) {
+  dist_t ds[NSLOT];
+  int slot_of[NSLOT]; /* ds[k] sits in stencil slot slot_of[k] */
+  int nd = 0;
+  for (int s = 0; s < NSLOT; ++s) {
+    int yy = y + SLOT_DY[s], xx = x + SLOT_DX[s];
+    if (yy < 0 || yy >= g->H || xx < 0 || xx >= g->W) continue;
+    grid_dist(g, yy, xx, &ds[nd]);
+    slot_of[nd] = s;
+    ++nd;
+  }
+  const dist_t* v = &ds[0]; /* slot 0 always exists */
+  int np = n_param(g->model, g->nb);
+  if (jmin) memset(jmin, 0, sizeof(double) * NSLOT * np);
+  if (jmax) memset(jmax, 0, sizeof(double) * NSLOT * np);
+
+  double bp[MAXBREAK];
+  int nbp = breakpoints(ds, nd, v->lo, v->hi, bp);
+  double smin = 0.0, smax = 0.0;
+  for (int i = 0; i + 1 < nbp; ++i) {
+    double c = 0.5 * (bp[i] + bp[i + 1]), h = 0.5 * (bp[i + 1] - bp[i]);
+    if (!(h > 0.0)) continue;
+    poly_t pdf, sv[NSLOT], fv[NSLOT], gs, gf, t;
+    d_poly(v, K_PDF, -1, c, h, &pdf);
+    p_set0(&gs, 1.0);
+    p_set0(&gf, 1.0);
+    for (int k = 1; k < nd; ++k) {
+      d_poly(&ds[k], K_SURV, -1, c, h, &sv[k]);
+      d_poly(&ds[k], K_CDF, -1, c, h, &fv[k]);
+      p_mul(&gs, &gs, &sv[k]);
+      p_mul(&gf, &gf, &fv[k]);
+    }
+    p_mul(&t, &pdf, &gs);
+    smin += p_integrate(&t, h);
+    p_mul(&t, &pdf, &gf);
+    smax += p_integrate(&t, h);
+    if (!jmin) continue;
+    /* own parameters: d pdf / d theta times the product of the factors */
+    int ownp = g->model == OR_HISTOGRAM ? g->nb : 2;
+    int off = g->model == OR_HISTOGRAM ? 2 : 0;
+    for (int q = 0; q < ownp; ++q) {
+      poly_t dpdf;
+      d_poly(v, K_PDF, q, c, h, &dpdf);
+      p_mul(&t, &dpdf, &gs);
+      jmin[0 * np + off + q] += p_integrate(&t, h);
+      p_mul(&t, &dpdf, &gf);
+      jmax[0 * np + off + q] += p_integrate(&t, h);
+    }
+    /* neighbour parameters: pdf * dS_k * prod_{j != k} S_j */
+    for (int k = 1; k < nd; ++k) {
+      poly_t los, lof; /* leave-one-out products */
+      p_set0(&los, 1.0);
+      p_set0(&lof, 1.0);
+      for (int j = 1; j < nd; ++j) {
+        if (j == k) continue;
+        p_mul(&los, &los, &sv[j]);
+        p_mul(&lof, &lof, &fv[j]);
+      }
+      p_mul(&los, &los, &pdf);
+      p_mul(&lof, &lof, &pdf);
+      for (int q = 0; q < ownp; ++q) {
+        poly_t dq;
+        d_poly(&ds[k], K_SURV, q, c, h, &dq);
+        p_mul(&t, &dq, &los);
+        jmin[slot_of[k] * np + off + q] += p_integrate(&t, h);
+        d_poly(&ds[k], K_CDF, q, c, h, &dq);
+        p_mul(&t, &dq, &lof);
+        jmax[slot_of[k] * np + off + q] += p_integrate(&t, h);
+      }
+    }
+  }
+  /* Leibniz terms where the uniform vertex pdf jumps (its support ends) */
+  if (jmin && g->model == OR_UNIFORM) {
+    double L = v->hi - v->lo;
+    double gs_lo = 1.0, gs_hi = 1.0, gf_lo = 1.0, gf_hi = 1.0;
+    for (int k = 1; k < nd; ++k) {
+      gs_lo *= d_point(&ds[k], K_SURV, v->lo);
+      gs_hi *= d_point(&ds[k], K_SURV, v->hi);
+      gf_lo *= d_point(&ds[k], K_CDF, v->lo);
+      gf_hi *= d_point(&ds[k], K_CDF, v->hi);
+    }
+    jmin[0] += -gs_lo / L;
+    jmin[1] += gs_hi / L;
+    jmax[0] += -gf_lo / L;
+    jmax[1] += gf_hi / L;
+  }
+  *pmin = smin;
+  *pmax = smax;
+}
+
+/* ------------------------------------------------------------------------ */
+/* public closed-form entry points                                            */
+/* ------------------------------------------------------------------------ */
+int or_n_param(int model, int nb) { return n_param(model, nb); }
+
+static int check_grid(int model, int H, int W, int nb) {
+  if (H < 1 || W < 1) return 1;
+  if (model < OR_UNIFORM || model > OR_HISTOGRAM) return 1;
+  if (model == OR_HISTOGRAM && (nb < 1 || nb > MAXNB)) return 1;
+  return 0;
+}
+
+int or_forward(int model, int H, int W, int nb, const double* params, double* pmin, double* pmax) {
+  if (check_grid(model, H, W, nb)) return 1;
+  grid_t g = {model, H, W, nb, params};
+  int64_t n = (int64_t)H * W;
+#pragma omp parallel for schedule(dynamic, 64)
+  for (int64_t i = 0; i < n; ++i) cf_vertex(&g, (int)(i / W), (int)(i % W), &pmin[i], &pmax[i], 0, 0);
+  return 0;
+}
+
+int or_forward_at(int model, int H, int W, int nb, const double* params, int64_t nidx,
+                  const int64_t* idx, double* pmin, double* pmax) {
+  if (check_grid(model, H, W, nb)) return 1;
+  grid_t g = {model, H, W, nb, params};
+#pragma omp parallel for schedule(dynamic, 16)
+  for (int64_t i = 0; i < nidx; ++i)
+    cf_vertex(&g, (int)(idx[i] / W), (int)(idx[i] % W), &pmin[i], &pmax[i], 0, 0);
+  return 0;
+}
+
+/* Jacobians of the stencil centred at each listed vertex: [nidx][NSLOT][np] */
+int or_jacobian_at(int model, int H, int W, int nb, const double* params, int64_t nidx,
+                   const int64_t* idx, double* jmin, double* jmax) {
+  if (check_grid(model, H, W, nb)) return 1;
+  grid_t g = {model, H, W, nb, params};
+  int np = n_param(model, nb);
+#pragma omp parallel for schedule(dynamic, 16)
+  for (int64_t i = 0; i < nidx; ++i) {
+    double a, b;
+    cf_vertex(&g, (int)(idx[i] / W), (int)(idx[i] % W), &a, &b, jmin + i * NSLOT * np,
+              jmax + i * NSLOT * np);
+  }
+  return 0;
+}
+
+/*
+ * Adjoint: grad[k][u] = sum over stencils v containing u of
+ *   g_min(v) dP_min(v)/dtheta_k(u) + g_max(v) dP_max(v)/dtheta_k(u).
+ * Computed for the listed vertices u only (out: [nidx][np]).
+ */
+int or_grad_at(int model, int H, int W, int nb, const double* params, const double* gmin,
+               const double* gmax, int64_t nidx, const int64_t* idx, double* out) {
+  if (check_grid(model, H, W, nb)) return 1;
+  grid_t g = {model, H, W, nb, params};
+  int np = n_param(model, nb);
+#pragma omp parallel for schedule(dynamic, 4)
+  for (int64_t i = 0; i < nidx; ++i) {
+    int y = (int)(idx[i] / W), x = (int)(idx[i] % W);
+    double* o = out + i * np;
+    for (int k = 0; k < np; ++k) o[k] = 0.0;
+    double jm[NSLOT * (2 + MAXNB)], jx[NSLOT * (2 + MAXNB)];
+    /* u sits in slot 0 of its own stencil and in slot s of the stencil
+       centred at u - offset(s) */
+    for (int s = 0; s < NSLOT; ++s) {
+      int vy = y - SLOT_DY[s], vx = x - SLOT_DX[s];
+      if (vy < 0 || vy >= H || vx < 0 || vx >= W) continue;
+      double a, b;
+      cf_vertex(&g, vy, vx, &a, &b, jm, jx);
+      int64_t at = (int64_t)vy * W + vx;
+      for (int k = 0; k < np; ++k) o[k] += gmin[at] * jm[s * np + k] + gmax[at] * jx[s * np + k];
+    }
+  }
+  return 0;
+}
+
+int or_grad(int model, int H, int W, int nb, const double* params, const double* gmin,
+            const double* gmax, double* grad) {
+  if (check_grid(model, H, W, nb)) return 1;
+  int64_t n = (int64_t)H * W;
+  int np = n_param(model, nb);
+  double* tmp = (double*)malloc(sizeof(double) * n * np);
+  int64_t* idx = (int64_t*)malloc(sizeof(int64_t) * n);
+  if (!tmp || !idx) {
+    free(tmp);
+    free(idx);
+    return 2;
+  }
+  for (int64_t i = 0; i < n; ++i) idx[i] = i;
+  int rc = or_grad_at(model, H, W, nb, params, gmin, gmax, n, idx, tmp);
+  for (int64_t i = 0; i < n; ++i)
+    for (int k = 0; k < np; ++k) grad[k * n + i] = tmp[i * np + k];
+  free(tmp);
+  free(idx);
+  return rc;
+}
+
+/* ------------------------------------------------------------------------ */
+/* fitting per-vertex models from ensemble members (Sec. 5.1, 5.2, 5.3)      */
+/* ------------------------------------------------------------------------ */
+/*
+ * members: [M][H][W] doubles.  single != 0 means the field is FP32: the
+ * members are FP32 values, and every decision that floating point makes
+ * (the widening of a degenerate range, the histogram bin of a member) is
+ * taken in FP32 arithmetic, as the device does.  Statistics are FP64.
+ *
+ *  uniform       lo = min, hi = max                         (Sec. 5.1, 5.2)
+ *  Epanechnikov  m = mean, w = bw * std(ddof) * M^(-1/5)     (Sec. 5.2: range
+ *                from sample mean and standard deviation)
+ *  histogram     lo = min, hi = max, nb equal-width bins, mass = count / M;
+ *                member in bin floor((x - lo) / (hi - lo) * nb), the maximum
+ *                in the last bin                             (Sec. 4.4)
+ *  degenerate    (all members equal) lo/hi = x -/+ eps * max(1, |x|);
+ *                Epanechnikov w = eps * max(1, |m|)
+ */
+int or_fit(int model, int single, const double* members, int M, int H, int W, int nb, int ddof,
+           double bw, double eps, double* params) {
+  if (H < 1 || W < 1 || M < 1) return 1;
+  if (model < OR_UNIFORM || model > OR_HISTOGRAM) return 1;
+  if (model == OR_HISTOGRAM && (nb < 1 || nb > MAXNB)) return 1;
+  int64_t n = (int64_t)H * W;
+#pragma omp parallel for schedule(static)
+  for (int64_t i = 0; i < n; ++i) {
+    double mn = members[i], mx = members[i], sum = 0.0;
+    for (int k = 0; k < M; ++k) {
+      double xk = members[(int64_t)k * n + i];
+      if (xk < mn) mn = xk;
+      if (xk > mx) mx = xk;
+      sum += xk;
+    }
+    double lo = mn, hi = mx;
+    if (mn == mx) {
+      if (single) {
+        float e = (float)eps * fmaxf(1.0f, fabsf((float)mn));
+        lo = (double)((float)mn - e);
+        hi = (double)((float)mn + e);
+      } else {
+        double e = eps * fmax(1.0, fabs(mn));
+        lo = mn - e;
+        hi = mn + e;
+      }
+    }
+    if (model == OR_UNIFORM) {
+      params[i] = lo;
+      params[n + i] = hi;
+    } else if (model == OR_EPANECHNIKOV) {
+      double mean = sum / (double)M, ss = 0.0;
+      for (int k = 0; k < M; ++k) {
+        double dk = members[(int64_t)k * n + i] - mean;
+        ss += dk * dk;
+      }
+      double w;
+      if (mn == mx) {
+        w = eps * fmax(1.0, fabs(mean));
+      } else {
+        double sd = sqrt(ss / (double)(M - ddof));
+        w = bw * sd * pow((double)M, -0.2);
+      }
+      params[i] = mean;
+      params[n + i] = w;
+    } else {
+      params[i] = lo;
+      params[n + i] = hi;
+      int cnt[MAXNB];
+      for (int j = 0; j < nb; ++j) cnt[j] = 0;
+      for (int k = 0; k < M; ++k) {
+        double xk = members[(int64_t)k * n + i];
+        int j;
+        if (single) {
+          float d = (float)xk - (float)lo;
+          float r = (float)hi - (float)lo;
+          float t = d / r;
+          float yb = t * (float)nb;
+          j = (int)yb;
+        } else {
+          double t = (xk - lo) / (hi - lo);
+          j = (int)(t * (double)nb);
+        }
+        if (j > nb - 1) j = nb - 1;
+        if (j < 0) j = 0;
+        cnt[j]++;
+      }
+      for (int j = 0; j < nb; ++j) params[(int64_t)(2 + j) * n + i] = (double)cnt[j] / (double)M;
+    }
+  }
+  return 0;
+}
+
+/* ------------------------------------------------------------------------ */
+/* multivariate Gaussian over the stencil, Monte Carlo                         */
+/* ------------------------------------------------------------------------ */
+/*
+ * Philox4x32-10 (Salmon, Moraes, Dror, Shaw, "Parallel random numbers: as
+ * easy as 1, 2, 3", SC'11): a 4x32-bit counter and a 2x32-bit key; ten
+ * rounds; each round multiplies counter words 0 and 2 by two fixed odd
+ * constants, keeps high and low halves of the 64-bit products, xors the high
+ * halves with the other two counter words and the key, and permutes; the key
+ * is advanced by two Weyl constants between rounds.
+ */
+void or_philox4x32_10(const uint32_t ctr_in[4], const uint32_t key_in[2], uint32_t out[4]) {
+  const uint32_t M0 = 0xD2511F53u, M1 = 0xCD9E8D57u;
+  const uint32_t W0 = 0x9E3779B9u, W1 = 0xBB67AE85u;
+  uint32_t c0 = ctr_in[0], c1 = ctr_in[1], c2 = ctr_in[2], c3 = ctr_in[3];
+  uint32_t k0 = key_in[0], k1 = key_in[1];
+  for (int r = 0; r < 10; ++r) {
+    uint64_t p0 = (uint64_t)M0 * c0, p1 = (uint64_t)M1 * c2;
+    uint32_t hi0 = (uint32_t)(p0 >> 32), lo0 = (uint32_t)p0;
+    uint32_t hi1 = (uint32_t)(p1 >> 32), lo1 = (uint32_t)p1;
+    uint32_t n0 = hi1 ^ c1 ^ k0, n1 = lo1, n2 = hi0 ^ c3 ^ k1, n3 = lo0;
+    c0 = n0;
+    c1 = n1;
+    c2 = n2;
+    c3 = n3;
+    k0 += W0;
+    k1 += W1;
+  }
+  out[0] = c0;
+  out[1] = c1;
+  out[2] = c2;
+  out[3] = c3;
+}
+
+/* 24 high bits of a 32-bit word, centred in (0, 1): exact in FP32 and FP64 */
+static double u24(uint32_t r) { return ((double)(r >> 8) + 0.5) * (1.0 / 16777216.0); }
+
+static double phi_cdf(double r) { return 0.5 * erfc(-r / sqrt(2.0)); }
+static double phi_pdf(double r) { return exp(-0.5 * r * r) / sqrt(2.0 * M_PI); }
+
+/* stencil variable order for the Gaussian model: e, n, w, s, v */
+static const int MVG_SLOT[5] = {1, 2, 3, 4, 0}; /* variable -> stencil slot */
+static int tri(int i, int j) { return i * (i + 1) / 2 + j; }
+
+/*
+ * Fit: mean plane; per vertex the 5x5 covariance of (e, n, w, s, v) across
+ * members (ddof), plus jitter on the diagonal; FP64 Cholesky.  An absent
+ * neighbour gets an identity row/column, which leaves the factor of the
+ * present variables equal to the factor of their own covariance.
+ * members [M][H][W]; params [16][H][W].  Returns 3 if a matrix is not
+ * positive definite.
+ */
+int or_mvg_fit(const double* members, int M, int H, int W, int ddof, double jitter, double* params) {
+  if (H < 1 || W < 1 || M < 2 || M - ddof < 1) return 1;
+  int64_t n = (int64_t)H * W;
+  int bad = 0;
+#pragma omp parallel for schedule(static)
+  for (int64_t i = 0; i < n; ++i) {
+    double s = 0.0;
+    for (int k = 0; k < M; ++k) s += members[(int64_t)k * n + i];
+    params[i] = s / (double)M;
+  }
+#pragma omp parallel for schedule(static) reduction(| : bad)
+  for (int64_t i = 0; i < n; ++i) {
+    int y = (int)(i / W), x = (int)(i % W);
+    int64_t at[5];
+    int present[5];
+    double mu[5];
+    for (int a = 0; a < 5; ++a) {
+      int s = MVG_SLOT[a];
+      int yy = y + SLOT_DY[s], xx = x + SLOT_DX[s];
+      present[a] = !(yy < 0 || yy >= H || xx < 0 || xx >= W);
+      at[a] = present[a] ? (int64_t)yy * W + xx : 0;
+      mu[a] = 0.0;
+      if (present[a]) {
+        double sm = 0.0;
+        for (int k = 0; k < M; ++k) sm += members[(int64_t)k * n + at[a]];
+        mu[a] = sm / (double)M;
+      }
+    }
+    double C[5][5];
+    for (int a = 0; a < 5; ++a)
+      for (int b = 0; b < 5; ++b) {
+        if (!present[a] || !present[b]) {
+          C[a][b] = (a == b) ? 1.0 : 0.0;
+          continue;
+        }
+        double acc = 0.0;
+        for (int k = 0; k < M; ++k)
+          acc += (members[(int64_t)k * n + at[a]] - mu[a]) * (members[(int64_t)k * n + at[b]] - mu[b]);
+        C[a][b] = acc / (double)(M - ddof) + (a == b ? jitter : 0.0);
+      }
+    double L[5][5];
+    memset(L, 0, sizeof(L));
+    for (int r = 0; r < 5; ++r) {
+      for (int c = 0; c <= r; ++c) {
+        double acc = C[r][c];
+        for (int k = 0; k < c; ++k) acc -= L[r][k] * L[c][k];
+        if (r == c) {
+          if (!(acc > 0.0)) {
+            bad |= 1;
+            acc = 1.0;
+          }
+          L[r][c] = sqrt(acc);
+        } else {
+          L[r][c] = acc / L[c][c];
+        }
+      }
+    }
+    for (int r = 0; r < 5; ++r)
+      for (int c = 0; c <= r; ++c) params[(int64_t)(1 + tri(r, c)) * n + i] = L[r][c];
+  }
+  return bad ? 3 : 0;
+}
+
+typedef struct {
+  double hit_min, hit_max, rb_min, rb_max;
+  int amb_min, amb_max;
+  double dmu_min[NSLOT], dmu_max[NSLOT]; /* by stencil slot */
+  double dl_min[15], dl_max[15];
+} mvg_out_t;
+
+/*
+ * One vertex.  Sample i uses Philox counters (i, vertex id, field_id, 0) and
+ * (i, vertex id, field_id, 1) under key (seed lo, seed hi).  Words of the
+ * first block give the uniform pairs (u0,u1), (u2,u3); the first two words of
+ * the second block give (u4,u5).  Box-Muller: z_2k = sqrt(-2 ln u_2k)
+ * cos(2 pi u_2k+1), z_2k+1 = sqrt(-2 ln u_2k) sin(2 pi u_2k+1); z0..z4 drive
+ * (e, n, w, s, v): x = mu + L z.
+ *
+ * Hit count: [x_v < min x_n] (resp. > max).  Conditional estimator: given
+ * z0..z3 the vertex value is N(c, L44^2) with c = mu_v + sum_j<4 L4j z_j, so
+ * Pr(min) = Phi((min_n x_n - c) / L44), Pr(max) = Phi((c - max_n x_n) / L44).
+ * Gradient: pathwise derivative of the conditional estimator.
+ * amb_*: samples whose hit decision has a margin below 1e-5 * max row norm of L.
+ */
+static void mvg_vertex(const double* par, int H, int W, int y, int x, int ns, uint64_t seed,
+                       uint32_t field_id, int want_grad, mvg_out_t* o) {
+  int64_t n = (int64_t)H * W, at_v = (int64_t)y * W + x;
+  double mu[5], L[5][5];
+  int present[5];
+  for (int a = 0; a < 5; ++a) {
+    int s = MVG_SLOT[a];
+    int yy = y + SLOT_DY[s], xx = x + SLOT_DX[s];
+    present[a] = !(yy < 0 || yy >= H || xx < 0 || xx >= W);
+    mu[a] = present[a] ? par[(int64_t)yy * W + xx] : 0.0;
+  }
+  for (int r = 0; r < 5; ++r)
+    for (int c = 0; c < 5; ++c) L[r][c] = c <= r ? par[(int64_t)(1 + tri(r, c)) * n + at_v] : 0.0;
+  double rowmax = 0.0;
+  for (int r = 0; r < 5; ++r) {
+    if (!present[r]) continue;
+    double s2 = 0.0;
+    for (int c = 0; c <= r; ++c) s2 += L[r][c] * L[r][c];
+    if (sqrt(s2) > rowmax) rowmax = sqrt(s2);
+  }
+  double tau = 1e-5 * rowmax;
+  int nnb = present[0] + present[1] + present[2] + present[3];
+  memset(o, 0, sizeof(*o));
+  uint32_t key[2] = {(uint32_t)seed, (uint32_t)(seed >> 32)};
+  double L44 = L[4][4];
+  for (int i = 0; i < ns; ++i) {
+    uint32_t c0[4] = {(uint32_t)i, (uint32_t)at_v, field_id, 0u}, r0[4];
+    uint32_t c1[4] = {(uint32_t)i, (uint32_t)at_v, field_id, 1u}, r1[4];
+    or_philox4x32_10(c0, key, r0);
+    or_philox4x32_10(c1, key, r1);
+    double u[6] = {u24(r0[0]), u24(r0[1]), u24(r0[2]), u24(r0[3]), u24(r1[0]), u24(r1[1])};
+    double z[6];
+    for (int k = 0; k < 3; ++k) {
+      double rad = sqrt(-2.0 * log(u[2 * k]));
+      z[2 * k] = rad * cos(2.0 * M_PI * u[2 * k + 1]);
+      z[2 * k + 1] = rad * sin(2.0 * M_PI * u[2 * k + 1]);
+    }
+    double xv[5];
+    for (int r = 0; r < 5; ++r) {
+      double acc = mu[r];
+      for (int c = 0; c <= r; ++c) acc += L[r][c] * z[c];
+      xv[r] = acc;
+    }
+    if (nnb == 0) {
+      o->hit_min += 1.0;
+      o->hit_max += 1.0;
+      o->rb_min += 1.0;
+      o->rb_max += 1.0;
+      continue;
+    }
+    int amin = -1, amax = -1;
+    for (int r = 0; r < 4; ++r) {
+      if (!present[r]) continue;
+      if (amin < 0 || xv[r] < xv[amin]) amin = r;
+      if (amax < 0 || xv[r] > xv[amax]) amax = r;
+    }
+    double lo = xv[amin], hi = xv[amax];
+    o->hit_min += xv[4] < lo ? 1.0 : 0.0;
+    o->hit_max += xv[4] > hi ? 1.0 : 0.0;
+    if (fabs(xv[4] - lo) < tau) o->amb_min++;
+    if (fabs(xv[4] - hi) < tau) o->amb_max++;
+    double cmean = mu[4];
+    for (int c = 0; c < 4; ++c) cmean += L[4][c] * z[c];
+    double rmin = (lo - cmean) / L44, rmax = (cmean - hi) / L44;
+    o->rb_min += phi_cdf(rmin);
+    o->rb_max += phi_cdf(rmax);
+    if (!want_grad) continue;
+    /* d Phi(r) = phi(r) dr;  r_min = (x_amin - c) / L44 */
+    double gmin = phi_pdf(rmin) / L44, gmax = phi_pdf(rmax) / L44;
+    o->dmu_min[MVG_SLOT[amin]] += gmin;
+    o->dmu_min[0] -= gmin;
+    for (int c = 0; c <= amin; ++c) o->dl_min[tri(amin, c)] += gmin * z[c];
+    for (int c = 0; c < 4; ++c) o->dl_min[tri(4, c)] -= gmin * z[c];
+    o->dl_min[tri(4, 4)] -= gmin * rmin;
+    /* r_max = (c - x_amax) / L44 */
+    o->dmu_max[0] += gmax;
+    o->dmu_max[MVG_SLOT[amax]] -= gmax;
+    for (int c = 0; c < 4; ++c) o->dl_max[tri(4, c)] += gmax * z[c];
+    for (int c = 0; c <= amax; ++c) o->dl_max[tri(amax, c)] -= gmax * z[c];
+    o->dl_max[tri(4, 4)] -= gmax * rmax;
+  }
+  double inv = 1.0 / (double)ns;
+  o->hit_min *= inv;
+  o->hit_max *= inv;
+  o->rb_min *= inv;
+  o->rb_max *= inv;
+  for (int k = 0; k < NSLOT; ++k) {
+    o->dmu_min[k] *= inv;
+    o->dmu_max[k] *= inv;
+  }
+  for (int k = 0; k < 15; ++k) {
+    o->dl_min[k] *= inv;
+    o->dl_max[k] *= inv;
+  }
+}
+
+/* out: [nidx][4] = hit_min, hit_max, rb_min, rb_max; amb: [nidx][2] */
+int or_mvg_forward_at(const double* params, int H, int W, int ns, uint64_t seed, uint32_t field_id,
+                      int64_t nidx, const int64_t* idx, double* out, int32_t* amb) {
+  if (H < 1 || W < 1 || ns < 1) return 1;
+#pragma omp parallel for schedule(dynamic, 4)
+  for (int64_t i = 0; i < nidx; ++i) {
+    mvg_out_t o;
+    mvg_vertex(params, H, W, (int)(idx[i] / W), (int)(idx[i] % W), ns, seed, field_id, 0, &o);
+    out[4 * i + 0] = o.hit_min;
+    out[4 * i + 1] = o.hit_max;
+    out[4 * i + 2] = o.rb_min;
+    out[4 * i + 3] = o.rb_max;
+    amb[2 * i + 0] = o.amb_min;
+    amb[2 * i + 1] = o.amb_max;
+  }
+  return 0;
+}
+
+/*
+ * Gradient of the conditional estimator: for listed vertices u,
+ * out[i][0] = d/dmu(u) gathered over the stencils containing u,
+ * out[i][1..15] = d/dL(u) (the factor is local to its stencil).
+ */
+int or_mvg_grad_at(const double* params, int H, int W, int ns, uint64_t seed, uint32_t field_id,
+                   const double* gmin, const double* gmax, int64_t nidx, const int64_t* idx,
+                   double* out) {
+  if (H < 1 || W < 1 || ns < 1) return 1;
+#pragma omp parallel for schedule(dynamic, 2)
+  for (int64_t i = 0; i < nidx; ++i) {
+    int y = (int)(idx[i] / W), x = (int)(idx[i] % W);
+    double* o = out + 16 * i;
+    for (int k = 0; k < 16; ++k) o[k] = 0.0;
+    for (int s = 0; s < NSLOT; ++s) {
+      int vy = y - SLOT_DY[s], vx = x - SLOT_DX[s];
+      if (vy < 0 || vy >= H || vx < 0 || vx >= W) continue;
+      mvg_out_t r;
+      mvg_vertex(params, H, W, vy, vx, ns, seed, field_id, 1, &r);
+      int64_t at = (int64_t)vy * W + vx;
+      o[0] += gmin[at] * r.dmu_min[s] + gmax[at] * r.dmu_max[s];
+      if (s == 0)
+        for (int k = 0; k < 15; ++k) o[1 + k] += gmin[at] * r.dl_min[k] + gmax[at] * r.dl_max[k];
+    }
+  }
+  return 0;
+}
