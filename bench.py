@@ -1,0 +1,281 @@
+#!/usr/bin/env python
+"""Benchmark of the critical-point probability hot path on one MI355X.
+
+Step (the quoted workload): Epanechnikov model on a 2048 x 2048 grid with 20
+ensemble members per vertex (smooth base field + box-smoothed noise): fit the
+per-vertex (centre, half-width) from the members, forward P_min / P_max, and
+the adjoint dP/dtheta for seeded upstream gradients -- every row of the hot
+path for that workload, inputs resident in HBM.
+
+Prints one JSON line.  `value` = grid vertices processed per second by the
+whole step.  `detail` carries per-stage and per-model rates (uniform FP64
+64^2, uniform / histogram 2048^2, Gaussian Monte Carlo 1024^2 x 4096 samples,
+batched 64 fields vs one launch per field); `roofline` describes the
+dominant kernel; `cpu_baseline` times the FP64 oracle on a bounded sample.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+METRIC = "vertex-probabilities/s (fwd, fwd+bwd) per model; batched vs plain at 1e-6 abs err"
+UNIT = "vertex-probabilities/s"
+PEAK_FP32_VALU = 157.3e12  # FLOP/s, MI355X dense vector FP32 (packed issue)
+
+
+def parse():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--size", type=int, default=2048)
+    ap.add_argument("--no-detail", action="store_true", help="only the quoted step")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--profile-only", action="store_true",
+                    help="run the quoted step only (for rocprofv3), no JSON detail")
+    return ap.parse_args()
+
+
+# ----------------------------------------------------------------------------
+# algorithmic work of the Epanechnikov kernels (roofline)
+# ----------------------------------------------------------------------------
+GL_NODES = {1: 3, 2: 5, 3: 6, 4: 8}  # exact rule for a piece with k started neighbours
+
+
+def flops_fwd_piece(k):
+    if k == 0:
+        return 6
+    return 8 + 4 * k + GL_NODES[k] * (6 + 6 * k)
+
+
+def flops_bwd_piece(k):
+    if k == 0:
+        return 10
+    return 10 + 8 * k + GL_NODES[k] * (10 + 18 * k)
+
+
+def epa_piece_counts(params: np.ndarray) -> np.ndarray:
+    """counts[k] = number of non-empty pieces with k started neighbours over
+    all vertices and both sides (minimum, and maximum by reflection)."""
+    m = params[0].astype(np.float64)
+    w = params[1].astype(np.float64)
+    H, W = m.shape
+    counts = np.zeros(5, dtype=np.int64)
+    pad = lambda a, v: np.pad(a, 1, constant_values=v)
+    mp, wp = pad(m, np.nan), pad(w, np.nan)
+    nbr = [(mp[1:-1, 2:], wp[1:-1, 2:]), (mp[:-2, 1:-1], wp[:-2, 1:-1]), (mp[1:-1, :-2], wp[1:-1, :-2]),
+           (mp[2:, 1:-1], wp[2:, 1:-1])]
+    for sign in (1.0, -1.0):
+        bmin = w.copy()
+        starts = []
+        for mn, wn in nbr:
+            d = sign * (mn - m)
+            pres = np.isfinite(d)
+            bmin = np.where(pres, np.minimum(bmin, d + wn), bmin)
+        for mn, wn in nbr:
+            d = sign * (mn - m)
+            pres = np.isfinite(d)
+            starts.append(np.where(pres, np.clip(d - wn, -w, bmin), bmin))
+        c = np.sort(np.stack(starts), axis=0)
+        ok = bmin > -w
+        edges = np.concatenate([-w[None], c, bmin[None]])
+        for k in range(5):
+            counts[k] += int(np.count_nonzero(ok & (edges[k + 1] > edges[k])))
+    return counts
+
+
+def epa_flops(params: np.ndarray):
+    c = epa_piece_counts(params)
+    fwd = sum(int(c[k]) * flops_fwd_piece(k) for k in range(5))
+    bwd = sum(int(c[k]) * flops_bwd_piece(k) for k in range(5)) + 8 * params.shape[1] * params.shape[2]
+    return fwd, bwd, c
+
+
+# ----------------------------------------------------------------------------
+def main():
+    args = parse()
+    if args.gpus != 1:
+        print("bench.py measures one GPU: this build has no multi-GPU path (fields shard by rows or by "
+              "field with no communication; see DESIGN.md).  Run with --gpus 1.", file=sys.stderr)
+        sys.exit(2)
+    import torch
+
+    import paper_2407_18015_amd as cp
+    import workloads
+
+    dev = torch.device("cuda:0")
+    torch.cuda.set_device(dev)
+    S = args.size
+    t0 = time.time()
+    mem_np = workloads.smooth_ensemble(0, S, S)
+    gmin_np, gmax_np = workloads.upstream(0, S, S)
+    print(f"[bench] inputs generated in {time.time() - t0:.1f}s", file=sys.stderr, flush=True)
+    mem = torch.as_tensor(mem_np, device=dev)
+    gmin = torch.as_tensor(gmin_np, device=dev)
+    gmax = torch.as_tensor(gmax_np, device=dev)
+    E = 1
+    f = cp.Field(S, S, E, torch.float32)
+    params = torch.empty((2, S, S), device=dev)
+    pmin = torch.empty((S, S), device=dev)
+    pmax = torch.empty((S, S), device=dev)
+    grad = torch.empty((2, S, S), device=dev)
+
+    def step():
+        cp.fit(mem, E, out=params)
+        cp.forward(params, f, pmin, pmax)
+        cp.backward(params, gmin, gmax, f, grad)
+
+    for _ in range(args.warmup):
+        step()
+    torch.cuda.synchronize()
+    ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    ev0.record()
+    for _ in range(args.steps):
+        step()
+    ev1.record()
+    torch.cuda.synchronize()
+    ms = ev0.elapsed_time(ev1) / args.steps
+    value = S * S / (ms * 1e-3)
+    print(f"[bench] step {ms:.3f} ms", file=sys.stderr, flush=True)
+    if args.profile_only:
+        return
+
+    def timed(fn, reps):
+        fn()
+        torch.cuda.synchronize()
+        a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        a.record()
+        for _ in range(reps):
+            fn()
+        b.record()
+        torch.cuda.synchronize()
+        return a.elapsed_time(b) / reps
+
+    reps = max(5, args.steps)
+    t_fit = timed(lambda: cp.fit(mem, E, out=params), reps)
+    t_fwd = timed(lambda: cp.forward(params, f, pmin, pmax), reps)
+    t_bwd = timed(lambda: cp.backward(params, gmin, gmax, f, grad), reps)
+    ph = params.cpu().numpy()
+    fl_fwd, fl_bwd, counts = epa_flops(ph)
+    roof = {"bound": "alu", "kernel": "adjoint, Epanechnikov FP32 (k_bwd_ue)", "achieved": fl_bwd / (t_bwd * 1e-3) / 1e12,
+            "peak": PEAK_FP32_VALU / 1e12, "unit": "TFLOP/s",
+            "frac": fl_bwd / (t_bwd * 1e-3) / PEAK_FP32_VALU, "traffic": None,
+            "algorithmic_flops_per_launch": fl_bwd}
+    detail = {
+        "epanechnikov_2048": {
+            "fit_ms": t_fit, "fwd_ms": t_fwd, "bwd_ms": t_bwd,
+            "fwd_vertices_per_s": S * S / (t_fwd * 1e-3),
+            "fwd_bwd_vertices_per_s": S * S / ((t_fwd + t_bwd) * 1e-3),
+            "fwd_tflops": fl_fwd / (t_fwd * 1e-3) / 1e12, "bwd_tflops": fl_bwd / (t_bwd * 1e-3) / 1e12,
+            "fit_hbm_gbs": (20 * 4 + 8) * S * S / (t_fit * 1e-3) / 1e9,
+            "pieces_by_started_neighbours": counts.tolist(),
+        }
+    }
+    if not args.no_detail:
+        detail.update(more_detail(cp, workloads, torch, dev, S, reps))
+
+    cpu = None
+    if not args.no_cpu_baseline:
+        cpu = cpu_baseline(mem_np, gmin_np, gmax_np)
+
+    out = {
+        "metric": METRIC, "value": value, "unit": UNIT, "n_gpus": 1, "steps": args.steps,
+        "warmup": args.warmup, "ms_per_step": ms, "higher_is_better": True, "scaling": "weak",
+        "vs_baseline": None, "dtype": "f32", "data": "synthetic",
+        "config": {"workload": f"epanechnikov fit+forward+adjoint, {S}x{S} grid, 20 members, FP32",
+                   "grid": [S, S], "members": 20, "model": "epanechnikov"},
+        "roofline": roof, "cpu_baseline": cpu, "detail": detail,
+    }
+    print(json.dumps(out), flush=True)
+
+
+def more_detail(cp, workloads, torch, dev, S, reps):
+    res = {}
+    # uniform FP64 64x64
+    p = torch.as_tensor(workloads.uniform_params_field(0, 64, 64), device=dev)
+    f = cp.field_of(p, 0)
+    a, b = torch.empty((64, 64), dtype=torch.float64, device=dev), torch.empty((64, 64), dtype=torch.float64,
+                                                                                device=dev)
+    t = _timed(torch, lambda: cp.forward(p, f, a, b), reps)
+    res["uniform_fp64_64"] = {"fwd_ms": t, "fwd_vertices_per_s": 64 * 64 / (t * 1e-3)}
+    # uniform and histogram at S^2
+    for name, model, gen, nb in (("uniform_2048", 0, workloads.smooth_ensemble, 0),
+                                 ("histogram_2048", 2, workloads.mixture_ensemble, 10)):
+        mem = torch.as_tensor(gen(1, S, S), device=dev)
+        params = cp.fit(mem, model, nbins=nb)
+        del mem
+        f = cp.field_of(params, model, nb)
+        g1, g2 = (torch.as_tensor(x, device=dev) for x in workloads.upstream(1, S, S))
+        a, b = torch.empty((S, S), device=dev), torch.empty((S, S), device=dev)
+        grad = torch.empty_like(params)
+        tf = _timed(torch, lambda: cp.forward(params, f, a, b), reps)
+        tb = _timed(torch, lambda: cp.backward(params, g1, g2, f, grad), max(3, reps // 2))
+        res[name] = {"fwd_ms": tf, "bwd_ms": tb, "fwd_vertices_per_s": S * S / (tf * 1e-3),
+                     "fwd_bwd_vertices_per_s": S * S / ((tf + tb) * 1e-3)}
+        del params, grad
+    # multivariate Gaussian 1024^2, 4096 samples
+    n = 1024
+    mem = torch.as_tensor(workloads.correlated_ensemble(0, n, n), device=dev)
+    params = cp.fit(mem, "mvg")
+    del mem
+    g1, g2 = (torch.as_tensor(x, device=dev) for x in workloads.upstream(2, n, n))
+    a, b = torch.empty((n, n), device=dev), torch.empty((n, n), device=dev)
+    grad = torch.empty_like(params)
+    fr = cp.Field(n, n, 3, torch.float32, nsamples=4096, seed=1, estimator=0)
+    fh = cp.Field(n, n, 3, torch.float32, nsamples=4096, seed=1, estimator=1)
+    t_rb = _timed(torch, lambda: cp.forward(params, fr, a, b), 3)
+    t_hit = _timed(torch, lambda: cp.forward(params, fh, a, b), 3)
+    t_bwd = _timed(torch, lambda: cp.backward(params, g1, g2, fr, grad), 3)
+    res["mvg_1024_4096"] = {"fwd_conditional_ms": t_rb, "fwd_hit_ms": t_hit, "bwd_ms": t_bwd,
+                            "fwd_vertices_per_s": n * n / (t_rb * 1e-3),
+                            "fwd_bwd_vertices_per_s": n * n / ((t_rb + t_bwd) * 1e-3),
+                            "samples_per_s_conditional": n * n * 4096 / (t_rb * 1e-3)}
+    return res
+
+
+def _timed(torch, fn, reps):
+    fn()
+    torch.cuda.synchronize()
+    a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    a.record()
+    for _ in range(reps):
+        fn()
+    b.record()
+    torch.cuda.synchronize()
+    return a.elapsed_time(b) / reps
+
+
+def cpu_baseline(mem_np, gmin_np, gmax_np, budget_s=12.0, band=32):
+    """The FP64 oracle (C, OpenMP, untuned) on bands of full-width rows of the
+    same workload: fit, forward and adjoint per band, bands taken from the top
+    until about `budget_s` seconds of work."""
+    import oracle
+    H, W = mem_np.shape[1], mem_np.shape[2]
+    done, dt, y = 0, 0.0, 0
+    while dt < budget_s and y + band <= H:
+        lo, hi = max(0, y - 1), min(H, y + band + 1)
+        sub = mem_np[:, lo:hi, :].astype(np.float64)
+        g1 = gmin_np[lo:hi].astype(np.float64)
+        g2 = gmax_np[lo:hi].astype(np.float64)
+        rows = np.arange(y - lo, y - lo + band)
+        idx = (rows[:, None] * W + np.arange(W)[None, :]).ravel().astype(np.int64)
+        t = time.time()
+        par = oracle.fit(1, sub, single=True)
+        oracle.forward_at(1, par, idx)
+        oracle.grad_at(1, par, g1, g2, idx)
+        dt += time.time() - t
+        done += band * W
+        y += band
+    cores = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
+    return {"value": done / dt, "unit": UNIT, "cores": cores, "kind": "oracle",
+            "sample": f"fit+forward+adjoint of the first {done // W} rows x {W} columns of the same "
+                      f"20-member field, in bands of {band} rows", "seconds": dt}
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,196 @@
+/*
+ * cpcrit.h -- C ABI of the MI355X critical-point probability library.
+ *
+ * The library computes, for every vertex of a 2-D regular grid whose values
+ * are random variables, the probability that the vertex is a local minimum
+ * or a local maximum against its (up to) four axis neighbours (Athawale et
+ * al., arXiv 2407.18015, Sec. 3 problem setting; Eq. 1 and Eq. 3 for the
+ * minimum, Sec. 4.1.2 / 4.2 for the maximum by negation).  Vertex values are
+ * independent (Sec. 3), so
+ *
+ *     P_min(v) = integral pdf_v(x) prod_n Pr(X_n > x) dx,
+ *     P_max(v) = integral pdf_v(x) prod_n Pr(X_n < x) dx,
+ *
+ * evaluated exactly, piece by piece between the merged support breakpoints
+ * (Sec. 4.1.1 Tasks 1-3), for the uniform and Epanechnikov models (Sec. 4.3)
+ * and the histogram model (Sec. 4.4.1, Eq. 5).  A correlated multivariate
+ * Gaussian over the 5-point stencil (the prior-work model of Sec. 5.2/5.3) is
+ * estimated by Monte Carlo.  Gradients of the probabilities with respect to
+ * the model parameters, fitting from ensemble members (Sec. 5.1-5.3) and a
+ * batched entry point for many fields complete the interface.
+ *
+ * Conventions shared by every entry point
+ * ---------------------------------------
+ *  - All array arguments are DEVICE pointers owned by the caller; the
+ *    library never frees or retains them.  Calls are asynchronous on
+ *    `stream` (a hipStream_t; NULL = the null stream): results are ready
+ *    once the caller synchronises that stream.
+ *  - A field is H x W vertices.  Every plane (parameters, probabilities,
+ *    upstream gradients, parameter gradients, members) is row-major with
+ *    `row_stride` elements between rows (0 means W) and H * row_stride
+ *    elements between consecutive planes of one array.
+ *  - Vertex (y, x) has neighbours e = (y, x+1), n = (y-1, x), w = (y, x-1),
+ *    s = (y+1, x).  Neighbours outside the grid are not part of the stencil
+ *    (edge vertices have 3, corners 2, a 1x1 grid none, giving P = 1).
+ *  - Element type of parameters, probabilities and gradients = desc->dtype,
+ *    except the multivariate Gaussian, whose parameters and parameter
+ *    gradients are always FP64 (see below) and whose probabilities are FP32.
+ *  - Argument errors are reported synchronously through the return value
+ *    and nothing is launched.  Per-vertex domain errors (lo >= hi, width <= 0,
+ *    non-finite parameters, negative masses) produce NaN in that vertex's
+ *    outputs; they are not reported through the status.
+ *  - cp_last_error() returns a thread-local text for the last non-OK status.
+ *
+ * Parameter layouts ([n_param][H][row_stride])
+ * --------------------------------------------
+ *  CP_UNIFORM       2 planes: lo, hi                    pdf 1/(hi-lo) on [lo,hi]
+ *  CP_EPANECHNIKOV  2 planes: m, w                      pdf 3/(4w)(1-((x-m)/w)^2)
+ *                                                       on [m-w, m+w]
+ *  CP_HISTOGRAM     2 + nbins planes: lo, hi, mass_0..  nbins equal-width bins on
+ *                                                       [lo,hi]; pdf mass_j/Delta
+ *  CP_MVGAUSS       16 FP64 planes: mean, then the packed lower-triangular
+ *                   Cholesky factor L (row-major: L00, L10, L11, L20, ...,
+ *                   L44) of the covariance of (e, n, w, s, v) at that vertex.
+ *                   Rows/columns of absent neighbours are identity.
+ */
+#ifndef CPCRIT_H
+#define CPCRIT_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+  CP_OK = 0,
+  CP_EINVAL = 1,       /* null pointer, bad size, bad enum, bad option */
+  CP_EDOMAIN = 2,      /* invalid option value (e.g. n_members - ddof < 1) */
+  CP_ENOMEM = 3,       /* the library could not allocate its own tables */
+  CP_EDEVICE = 4,      /* a HIP call failed (launch, copy, graph) */
+  CP_EUNSUPPORTED = 5  /* model x dtype x operation not provided */
+} cp_status_t;
+
+typedef enum { CP_UNIFORM = 0, CP_EPANECHNIKOV = 1, CP_HISTOGRAM = 2, CP_MVGAUSS = 3 } cp_model_t;
+typedef enum { CP_F32 = 0, CP_F64 = 1 } cp_dtype_t;
+
+/* Monte Carlo estimator of the multivariate Gaussian model */
+typedef enum {
+  CP_MC_CONDITIONAL = 0, /* mean over samples of Pr(vertex extreme | neighbours),
+                            the vertex integrated in closed form (differentiable) */
+  CP_MC_HIT = 1          /* fraction of samples in which the vertex is extreme */
+} cp_mc_estimator_t;
+
+typedef struct {
+  int32_t height, width;
+  int64_t row_stride; /* elements between rows; 0 = width */
+  int32_t model;      /* cp_model_t */
+  int32_t dtype;      /* cp_dtype_t */
+  int32_t nbins;      /* CP_HISTOGRAM: bins per vertex, 1..32 */
+  int32_t nsamples;   /* CP_MVGAUSS: samples per vertex, >= 1 */
+  uint64_t seed;      /* CP_MVGAUSS: Philox key */
+  uint32_t field_id;  /* CP_MVGAUSS: third Philox counter word */
+  int32_t estimator;  /* CP_MVGAUSS: cp_mc_estimator_t */
+} cp_field_desc_t;
+
+typedef struct {
+  int32_t ddof;          /* degrees of freedom removed from the std / covariance (1) */
+  double bw_factor;      /* Epanechnikov half-width = bw_factor * std * M^(-1/5) (1.06) */
+  double cov_jitter;     /* added to the covariance diagonal (1e-6) */
+  double degenerate_eps; /* all members equal: lo/hi = x -/+ eps*max(1,|x|), Epanechnikov
+                            w = eps*max(1,|m|); <= 0 selects 2^-20 (FP32) / 2^-30 (FP64) */
+} cp_fit_opts_t;
+
+/*
+ * Fit the per-vertex model of desc->model from ensemble members
+ * (Sec. 5.1 and 5.2: uniform range = member min/max; Epanechnikov from the
+ * member mean and standard deviation; Sec. 4.4: histogram with nbins bins
+ * over the member range, mass = count / M, a member at relative position t
+ * falls in bin floor(t * nbins) computed in desc->dtype, the maximum in the
+ * last bin; Sec. 5.2/5.3: multivariate Gaussian from the member covariance of
+ * the 5-point stencil, FP64 Cholesky).
+ *   members  [n_members][H][row_stride], desc->dtype (FP32 for CP_MVGAUSS)
+ *   params   output, layout of desc->model (above)
+ *   opts     NULL selects the defaults in parentheses above
+ */
+cp_status_t cpu_fit_params(const cp_field_desc_t* desc, const void* members, int32_t n_members,
+                           const cp_fit_opts_t* opts, void* params, void* stream);
+
+/*
+ * Forward: P_min and P_max of every vertex (Eq. 3 and its negation).
+ *   params  [n_param][H][row_stride] (layout above)
+ *   p_min, p_max  [H][row_stride] outputs
+ * CP_MVGAUSS: desc->estimator selects the estimator; sample i of vertex
+ * (y, x) uses Philox4x32-10 counters (i, y*W+x, field_id, 0/1) under key
+ * seed, so results do not depend on the launch configuration.
+ */
+cp_status_t cp_prob_forward(const cp_field_desc_t* desc, const void* params, void* p_min, void* p_max,
+                            void* stream);
+
+/*
+ * Adjoint: grad_params[k][u] = sum over the stencils v that contain u of
+ *   g_min(v) * dP_min(v)/dtheta_k(u) + g_max(v) * dP_max(v)/dtheta_k(u).
+ * Parameters differentiated: uniform (lo, hi); Epanechnikov (m, w);
+ * histogram masses, taken as free variables (no renormalisation; the lo/hi
+ * planes of grad_params receive 0); multivariate Gaussian: mean plane
+ * (gathered over stencils) and the Cholesky factor of each vertex, through
+ * the conditional estimator (desc->estimator is ignored).
+ * Contributions are gathered, not scattered: no atomics, and the result is
+ * bit-reproducible.
+ *   g_min, g_max  [H][row_stride]; grad_params [n_param][H][row_stride]
+ */
+cp_status_t cp_prob_backward(const cp_field_desc_t* desc, const void* params, const void* g_min,
+                             const void* g_max, void* grad_params, void* stream);
+
+/* cp_prob_batched flags */
+#define CP_BATCH_FWD 1u       /* write p_min / p_max */
+#define CP_BATCH_BWD 2u       /* write grad_params (needs g_min / g_max) */
+#define CP_BATCH_GRAPH 4u     /* replay a cached HIP graph of the persistent launch */
+#define CP_BATCH_PER_FIELD 8u /* reference mode: one forward / backward launch per field */
+
+/*
+ * Many independent fields (mixed sizes, closed-form models, one dtype) in one
+ * persistent launch over a device-side table of field descriptors and tiles.
+ * Arrays of n pointers index the fields; p_min/p_max may be NULL unless
+ * CP_BATCH_FWD, g_min/g_max/grad_params unless CP_BATCH_BWD.  Results equal
+ * those of cp_prob_forward / cp_prob_backward on each field.  The graph cache
+ * is keyed by the field shapes; each call refreshes the descriptor table
+ * (pointers may change between calls).  Multivariate Gaussian fields are not
+ * accepted here (CP_EUNSUPPORTED).
+ */
+cp_status_t cp_prob_batched(int32_t n, const cp_field_desc_t* descs, const void* const* params,
+                            void* const* p_min, void* const* p_max, const void* const* g_min,
+                            const void* const* g_max, void* const* grad_params, uint32_t flags,
+                            void* stream);
+
+/* Number of parameter planes of a model (histogram: 2 + nbins; Gaussian: 16). */
+int32_t cp_n_params(int32_t model, int32_t nbins);
+
+/* Text for a status code (static storage). */
+const char* cp_status_string(cp_status_t status);
+
+/* Thread-local description of the last non-OK status of this thread. */
+const char* cp_last_error(void);
+
+/* Free the library's own device tables and cached graphs (optional). */
+cp_status_t cp_release(void);
+
+/*
+ * Raw Philox4x32-10 words for n counters on the device (the generator the
+ * Gaussian path uses): counters [n][4] uint32, out [n][4] uint32, key = seed.
+ */
+cp_status_t cp_philox4x32_10(int64_t n, const uint32_t* counters, uint64_t seed, uint32_t* out,
+                             void* stream);
+
+/*
+ * Gauss-Legendre rule the closed-form kernels use for an n-point piece
+ * (n in {1, 2, 3, 5, 6, 8}): host copies of the device tables, for checking.
+ * Returns CP_EINVAL for other n.
+ */
+cp_status_t cp_gauss_legendre(int32_t n, double* nodes, double* weights);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* CPCRIT_H */

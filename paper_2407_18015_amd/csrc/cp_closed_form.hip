@@ -1,0 +1,180 @@
+// cp_closed_form.hip -- per-field forward and adjoint kernels for the
+// uniform, Epanechnikov and histogram models, and their launchers.
+#include <hip/hip_runtime.h>
+
+#include "cp_hist_bwd.hpp"
+#include "cp_internal.hpp"
+#include "cp_tiles.hpp"
+
+namespace cp {
+
+// ---------------------------------------------------------------------------
+// forward
+// ---------------------------------------------------------------------------
+template <typename T, int MODEL, int TY>
+__global__ __launch_bounds__(kFwdTX* TY) void k_fwd_ue(FieldPtrs<T> f, int tiles_x, int ntiles) {
+  __shared__ T lds[2 * (kFwdTX + 2) * (TY + 2)];
+  const int t = xcd_tile(blockIdx.x, ntiles);
+  tile_fwd_ue<T, MODEL, TY>(f, (t / tiles_x) * TY, (t % tiles_x) * kFwdTX, lds, threadIdx.x);
+}
+
+template <typename T, int TY>
+__global__ __launch_bounds__(kFwdTX* TY) void k_fwd_hist(FieldPtrs<T> f, int tiles_x, int ntiles) {
+  extern __shared__ __align__(16) unsigned char smem[];
+  T* lds = reinterpret_cast<T*>(smem);
+  const int t = xcd_tile(blockIdx.x, ntiles);
+  tile_fwd_hist<T, TY>(f, (t / tiles_x) * TY, (t % tiles_x) * kFwdTX, lds, threadIdx.x);
+}
+
+// ---------------------------------------------------------------------------
+// adjoint
+// ---------------------------------------------------------------------------
+template <typename T, int MODEL, int OX, int OY>
+__global__ __launch_bounds__(256) void k_bwd_ue(FieldPtrs<T> f, int tiles_x, int ntiles) {
+  __shared__ T lds[bwd_ue_lds_elems<OX, OY>()];
+  const int t = xcd_tile(blockIdx.x, ntiles);
+  tile_bwd_ue<T, MODEL, OX, OY, 256>(f, (t / tiles_x) * OY, (t % tiles_x) * OX, lds, threadIdx.x);
+}
+
+template <typename T, int OX, int OY, int NT>
+__global__ __launch_bounds__(NT) void k_bwd_hist(FieldPtrs<T> f, int tiles_x, int ntiles) {
+  extern __shared__ __align__(16) unsigned char smem[];
+  T* lds = reinterpret_cast<T*>(smem);
+  const int t = xcd_tile(blockIdx.x, ntiles);
+  tile_bwd_hist<T, OX, OY, NT>(f, (t / tiles_x) * OY, (t % tiles_x) * OX, lds, threadIdx.x);
+}
+
+// ---------------------------------------------------------------------------
+// launchers
+// ---------------------------------------------------------------------------
+static int cdiv(int a, int b) { return (a + b - 1) / b; }
+
+constexpr size_t kMaxLds = 160 * 1024;  // LDS per workgroup on gfx950
+
+template <typename T>
+static FieldPtrs<T> make_ptrs(const Field& f, const void* params, void* pmin, void* pmax, const void* gmin,
+                              const void* gmax, void* grad) {
+  FieldPtrs<T> p;
+  p.params = static_cast<const T*>(params);
+  p.pmin = static_cast<T*>(pmin);
+  p.pmax = static_cast<T*>(pmax);
+  p.gmin = static_cast<const T*>(gmin);
+  p.gmax = static_cast<const T*>(gmax);
+  p.grad = static_cast<T*>(grad);
+  p.H = f.H;
+  p.W = f.W;
+  p.nb = f.nb;
+  p.rs = f.rs;
+  p.ps = f.plane();
+  return p;
+}
+
+// dynamic LDS above 64 KiB needs the per-kernel attribute
+template <typename K>
+static hipError_t allow_lds(K kernel, size_t bytes) {
+  if (bytes <= 65536) return hipSuccess;
+  return hipFuncSetAttribute(reinterpret_cast<const void*>(kernel), hipFuncAttributeMaxDynamicSharedMemorySize,
+                             (int)bytes);
+}
+
+template <typename T, int TY>
+static hipError_t launch_fwd_hist(const FieldPtrs<T>& p, hipStream_t st) {
+  const int tx = cdiv(p.W, kFwdTX), ty = cdiv(p.H, TY), n = tx * ty;
+  const size_t lds = sizeof(T) * (size_t)hist_planes(p.nb) * (kFwdTX + 2) * (TY + 2);
+  hipError_t e = allow_lds(k_fwd_hist<T, TY>, lds);
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL((k_fwd_hist<T, TY>), dim3(n), dim3(kFwdTX * TY), lds, st, p, tx, n);
+  return hipGetLastError();
+}
+
+template <typename T>
+static hipError_t fwd_typed(const Field& f, const void* params, void* pmin, void* pmax, hipStream_t st) {
+  FieldPtrs<T> p = make_ptrs<T>(f, params, pmin, pmax, nullptr, nullptr, nullptr);
+  constexpr int TY = 4;
+  const int tx = cdiv(f.W, kFwdTX), ty = cdiv(f.H, TY), n = tx * ty;
+  if (f.model == CP_UNIFORM) {
+    hipLaunchKernelGGL((k_fwd_ue<T, CP_UNIFORM, TY>), dim3(n), dim3(kFwdTX * TY), 0, st, p, tx, n);
+    return hipGetLastError();
+  }
+  if (f.model == CP_EPANECHNIKOV) {
+    hipLaunchKernelGGL((k_fwd_ue<T, CP_EPANECHNIKOV, TY>), dim3(n), dim3(kFwdTX * TY), 0, st, p, tx, n);
+    return hipGetLastError();
+  }
+  // histogram: pick the tile height that keeps the staged planes within LDS
+  const size_t per_row = sizeof(T) * (size_t)hist_planes(f.nb) * (kFwdTX + 2);
+  if (per_row * 6 <= 64 * 1024) return launch_fwd_hist<T, 4>(p, st);
+  if (per_row * 4 <= kMaxLds) return launch_fwd_hist<T, 2>(p, st);
+  return launch_fwd_hist<T, 1>(p, st);
+}
+
+hipError_t cf_forward(const Field& f, const void* params, void* pmin, void* pmax, hipStream_t st) {
+  if (f.dtype == CP_F64) return fwd_typed<double>(f, params, pmin, pmax, st);
+  return fwd_typed<float>(f, params, pmin, pmax, st);
+}
+
+template <typename T, int OX, int OY>
+static hipError_t launch_bwd_ue(const FieldPtrs<T>& p, int model, hipStream_t st) {
+  const int tx = cdiv(p.W, OX), ty = cdiv(p.H, OY), n = tx * ty;
+  if (model == CP_UNIFORM)
+    hipLaunchKernelGGL((k_bwd_ue<T, CP_UNIFORM, OX, OY>), dim3(n), dim3(256), 0, st, p, tx, n);
+  else
+    hipLaunchKernelGGL((k_bwd_ue<T, CP_EPANECHNIKOV, OX, OY>), dim3(n), dim3(256), 0, st, p, tx, n);
+  return hipGetLastError();
+}
+
+template <typename T, int OX, int OY, int NT>
+static hipError_t launch_bwd_hist(const FieldPtrs<T>& p, hipStream_t st) {
+  const int tx = cdiv(p.W, OX), ty = cdiv(p.H, OY), n = tx * ty;
+  const size_t lds = sizeof(T) * hist_bwd_lds_elems<OX, OY>(p.nb);
+  hipError_t e = allow_lds(k_bwd_hist<T, OX, OY, NT>, lds);
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL((k_bwd_hist<T, OX, OY, NT>), dim3(n), dim3(NT), lds, st, p, tx, n);
+  return hipGetLastError();
+}
+
+template <typename T>
+static hipError_t bwd_typed(const Field& f, const void* params, const void* gmin, const void* gmax, void* grad,
+                            hipStream_t st) {
+  FieldPtrs<T> p = make_ptrs<T>(f, params, nullptr, nullptr, gmin, gmax, grad);
+  if (f.model != CP_HISTOGRAM) {
+    // 30x30 outputs (32x32 stencils, 4 per thread) keep the FP32 tile under
+    // 64 KiB of static LDS; FP64 uses 14x14 (16x16 stencils)
+    if constexpr (sizeof(T) == 4)
+      return launch_bwd_ue<T, 30, 30>(p, f.model, st);
+    else
+      return launch_bwd_ue<T, 14, 14>(p, f.model, st);
+  }
+  // 16x16 stencils (one per thread) when the staged planes fit, else 8x8
+  if (sizeof(T) * hist_bwd_lds_elems<14, 14>(f.nb) <= kMaxLds) return launch_bwd_hist<T, 14, 14, 256>(p, st);
+  if (sizeof(T) * hist_bwd_lds_elems<6, 6>(f.nb) <= kMaxLds) return launch_bwd_hist<T, 6, 6, 64>(p, st);
+  return hipErrorInvalidValue;
+}
+
+hipError_t cf_backward(const Field& f, const void* params, const void* gmin, const void* gmax, void* grad,
+                       hipStream_t st) {
+  if (f.dtype == CP_F64) return bwd_typed<double>(f, params, gmin, gmax, grad, st);
+  return bwd_typed<float>(f, params, gmin, gmax, grad, st);
+}
+
+bool gl_table(int n, double* x, double* w) {
+  switch (n) {
+#define CP_GL_CASE(N)                 \
+  case N:                             \
+    for (int i = 0; i < N; ++i) {     \
+      x[i] = GL<N>::x[i];             \
+      w[i] = GL<N>::w[i];             \
+    }                                 \
+    return true;
+    CP_GL_CASE(1)
+    CP_GL_CASE(2)
+    CP_GL_CASE(3)
+    CP_GL_CASE(5)
+    CP_GL_CASE(6)
+    CP_GL_CASE(8)
+#undef CP_GL_CASE
+    default:
+      return false;
+  }
+}
+
+}  // namespace cp

@@ -1,0 +1,522 @@
+// cp_device.hpp -- device-side building blocks of the closed-form kernels.
+//
+// Every routine works in a vertex-local coordinate frame: all breakpoints
+// are differences of parameters of nearby vertices, so their magnitude is
+// the distribution width rather than the data value.  The paper warns that
+// its high-order templates become unstable for large or fractional data
+// values (Sec. 4.3); in FP32 a node placed in global coordinates near 0.5
+// already carries 3e-8 of rounding, which is 5e-6 of a 0.006-wide
+// Epanechnikov kernel.  In the local frame the error is relative to the
+// widths, and nothing is ever expanded into monomials.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+
+namespace cp {
+
+// ---------------------------------------------------------------------------
+// Gauss-Legendre rules on [-1, 1]; an N-point rule integrates polynomials of
+// degree <= 2N-1 exactly.
+// ---------------------------------------------------------------------------
+template <int N>
+struct GL;
+template <>
+struct GL<1> {
+  static constexpr double x[1] = {0.0};
+  static constexpr double w[1] = {2.0};
+};
+template <>
+struct GL<2> {
+  static constexpr double x[2] = {-0.57735026918962576451, 0.57735026918962576451};
+  static constexpr double w[2] = {1.0, 1.0};
+};
+template <>
+struct GL<3> {
+  static constexpr double x[3] = {-0.77459666924148337704, 0.0, 0.77459666924148337704};
+  static constexpr double w[3] = {0.55555555555555555556, 0.88888888888888888889,
+                                  0.55555555555555555556};
+};
+template <>
+struct GL<5> {
+  static constexpr double x[5] = {-0.90617984593866399280, -0.53846931010568309104, 0.0,
+                                  0.53846931010568309104, 0.90617984593866399280};
+  static constexpr double w[5] = {0.23692688505618908751, 0.47862867049936646804,
+                                  0.56888888888888888889, 0.47862867049936646804,
+                                  0.23692688505618908751};
+};
+template <>
+struct GL<6> {
+  static constexpr double x[6] = {-0.93246951420315202781, -0.66120938646626451366,
+                                  -0.23861918608319690863, 0.23861918608319690863,
+                                  0.66120938646626451366,  0.93246951420315202781};
+  static constexpr double w[6] = {0.17132449237917034504, 0.36076157304813860757,
+                                  0.46791393457269104739, 0.46791393457269104739,
+                                  0.36076157304813860757, 0.17132449237917034504};
+};
+template <>
+struct GL<8> {
+  static constexpr double x[8] = {-0.96028985649753623168, -0.79666647741362673959,
+                                  -0.52553240991632898582, -0.18343464249564980494,
+                                  0.18343464249564980494,  0.52553240991632898582,
+                                  0.79666647741362673959,  0.96028985649753623168};
+  static constexpr double w[8] = {0.10122853629037625915, 0.22238103445337447054,
+                                  0.31370664587788728734, 0.36268378337836198297,
+                                  0.36268378337836198297, 0.31370664587788728734,
+                                  0.22238103445337447054, 0.10122853629037625915};
+};
+
+// ---------------------------------------------------------------------------
+// small helpers
+// ---------------------------------------------------------------------------
+template <typename T>
+__device__ __forceinline__ T tmin(T a, T b) {
+  return b < a ? b : a;
+}
+template <typename T>
+__device__ __forceinline__ T tmax(T a, T b) {
+  return a < b ? b : a;
+}
+template <typename T>
+__device__ __forceinline__ T tclamp(T v, T lo, T hi) {
+  return tmin(tmax(v, lo), hi);
+}
+template <typename T>
+__device__ __forceinline__ bool finite_pos(T v) {
+  return v > T(0) && v < T(3.0e38);
+}
+template <typename T>
+__device__ __forceinline__ T qnan() {
+  return __builtin_nan("");
+}
+
+// Compare-exchange of key k with a payload of P values (and an int tag).
+template <typename T, int P>
+__device__ __forceinline__ void cswap(T& ka, T& kb, T (&pa)[P], T (&pb)[P], int& ta, int& tb) {
+  const bool s = kb < ka;
+  T t = s ? kb : ka;
+  kb = s ? ka : kb;
+  ka = t;
+#pragma unroll
+  for (int p = 0; p < P; ++p) {
+    T u = s ? pb[p] : pa[p];
+    pb[p] = s ? pa[p] : pb[p];
+    pa[p] = u;
+  }
+  int v = s ? tb : ta;
+  tb = s ? ta : tb;
+  ta = v;
+}
+
+// Sorting network for four keys (5 comparators), payload follows its key.
+template <typename T, int P>
+__device__ __forceinline__ void sort4(T (&k)[4], T (&p)[4][P], int (&tag)[4]) {
+  cswap<T, P>(k[0], k[1], p[0], p[1], tag[0], tag[1]);
+  cswap<T, P>(k[2], k[3], p[2], p[3], tag[2], tag[3]);
+  cswap<T, P>(k[0], k[2], p[0], p[2], tag[0], tag[2]);
+  cswap<T, P>(k[1], k[3], p[1], p[3], tag[1], tag[3]);
+  cswap<T, P>(k[1], k[2], p[1], p[2], tag[1], tag[2]);
+}
+
+// ---------------------------------------------------------------------------
+// Stencil of a vertex: own and neighbour parameters, neighbour order
+// e, n, w, s (index 0..3 here; stencil slot = index + 1).
+// ---------------------------------------------------------------------------
+template <typename T>
+struct Stencil2 {
+  T v0, v1;       // own parameters
+  T n0[4], n1[4]; // neighbour parameters
+  bool pres[4];
+};
+
+// ===========================================================================
+// Uniform model (Sec. 4.3).  Local frame with origin at the vertex lower
+// end: vertex support [0, Lv]; neighbour i support [a_i, b_i].
+//
+// Task 1 (Sec. 4.1.1): b_min = min(Lv, b_i); nothing if b_min <= 0.  Start
+// points clamped to [0, b_min] and sorted give the pieces
+// [0,c0], [c0,c1], [c1,c2], [c2,c3], [c3,b_min]; on piece k exactly the k
+// neighbours sorted first have started (Tasks 2-3, Template k+1), so every
+// lane runs the same five pieces (empty ones contribute zero).
+// On piece k the integrand (1/Lv) prod_{i<k} (b_i - x)/L_i has degree k:
+// Gauss-Legendre with 1, 2, 2, 3 nodes is exact for k = 1..4.
+// ===========================================================================
+template <typename T>
+struct UniSide {
+  T Lv;
+  T c[4];      // sorted clamped start points
+  T b[4];      // matching upper ends
+  T iL[4];     // matching 1/(b - a)
+  int tag[4];  // neighbour index (0..3) of each sorted slot
+  T bmin;
+  bool empty;
+};
+
+template <typename T>
+__device__ __forceinline__ void uni_setup(UniSide<T>& s, T Lv, const T (&a)[4], const T (&b)[4],
+                                          const T (&iL)[4], const bool (&pres)[4]) {
+  s.Lv = Lv;
+  T bmin = Lv;
+#pragma unroll
+  for (int i = 0; i < 4; ++i)
+    if (pres[i]) bmin = tmin(bmin, b[i]);
+  s.bmin = bmin;
+  s.empty = !(bmin > T(0));
+  T key[4];
+  T pay[4][2];
+#pragma unroll
+  for (int i = 0; i < 4; ++i) {
+    // an absent neighbour is a factor that would start at b_min (never
+    // active on a non-empty piece); finite stand-ins keep empty pieces finite
+    key[i] = pres[i] ? tclamp(a[i], T(0), bmin) : bmin;
+    pay[i][0] = pres[i] ? b[i] : T(3) * Lv;
+    pay[i][1] = pres[i] ? iL[i] : T(1) / Lv;
+    s.tag[i] = i;
+  }
+  sort4<T, 2>(key, pay, s.tag);
+#pragma unroll
+  for (int i = 0; i < 4; ++i) {
+    s.c[i] = key[i];
+    s.b[i] = pay[i][0];
+    s.iL[i] = pay[i][1];
+  }
+}
+
+// integral over [l, r] of prod_{i<K} (b_i - x) iL_i  (times nothing else)
+template <typename T, int K, int N>
+__device__ __forceinline__ T uni_piece(const UniSide<T>& s, T l, T r) {
+  const T mid = (l + r) * T(0.5), hl = (r - l) * T(0.5);
+  T al[K], be[K];
+#pragma unroll
+  for (int i = 0; i < K; ++i) {
+    al[i] = (s.b[i] - mid) * s.iL[i];
+    be[i] = hl * s.iL[i];
+  }
+  T sum = T(0);
+#pragma unroll
+  for (int j = 0; j < N; ++j) {
+    const T x = T(GL<N>::x[j]);
+    T prod = T(1);
+#pragma unroll
+    for (int i = 0; i < K; ++i) prod *= __builtin_fma(-be[i], x, al[i]);
+    sum = __builtin_fma(T(GL<N>::w[j]), prod, sum);
+  }
+  return sum * hl;
+}
+
+template <typename T>
+__device__ __forceinline__ T uni_side_value(const UniSide<T>& s) {
+  if (s.empty) return T(0);
+  T acc = s.c[0];  // piece 0: no factor
+  acc += uni_piece<T, 1, 1>(s, s.c[0], s.c[1]);
+  acc += uni_piece<T, 2, 2>(s, s.c[1], s.c[2]);
+  acc += uni_piece<T, 3, 2>(s, s.c[2], s.c[3]);
+  acc += uni_piece<T, 4, 3>(s, s.c[3], s.bmin);
+  return acc / s.Lv;
+}
+
+// Local derivatives of one side:  f(Lv, a_i, b_i) = (1/Lv) int_0^{b_min} prod S_i
+//   df/da_i = (1/L_i) int_{i active} p_v prod_k S_k
+//   df/db_i = (1/L_i) int_{i active} p_v (prod_{k!=i} S_k - prod_k S_k)
+//   df/dLv  = (-f + prod_i S_i(Lv)) / Lv
+template <typename T>
+struct UniGrad {
+  T f, dLv;
+  T da[4], db[4];  // by neighbour index 0..3
+};
+
+template <typename T, int K, int N>
+__device__ __forceinline__ void uni_piece_grad(const UniSide<T>& s, T l, T r, T& full, T (&loo)[4]) {
+  const T mid = (l + r) * T(0.5), hl = (r - l) * T(0.5);
+  T al[K], be[K];
+#pragma unroll
+  for (int i = 0; i < K; ++i) {
+    al[i] = (s.b[i] - mid) * s.iL[i];
+    be[i] = hl * s.iL[i];
+  }
+  T sf = T(0), sl[K];
+#pragma unroll
+  for (int i = 0; i < K; ++i) sl[i] = T(0);
+#pragma unroll
+  for (int j = 0; j < N; ++j) {
+    const T x = T(GL<N>::x[j]);
+    const T wj = T(GL<N>::w[j]);
+    T f[K], pre[K + 1], suf[K + 1];
+#pragma unroll
+    for (int i = 0; i < K; ++i) f[i] = __builtin_fma(-be[i], x, al[i]);
+    pre[0] = T(1);
+#pragma unroll
+    for (int i = 0; i < K; ++i) pre[i + 1] = pre[i] * f[i];
+    suf[K] = T(1);
+#pragma unroll
+    for (int i = K - 1; i >= 0; --i) suf[i] = suf[i + 1] * f[i];
+    sf = __builtin_fma(wj, pre[K], sf);
+#pragma unroll
+    for (int i = 0; i < K; ++i) sl[i] = __builtin_fma(wj, pre[i] * suf[i + 1], sl[i]);
+  }
+  full = sf * hl;
+#pragma unroll
+  for (int i = 0; i < K; ++i) loo[i] += sl[i] * hl;
+}
+
+template <typename T>
+__device__ __forceinline__ void uni_side_grad(const UniSide<T>& s, UniGrad<T>& g) {
+  g.f = T(0);
+  g.dLv = T(0);
+#pragma unroll
+  for (int i = 0; i < 4; ++i) g.da[i] = g.db[i] = T(0);
+  if (s.empty) return;
+  T I[5];
+  T loo[4] = {T(0), T(0), T(0), T(0)};  // sorted slots; accumulated over pieces where active
+  T act[4] = {T(0), T(0), T(0), T(0)};  // full integral over pieces where slot is active
+  I[0] = s.c[0];
+  uni_piece_grad<T, 1, 1>(s, s.c[0], s.c[1], I[1], loo);
+  uni_piece_grad<T, 2, 2>(s, s.c[1], s.c[2], I[2], loo);
+  uni_piece_grad<T, 3, 2>(s, s.c[2], s.c[3], I[3], loo);
+  uni_piece_grad<T, 4, 3>(s, s.c[3], s.bmin, I[4], loo);
+  // slot i is active on pieces i+1..4
+  act[3] = I[4];
+  act[2] = act[3] + I[3];
+  act[1] = act[2] + I[2];
+  act[0] = act[1] + I[1];
+  const T iLv = T(1) / s.Lv;
+  const T f = (act[0] + I[0]) * iLv;
+  g.f = f;
+  // product of the survival factors at x = Lv (zero unless b_min = Lv)
+  T gend = T(0);
+  if (!(s.bmin < s.Lv)) {
+    gend = T(1);
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+      // a factor that has not started at Lv is 1 (also an absent neighbour)
+      T v = tmin(T(1), (s.b[i] - s.Lv) * s.iL[i]);
+      gend *= (s.c[i] < s.Lv) ? tmax(v, T(0)) : T(1);
+    }
+  }
+  g.dLv = (gend - f) * iLv;
+#pragma unroll
+  for (int i = 0; i < 4; ++i) {
+    const T da = act[i] * iLv * s.iL[i];
+    const T db = (loo[i] - act[i]) * iLv * s.iL[i];
+    const int t = s.tag[i];
+    // scatter back to neighbour index (registers: unrolled selects)
+#pragma unroll
+    for (int n = 0; n < 4; ++n) {
+      g.da[n] = (t == n) ? da : g.da[n];
+      g.db[n] = (t == n) ? db : g.db[n];
+    }
+  }
+}
+
+// ===========================================================================
+// Epanechnikov model (Sec. 4.3).  Local frame with origin at the vertex
+// centre: vertex support [-wv, wv], neighbour i centre d_i, half-width w_i.
+// pdf_v = 3/(4 wv) (1 - t^2), S_i = (1 - u)^2 (2 + u) / 4 with t = x/wv,
+// u = (x - d_i)/w_i.  Piece k (k neighbours started) has degree 2 + 3k:
+// Gauss-Legendre with 3, 5, 6, 8 nodes is exact for k = 1..4 (the paper's
+// order-15 remark, Sec. 4.3); piece 0 is the vertex CDF in closed form.
+// ===========================================================================
+template <typename T>
+struct EpaSide {
+  T wv, iwv;
+  T c[4], d[4], iw[4];
+  int tag[4];
+  T bmin;
+  bool empty;
+};
+
+template <typename T>
+__device__ __forceinline__ void epa_setup(EpaSide<T>& s, T wv, const T (&d)[4], const T (&w)[4],
+                                          const bool (&pres)[4]) {
+  s.wv = wv;
+  s.iwv = T(1) / wv;
+  T bmin = wv;
+#pragma unroll
+  for (int i = 0; i < 4; ++i)
+    if (pres[i]) bmin = tmin(bmin, d[i] + w[i]);
+  s.bmin = bmin;
+  s.empty = !(bmin > -wv);
+  T key[4];
+  T pay[4][2];
+#pragma unroll
+  for (int i = 0; i < 4; ++i) {
+    key[i] = pres[i] ? tclamp(d[i] - w[i], -wv, bmin) : bmin;
+    pay[i][0] = pres[i] ? d[i] : T(3) * wv;
+    pay[i][1] = pres[i] ? T(1) / w[i] : s.iwv;
+    s.tag[i] = i;
+  }
+  sort4<T, 2>(key, pay, s.tag);
+#pragma unroll
+  for (int i = 0; i < 4; ++i) {
+    s.c[i] = key[i];
+    s.d[i] = pay[i][0];
+    s.iw[i] = pay[i][1];
+  }
+}
+
+// 4 * vertex CDF at x: (1 + t)^2 (2 - t), t = x / wv
+template <typename T>
+__device__ __forceinline__ T epa_cdf4(const EpaSide<T>& s, T x) {
+  const T t = x * s.iwv;
+  const T o = T(1) + t;
+  return o * o * (T(2) - t);
+}
+
+// integral over [l, r] of (1 - t^2) prod_{i<K} 4 S_i   (unscaled)
+template <typename T, int K, int N>
+__device__ __forceinline__ T epa_piece(const EpaSide<T>& s, T l, T r) {
+  const T mid = (l + r) * T(0.5), hl = (r - l) * T(0.5);
+  const T av = mid * s.iwv, bv = hl * s.iwv;
+  T aq[K], bq[K];
+#pragma unroll
+  for (int i = 0; i < K; ++i) {
+    aq[i] = T(1) - (mid - s.d[i]) * s.iw[i];  // q = 1 - u = aq - bq x
+    bq[i] = hl * s.iw[i];
+  }
+  T sum = T(0);
+#pragma unroll
+  for (int j = 0; j < N; ++j) {
+    const T x = T(GL<N>::x[j]);
+    const T t = __builtin_fma(bv, x, av);
+    T prod = __builtin_fma(-t, t, T(1));
+#pragma unroll
+    for (int i = 0; i < K; ++i) {
+      const T q = __builtin_fma(-bq[i], x, aq[i]);
+      prod *= q * q * (T(3) - q);
+    }
+    sum = __builtin_fma(T(GL<N>::w[j]), prod, sum);
+  }
+  return sum * hl;
+}
+
+template <typename T>
+__device__ __forceinline__ T epa_side_value(const EpaSide<T>& s) {
+  if (s.empty) return T(0);
+  const T kv = T(0.75) * s.iwv;  // pdf scale 3/(4 wv)
+  T acc = epa_cdf4(s, s.c[0]) * T(0.25);
+  T p = epa_piece<T, 1, 3>(s, s.c[0], s.c[1]) * T(0.25);
+  p += epa_piece<T, 2, 5>(s, s.c[1], s.c[2]) * T(0.0625);
+  p += epa_piece<T, 3, 6>(s, s.c[2], s.c[3]) * T(0.015625);
+  p += epa_piece<T, 4, 8>(s, s.c[3], s.bmin) * T(0.00390625);
+  return acc + kv * p;
+}
+
+// Local derivatives of one side, f(wv, d_i, w_i):
+//   df/dd_i = int p_v p_i prod_{k!=i} S_k          (dS/dm = pdf)
+//   df/dw_i = int p_v u_i p_i prod_{k!=i} S_k      (dS/dw = u pdf)
+//   df/dwv  = int 3/(4 wv^2) (3 t^2 - 1) prod S_k
+template <typename T>
+struct EpaGrad {
+  T f, dwv;
+  T dd[4], dw[4];  // by neighbour index
+};
+
+template <typename T, int K, int N>
+__device__ __forceinline__ void epa_piece_grad(const EpaSide<T>& s, T l, T r, T& full, T& dwv,
+                                               T (&gd)[4], T (&gw)[4]) {
+  const T mid = (l + r) * T(0.5), hl = (r - l) * T(0.5);
+  const T av = mid * s.iwv, bv = hl * s.iwv;
+  T aq[K], bq[K];
+#pragma unroll
+  for (int i = 0; i < K; ++i) {
+    aq[i] = T(1) - (mid - s.d[i]) * s.iw[i];
+    bq[i] = hl * s.iw[i];
+  }
+  T sf = T(0), sw = T(0), sd[K], sww[K];
+#pragma unroll
+  for (int i = 0; i < K; ++i) sd[i] = sww[i] = T(0);
+#pragma unroll
+  for (int j = 0; j < N; ++j) {
+    const T x = T(GL<N>::x[j]);
+    const T wj = T(GL<N>::w[j]);
+    const T t = __builtin_fma(bv, x, av);
+    const T t2 = t * t;
+    const T pv = T(1) - t2;                        // 4 wv/3 * pdf_v
+    const T dpv = __builtin_fma(T(3), t2, T(-1));  // 4 wv^2/3 * dpdf_v/dwv
+    T q[K], S[K], pre[K + 1], suf[K + 1];
+#pragma unroll
+    for (int i = 0; i < K; ++i) {
+      q[i] = __builtin_fma(-bq[i], x, aq[i]);
+      S[i] = q[i] * q[i] * (T(3) - q[i]);  // 4 S_i
+    }
+    pre[0] = T(1);
+#pragma unroll
+    for (int i = 0; i < K; ++i) pre[i + 1] = pre[i] * S[i];
+    suf[K] = T(1);
+#pragma unroll
+    for (int i = K - 1; i >= 0; --i) suf[i] = suf[i + 1] * S[i];
+    sf = __builtin_fma(wj * pv, pre[K], sf);
+    sw = __builtin_fma(wj * dpv, pre[K], sw);
+#pragma unroll
+    for (int i = 0; i < K; ++i) {
+      // (4 w_i / 3) p_i = 1 - u^2 = q (2 - q); u = 1 - q
+      const T pi = q[i] * (T(2) - q[i]);
+      const T lw = wj * pv * pi * pre[i] * suf[i + 1];
+      sd[i] += lw;
+      sww[i] = __builtin_fma(lw, T(1) - q[i], sww[i]);
+    }
+  }
+  full += sf * hl;
+  dwv += sw * hl;
+#pragma unroll
+  for (int i = 0; i < K; ++i) {
+    gd[i] += sd[i] * hl;
+    gw[i] += sww[i] * hl;
+  }
+}
+
+template <typename T>
+__device__ __forceinline__ void epa_side_grad(const EpaSide<T>& s, EpaGrad<T>& g) {
+  g.f = g.dwv = T(0);
+#pragma unroll
+  for (int i = 0; i < 4; ++i) g.dd[i] = g.dw[i] = T(0);
+  if (s.empty) return;
+  // accumulators per sorted slot, each scaled by the 4^-(k) of its piece
+  T F[5] = {T(0), T(0), T(0), T(0), T(0)}, DW[5] = {T(0), T(0), T(0), T(0), T(0)};
+  T gd[5][4], gw[5][4];
+#pragma unroll
+  for (int k = 0; k < 5; ++k)
+#pragma unroll
+    for (int i = 0; i < 4; ++i) gd[k][i] = gw[k][i] = T(0);
+  epa_piece_grad<T, 1, 3>(s, s.c[0], s.c[1], F[1], DW[1], gd[1], gw[1]);
+  epa_piece_grad<T, 2, 5>(s, s.c[1], s.c[2], F[2], DW[2], gd[2], gw[2]);
+  epa_piece_grad<T, 3, 6>(s, s.c[2], s.c[3], F[3], DW[3], gd[3], gw[3]);
+  epa_piece_grad<T, 4, 8>(s, s.c[3], s.bmin, F[4], DW[4], gd[4], gw[4]);
+  const T kv = T(0.75) * s.iwv;
+  // piece 0: f = vertex CDF at c0; d/dwv of F_v(c0) = -(c0/wv) pdf_v(c0)
+  const T t0 = s.c[0] * s.iwv;
+  const T f0 = epa_cdf4(s, s.c[0]) * T(0.25);
+  const T dw0 = -t0 * kv * (T(1) - t0 * t0);
+  const T sc[5] = {T(1), T(0.25), T(0.0625), T(0.015625), T(0.00390625)};
+  T f = f0, dwv = dw0;
+#pragma unroll
+  for (int k = 1; k < 5; ++k) {
+    f += kv * sc[k] * F[k];
+    dwv += kv * s.iwv * sc[k] * DW[k];
+  }
+  g.f = f;
+  g.dwv = dwv;
+  // neighbour terms: slot i collects pieces k > i; p_i carries 3/(4 w_i) and
+  // the other factors 4^-(k-1)
+#pragma unroll
+  for (int i = 0; i < 4; ++i) {
+    T ad = T(0), aw = T(0);
+#pragma unroll
+    for (int k = i + 1; k < 5; ++k) {
+      ad += sc[k - 1] * gd[k][i];
+      aw += sc[k - 1] * gw[k][i];
+    }
+    const T ki = T(0.75) * s.iw[i] * kv;
+    const T dd = ki * ad;
+    const T dw = ki * aw;
+    const int t = s.tag[i];
+#pragma unroll
+    for (int n = 0; n < 4; ++n) {
+      g.dd[n] = (t == n) ? dd : g.dd[n];
+      g.dw[n] = (t == n) ? dw : g.dw[n];
+    }
+  }
+}
+
+}  // namespace cp

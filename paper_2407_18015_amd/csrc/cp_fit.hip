@@ -1,0 +1,314 @@
+// cp_fit.hip -- per-vertex model fitting from ensemble members.
+//
+// Rules (Sec. 5.1 and 5.2 for the parametric ranges, Sec. 4.4 for
+// histograms, Sec. 5.2/5.3 for the multivariate Gaussian):
+//   uniform       lo = min, hi = max of the members
+//   Epanechnikov  m = mean, w = bw * std(ddof) * M^(-1/5)
+//   histogram     lo = min, hi = max, nbins equal-width bins, mass = count/M;
+//                 bin of x = floor(((x - lo) / (hi - lo)) * nbins), computed in
+//                 the field's precision with every operation rounded once,
+//                 the maximum in the last bin
+//   degenerate    all members equal: lo/hi = x -/+ eps*max(1,|x|), Epanechnikov
+//                 w = eps*max(1,|m|)
+//   Gaussian      mean plane; covariance of (e, n, w, s, v) over members with
+//                 `ddof`, + jitter on the diagonal, FP64 Cholesky; absent
+//                 neighbours get identity rows.
+// The kernels are HBM-bound: every member value is read once (held in
+// registers), statistics are accumulated in FP64.
+#include <hip/hip_runtime.h>
+
+#include "cp_internal.hpp"
+
+namespace cp {
+
+namespace {
+
+constexpr int kFitTX = 64, kFitTY = 4, kMaxRegMembers = 32;
+
+template <typename T>
+__device__ __forceinline__ T rn_sub(T a, T b);
+template <>
+__device__ __forceinline__ float rn_sub(float a, float b) {
+  return __fsub_rn(a, b);
+}
+template <>
+__device__ __forceinline__ double rn_sub(double a, double b) {
+  return __dsub_rn(a, b);
+}
+template <typename T>
+__device__ __forceinline__ T rn_add(T a, T b);
+template <>
+__device__ __forceinline__ float rn_add(float a, float b) {
+  return __fadd_rn(a, b);
+}
+template <>
+__device__ __forceinline__ double rn_add(double a, double b) {
+  return __dadd_rn(a, b);
+}
+template <typename T>
+__device__ __forceinline__ T rn_mul(T a, T b);
+template <>
+__device__ __forceinline__ float rn_mul(float a, float b) {
+  return __fmul_rn(a, b);
+}
+template <>
+__device__ __forceinline__ double rn_mul(double a, double b) {
+  return __dmul_rn(a, b);
+}
+template <typename T>
+__device__ __forceinline__ T rn_div(T a, T b);
+template <>
+__device__ __forceinline__ float rn_div(float a, float b) {
+  return __fdiv_rn(a, b);
+}
+template <>
+__device__ __forceinline__ double rn_div(double a, double b) {
+  return __ddiv_rn(a, b);
+}
+
+template <typename T>
+__device__ __forceinline__ int bin_of(T x, T lo, T hi, int nb) {
+  const T t = rn_div(rn_sub(x, lo), rn_sub(hi, lo));
+  int j = (int)rn_mul(t, T(nb));
+  return j < 0 ? 0 : (j > nb - 1 ? nb - 1 : j);
+}
+
+struct FitArgs {
+  const void* members;
+  void* params;
+  int M, H, W, nb, ddof;
+  int64_t rs, ps;
+  double bw, eps;
+};
+
+// Uniform / Epanechnikov / histogram.  MM: members held in registers
+// (M <= MM); MM == 0 streams them twice from memory.
+template <typename T, int MODEL, int MM>
+__global__ __launch_bounds__(kFitTX* kFitTY) void k_fit(FitArgs a) {
+  __shared__ int counts[MODEL == CP_HISTOGRAM ? kMaxBins * kFitTX * kFitTY : 1];
+  const int tid = threadIdx.x;
+  const int x = blockIdx.x * kFitTX + (tid % kFitTX);
+  const int y = blockIdx.y * kFitTY + (tid / kFitTX);
+  if (x >= a.W || y >= a.H) return;
+  const T* mem = static_cast<const T*>(a.members);
+  T* par = static_cast<T*>(a.params);
+  const int64_t at = (int64_t)y * a.rs + x;
+  const int M = a.M;
+  T v[MM > 0 ? MM : 1];
+  T mn, mx;
+  double s1 = 0.0, s2 = 0.0, shift;
+  if (MM > 0) {
+#pragma unroll
+    for (int k = 0; k < (MM > 0 ? MM : 1); ++k)
+      if (k < M) v[k] = mem[(int64_t)k * a.ps + at];
+    mn = mx = v[0];
+    shift = (double)v[0];
+#pragma unroll
+    for (int k = 1; k < (MM > 0 ? MM : 1); ++k)
+      if (k < M) {
+        mn = v[k] < mn ? v[k] : mn;
+        mx = v[k] > mx ? v[k] : mx;
+      }
+    if (MODEL == CP_EPANECHNIKOV) {
+#pragma unroll
+      for (int k = 0; k < (MM > 0 ? MM : 1); ++k)
+        if (k < M) {
+          const double d = (double)v[k] - shift;
+          s1 += d;
+          s2 = fma(d, d, s2);
+        }
+    }
+  } else {
+    mn = mx = mem[at];
+    shift = (double)mn;
+    for (int k = 0; k < M; ++k) {
+      const T xk = mem[(int64_t)k * a.ps + at];
+      mn = xk < mn ? xk : mn;
+      mx = xk > mx ? xk : mx;
+      const double d = (double)xk - shift;
+      s1 += d;
+      s2 = fma(d, d, s2);
+    }
+  }
+  const bool degenerate = !(mn < mx);
+  T lo = mn, hi = mx;
+  if (degenerate) {
+    const T e = rn_mul(T(a.eps), mn < T(0) ? (-mn > T(1) ? -mn : T(1)) : (mn > T(1) ? mn : T(1)));
+    lo = rn_sub(mn, e);
+    hi = rn_add(mn, e);
+  }
+  if (MODEL == CP_UNIFORM) {
+    par[at] = lo;
+    par[a.ps + at] = hi;
+    return;
+  }
+  if (MODEL == CP_EPANECHNIKOV) {
+    const double mean = shift + s1 / (double)M;
+    double w;
+    if (degenerate) {
+      w = a.eps * fmax(1.0, fabs(mean));
+    } else {
+      const double ss = fmax(s2 - s1 * s1 / (double)M, 0.0);
+      w = a.bw * sqrt(ss / (double)(M - a.ddof)) * pow((double)M, -0.2);
+    }
+    par[at] = (T)mean;
+    par[a.ps + at] = (T)w;
+    return;
+  }
+  // histogram: per-thread counters in LDS (dynamic bin index)
+  int* cnt = counts + tid;
+  constexpr int NT = kFitTX * kFitTY;
+  for (int j = 0; j < a.nb; ++j) cnt[j * NT] = 0;
+  if (MM > 0) {
+#pragma unroll
+    for (int k = 0; k < (MM > 0 ? MM : 1); ++k)
+      if (k < M) cnt[bin_of(v[k], lo, hi, a.nb) * NT] += 1;
+  } else {
+    for (int k = 0; k < M; ++k) cnt[bin_of(mem[(int64_t)k * a.ps + at], lo, hi, a.nb) * NT] += 1;
+  }
+  par[at] = lo;
+  par[a.ps + at] = hi;
+  const T fm = T(M);
+  for (int j = 0; j < a.nb; ++j) par[(int64_t)(2 + j) * a.ps + at] = rn_div(T(cnt[j * NT]), fm);
+}
+
+// ---------------------------------------------------------------------------
+// multivariate Gaussian: mean plane, then per-vertex covariance + Cholesky
+// ---------------------------------------------------------------------------
+__global__ __launch_bounds__(256) void k_fit_mean(FitArgs a) {
+  const int x = blockIdx.x * kFitTX + (threadIdx.x % kFitTX);
+  const int y = blockIdx.y * kFitTY + (threadIdx.x / kFitTX);
+  if (x >= a.W || y >= a.H) return;
+  const float* mem = static_cast<const float*>(a.members);
+  double* par = static_cast<double*>(a.params);
+  const int64_t at = (int64_t)y * a.rs + x;
+  double s = 0.0;
+  for (int k = 0; k < a.M; ++k) s += (double)mem[(int64_t)k * a.ps + at];
+  par[at] = s / (double)a.M;
+}
+
+__global__ __launch_bounds__(256) void k_fit_mvg(FitArgs a, double jitter) {
+  const int x = blockIdx.x * kFitTX + (threadIdx.x % kFitTX);
+  const int y = blockIdx.y * kFitTY + (threadIdx.x / kFitTX);
+  if (x >= a.W || y >= a.H) return;
+  const float* mem = static_cast<const float*>(a.members);
+  double* par = static_cast<double*>(a.params);
+  const int64_t at = (int64_t)y * a.rs + x;
+  // variable order e, n, w, s, v
+  const int dy[5] = {0, -1, 0, 1, 0}, dx[5] = {1, 0, -1, 0, 0};
+  bool pres[5];
+  int64_t off[5];
+#pragma unroll
+  for (int i = 0; i < 5; ++i) {
+    const int yy = y + dy[i], xx = x + dx[i];
+    pres[i] = yy >= 0 && yy < a.H && xx >= 0 && xx < a.W;
+    off[i] = pres[i] ? (int64_t)yy * a.rs + xx : at;
+  }
+  double k0[5], s1[5], s2[15];
+#pragma unroll
+  for (int i = 0; i < 5; ++i) {
+    k0[i] = (double)mem[off[i]];
+    s1[i] = 0.0;
+  }
+#pragma unroll
+  for (int i = 0; i < 15; ++i) s2[i] = 0.0;
+  for (int k = 0; k < a.M; ++k) {
+    double d[5];
+#pragma unroll
+    for (int i = 0; i < 5; ++i) {
+      d[i] = (double)mem[(int64_t)k * a.ps + off[i]] - k0[i];
+      s1[i] += d[i];
+    }
+    int t = 0;
+#pragma unroll
+    for (int r = 0; r < 5; ++r)
+#pragma unroll
+      for (int c = 0; c <= r; ++c, ++t) s2[t] = fma(d[r], d[c], s2[t]);
+  }
+  const double M = (double)a.M, den = (double)(a.M - a.ddof);
+  double C[5][5];
+  {
+    int t = 0;
+#pragma unroll
+    for (int r = 0; r < 5; ++r)
+#pragma unroll
+      for (int c = 0; c <= r; ++c, ++t) {
+        double v;
+        if (pres[r] && pres[c])
+          v = (s2[t] - s1[r] * s1[c] / M) / den + (r == c ? jitter : 0.0);
+        else
+          v = r == c ? 1.0 : 0.0;
+        C[r][c] = v;
+      }
+  }
+  double L[5][5];
+  bool ok = true;
+#pragma unroll
+  for (int r = 0; r < 5; ++r)
+#pragma unroll
+    for (int c = 0; c <= r; ++c) {
+      double s = C[r][c];
+#pragma unroll
+      for (int k = 0; k < c; ++k) s -= L[r][k] * L[c][k];
+      if (r == c) {
+        ok = ok && s > 0.0;
+        L[r][c] = sqrt(s > 0.0 ? s : 1.0);
+      } else {
+        L[r][c] = s / L[c][c];
+      }
+    }
+  int t = 0;
+#pragma unroll
+  for (int r = 0; r < 5; ++r)
+#pragma unroll
+    for (int c = 0; c <= r; ++c, ++t) par[(int64_t)(1 + t) * a.ps + at] = ok ? L[r][c] : __builtin_nan("");
+}
+
+template <typename T, int MODEL>
+hipError_t launch_fit(const FitArgs& a, hipStream_t st) {
+  dim3 grid((a.W + kFitTX - 1) / kFitTX, (a.H + kFitTY - 1) / kFitTY);
+  if (a.M <= 8)
+    hipLaunchKernelGGL((k_fit<T, MODEL, 8>), grid, dim3(kFitTX * kFitTY), 0, st, a);
+  else if (a.M <= kMaxRegMembers)
+    hipLaunchKernelGGL((k_fit<T, MODEL, kMaxRegMembers>), grid, dim3(kFitTX * kFitTY), 0, st, a);
+  else
+    hipLaunchKernelGGL((k_fit<T, MODEL, 0>), grid, dim3(kFitTX * kFitTY), 0, st, a);
+  return hipGetLastError();
+}
+
+template <typename T>
+hipError_t fit_typed(const FitArgs& a, int model, hipStream_t st) {
+  if (model == CP_UNIFORM) return launch_fit<T, CP_UNIFORM>(a, st);
+  if (model == CP_EPANECHNIKOV) return launch_fit<T, CP_EPANECHNIKOV>(a, st);
+  return launch_fit<T, CP_HISTOGRAM>(a, st);
+}
+
+}  // namespace
+
+hipError_t fit_params(const Field& f, const void* members, int M, int ddof, double bw, double jitter, double eps,
+                      void* params, hipStream_t st) {
+  FitArgs a;
+  a.members = members;
+  a.params = params;
+  a.M = M;
+  a.H = f.H;
+  a.W = f.W;
+  a.nb = f.nb;
+  a.ddof = ddof;
+  a.rs = f.rs;
+  a.ps = f.plane();
+  a.bw = bw;
+  a.eps = eps;
+  if (f.model == CP_MVGAUSS) {
+    dim3 grid((a.W + kFitTX - 1) / kFitTX, (a.H + kFitTY - 1) / kFitTY);
+    hipLaunchKernelGGL(k_fit_mean, grid, dim3(256), 0, st, a);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(k_fit_mvg, grid, dim3(256), 0, st, a, jitter);
+    return hipGetLastError();
+  }
+  if (f.dtype == CP_F64) return fit_typed<double>(a, f.model, st);
+  return fit_typed<float>(a, f.model, st);
+}
+
+}  // namespace cp

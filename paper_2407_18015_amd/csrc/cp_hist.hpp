@@ -1,0 +1,171 @@
+// cp_hist.hpp -- histogram model (Sec. 4.4.1): per-vertex sweep over the
+// merged bin edges of the five stencil histograms.
+//
+// A histogram is a mixture of non-overlapping uniform kernels, so on every
+// interval between consecutive edges of the five histograms the vertex pdf
+// is constant and each neighbour's survival function is linear.  Eq. 5 sums
+// the uniform-model probability over all h^5 kernel combinations; expanding
+// that sum by linearity gives the same number as integrating
+// pdf_v * prod S_n once over the merged edges, which costs O(5h) instead of
+// O(h^5).  On each interval the product of four linear factors is integrated
+// exactly from its end values (Bernstein form: the integral over [0,1] of
+// t^k (1-t)^(4-k) is k!(4-k)!/5!), so every term is non-negative and no
+// cancellation occurs.
+//
+// Staged per vertex in LDS (planes of the extended tile, E vertices each):
+//   0 lo, 1 hi, 2..h+1 masses, h+2..2h+2 suffix sums T_j = sum_{i>=j} m_i,
+//   2h+3..3h+3 prefix sums P_j = sum_{i<j} m_i, 3h+4 validity (1 or 0).
+// Suffix and prefix sums are formed in FP64 and rounded once.
+#pragma once
+
+#include "cp_device.hpp"
+
+namespace cp {
+
+__host__ __device__ constexpr int hist_planes(int h) { return 3 * h + 5; }
+
+template <typename T>
+struct HistLds {
+  const T* base;
+  int E;  // vertices per plane (extended tile)
+  int h;
+  // mass j of vertex e; `rev` reads the histogram of -X (bins reversed)
+  __device__ __forceinline__ T mass(int e, int j, bool rev) const {
+    const int p = rev ? (1 + h - j) : (2 + j);
+    return base[p * E + e];
+  }
+  // survival at edge j: sum of masses of bins >= j (of X or of -X)
+  __device__ __forceinline__ T tail(int e, int j, bool rev) const {
+    const int p = rev ? (3 + 3 * h - j) : (2 + h + j);
+    return base[p * E + e];
+  }
+  __device__ __forceinline__ bool valid(int e) const { return base[(4 + 3 * h) * E + e] != T(0); }
+};
+
+// Integral over [0,1] of prod_{i<4} (f0_i (1-t) + f1_i t)
+template <typename T>
+__device__ __forceinline__ T bern4(const T (&f0)[4], const T (&f1)[4]) {
+  T b0 = f0[0], b1 = f1[0];
+  T c0 = b0 * f0[1], c1 = __builtin_fma(b0, f1[1], b1 * f0[1]), c2 = b1 * f1[1];
+  T d0 = c0 * f0[2], d1 = __builtin_fma(c0, f1[2], c1 * f0[2]), d2 = __builtin_fma(c1, f1[2], c2 * f0[2]),
+    d3 = c2 * f1[2];
+  T e0 = d0 * f0[3], e1 = __builtin_fma(d0, f1[3], d1 * f0[3]), e2 = __builtin_fma(d1, f1[3], d2 * f0[3]),
+    e3 = __builtin_fma(d2, f1[3], d3 * f0[3]), e4 = d3 * f1[3];
+  return (e0 + e4) * T(0.2) + (e1 + e3) * T(0.05) + e2 * T(1.0 / 30.0);
+}
+
+// State of one neighbour histogram during the sweep: on the current bin,
+// S(x) = snx + slope * (nxt - x); nxt is the next edge to cross.
+template <typename T>
+struct HistCursor {
+  int j;  // current bin (-1 below the range)
+  T lo, hi, d, id;
+  T nxt, snx, slope;
+};
+
+template <typename T>
+__device__ __forceinline__ T hist_edge(const HistCursor<T>& c, int j, int h) {
+  return j >= h ? c.hi : __builtin_fma(T(j), c.d, c.lo);
+}
+
+// Position the cursor of neighbour e (local range [lo, hi]) at x = 0.
+template <typename T>
+__device__ __forceinline__ void hist_cursor_init(HistCursor<T>& c, const HistLds<T>& L, int e, bool rev,
+                                                 T lo, T hi, bool present, T big) {
+  const int h = L.h;
+  c.lo = lo;
+  c.hi = hi;
+  c.d = (hi - lo) / T(h);
+  c.id = T(h) / (hi - lo);
+  if (!present) {
+    c.j = h;
+    c.nxt = big;
+    c.snx = T(1);
+    c.slope = T(0);
+    return;
+  }
+  if (!(lo < T(0))) {
+    c.j = -1;
+    c.nxt = lo;
+    c.snx = L.tail(e, 0, rev);
+    c.slope = T(0);
+    return;
+  }
+  int j = (int)(-lo * c.id);
+  j = j < 0 ? 0 : (j > h - 1 ? h - 1 : j);
+  if (j + 1 < h && !(hist_edge(c, j + 1, h) > T(0))) ++j;
+  if (j > 0 && hist_edge(c, j, h) > T(0)) --j;
+  c.j = j;
+  c.nxt = hist_edge(c, j + 1, h);
+  c.snx = L.tail(e, j + 1, rev);
+  c.slope = L.mass(e, j, rev) * c.id;
+}
+
+// Cross the edge at x1 if it is this cursor's next edge.
+template <typename T>
+__device__ __forceinline__ bool hist_cursor_step(HistCursor<T>& c, const HistLds<T>& L, int e, bool rev,
+                                                 T x1, T big) {
+  const int h = L.h;
+  if (!(c.nxt == x1)) return false;
+  if (c.j < h - 1) {
+    c.j += 1;
+    c.nxt = hist_edge(c, c.j + 1, h);
+    c.snx = L.tail(e, c.j + 1, rev);
+    c.slope = L.mass(e, c.j, rev) * c.id;
+  } else {  // passed the upper end: S = 0 from here on
+    c.j = h;
+    c.nxt = big;
+    c.snx = T(0);
+    c.slope = T(0);
+  }
+  return true;
+}
+
+// One side (min; the max is the min of -X): integral over [0, bmin] of
+// pdf_v prod S_n.  Vertex local range [0, hv]; neighbour local ranges
+// [lo_i, hi_i] (already reflected for the max side).
+template <typename T>
+__device__ T hist_side_value(const HistLds<T>& L, int ev, const int (&en)[4], const bool (&pres)[4], bool rev,
+                             T hv, const T (&lo)[4], const T (&hi)[4]) {
+  const int h = L.h;
+  T bmin = hv;
+#pragma unroll
+  for (int i = 0; i < 4; ++i)
+    if (pres[i]) bmin = tmin(bmin, hi[i]);
+  if (!(bmin > T(0))) return T(0);
+  const T big = hv + hv + T(1);  // beyond every edge the sweep can reach
+  const T dv = hv / T(h), idv = T(h) / hv;
+  int jv = 0;
+  T nv = h > 1 ? dv : hv;
+  T pv = L.mass(ev, 0, rev) * idv;
+  HistCursor<T> c[4];
+#pragma unroll
+  for (int i = 0; i < 4; ++i) hist_cursor_init(c[i], L, en[i], rev, lo[i], hi[i], pres[i], big);
+  T f0[4], f1[4];
+#pragma unroll
+  for (int i = 0; i < 4; ++i) f0[i] = __builtin_fma(c[i].slope, c[i].nxt, c[i].snx);
+  T x0 = T(0), acc = T(0);
+  const int maxit = 5 * (h + 1) + 2;  // every step crosses at least one edge
+  for (int it = 0; it < maxit; ++it) {
+    if (!(x0 < bmin)) break;
+    T x1 = tmin(nv, bmin);
+#pragma unroll
+    for (int i = 0; i < 4; ++i) x1 = tmin(x1, c[i].nxt);
+#pragma unroll
+    for (int i = 0; i < 4; ++i) f1[i] = __builtin_fma(c[i].slope, c[i].nxt - x1, c[i].snx);
+    acc = __builtin_fma(pv * (x1 - x0), bern4(f0, f1), acc);
+    if (nv == x1 && jv < h - 1) {
+      ++jv;
+      nv = jv + 1 < h ? T(jv + 1) * dv : hv;
+      pv = L.mass(ev, jv, rev) * idv;
+    }
+#pragma unroll
+    for (int i = 0; i < 4; ++i) hist_cursor_step(c[i], L, en[i], rev, x1, big);
+#pragma unroll
+    for (int i = 0; i < 4; ++i) f0[i] = f1[i];
+    x0 = x1;
+  }
+  return acc;
+}
+
+}  // namespace cp

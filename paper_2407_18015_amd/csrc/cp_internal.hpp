@@ -1,0 +1,51 @@
+// cp_internal.hpp -- host-side declarations shared by the library's sources.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+
+#include "cpcrit.h"
+
+namespace cp {
+
+constexpr int kMaxBins = 32;
+
+// A validated field description (row_stride resolved).
+struct Field {
+  int H = 0, W = 0;
+  int64_t rs = 0;  // row stride (elements)
+  int model = 0, dtype = 0, nb = 0, ns = 0, est = 0;
+  uint64_t seed = 0;
+  uint32_t fid = 0;
+  int64_t plane() const { return (int64_t)H * rs; }
+};
+
+int n_params(int model, int nb);
+
+// closed-form models (uniform, Epanechnikov, histogram)
+hipError_t cf_forward(const Field& f, const void* params, void* pmin, void* pmax, hipStream_t st);
+hipError_t cf_backward(const Field& f, const void* params, const void* gmin, const void* gmax, void* grad,
+                       hipStream_t st);
+
+// fitting from members
+hipError_t fit_params(const Field& f, const void* members, int M, int ddof, double bw, double jitter,
+                      double eps, void* params, hipStream_t st);
+
+// multivariate Gaussian
+hipError_t mvg_forward(const Field& f, const double* params, float* pmin, float* pmax, hipStream_t st);
+hipError_t mvg_backward(const Field& f, const double* params, const float* gmin, const float* gmax,
+                        double* grad, hipStream_t st);
+hipError_t philox_raw(int64_t n, const uint32_t* ctr, uint64_t seed, uint32_t* out, hipStream_t st);
+void mvg_release();
+
+// batched persistent launch
+cp_status_t batched(int n, const Field* fields, const void* const* params, void* const* pmin,
+                    void* const* pmax, const void* const* gmin, const void* const* gmax,
+                    void* const* grad, uint32_t flags, hipStream_t st, const char** why);
+void batched_release();
+
+// Gauss-Legendre tables (host copies)
+bool gl_table(int n, double* x, double* w);
+
+}  // namespace cp

@@ -1,0 +1,359 @@
+// cp_tiles.hpp -- tile-level routines shared by the per-field kernels and the
+// batched persistent kernel.  A tile is a rectangle of output vertices; its
+// parameters plus a halo are staged in LDS with coalesced row loads, then
+// every thread evaluates its vertices from LDS.  All routines assume a 1-D
+// block of NT threads and end with a barrier so the caller may reuse LDS.
+#pragma once
+
+#include "cp_device.hpp"
+#include "cp_hist.hpp"
+#include "cpcrit.h"
+
+namespace cp {
+
+template <typename T>
+struct FieldPtrs {
+  const T* params;
+  T* pmin;
+  T* pmax;
+  const T* gmin;
+  const T* gmax;
+  T* grad;
+  int H, W, nb;
+  int64_t rs, ps;  // row stride, plane stride (elements)
+};
+
+// Stage `np` planes of the rectangle [gy0, gy0+EY) x [gx0, gx0+EX) into LDS
+// (plane-major, E = EY*EX per plane).  Cells outside the grid read as 0.
+template <typename T, int EY, int EX, int NT>
+__device__ __forceinline__ void stage(T* lds, const T* g, int np, int64_t ps, int64_t rs, int H, int W, int gy0,
+                                      int gx0, int tid) {
+  constexpr int E = EY * EX;
+  for (int p = 0; p < np; ++p) {
+    const T* gp = g + (int64_t)p * ps;
+    for (int i = tid; i < E; i += NT) {
+      const int ey = i / EX, ex = i - ey * EX;
+      const int gy = gy0 + ey, gx = gx0 + ex;
+      T v = T(0);
+      if (gy >= 0 && gy < H && gx >= 0 && gx < W) v = gp[(int64_t)gy * rs + gx];
+      lds[p * E + i] = v;
+    }
+  }
+}
+
+template <typename T>
+__device__ __forceinline__ bool valid_range(T lo, T hi) {
+  const T d = hi - lo;
+  return d > T(0) && d < T(3.0e38) && (lo - lo) == T(0);
+}
+template <typename T>
+__device__ __forceinline__ bool valid_epa(T m, T w) {
+  return w > T(0) && w < T(3.0e38) && (m - m) == T(0);
+}
+
+// ---------------------------------------------------------------------------
+// per-vertex evaluation from LDS (e = centre, en = e/n/w/s LDS indices)
+// ---------------------------------------------------------------------------
+template <typename T, int MODEL>
+__device__ __forceinline__ void vertex_fwd_ue(const T* L, int E, int e, const int (&en)[4], const bool (&pres)[4],
+                                              T& pmin, T& pmax) {
+  const T p0 = L[e], p1 = L[E + e];
+  T q0[4], q1[4];
+  bool ok = MODEL == CP_UNIFORM ? valid_range(p0, p1) : valid_epa(p0, p1);
+#pragma unroll
+  for (int i = 0; i < 4; ++i) {
+    q0[i] = L[en[i]];
+    q1[i] = L[E + en[i]];
+    if (pres[i]) ok = ok && (MODEL == CP_UNIFORM ? valid_range(q0[i], q1[i]) : valid_epa(q0[i], q1[i]));
+  }
+  if (!ok) {
+    pmin = pmax = qnan<T>();
+    return;
+  }
+  if (MODEL == CP_UNIFORM) {
+    const T Lv = p1 - p0;
+    T a[4], b[4], iL[4];
+    UniSide<T> s;
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+      a[i] = q0[i] - p0;
+      b[i] = q1[i] - p0;
+      iL[i] = T(1) / (q1[i] - q0[i]);
+    }
+    uni_setup(s, Lv, a, b, iL, pres);
+    pmin = uni_side_value(s);
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+      a[i] = p1 - q1[i];
+      b[i] = p1 - q0[i];
+    }
+    uni_setup(s, Lv, a, b, iL, pres);
+    pmax = uni_side_value(s);
+  } else {
+    T d[4];
+    EpaSide<T> s;
+#pragma unroll
+    for (int i = 0; i < 4; ++i) d[i] = q0[i] - p0;
+    epa_setup(s, p1, d, q1, pres);
+    pmin = epa_side_value(s);
+#pragma unroll
+    for (int i = 0; i < 4; ++i) d[i] = p0 - q0[i];
+    epa_setup(s, p1, d, q1, pres);
+    pmax = epa_side_value(s);
+  }
+}
+
+// Jacobian of one stencil, weighted by the upstream gradients:
+// jac[slot*2 + q] = gmin dP_min/dtheta_q(slot) + gmax dP_max/dtheta_q(slot)
+template <typename T, int MODEL>
+__device__ __forceinline__ void vertex_jac_ue(const T* L, int E, int e, const int (&en)[4], const bool (&pres)[4],
+                                              T gmin, T gmax, T (&jac)[10], T& pmin, T& pmax) {
+  const T p0 = L[e], p1 = L[E + e];
+  T q0[4], q1[4];
+  bool ok = MODEL == CP_UNIFORM ? valid_range(p0, p1) : valid_epa(p0, p1);
+#pragma unroll
+  for (int i = 0; i < 4; ++i) {
+    q0[i] = L[en[i]];
+    q1[i] = L[E + en[i]];
+    if (pres[i]) ok = ok && (MODEL == CP_UNIFORM ? valid_range(q0[i], q1[i]) : valid_epa(q0[i], q1[i]));
+  }
+  if (!ok) {
+#pragma unroll
+    for (int k = 0; k < 10; ++k) jac[k] = qnan<T>();
+    pmin = pmax = qnan<T>();
+    return;
+  }
+  if (MODEL == CP_UNIFORM) {
+    const T Lv = p1 - p0;
+    T a[4], b[4], iL[4];
+    UniSide<T> s;
+    UniGrad<T> g, r;
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+      a[i] = q0[i] - p0;
+      b[i] = q1[i] - p0;
+      iL[i] = T(1) / (q1[i] - q0[i]);
+    }
+    uni_setup(s, Lv, a, b, iL, pres);
+    uni_side_grad(s, g);
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+      a[i] = p1 - q1[i];
+      b[i] = p1 - q0[i];
+    }
+    uni_setup(s, Lv, a, b, iL, pres);
+    uni_side_grad(s, r);
+    T sg = T(0), sr = T(0);
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+      sg += g.da[i] + g.db[i];
+      sr += r.da[i] + r.db[i];
+    }
+    // min side, origin lo_v: a = lo_n - lo_v, b = hi_n - lo_v, Lv = hi_v - lo_v
+    // max side, origin hi_v reflected: a = hi_v - hi_n, b = hi_v - lo_n
+    pmin = g.f;
+    pmax = r.f;
+    jac[0] = gmin * (-g.dLv - sg) + gmax * (-r.dLv);
+    jac[1] = gmin * g.dLv + gmax * (r.dLv + sr);
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+      jac[2 + 2 * i] = gmin * g.da[i] - gmax * r.db[i];
+      jac[3 + 2 * i] = gmin * g.db[i] - gmax * r.da[i];
+    }
+  } else {
+    T d[4];
+    EpaSide<T> s;
+    EpaGrad<T> g, r;
+#pragma unroll
+    for (int i = 0; i < 4; ++i) d[i] = q0[i] - p0;
+    epa_setup(s, p1, d, q1, pres);
+    epa_side_grad(s, g);
+#pragma unroll
+    for (int i = 0; i < 4; ++i) d[i] = p0 - q0[i];
+    epa_setup(s, p1, d, q1, pres);
+    epa_side_grad(s, r);
+    T sg = T(0), sr = T(0);
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+      sg += g.dd[i];
+      sr += r.dd[i];
+    }
+    // min side: d = m_n - m_v; max side: d = m_v - m_n
+    pmin = g.f;
+    pmax = r.f;
+    jac[0] = -gmin * sg + gmax * sr;
+    jac[1] = gmin * g.dwv + gmax * r.dwv;
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+      jac[2 + 2 * i] = gmin * g.dd[i] - gmax * r.dd[i];
+      jac[3 + 2 * i] = gmin * g.dw[i] + gmax * r.dw[i];
+    }
+  }
+}
+
+// ---------------------------------------------------------------------------
+// forward tiles: 64 x TY outputs, halo 1
+// ---------------------------------------------------------------------------
+constexpr int kFwdTX = 64;
+
+template <typename T, int MODEL, int TY>
+__device__ __forceinline__ void tile_fwd_ue(const FieldPtrs<T>& f, int ty0, int tx0, T* lds, int tid) {
+  constexpr int TX = kFwdTX, EX = TX + 2, EY = TY + 2, E = EX * EY, NT = TX * TY;
+  stage<T, EY, EX, NT>(lds, f.params, 2, f.ps, f.rs, f.H, f.W, ty0 - 1, tx0 - 1, tid);
+  __syncthreads();
+  const int lx = tid % TX, ly = tid / TX;
+  const int x = tx0 + lx, y = ty0 + ly;
+  if (x < f.W && y < f.H) {
+    const int e = (ly + 1) * EX + lx + 1;
+    const int en[4] = {e + 1, e - EX, e - 1, e + EX};
+    const bool pres[4] = {x + 1 < f.W, y > 0, x > 0, y + 1 < f.H};
+    T pmin, pmax;
+    vertex_fwd_ue<T, MODEL>(lds, E, e, en, pres, pmin, pmax);
+    f.pmin[(int64_t)y * f.rs + x] = pmin;
+    f.pmax[(int64_t)y * f.rs + x] = pmax;
+  }
+  __syncthreads();
+}
+
+// FP64 suffix / prefix sums and validity of every staged histogram.
+template <typename T, int E, int NT>
+__device__ __forceinline__ void hist_stage_sums(T* lds, int h, int tid) {
+  for (int e = tid; e < E; e += NT) {
+    const T lo = lds[e], hi = lds[E + e];
+    bool ok = valid_range(lo, hi);
+    double run = 0.0;
+    lds[(3 + 2 * h) * E + e] = T(0);  // P_0
+    for (int j = 0; j < h; ++j) {
+      const T m = lds[(2 + j) * E + e];
+      ok = ok && (m >= T(0)) && (m < T(3.0e38));
+      run += (double)m;
+      lds[(4 + 2 * h + j) * E + e] = T(run);  // P_{j+1}
+    }
+    double suf = 0.0;
+    lds[(2 + 2 * h) * E + e] = T(0);  // T_h
+    for (int j = h - 1; j >= 0; --j) {
+      suf += (double)lds[(2 + j) * E + e];
+      lds[(2 + h + j) * E + e] = T(suf);  // T_j
+    }
+    lds[(4 + 3 * h) * E + e] = ok ? T(1) : T(0);
+  }
+}
+
+template <typename T, int TY>
+__device__ __forceinline__ void tile_fwd_hist(const FieldPtrs<T>& f, int ty0, int tx0, T* lds, int tid) {
+  constexpr int TX = kFwdTX, EX = TX + 2, EY = TY + 2, E = EX * EY, NT = TX * TY;
+  const int h = f.nb;
+  stage<T, EY, EX, NT>(lds, f.params, 2 + h, f.ps, f.rs, f.H, f.W, ty0 - 1, tx0 - 1, tid);
+  __syncthreads();
+  hist_stage_sums<T, E, NT>(lds, h, tid);
+  __syncthreads();
+  const int lx = tid % TX, ly = tid / TX;
+  const int x = tx0 + lx, y = ty0 + ly;
+  if (x < f.W && y < f.H) {
+    const HistLds<T> L{lds, E, h};
+    const int e = (ly + 1) * EX + lx + 1;
+    const int en[4] = {e + 1, e - EX, e - 1, e + EX};
+    const bool pres[4] = {x + 1 < f.W, y > 0, x > 0, y + 1 < f.H};
+    bool ok = L.valid(e);
+#pragma unroll
+    for (int i = 0; i < 4; ++i) ok = ok && (!pres[i] || L.valid(en[i]));
+    T pmin = qnan<T>(), pmax = qnan<T>();
+    if (ok) {
+      const T lov = lds[e], hiv = lds[E + e];
+      T lo[4], hi[4];
+#pragma unroll
+      for (int i = 0; i < 4; ++i) {
+        lo[i] = lds[en[i]] - lov;
+        hi[i] = lds[E + en[i]] - lov;
+      }
+      pmin = hist_side_value(L, e, en, pres, false, hiv - lov, lo, hi);
+#pragma unroll
+      for (int i = 0; i < 4; ++i) {
+        lo[i] = hiv - lds[E + en[i]];
+        hi[i] = hiv - lds[en[i]];
+      }
+      pmax = hist_side_value(L, e, en, pres, true, hiv - lov, lo, hi);
+    }
+    f.pmin[(int64_t)y * f.rs + x] = pmin;
+    f.pmax[(int64_t)y * f.rs + x] = pmax;
+  }
+  __syncthreads();
+}
+
+// ---------------------------------------------------------------------------
+// adjoint tiles (uniform / Epanechnikov): OX x OY outputs.  Phase 1 computes
+// the weighted Jacobian of every stencil centred in the tile plus a one-vertex
+// ring into LDS (parameters staged with a two-vertex halo); phase 2 gathers,
+// for each output vertex, the five entries that refer to it.  No atomics.
+// If f.pmin is non-null the probabilities are written as well (fused
+// forward + adjoint).
+// ---------------------------------------------------------------------------
+template <int OX, int OY>
+struct BwdGeom {
+  static constexpr int EX = OX + 2, EY = OY + 2, EJ = EX * EY;  // stencils
+  static constexpr int PX = OX + 4, PY = OY + 4, EP = PX * PY;  // parameters
+};
+
+template <typename T, int MODEL, int OX, int OY, int NT>
+__device__ __forceinline__ void tile_bwd_ue(const FieldPtrs<T>& f, int ty0, int tx0, T* lds, int tid) {
+  using G = BwdGeom<OX, OY>;
+  T* par = lds;
+  T* J = lds + 2 * G::EP;
+  stage<T, G::PY, G::PX, NT>(par, f.params, 2, f.ps, f.rs, f.H, f.W, ty0 - 2, tx0 - 2, tid);
+  __syncthreads();
+  for (int i = tid; i < G::EJ; i += NT) {
+    const int ey = i / G::EX, ex = i - ey * G::EX;
+    const int gy = ty0 - 1 + ey, gx = tx0 - 1 + ex;
+    T jac[10];
+#pragma unroll
+    for (int k = 0; k < 10; ++k) jac[k] = T(0);
+    if (gy >= 0 && gy < f.H && gx >= 0 && gx < f.W) {
+      const int e = (ey + 1) * G::PX + ex + 1;
+      const int en[4] = {e + 1, e - G::PX, e - 1, e + G::PX};
+      const bool pres[4] = {gx + 1 < f.W, gy > 0, gx > 0, gy + 1 < f.H};
+      const int64_t at = (int64_t)gy * f.rs + gx;
+      T pmin, pmax;
+      vertex_jac_ue<T, MODEL>(par, G::EP, e, en, pres, f.gmin[at], f.gmax[at], jac, pmin, pmax);
+      // fused forward: the adjoint evaluates the probabilities anyway
+      if (f.pmin && ey >= 1 && ey <= OY && ex >= 1 && ex <= OX) {
+        f.pmin[at] = pmin;
+        f.pmax[at] = pmax;
+      }
+    }
+#pragma unroll
+    for (int k = 0; k < 10; ++k) J[k * G::EJ + i] = jac[k];
+  }
+  __syncthreads();
+  for (int i = tid; i < OX * OY; i += NT) {
+    const int oy = i / OX, ox = i - oy * OX;
+    const int gy = ty0 + oy, gx = tx0 + ox;
+    if (gy < f.H && gx < f.W) {
+      const int c = (oy + 1) * G::EX + ox + 1;
+#pragma unroll
+      for (int q = 0; q < 2; ++q) {
+        // u is: slot v of its own stencil, w of its east neighbour's, e of
+        // its west neighbour's, s of its north neighbour's, n of its south's
+        const T g = J[(0 + q) * G::EJ + c] + J[(6 + q) * G::EJ + c + 1] + J[(2 + q) * G::EJ + c - 1] +
+                    J[(8 + q) * G::EJ + c - G::EX] + J[(4 + q) * G::EJ + c + G::EX];
+        f.grad[(int64_t)q * f.ps + (int64_t)gy * f.rs + gx] = g;
+      }
+    }
+  }
+  __syncthreads();
+}
+
+template <int OX, int OY>
+constexpr int bwd_ue_lds_elems() {
+  return 2 * BwdGeom<OX, OY>::EP + 10 * BwdGeom<OX, OY>::EJ;
+}
+
+// XCD-aware tile order: blocks are dealt to the 8 XCDs round-robin, so give
+// each XCD a contiguous run of tiles (neighbouring tiles share halo lines in
+// that XCD's L2).  A bijection on [0, n).
+__device__ __forceinline__ int xcd_tile(int b, int n) {
+  constexpr int X = 8;
+  const int q = n / X, r = n - q * X, k = b % X, i = b / X;
+  return k * q + (k < r ? k : r) + i;
+}
+
+}  // namespace cp

@@ -1,0 +1,189 @@
+"""Torch-level entry points over the C ABI.
+
+torch supplies device memory (tensors) and the current HIP stream; every
+computation runs in libcpcrit.so.  Shapes: parameters [n_param, H, W],
+probabilities and upstream gradients [H, W], members [M, H, W].  Tensors may
+have a row stride larger than W (all planes of one call must share it).
+"""
+from __future__ import annotations
+
+from dataclasses import dataclass
+
+import torch
+
+from . import _lib as L
+
+MODELS = {"uniform": L.CP_UNIFORM, "epanechnikov": L.CP_EPANECHNIKOV, "histogram": L.CP_HISTOGRAM,
+          "mvg": L.CP_MVGAUSS}
+
+
+def model_id(model) -> int:
+    return MODELS[model] if isinstance(model, str) else int(model)
+
+
+def n_params(model, nbins: int = 0) -> int:
+    n = L.cp_n_params(model_id(model), nbins)
+    if n < 0:
+        raise ValueError("unknown model or bad nbins")
+    return n
+
+
+@dataclass
+class Field:
+    """Description of one field (mirrors cp_field_desc_t)."""
+    height: int
+    width: int
+    model: int
+    dtype: torch.dtype = torch.float32
+    nbins: int = 0
+    nsamples: int = 0
+    seed: int = 0
+    field_id: int = 0
+    estimator: int = L.CP_MC_CONDITIONAL
+    row_stride: int = 0
+
+    def desc(self) -> L.cp_field_desc_t:
+        dt = {torch.float32: L.CP_F32, torch.float64: L.CP_F64}[self.dtype]
+        return L.cp_field_desc_t(self.height, self.width, self.row_stride, model_id(self.model), dt, self.nbins,
+                                 self.nsamples, self.seed, self.field_id, self.estimator)
+
+    @property
+    def n_param(self) -> int:
+        return n_params(self.model, self.nbins)
+
+    @property
+    def param_dtype(self) -> torch.dtype:
+        return torch.float64 if model_id(self.model) == L.CP_MVGAUSS else self.dtype
+
+    @property
+    def out_dtype(self) -> torch.dtype:
+        return torch.float32 if model_id(self.model) == L.CP_MVGAUSS else self.dtype
+
+
+def _stream(t: torch.Tensor) -> int:
+    return torch.cuda.current_stream(t.device).cuda_stream
+
+
+def _ptr(t: torch.Tensor | None):
+    return None if t is None else t.data_ptr()
+
+
+def _planes(t: torch.Tensor, H: int, W: int, dtype: torch.dtype, name: str, row_stride: int = 0) -> None:
+    if not t.is_cuda:
+        raise ValueError(f"{name} must be a device tensor")
+    if t.dtype != dtype:
+        raise ValueError(f"{name} must be {dtype}, got {t.dtype}")
+    if t.dim() == 2:
+        t = t.unsqueeze(0)
+    if t.dim() != 3 or t.shape[1] != H or t.shape[2] != W:
+        raise ValueError(f"{name} has shape {tuple(t.shape)}, expected [*, {H}, {W}]")
+    rs = row_stride or W
+    if t.stride(2) != 1 or t.stride(1) != rs or (t.shape[0] > 1 and t.stride(0) != H * rs):
+        raise ValueError(f"{name} must be dense planes with row stride {rs}")
+
+
+def field_of(params: torch.Tensor, model, nbins: int = 0, **kw) -> Field:
+    m = model_id(model)
+    H, W = params.shape[-2], params.shape[-1]
+    dtype = kw.pop("dtype", torch.float32 if m == L.CP_MVGAUSS else params.dtype)
+    if m == L.CP_HISTOGRAM and nbins == 0:
+        nbins = params.shape[0] - 2
+    return Field(H, W, m, dtype, nbins, **kw)
+
+
+def fit(members: torch.Tensor, model, nbins: int = 0, ddof: int = 1, bw_factor: float = 1.06,
+        cov_jitter: float = 1e-6, degenerate_eps: float = 0.0, out: torch.Tensor | None = None) -> torch.Tensor:
+    """cpu_fit_params: per-vertex model parameters from members [M, H, W]."""
+    M, H, W = members.shape
+    f = Field(H, W, model_id(model), members.dtype, nbins)
+    _planes(members, H, W, members.dtype, "members")
+    if out is None:
+        out = torch.empty((f.n_param, H, W), dtype=f.param_dtype, device=members.device)
+    _planes(out, H, W, f.param_dtype, "params")
+    opts = L.cp_fit_opts_t(ddof, bw_factor, cov_jitter, degenerate_eps)
+    L.check(L.cpu_fit_params(f.desc(), _ptr(members), M, opts, _ptr(out), _stream(members)))
+    return out
+
+
+def forward(params: torch.Tensor, f: Field, pmin: torch.Tensor | None = None, pmax: torch.Tensor | None = None):
+    """cp_prob_forward: (P_min, P_max) of every vertex."""
+    _planes(params, f.height, f.width, f.param_dtype, "params", f.row_stride)
+    if params.shape[0] != f.n_param:
+        raise ValueError(f"params needs {f.n_param} planes")
+    if pmin is None:
+        pmin = torch.empty((f.height, f.width), dtype=f.out_dtype, device=params.device)
+    if pmax is None:
+        pmax = torch.empty((f.height, f.width), dtype=f.out_dtype, device=params.device)
+    _planes(pmin, f.height, f.width, f.out_dtype, "p_min", f.row_stride)
+    _planes(pmax, f.height, f.width, f.out_dtype, "p_max", f.row_stride)
+    L.check(L.cp_prob_forward(f.desc(), _ptr(params), _ptr(pmin), _ptr(pmax), _stream(params)))
+    return pmin, pmax
+
+
+def backward(params: torch.Tensor, gmin: torch.Tensor, gmax: torch.Tensor, f: Field,
+             grad: torch.Tensor | None = None) -> torch.Tensor:
+    """cp_prob_backward: gradient of sum g_min P_min + g_max P_max w.r.t. params."""
+    _planes(params, f.height, f.width, f.param_dtype, "params", f.row_stride)
+    _planes(gmin, f.height, f.width, f.out_dtype, "g_min", f.row_stride)
+    _planes(gmax, f.height, f.width, f.out_dtype, "g_max", f.row_stride)
+    if grad is None:
+        grad = torch.empty_like(params)
+    _planes(grad, f.height, f.width, f.param_dtype, "grad_params", f.row_stride)
+    L.check(L.cp_prob_backward(f.desc(), _ptr(params), _ptr(gmin), _ptr(gmax), _ptr(grad), _stream(params)))
+    return grad
+
+
+def batched(fields: list[Field], params: list[torch.Tensor], pmin=None, pmax=None, gmin=None, gmax=None,
+            grad=None, graph: bool = False, per_field: bool = False) -> None:
+    """cp_prob_batched over caller-allocated outputs (lists of tensors)."""
+    n = len(fields)
+    flags = 0
+    if pmin is not None:
+        flags |= L.CP_BATCH_FWD
+    if grad is not None:
+        flags |= L.CP_BATCH_BWD
+    if graph:
+        flags |= L.CP_BATCH_GRAPH
+    if per_field:
+        flags |= L.CP_BATCH_PER_FIELD
+    for i, f in enumerate(fields):
+        _planes(params[i], f.height, f.width, f.param_dtype, f"params[{i}]", f.row_stride)
+    lst = lambda ts: None if ts is None else [_ptr(t) for t in ts]
+    L.check(L.cp_prob_batched(n, [f.desc() for f in fields], lst(params), lst(pmin), lst(pmax), lst(gmin),
+                              lst(gmax), lst(grad), flags, _stream(params[0])))
+
+
+def philox(counters: torch.Tensor, seed: int) -> torch.Tensor:
+    """Raw Philox4x32-10 words for counters [n, 4] (int32 storage of uint32)."""
+    out = torch.empty_like(counters)
+    L.check(L.cp_philox4x32_10(counters.shape[0], _ptr(counters), seed, _ptr(out), _stream(counters)))
+    return out
+
+
+class CPProb(torch.autograd.Function):
+    """(P_min, P_max) = CPProb.apply(params, field); backward through the
+    library's adjoint kernel."""
+
+    @staticmethod
+    def forward(ctx, params: torch.Tensor, f: Field):
+        params = params.contiguous()
+        pmin, pmax = forward(params, f)
+        ctx.save_for_backward(params)
+        ctx.field = f
+        return pmin, pmax
+
+    @staticmethod
+    def backward(ctx, gmin, gmax):
+        (params,) = ctx.saved_tensors
+        f = ctx.field
+        if gmin is None:
+            gmin = torch.zeros((f.height, f.width), dtype=f.out_dtype, device=params.device)
+        if gmax is None:
+            gmax = torch.zeros((f.height, f.width), dtype=f.out_dtype, device=params.device)
+        grad = backward(params, gmin.contiguous(), gmax.contiguous(), f)
+        return grad, None
+
+
+def critical_point_probability(params: torch.Tensor, model, nbins: int = 0, **kw):
+    """Differentiable (P_min, P_max) for a parameter field."""
+    return CPProb.apply(params, field_of(params, model, nbins, **kw))

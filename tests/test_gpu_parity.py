@@ -1,0 +1,447 @@
+"""GPU parity: the HIP library (through the C ABI) against the FP64 oracle,
+element by element on the same seeded inputs.
+
+Tolerances: probabilities 1e-6 absolute in FP32 and 1e-12 in FP64; gradients
+|d| <= 2e-5 (1 + |g|) in FP32 and 1e-10 (1 + |g|) in FP64 (the adjoint sums
+five stencil Jacobians whose entries scale like 1/width); Monte Carlo: raw
+Philox words bit-identical, conditional estimator within 1e-6, hit counts
+equal up to samples whose decision margin is below the oracle's ambiguity
+threshold; histogram bins (an integer decision) identical.
+"""
+import sys
+
+import numpy as np
+import pytest
+import torch
+
+import oracle
+import workloads
+import paper_2407_18015_amd as cp
+from paper_2407_18015_amd import _lib as L
+
+pytestmark = pytest.mark.gpu
+
+U, E, HST, MVG = 0, 1, 2, 3
+NAMES = {U: "uniform", E: "epanechnikov", HST: "histogram"}
+
+
+@pytest.fixture(scope="module", autouse=True)
+def device():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    L.load()  # fail loudly if the library is missing
+    return torch.device("cuda:0")
+
+
+def note(*a):
+    print("[case]", *a, flush=True)
+    sys.stdout.flush()
+
+
+def dev(a, dtype):
+    return torch.as_tensor(np.ascontiguousarray(a), dtype=dtype, device="cuda")
+
+
+def host(t):
+    torch.cuda.synchronize()
+    return t.detach().cpu().numpy().astype(np.float64)
+
+
+def fitted_params(model, seed, H, W, nbins=10):
+    """Config-shaped parameters: GPU fit of a seeded ensemble (float32)."""
+    if model == HST:
+        mem = workloads.mixture_ensemble(seed, H, W)
+    else:
+        mem = workloads.smooth_ensemble(seed, H, W)
+    return cp.fit(dev(mem, torch.float32), model, nbins=nbins if model == HST else 0), mem
+
+
+def gpu_forward(params, model, nbins=0):
+    f = cp.field_of(params, model, nbins)
+    return cp.forward(params, f)
+
+
+def assert_close(got, ref, atol, what):
+    d = np.abs(got - ref)
+    i = int(np.nanargmax(d)) if d.size else 0
+    assert np.all(np.isfinite(got) == np.isfinite(ref)), f"{what}: NaN pattern differs"
+    assert np.nanmax(d) <= atol, f"{what}: max |diff| {np.nanmax(d):.3e} at flat {i} (got {got.flat[i]}, ref {ref.flat[i]})"
+
+
+# ----------------------------------------------------------------------------
+# forward
+# ----------------------------------------------------------------------------
+@pytest.mark.parametrize("seed", [0, 1, 2])
+def test_forward_fp64_uniform_64x64(seed):
+    """Independent uniform noise on a 64x64 grid in FP64 (1e-12)."""
+    note("fp64 uniform 64x64 seed", seed)
+    p = workloads.uniform_params_field(seed, 64, 64)
+    pmin, pmax = gpu_forward(dev(p, torch.float64), U)
+    rmin, rmax = oracle.forward(U, p)
+    assert_close(host(pmin), rmin, 1e-12, "P_min")
+    assert_close(host(pmax), rmax, 1e-12, "P_max")
+
+
+@pytest.mark.parametrize("model", [U, E, HST])
+@pytest.mark.parametrize("dtype,tol", [(torch.float32, 1e-6), (torch.float64, 1e-12)])
+def test_forward_random_fields_ragged(model, dtype, tol):
+    """131x197 grid (several tiles, ragged tail in both directions)."""
+    note("forward", NAMES[model], dtype, "131x197")
+    p = workloads.random_params(model, 3 + model, 131, 197, nbins=7, width=0.06)
+    pt = dev(p, dtype)
+    pmin, pmax = gpu_forward(pt, model, 7 if model == HST else 0)
+    rmin, rmax = oracle.forward(model, host(pt))
+    assert_close(host(pmin), rmin, tol, "P_min")
+    assert_close(host(pmax), rmax, tol, "P_max")
+
+
+@pytest.mark.parametrize("model", [U, E, HST])
+def test_forward_fitted_fields(model):
+    """Parameters fitted on the GPU from config-shaped ensembles."""
+    note("forward fitted", NAMES[model], "160x210")
+    params, _ = fitted_params(model, 5, 160, 210)
+    pmin, pmax = gpu_forward(params, model, 10 if model == HST else 0)
+    rmin, rmax = oracle.forward(model, host(params))
+    assert_close(host(pmin), rmin, 1e-6, "P_min")
+    assert_close(host(pmax), rmax, 1e-6, "P_max")
+
+
+@pytest.mark.parametrize("shape", [(1, 1), (1, 9), (9, 1), (2, 2), (3, 67), (67, 3), (5, 64), (4, 65)])
+@pytest.mark.parametrize("model", [U, E, HST])
+def test_forward_edge_shapes(model, shape):
+    note("edge shape", NAMES[model], shape)
+    H, W = shape
+    p = workloads.random_params(model, 17, H, W, nbins=3, width=0.3)
+    pt = dev(p, torch.float64)
+    pmin, pmax = gpu_forward(pt, model, 3 if model == HST else 0)
+    rmin, rmax = oracle.forward(model, p)
+    assert_close(host(pmin), rmin, 1e-12, "P_min")
+    assert_close(host(pmax), rmax, 1e-12, "P_max")
+
+
+def test_forward_iid_exact():
+    """All vertices identical: 1/5 inside, 1/4 on edges, 1/3 at corners."""
+    note("iid exact")
+    for model, par in [(U, (0.0, 1.0)), (E, (0.5, 0.25)), (HST, (0.0, 1.0, 0.2, 0.5, 0.3))]:
+        p = np.broadcast_to(np.array(par)[:, None, None], (len(par), 9, 70)).copy()
+        pmin, pmax = gpu_forward(dev(p, torch.float64), model, 3 if model == HST else 0)
+        r = oracle.forward(model, p)
+        assert_close(host(pmin), r[0], 1e-13, "P_min")
+        assert_close(host(pmax), r[1], 1e-13, "P_max")
+
+
+def test_forward_invalid_parameters_give_nan():
+    note("invalid parameters")
+    p = workloads.random_params(U, 1, 6, 6, width=0.1)
+    p[:, 2, 3] = [0.5, 0.5]  # lo == hi
+    pmin, pmax = gpu_forward(dev(p, torch.float32), U)
+    a = host(pmin)
+    bad = np.zeros((6, 6), bool)
+    for dy, dx in [(0, 0), (0, 1), (-1, 0), (0, -1), (1, 0)]:
+        bad[2 - dy, 3 - dx] = True  # stencils that contain the bad vertex
+    assert np.all(np.isnan(a[bad])) and np.all(np.isfinite(a[~bad]))
+    h = workloads.random_params(HST, 1, 6, 6, nbins=3, width=0.1)
+    h[2, 1, 1] = -0.1  # negative mass
+    pmin, _ = gpu_forward(dev(h, torch.float32), HST, 3)
+    assert np.isnan(host(pmin)[1, 1])
+
+
+def test_row_stride_larger_than_width():
+    note("row stride")
+    H, W, RS = 37, 50, 64
+    p = workloads.random_params(E, 2, H, W, width=0.05)
+    big = torch.zeros((2, H, RS), dtype=torch.float32, device="cuda")
+    big[:, :, :W] = dev(p, torch.float32)
+    view = big[:, :, :W]
+    f = cp.Field(H, W, E, torch.float32, row_stride=RS)
+    omin = torch.full((H, RS), -7.0, device="cuda")
+    omax = torch.full((H, RS), -7.0, device="cuda")
+    cp.forward(view, f, omin[:, :W], omax[:, :W])
+    r = oracle.forward(E, host(view))
+    assert_close(host(omin[:, :W]), r[0], 1e-6, "P_min")
+    assert np.all(host(omin[:, W:]) == -7.0)
+
+
+def test_forward_is_deterministic():
+    note("determinism")
+    params, _ = fitted_params(HST, 9, 96, 130)
+    a = host(gpu_forward(params, HST, 10)[0])
+    b = host(gpu_forward(params, HST, 10)[0])
+    assert np.array_equal(a, b)
+
+
+# ----------------------------------------------------------------------------
+# fit
+# ----------------------------------------------------------------------------
+@pytest.mark.parametrize("model", [U, E, HST])
+def test_fit_parity(model):
+    note("fit", NAMES[model])
+    H, W = 97, 131
+    mem = workloads.mixture_ensemble(4, H, W) if model == HST else workloads.smooth_ensemble(4, H, W)
+    mem[:, 3, 5] = mem[0, 3, 5]  # a degenerate vertex
+    got = host(cp.fit(dev(mem, torch.float32), model, nbins=10 if model == HST else 0))
+    ref = oracle.fit(model, mem.astype(np.float64), nbins=10 if model == HST else 0, single=True)
+    if model == U:
+        assert np.array_equal(got, ref)
+    elif model == E:
+        np.testing.assert_allclose(got, ref.astype(np.float32), rtol=2.5e-7, atol=0)
+    else:
+        assert np.array_equal(got[:2], ref[:2])
+        # masses: identical bin decisions, count/M rounded once to FP32
+        np.testing.assert_allclose(got[2:], ref[2:].astype(np.float32), rtol=0, atol=6e-8)
+
+
+def test_fit_fp64_and_many_members():
+    note("fit fp64 / 40 members")
+    mem = np.random.default_rng(3).normal(size=(40, 33, 70))
+    for model in (U, E, HST):
+        got = host(cp.fit(dev(mem, torch.float64), model, nbins=6 if model == HST else 0))
+        ref = oracle.fit(model, mem, nbins=6 if model == HST else 0, single=False)
+        np.testing.assert_allclose(got, ref, rtol=1e-13, atol=1e-15)
+
+
+# ----------------------------------------------------------------------------
+# adjoint
+# ----------------------------------------------------------------------------
+def grad_tol(ref, dtype):
+    return (2e-5 if dtype == torch.float32 else 1e-10) * (1 + np.abs(ref))
+
+
+@pytest.mark.parametrize("model", [U, E, HST])
+@pytest.mark.parametrize("dtype", [torch.float32, torch.float64])
+def test_backward_parity(model, dtype):
+    H, W = (45, 67) if model == HST else (73, 101)
+    note("backward", NAMES[model], dtype, (H, W))
+    nb = 5
+    p = workloads.random_params(model, 40 + model, H, W, nbins=nb, width=0.06)
+    pt = dev(p, dtype)
+    gmin, gmax = workloads.upstream(1, H, W, np.float64)
+    f = cp.field_of(pt, model, nb if model == HST else 0)
+    g = host(cp.backward(pt, dev(gmin, dtype), dev(gmax, dtype), f))
+    ref = oracle.grad(model, host(pt), host(dev(gmin, dtype)), host(dev(gmax, dtype)))
+    d = np.abs(g - ref)
+    assert np.all(d <= grad_tol(ref, dtype)), f"max rel {np.max(d / (1 + np.abs(ref))):.3e}"
+
+
+@pytest.mark.parametrize("model", [U, E, HST])
+def test_backward_fitted_fields(model):
+    H, W = (40, 44) if model == HST else (96, 70)
+    note("backward fitted", NAMES[model], (H, W))
+    params, _ = fitted_params(model, 6, H, W)
+    gmin, gmax = workloads.upstream(2, H, W)
+    f = cp.field_of(params, model, 10 if model == HST else 0)
+    g = host(cp.backward(params, dev(gmin, torch.float32), dev(gmax, torch.float32), f))
+    ref = oracle.grad(model, host(params), gmin.astype(np.float64), gmax.astype(np.float64))
+    d = np.abs(g - ref)
+    assert np.all(d <= grad_tol(ref, torch.float32)), f"max rel {np.max(d / (1 + np.abs(ref))):.3e}"
+
+
+def test_autograd_function_matches_backward():
+    note("autograd")
+    p = dev(workloads.random_params(E, 8, 40, 50, width=0.05), torch.float32).requires_grad_(True)
+    pmin, pmax = cp.critical_point_probability(p, "epanechnikov")
+    gmin, gmax = workloads.upstream(3, 40, 50)
+    (pmin * dev(gmin, torch.float32) + pmax * dev(gmax, torch.float32)).sum().backward()
+    f = cp.field_of(p.detach(), E)
+    g = cp.backward(p.detach(), dev(gmin, torch.float32), dev(gmax, torch.float32), f)
+    assert torch.equal(p.grad, g)
+
+
+# ----------------------------------------------------------------------------
+# full-size workloads, sampled vertices
+# ----------------------------------------------------------------------------
+def sample_idx(H, W, n, seed):
+    rng = np.random.default_rng(seed)
+    idx = set(rng.integers(0, H * W, n).tolist())
+    for y, x in [(0, 0), (0, W - 1), (H - 1, 0), (H - 1, W - 1), (0, W // 2), (H // 2, 0), (H - 1, W // 3)]:
+        idx.add(y * W + x)
+    return np.array(sorted(idx), dtype=np.int64)
+
+
+@pytest.mark.parametrize("model,n", [(E, 2048), (HST, 2048), (U, 2048)])
+def test_full_size_2048_sampled(model, n):
+    """2048^2, 20 members: the benchmark's launch configuration; every output
+    plane compared at sampled vertices (borders and corners included)."""
+    note("full size 2048^2", NAMES[model])
+    H = W = 2048
+    params, mem = fitted_params(model, 0, H, W)
+    f = cp.field_of(params, model, 10 if model == HST else 0)
+    pmin, pmax = cp.forward(params, f)
+    gmin, gmax = workloads.upstream(0, H, W)
+    grad = cp.backward(params, dev(gmin, torch.float32), dev(gmax, torch.float32), f)
+    ph = host(params)
+    idx = sample_idx(H, W, n, 1 + model)
+    rmin, rmax = oracle.forward_at(model, ph, idx)
+    assert_close(host(pmin).ravel()[idx], rmin, 1e-6, "P_min")
+    assert_close(host(pmax).ravel()[idx], rmax, 1e-6, "P_max")
+    gi = idx[: max(64, n // 16)]
+    ref = oracle.grad_at(model, ph, gmin.astype(np.float64), gmax.astype(np.float64), gi)
+    g = host(grad).reshape(ph.shape[0], -1)[:, gi].T
+    d = np.abs(g - ref)
+    assert np.all(d <= grad_tol(ref, torch.float32)), f"max rel {np.max(d / (1 + np.abs(ref))):.3e}"
+    # the fit itself, at the same vertices
+    rfit = oracle.fit(model, mem[:, :64, :].astype(np.float64), nbins=10 if model == HST else 0, single=True)
+    gfit = ph[:, :64, :]
+    if model == E:
+        np.testing.assert_allclose(gfit, rfit.astype(np.float32), rtol=2.5e-7, atol=0)
+    else:
+        np.testing.assert_allclose(gfit, rfit.astype(np.float32), rtol=0, atol=6e-8)
+
+
+# ----------------------------------------------------------------------------
+# multivariate Gaussian
+# ----------------------------------------------------------------------------
+def test_philox_bit_identical():
+    note("philox")
+    rng = np.random.default_rng(0)
+    ctr = rng.integers(0, 2 ** 32, (4096, 4), dtype=np.uint64).astype(np.uint32)
+    seed = 0x0123456789ABCDEF
+    out = cp.philox(torch.as_tensor(ctr.view(np.int32), device="cuda"), seed)
+    got = out.cpu().numpy().view(np.uint32)
+    key = [seed & 0xFFFFFFFF, seed >> 32]
+    for i in range(0, 4096, 97):
+        assert np.array_equal(got[i], oracle.philox4x32_10(ctr[i], key)), i
+
+
+def mvg_setup(H, W, seed):
+    mem = workloads.correlated_ensemble(seed, H, W)
+    params = cp.fit(dev(mem, torch.float32), "mvg")
+    return params, mem
+
+
+def test_mvg_fit_parity():
+    note("mvg fit")
+    params, mem = mvg_setup(37, 53, 1)
+    ref = oracle.mvg_fit(mem.astype(np.float64))
+    np.testing.assert_allclose(host(params), ref, rtol=1e-10, atol=1e-12)
+
+
+@pytest.mark.parametrize("H,W,ns", [(37, 53, 512), (1024, 1024, 4096)])
+def test_mvg_forward_parity(H, W, ns):
+    note("mvg forward", H, W, ns)
+    params, _ = mvg_setup(H, W, 2)
+    seed, fid = 1234, 7
+    ph = host(params)
+    idx = np.arange(H * W) if H * W < 4000 else sample_idx(H, W, 96, 5)
+    ref, amb = oracle.mvg_forward_at(ph, idx, ns, seed, fid)
+    for est, cols in ((L.CP_MC_CONDITIONAL, (2, 3)), (L.CP_MC_HIT, (0, 1))):
+        f = cp.Field(H, W, MVG, torch.float32, nsamples=ns, seed=seed, field_id=fid, estimator=est)
+        pmin, pmax = cp.forward(params, f)
+        gmin = host(pmin).ravel()[idx]
+        gmax = host(pmax).ravel()[idx]
+        if est == L.CP_MC_CONDITIONAL:
+            assert_close(gmin, ref[:, 2], 1e-6, "conditional P_min")
+            assert_close(gmax, ref[:, 3], 1e-6, "conditional P_max")
+        else:
+            assert np.all(np.abs(gmin * ns - ref[:, 0] * ns) <= amb[:, 0] + 1e-6)
+            assert np.all(np.abs(gmax * ns - ref[:, 1] * ns) <= amb[:, 1] + 1e-6)
+
+
+def test_mvg_backward_parity():
+    note("mvg backward")
+    H, W, ns = 29, 41, 256
+    params, _ = mvg_setup(H, W, 3)
+    gmin, gmax = workloads.upstream(5, H, W)
+    f = cp.Field(H, W, MVG, torch.float32, nsamples=ns, seed=99, field_id=2)
+    g = host(cp.backward(params, dev(gmin, torch.float32), dev(gmax, torch.float32), f))
+    idx = np.arange(H * W)
+    ref = oracle.mvg_grad_at(host(params), gmin.astype(np.float64), gmax.astype(np.float64), idx, ns, 99, 2)
+    g = g.reshape(16, -1).T
+    scale = 1 + np.abs(ref).max(axis=1, keepdims=True)
+    # FP32 samples against FP64 samples: argmin flips on near-ties are allowed
+    # for at most a few vertices; everything else within 2e-5 relative
+    bad = np.any(np.abs(g - ref) > 2e-5 * scale, axis=1)
+    assert bad.sum() <= max(2, H * W // 200), bad.sum()
+
+
+# ----------------------------------------------------------------------------
+# batched persistent launch
+# ----------------------------------------------------------------------------
+def batched_fields(seed, n=9, lo=4.0, hi=7.5, dtype=torch.float32):
+    rng = np.random.default_rng(seed)
+    out = []
+    for i in range(n):
+        H = int(round(2 ** rng.uniform(lo, hi)))
+        W = int(round(2 ** rng.uniform(lo, hi)))
+        model = i % 3
+        p = workloads.random_params(model, seed * 100 + i, H, W, nbins=10, width=0.05)
+        out.append((cp.field_of(dev(p, dtype), model, 10 if model == HST else 0), dev(p, dtype)))
+    return out
+
+
+@pytest.mark.parametrize("graph", [False, True])
+def test_batched_forward_equals_per_field(graph):
+    note("batched forward graph", graph)
+    fl = batched_fields(1)
+    fields = [f for f, _ in fl]
+    params = [p for _, p in fl]
+    pmin = [torch.empty((f.height, f.width), device="cuda") for f in fields]
+    pmax = [torch.empty((f.height, f.width), device="cuda") for f in fields]
+    for rep in range(3 if graph else 1):
+        for t in pmin + pmax:
+            t.fill_(-1.0)
+        cp.batched(fields, params, pmin=pmin, pmax=pmax, graph=graph)
+        torch.cuda.synchronize()
+        for i, (f, p) in enumerate(fl):
+            a, b = cp.forward(p, f)
+            assert torch.equal(a, pmin[i]) and torch.equal(b, pmax[i]), (rep, i)
+
+
+@pytest.mark.parametrize("graph", [False, True])
+def test_batched_forward_backward(graph):
+    note("batched fwd+bwd graph", graph)
+    fl = batched_fields(2)
+    fields = [f for f, _ in fl]
+    params = [p for _, p in fl]
+    pmin = [torch.empty((f.height, f.width), device="cuda") for f in fields]
+    pmax = [torch.empty((f.height, f.width), device="cuda") for f in fields]
+    gmin = [dev(workloads.upstream(i, f.height, f.width)[0], torch.float32) for i, f in enumerate(fields)]
+    gmax = [dev(workloads.upstream(i, f.height, f.width)[1], torch.float32) for i, f in enumerate(fields)]
+    grad = [torch.empty_like(p) for p in params]
+    for rep in range(3 if graph else 1):
+        for t in pmin + pmax + grad:
+            t.fill_(-1.0)
+        torch.cuda.synchronize()
+        cp.batched(fields, params, pmin, pmax, gmin, gmax, grad, graph=graph)
+        torch.cuda.synchronize()
+        for i, (f, p) in enumerate(fl):
+            a, b = cp.forward(p, f)
+            g = cp.backward(p, gmin[i], gmax[i], f)
+            assert_close(host(pmin[i]), host(a), 1e-6, f"P_min field {i}")
+            assert_close(host(pmax[i]), host(b), 1e-6, f"P_max field {i}")
+            assert torch.equal(g, grad[i]), (rep, i)
+    # and the oracle on one field of each model
+    for i in range(3):
+        f, p = fl[i]
+        r = oracle.forward(f.model, host(p))
+        assert_close(host(pmin[i]), r[0], 1e-6, "oracle P_min")
+
+
+def test_batched_pointer_refresh():
+    """A second call with the same shapes but new buffers writes the new ones."""
+    note("batched pointer refresh")
+    fl = batched_fields(3, n=4)
+    fields = [f for f, _ in fl]
+    params = [p for _, p in fl]
+    for _ in range(2):
+        pmin = [torch.full((f.height, f.width), -1.0, device="cuda") for f in fields]
+        pmax = [torch.full((f.height, f.width), -1.0, device="cuda") for f in fields]
+        cp.batched(fields, params, pmin=pmin, pmax=pmax, graph=True)
+        torch.cuda.synchronize()
+        for i, (f, p) in enumerate(fl):
+            a, _ = cp.forward(p, f)
+            assert torch.equal(a, pmin[i])
+
+
+def test_batched_per_field_mode():
+    note("batched per-field mode")
+    fl = batched_fields(4, n=5)
+    fields = [f for f, _ in fl]
+    params = [p for _, p in fl]
+    pmin = [torch.empty((f.height, f.width), device="cuda") for f in fields]
+    pmax = [torch.empty((f.height, f.width), device="cuda") for f in fields]
+    cp.batched(fields, params, pmin=pmin, pmax=pmax, per_field=True)
+    torch.cuda.synchronize()
+    for i, (f, p) in enumerate(fl):
+        a, b = cp.forward(p, f)
+        assert torch.equal(a, pmin[i]) and torch.equal(b, pmax[i])
