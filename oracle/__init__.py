@@ -55,8 +55,8 @@ def _load():
         "or_forward": (i32, [i32, i32, i32, i32, P, P, P]),
         "or_forward_at": (i32, [i32, i32, i32, i32, P, i64, P, P, P]),
         "or_jacobian_at": (i32, [i32, i32, i32, i32, P, i64, P, P, P]),
-        "or_grad_at": (i32, [i32, i32, i32, i32, P, P, P, i64, P, P]),
-        "or_grad": (i32, [i32, i32, i32, i32, P, P, P, P]),
+        "or_grad_at": (i32, [i32, i32, i32, i32, P, P, P, i64, P, P, i32]),
+        "or_grad": (i32, [i32, i32, i32, i32, P, P, P, P, i32]),
         "or_fit": (i32, [i32, i32, P, i32, i32, i32, i32, i32, f64, f64, P]),
         "or_philox4x32_10": (None, [P, P, P]),
         "or_mvg_fit": (i32, [P, i32, i32, i32, i32, f64, P]),
@@ -126,23 +126,25 @@ def jacobian_at(model: int, params, idx) -> tuple[np.ndarray, np.ndarray]:
     return jmin, jmax
 
 
-def grad(model: int, params, gmin, gmax) -> np.ndarray:
-    """Adjoint over the whole grid: [n_param][H][W]."""
+def grad(model: int, params, gmin, gmax, absolute: bool = False) -> np.ndarray:
+    """Adjoint over the whole grid: [n_param][H][W].  absolute=True returns
+    the sum of the magnitudes of the contributing terms instead."""
     params, H, W, nb = _grid(params, model)
     gmin = _f64(gmin); gmax = _f64(gmax)
     out = np.empty_like(params)
-    _check(_load().or_grad(model, H, W, nb, _ptr(params), _ptr(gmin), _ptr(gmax), _ptr(out)), "grad")
+    _check(_load().or_grad(model, H, W, nb, _ptr(params), _ptr(gmin), _ptr(gmax), _ptr(out), int(absolute)),
+           "grad")
     return out
 
 
-def grad_at(model: int, params, gmin, gmax, idx) -> np.ndarray:
-    """Adjoint at flat vertex indices: [n][n_param]."""
+def grad_at(model: int, params, gmin, gmax, idx, absolute: bool = False) -> np.ndarray:
+    """Adjoint at flat vertex indices: [n][n_param] (absolute: see grad)."""
     params, H, W, nb = _grid(params, model)
     gmin = _f64(gmin); gmax = _f64(gmax)
     idx = np.ascontiguousarray(idx, dtype=np.int64)
     out = np.empty((idx.size, params.shape[0]))
     _check(_load().or_grad_at(model, H, W, nb, _ptr(params), _ptr(gmin), _ptr(gmax), idx.size,
-                              _ptr(idx), _ptr(out)), "grad_at")
+                              _ptr(idx), _ptr(out), int(absolute)), "grad_at")
     return out
 
 

@@ -491,9 +491,11 @@ int or_jacobian_at(int model, int H, int W, int nb, const double* params, int64_
  * Adjoint: grad[k][u] = sum over stencils v containing u of
  *   g_min(v) dP_min(v)/dtheta_k(u) + g_max(v) dP_max(v)/dtheta_k(u).
  * Computed for the listed vertices u only (out: [nidx][np]).
+ * absval != 0 sums the magnitudes of those ten terms instead (the scale of
+ * the cancellation in the sum, used to state rounding tolerances).
  */
 int or_grad_at(int model, int H, int W, int nb, const double* params, const double* gmin,
-               const double* gmax, int64_t nidx, const int64_t* idx, double* out) {
+               const double* gmax, int64_t nidx, const int64_t* idx, double* out, int absval) {
   if (check_grid(model, H, W, nb)) return 1;
   grid_t g = {model, H, W, nb, params};
   int np = n_param(model, nb);
@@ -511,14 +513,17 @@ int or_grad_at(int model, int H, int W, int nb, const double* params, const doub
       double a, b;
       cf_vertex(&g, vy, vx, &a, &b, jm, jx);
       int64_t at = (int64_t)vy * W + vx;
-      for (int k = 0; k < np; ++k) o[k] += gmin[at] * jm[s * np + k] + gmax[at] * jx[s * np + k];
+      for (int k = 0; k < np; ++k) {
+        double a = gmin[at] * jm[s * np + k], b = gmax[at] * jx[s * np + k];
+        o[k] += absval ? fabs(a) + fabs(b) : a + b;
+      }
     }
   }
   return 0;
 }
 
 int or_grad(int model, int H, int W, int nb, const double* params, const double* gmin,
-            const double* gmax, double* grad) {
+            const double* gmax, double* grad, int absval) {
   if (check_grid(model, H, W, nb)) return 1;
   int64_t n = (int64_t)H * W;
   int np = n_param(model, nb);
@@ -530,7 +535,7 @@ int or_grad(int model, int H, int W, int nb, const double* params, const double*
     return 2;
   }
   for (int64_t i = 0; i < n; ++i) idx[i] = i;
-  int rc = or_grad_at(model, H, W, nb, params, gmin, gmax, n, idx, tmp);
+  int rc = or_grad_at(model, H, W, nb, params, gmin, gmax, n, idx, tmp, absval);
   for (int64_t i = 0; i < n; ++i)
     for (int k = 0; k < np; ++k) grad[k * n + i] = tmp[i * np + k];
   free(tmp);

@@ -14,7 +14,22 @@
 
 #include <cstdint>
 
+// Pure arithmetic is host+device so it can also be exercised on the CPU.
+#define CP_HD __host__ __device__ __forceinline__
+
 namespace cp {
+
+// Fused multiply-add in the operand precision (FP32 stays FP32).
+template <typename T>
+CP_HD T cfma(T a, T b, T c);
+template <>
+CP_HD float cfma<float>(float a, float b, float c) {
+  return __builtin_fmaf(a, b, c);
+}
+template <>
+CP_HD double cfma<double>(double a, double b, double c) {
+  return __builtin_fma(a, b, c);
+}
 
 // ---------------------------------------------------------------------------
 // Gauss-Legendre rules on [-1, 1]; an N-point rule integrates polynomials of
@@ -71,29 +86,25 @@ struct GL<8> {
 // small helpers
 // ---------------------------------------------------------------------------
 template <typename T>
-__device__ __forceinline__ T tmin(T a, T b) {
+CP_HD T tmin(T a, T b) {
   return b < a ? b : a;
 }
 template <typename T>
-__device__ __forceinline__ T tmax(T a, T b) {
+CP_HD T tmax(T a, T b) {
   return a < b ? b : a;
 }
 template <typename T>
-__device__ __forceinline__ T tclamp(T v, T lo, T hi) {
+CP_HD T tclamp(T v, T lo, T hi) {
   return tmin(tmax(v, lo), hi);
 }
 template <typename T>
-__device__ __forceinline__ bool finite_pos(T v) {
-  return v > T(0) && v < T(3.0e38);
-}
-template <typename T>
-__device__ __forceinline__ T qnan() {
+CP_HD T qnan() {
   return __builtin_nan("");
 }
 
 // Compare-exchange of key k with a payload of P values (and an int tag).
 template <typename T, int P>
-__device__ __forceinline__ void cswap(T& ka, T& kb, T (&pa)[P], T (&pb)[P], int& ta, int& tb) {
+CP_HD void cswap(T& ka, T& kb, T (&pa)[P], T (&pb)[P], int& ta, int& tb) {
   const bool s = kb < ka;
   T t = s ? kb : ka;
   kb = s ? ka : kb;
@@ -111,24 +122,13 @@ __device__ __forceinline__ void cswap(T& ka, T& kb, T (&pa)[P], T (&pb)[P], int&
 
 // Sorting network for four keys (5 comparators), payload follows its key.
 template <typename T, int P>
-__device__ __forceinline__ void sort4(T (&k)[4], T (&p)[4][P], int (&tag)[4]) {
+CP_HD void sort4(T (&k)[4], T (&p)[4][P], int (&tag)[4]) {
   cswap<T, P>(k[0], k[1], p[0], p[1], tag[0], tag[1]);
   cswap<T, P>(k[2], k[3], p[2], p[3], tag[2], tag[3]);
   cswap<T, P>(k[0], k[2], p[0], p[2], tag[0], tag[2]);
   cswap<T, P>(k[1], k[3], p[1], p[3], tag[1], tag[3]);
   cswap<T, P>(k[1], k[2], p[1], p[2], tag[1], tag[2]);
 }
-
-// ---------------------------------------------------------------------------
-// Stencil of a vertex: own and neighbour parameters, neighbour order
-// e, n, w, s (index 0..3 here; stencil slot = index + 1).
-// ---------------------------------------------------------------------------
-template <typename T>
-struct Stencil2 {
-  T v0, v1;       // own parameters
-  T n0[4], n1[4]; // neighbour parameters
-  bool pres[4];
-};
 
 // ===========================================================================
 // Uniform model (Sec. 4.3).  Local frame with origin at the vertex lower
@@ -154,7 +154,7 @@ struct UniSide {
 };
 
 template <typename T>
-__device__ __forceinline__ void uni_setup(UniSide<T>& s, T Lv, const T (&a)[4], const T (&b)[4],
+CP_HD void uni_setup(UniSide<T>& s, T Lv, const T (&a)[4], const T (&b)[4],
                                           const T (&iL)[4], const bool (&pres)[4]) {
   s.Lv = Lv;
   T bmin = Lv;
@@ -185,7 +185,7 @@ __device__ __forceinline__ void uni_setup(UniSide<T>& s, T Lv, const T (&a)[4], 
 
 // integral over [l, r] of prod_{i<K} (b_i - x) iL_i  (times nothing else)
 template <typename T, int K, int N>
-__device__ __forceinline__ T uni_piece(const UniSide<T>& s, T l, T r) {
+CP_HD T uni_piece(const UniSide<T>& s, T l, T r) {
   const T mid = (l + r) * T(0.5), hl = (r - l) * T(0.5);
   T al[K], be[K];
 #pragma unroll
@@ -199,14 +199,14 @@ __device__ __forceinline__ T uni_piece(const UniSide<T>& s, T l, T r) {
     const T x = T(GL<N>::x[j]);
     T prod = T(1);
 #pragma unroll
-    for (int i = 0; i < K; ++i) prod *= __builtin_fma(-be[i], x, al[i]);
-    sum = __builtin_fma(T(GL<N>::w[j]), prod, sum);
+    for (int i = 0; i < K; ++i) prod *= cfma(-be[i], x, al[i]);
+    sum = cfma(T(GL<N>::w[j]), prod, sum);
   }
   return sum * hl;
 }
 
 template <typename T>
-__device__ __forceinline__ T uni_side_value(const UniSide<T>& s) {
+CP_HD T uni_side_value(const UniSide<T>& s) {
   if (s.empty) return T(0);
   T acc = s.c[0];  // piece 0: no factor
   acc += uni_piece<T, 1, 1>(s, s.c[0], s.c[1]);
@@ -227,7 +227,7 @@ struct UniGrad {
 };
 
 template <typename T, int K, int N>
-__device__ __forceinline__ void uni_piece_grad(const UniSide<T>& s, T l, T r, T& full, T (&loo)[4]) {
+CP_HD void uni_piece_grad(const UniSide<T>& s, T l, T r, T& full, T (&loo)[4]) {
   const T mid = (l + r) * T(0.5), hl = (r - l) * T(0.5);
   T al[K], be[K];
 #pragma unroll
@@ -244,16 +244,16 @@ __device__ __forceinline__ void uni_piece_grad(const UniSide<T>& s, T l, T r, T&
     const T wj = T(GL<N>::w[j]);
     T f[K], pre[K + 1], suf[K + 1];
 #pragma unroll
-    for (int i = 0; i < K; ++i) f[i] = __builtin_fma(-be[i], x, al[i]);
+    for (int i = 0; i < K; ++i) f[i] = cfma(-be[i], x, al[i]);
     pre[0] = T(1);
 #pragma unroll
     for (int i = 0; i < K; ++i) pre[i + 1] = pre[i] * f[i];
     suf[K] = T(1);
 #pragma unroll
     for (int i = K - 1; i >= 0; --i) suf[i] = suf[i + 1] * f[i];
-    sf = __builtin_fma(wj, pre[K], sf);
+    sf = cfma(wj, pre[K], sf);
 #pragma unroll
-    for (int i = 0; i < K; ++i) sl[i] = __builtin_fma(wj, pre[i] * suf[i + 1], sl[i]);
+    for (int i = 0; i < K; ++i) sl[i] = cfma(wj, pre[i] * suf[i + 1], sl[i]);
   }
   full = sf * hl;
 #pragma unroll
@@ -261,7 +261,7 @@ __device__ __forceinline__ void uni_piece_grad(const UniSide<T>& s, T l, T r, T&
 }
 
 template <typename T>
-__device__ __forceinline__ void uni_side_grad(const UniSide<T>& s, UniGrad<T>& g) {
+CP_HD void uni_side_grad(const UniSide<T>& s, UniGrad<T>& g) {
   g.f = T(0);
   g.dLv = T(0);
 #pragma unroll
@@ -327,7 +327,7 @@ struct EpaSide {
 };
 
 template <typename T>
-__device__ __forceinline__ void epa_setup(EpaSide<T>& s, T wv, const T (&d)[4], const T (&w)[4],
+CP_HD void epa_setup(EpaSide<T>& s, T wv, const T (&d)[4], const T (&w)[4],
                                           const bool (&pres)[4]) {
   s.wv = wv;
   s.iwv = T(1) / wv;
@@ -357,7 +357,7 @@ __device__ __forceinline__ void epa_setup(EpaSide<T>& s, T wv, const T (&d)[4], 
 
 // 4 * vertex CDF at x: (1 + t)^2 (2 - t), t = x / wv
 template <typename T>
-__device__ __forceinline__ T epa_cdf4(const EpaSide<T>& s, T x) {
+CP_HD T epa_cdf4(const EpaSide<T>& s, T x) {
   const T t = x * s.iwv;
   const T o = T(1) + t;
   return o * o * (T(2) - t);
@@ -365,7 +365,7 @@ __device__ __forceinline__ T epa_cdf4(const EpaSide<T>& s, T x) {
 
 // integral over [l, r] of (1 - t^2) prod_{i<K} 4 S_i   (unscaled)
 template <typename T, int K, int N>
-__device__ __forceinline__ T epa_piece(const EpaSide<T>& s, T l, T r) {
+CP_HD T epa_piece(const EpaSide<T>& s, T l, T r) {
   const T mid = (l + r) * T(0.5), hl = (r - l) * T(0.5);
   const T av = mid * s.iwv, bv = hl * s.iwv;
   T aq[K], bq[K];
@@ -378,20 +378,20 @@ __device__ __forceinline__ T epa_piece(const EpaSide<T>& s, T l, T r) {
 #pragma unroll
   for (int j = 0; j < N; ++j) {
     const T x = T(GL<N>::x[j]);
-    const T t = __builtin_fma(bv, x, av);
-    T prod = __builtin_fma(-t, t, T(1));
+    const T t = cfma(bv, x, av);
+    T prod = cfma(-t, t, T(1));
 #pragma unroll
     for (int i = 0; i < K; ++i) {
-      const T q = __builtin_fma(-bq[i], x, aq[i]);
+      const T q = cfma(-bq[i], x, aq[i]);
       prod *= q * q * (T(3) - q);
     }
-    sum = __builtin_fma(T(GL<N>::w[j]), prod, sum);
+    sum = cfma(T(GL<N>::w[j]), prod, sum);
   }
   return sum * hl;
 }
 
 template <typename T>
-__device__ __forceinline__ T epa_side_value(const EpaSide<T>& s) {
+CP_HD T epa_side_value(const EpaSide<T>& s) {
   if (s.empty) return T(0);
   const T kv = T(0.75) * s.iwv;  // pdf scale 3/(4 wv)
   T acc = epa_cdf4(s, s.c[0]) * T(0.25);
@@ -405,7 +405,10 @@ __device__ __forceinline__ T epa_side_value(const EpaSide<T>& s) {
 // Local derivatives of one side, f(wv, d_i, w_i):
 //   df/dd_i = int p_v p_i prod_{k!=i} S_k          (dS/dm = pdf)
 //   df/dw_i = int p_v u_i p_i prod_{k!=i} S_k      (dS/dw = u pdf)
-//   df/dwv  = int 3/(4 wv^2) (3 t^2 - 1) prod S_k
+//   df/dwv  = -(1/wv) sum_i int x p_v p_i prod_{k!=i} S_k
+// The last line is the scale invariance of P about the vertex centre
+// (wv df/dwv + sum_i (d_i df/dd_i + w_i df/dw_i) = 0); integrating
+// dpdf_v/dwv directly would cancel (its integral over the support is 0).
 template <typename T>
 struct EpaGrad {
   T f, dwv;
@@ -413,8 +416,7 @@ struct EpaGrad {
 };
 
 template <typename T, int K, int N>
-__device__ __forceinline__ void epa_piece_grad(const EpaSide<T>& s, T l, T r, T& full, T& dwv,
-                                               T (&gd)[4], T (&gw)[4]) {
+CP_HD void epa_piece_grad(const EpaSide<T>& s, T l, T r, T& full, T (&gd)[4], T (&gw)[4], T (&gx)[4]) {
   const T mid = (l + r) * T(0.5), hl = (r - l) * T(0.5);
   const T av = mid * s.iwv, bv = hl * s.iwv;
   T aq[K], bq[K];
@@ -423,21 +425,20 @@ __device__ __forceinline__ void epa_piece_grad(const EpaSide<T>& s, T l, T r, T&
     aq[i] = T(1) - (mid - s.d[i]) * s.iw[i];
     bq[i] = hl * s.iw[i];
   }
-  T sf = T(0), sw = T(0), sd[K], sww[K];
+  T sf = T(0), sd[K], sww[K], sxx[K];
 #pragma unroll
-  for (int i = 0; i < K; ++i) sd[i] = sww[i] = T(0);
+  for (int i = 0; i < K; ++i) sd[i] = sww[i] = sxx[i] = T(0);
 #pragma unroll
   for (int j = 0; j < N; ++j) {
     const T x = T(GL<N>::x[j]);
     const T wj = T(GL<N>::w[j]);
-    const T t = __builtin_fma(bv, x, av);
-    const T t2 = t * t;
-    const T pv = T(1) - t2;                        // 4 wv/3 * pdf_v
-    const T dpv = __builtin_fma(T(3), t2, T(-1));  // 4 wv^2/3 * dpdf_v/dwv
+    const T t = cfma(bv, x, av);
+    const T pv = cfma(-t, t, T(1));  // 4 wv/3 * pdf_v
+    const T xl = cfma(hl, x, mid);   // node in the vertex frame
     T q[K], S[K], pre[K + 1], suf[K + 1];
 #pragma unroll
     for (int i = 0; i < K; ++i) {
-      q[i] = __builtin_fma(-bq[i], x, aq[i]);
+      q[i] = cfma(-bq[i], x, aq[i]);
       S[i] = q[i] * q[i] * (T(3) - q[i]);  // 4 S_i
     }
     pre[0] = T(1);
@@ -446,70 +447,64 @@ __device__ __forceinline__ void epa_piece_grad(const EpaSide<T>& s, T l, T r, T&
     suf[K] = T(1);
 #pragma unroll
     for (int i = K - 1; i >= 0; --i) suf[i] = suf[i + 1] * S[i];
-    sf = __builtin_fma(wj * pv, pre[K], sf);
-    sw = __builtin_fma(wj * dpv, pre[K], sw);
+    sf = cfma(wj * pv, pre[K], sf);
 #pragma unroll
     for (int i = 0; i < K; ++i) {
       // (4 w_i / 3) p_i = 1 - u^2 = q (2 - q); u = 1 - q
       const T pi = q[i] * (T(2) - q[i]);
       const T lw = wj * pv * pi * pre[i] * suf[i + 1];
       sd[i] += lw;
-      sww[i] = __builtin_fma(lw, T(1) - q[i], sww[i]);
+      sww[i] = cfma(lw, T(1) - q[i], sww[i]);
+      sxx[i] = cfma(lw, xl, sxx[i]);
     }
   }
   full += sf * hl;
-  dwv += sw * hl;
 #pragma unroll
   for (int i = 0; i < K; ++i) {
     gd[i] += sd[i] * hl;
     gw[i] += sww[i] * hl;
+    gx[i] += sxx[i] * hl;
   }
 }
 
 template <typename T>
-__device__ __forceinline__ void epa_side_grad(const EpaSide<T>& s, EpaGrad<T>& g) {
+CP_HD void epa_side_grad(const EpaSide<T>& s, EpaGrad<T>& g) {
   g.f = g.dwv = T(0);
 #pragma unroll
   for (int i = 0; i < 4; ++i) g.dd[i] = g.dw[i] = T(0);
   if (s.empty) return;
-  // accumulators per sorted slot, each scaled by the 4^-(k) of its piece
-  T F[5] = {T(0), T(0), T(0), T(0), T(0)}, DW[5] = {T(0), T(0), T(0), T(0), T(0)};
-  T gd[5][4], gw[5][4];
+  T F[5] = {T(0), T(0), T(0), T(0), T(0)};
+  T gd[5][4], gw[5][4], gx[5][4];
 #pragma unroll
   for (int k = 0; k < 5; ++k)
 #pragma unroll
-    for (int i = 0; i < 4; ++i) gd[k][i] = gw[k][i] = T(0);
-  epa_piece_grad<T, 1, 3>(s, s.c[0], s.c[1], F[1], DW[1], gd[1], gw[1]);
-  epa_piece_grad<T, 2, 5>(s, s.c[1], s.c[2], F[2], DW[2], gd[2], gw[2]);
-  epa_piece_grad<T, 3, 6>(s, s.c[2], s.c[3], F[3], DW[3], gd[3], gw[3]);
-  epa_piece_grad<T, 4, 8>(s, s.c[3], s.bmin, F[4], DW[4], gd[4], gw[4]);
+    for (int i = 0; i < 4; ++i) gd[k][i] = gw[k][i] = gx[k][i] = T(0);
+  epa_piece_grad<T, 1, 3>(s, s.c[0], s.c[1], F[1], gd[1], gw[1], gx[1]);
+  epa_piece_grad<T, 2, 5>(s, s.c[1], s.c[2], F[2], gd[2], gw[2], gx[2]);
+  epa_piece_grad<T, 3, 6>(s, s.c[2], s.c[3], F[3], gd[3], gw[3], gx[3]);
+  epa_piece_grad<T, 4, 8>(s, s.c[3], s.bmin, F[4], gd[4], gw[4], gx[4]);
   const T kv = T(0.75) * s.iwv;
-  // piece 0: f = vertex CDF at c0; d/dwv of F_v(c0) = -(c0/wv) pdf_v(c0)
-  const T t0 = s.c[0] * s.iwv;
-  const T f0 = epa_cdf4(s, s.c[0]) * T(0.25);
-  const T dw0 = -t0 * kv * (T(1) - t0 * t0);
   const T sc[5] = {T(1), T(0.25), T(0.0625), T(0.015625), T(0.00390625)};
-  T f = f0, dwv = dw0;
+  T f = epa_cdf4(s, s.c[0]) * T(0.25);
 #pragma unroll
-  for (int k = 1; k < 5; ++k) {
-    f += kv * sc[k] * F[k];
-    dwv += kv * s.iwv * sc[k] * DW[k];
-  }
+  for (int k = 1; k < 5; ++k) f += kv * sc[k] * F[k];
   g.f = f;
-  g.dwv = dwv;
   // neighbour terms: slot i collects pieces k > i; p_i carries 3/(4 w_i) and
   // the other factors 4^-(k-1)
+  T xsum = T(0);
 #pragma unroll
   for (int i = 0; i < 4; ++i) {
-    T ad = T(0), aw = T(0);
+    T ad = T(0), aw = T(0), ax = T(0);
 #pragma unroll
     for (int k = i + 1; k < 5; ++k) {
       ad += sc[k - 1] * gd[k][i];
       aw += sc[k - 1] * gw[k][i];
+      ax += sc[k - 1] * gx[k][i];
     }
     const T ki = T(0.75) * s.iw[i] * kv;
     const T dd = ki * ad;
     const T dw = ki * aw;
+    xsum += ki * ax;
     const int t = s.tag[i];
 #pragma unroll
     for (int n = 0; n < 4; ++n) {
@@ -517,6 +512,7 @@ __device__ __forceinline__ void epa_side_grad(const EpaSide<T>& s, EpaGrad<T>& g
       g.dw[n] = (t == n) ? dw : g.dw[n];
     }
   }
+  g.dwv = -xsum * s.iwv;
 }
 
 }  // namespace cp

@@ -30,27 +30,27 @@ struct HistLds {
   int E;  // vertices per plane (extended tile)
   int h;
   // mass j of vertex e; `rev` reads the histogram of -X (bins reversed)
-  __device__ __forceinline__ T mass(int e, int j, bool rev) const {
+  CP_HD T mass(int e, int j, bool rev) const {
     const int p = rev ? (1 + h - j) : (2 + j);
     return base[p * E + e];
   }
   // survival at edge j: sum of masses of bins >= j (of X or of -X)
-  __device__ __forceinline__ T tail(int e, int j, bool rev) const {
+  CP_HD T tail(int e, int j, bool rev) const {
     const int p = rev ? (3 + 3 * h - j) : (2 + h + j);
     return base[p * E + e];
   }
-  __device__ __forceinline__ bool valid(int e) const { return base[(4 + 3 * h) * E + e] != T(0); }
+  CP_HD bool valid(int e) const { return base[(4 + 3 * h) * E + e] != T(0); }
 };
 
 // Integral over [0,1] of prod_{i<4} (f0_i (1-t) + f1_i t)
 template <typename T>
-__device__ __forceinline__ T bern4(const T (&f0)[4], const T (&f1)[4]) {
+CP_HD T bern4(const T (&f0)[4], const T (&f1)[4]) {
   T b0 = f0[0], b1 = f1[0];
-  T c0 = b0 * f0[1], c1 = __builtin_fma(b0, f1[1], b1 * f0[1]), c2 = b1 * f1[1];
-  T d0 = c0 * f0[2], d1 = __builtin_fma(c0, f1[2], c1 * f0[2]), d2 = __builtin_fma(c1, f1[2], c2 * f0[2]),
+  T c0 = b0 * f0[1], c1 = cfma(b0, f1[1], b1 * f0[1]), c2 = b1 * f1[1];
+  T d0 = c0 * f0[2], d1 = cfma(c0, f1[2], c1 * f0[2]), d2 = cfma(c1, f1[2], c2 * f0[2]),
     d3 = c2 * f1[2];
-  T e0 = d0 * f0[3], e1 = __builtin_fma(d0, f1[3], d1 * f0[3]), e2 = __builtin_fma(d1, f1[3], d2 * f0[3]),
-    e3 = __builtin_fma(d2, f1[3], d3 * f0[3]), e4 = d3 * f1[3];
+  T e0 = d0 * f0[3], e1 = cfma(d0, f1[3], d1 * f0[3]), e2 = cfma(d1, f1[3], d2 * f0[3]),
+    e3 = cfma(d2, f1[3], d3 * f0[3]), e4 = d3 * f1[3];
   return (e0 + e4) * T(0.2) + (e1 + e3) * T(0.05) + e2 * T(1.0 / 30.0);
 }
 
@@ -64,13 +64,13 @@ struct HistCursor {
 };
 
 template <typename T>
-__device__ __forceinline__ T hist_edge(const HistCursor<T>& c, int j, int h) {
-  return j >= h ? c.hi : __builtin_fma(T(j), c.d, c.lo);
+CP_HD T hist_edge(const HistCursor<T>& c, int j, int h) {
+  return j >= h ? c.hi : cfma(T(j), c.d, c.lo);
 }
 
 // Position the cursor of neighbour e (local range [lo, hi]) at x = 0.
 template <typename T>
-__device__ __forceinline__ void hist_cursor_init(HistCursor<T>& c, const HistLds<T>& L, int e, bool rev,
+CP_HD void hist_cursor_init(HistCursor<T>& c, const HistLds<T>& L, int e, bool rev,
                                                  T lo, T hi, bool present, T big) {
   const int h = L.h;
   c.lo = lo;
@@ -103,7 +103,7 @@ __device__ __forceinline__ void hist_cursor_init(HistCursor<T>& c, const HistLds
 
 // Cross the edge at x1 if it is this cursor's next edge.
 template <typename T>
-__device__ __forceinline__ bool hist_cursor_step(HistCursor<T>& c, const HistLds<T>& L, int e, bool rev,
+CP_HD bool hist_cursor_step(HistCursor<T>& c, const HistLds<T>& L, int e, bool rev,
                                                  T x1, T big) {
   const int h = L.h;
   if (!(c.nxt == x1)) return false;
@@ -125,7 +125,7 @@ __device__ __forceinline__ bool hist_cursor_step(HistCursor<T>& c, const HistLds
 // pdf_v prod S_n.  Vertex local range [0, hv]; neighbour local ranges
 // [lo_i, hi_i] (already reflected for the max side).
 template <typename T>
-__device__ T hist_side_value(const HistLds<T>& L, int ev, const int (&en)[4], const bool (&pres)[4], bool rev,
+__host__ __device__ T hist_side_value(const HistLds<T>& L, int ev, const int (&en)[4], const bool (&pres)[4], bool rev,
                              T hv, const T (&lo)[4], const T (&hi)[4]) {
   const int h = L.h;
   T bmin = hv;
@@ -143,7 +143,7 @@ __device__ T hist_side_value(const HistLds<T>& L, int ev, const int (&en)[4], co
   for (int i = 0; i < 4; ++i) hist_cursor_init(c[i], L, en[i], rev, lo[i], hi[i], pres[i], big);
   T f0[4], f1[4];
 #pragma unroll
-  for (int i = 0; i < 4; ++i) f0[i] = __builtin_fma(c[i].slope, c[i].nxt, c[i].snx);
+  for (int i = 0; i < 4; ++i) f0[i] = cfma(c[i].slope, c[i].nxt, c[i].snx);
   T x0 = T(0), acc = T(0);
   const int maxit = 5 * (h + 1) + 2;  // every step crosses at least one edge
   for (int it = 0; it < maxit; ++it) {
@@ -152,8 +152,8 @@ __device__ T hist_side_value(const HistLds<T>& L, int ev, const int (&en)[4], co
 #pragma unroll
     for (int i = 0; i < 4; ++i) x1 = tmin(x1, c[i].nxt);
 #pragma unroll
-    for (int i = 0; i < 4; ++i) f1[i] = __builtin_fma(c[i].slope, c[i].nxt - x1, c[i].snx);
-    acc = __builtin_fma(pv * (x1 - x0), bern4(f0, f1), acc);
+    for (int i = 0; i < 4; ++i) f1[i] = cfma(c[i].slope, c[i].nxt - x1, c[i].snx);
+    acc = cfma(pv * (x1 - x0), bern4(f0, f1), acc);
     if (nv == x1 && jv < h - 1) {
       ++jv;
       nv = jv + 1 < h ? T(jv + 1) * dv : hv;

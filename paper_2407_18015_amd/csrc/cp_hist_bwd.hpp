@@ -23,7 +23,7 @@ namespace cp {
 // `rev` (max side): sweep bin j is mass index h-1-j of the original field.
 // Returns the side probability.
 template <typename T>
-__device__ T hist_side_jac(const HistLds<T>& L, int ev, const int (&en)[4], const bool (&pres)[4], bool rev,
+__host__ __device__ T hist_side_jac(const HistLds<T>& L, int ev, const int (&en)[4], const bool (&pres)[4], bool rev,
                            T hv, const T (&lo)[4], const T (&hi)[4], T g, T* J, int EJ, int sj) {
   const int h = L.h;
   T bmin = hv;
@@ -54,40 +54,40 @@ __device__ T hist_side_jac(const HistLds<T>& L, int ev, const int (&en)[4], cons
     T full = T(0), loo[4] = {T(0), T(0), T(0), T(0)}, kb[4] = {T(0), T(0), T(0), T(0)};
 #pragma unroll
     for (int k = 0; k < 3; ++k) {
-      const T x = __builtin_fma(hl, T(GL<3>::x[k]), mid);
+      const T x = cfma(hl, T(GL<3>::x[k]), mid);
       const T w = T(GL<3>::w[k]);
       T S[4], K[4];
 #pragma unroll
       for (int i = 0; i < 4; ++i) {
         const T r = c[i].nxt - x;
-        S[i] = __builtin_fma(c[i].slope, r, c[i].snx);
+        S[i] = cfma(c[i].slope, r, c[i].snx);
         K[i] = (c[i].j >= 0 && c[i].j < h) ? r * c[i].id : T(0);
       }
       const T p01 = S[0] * S[1], p23 = S[2] * S[3];
       const T lo0 = S[1] * p23, lo1 = S[0] * p23, lo2 = p01 * S[3], lo3 = p01 * S[2];
-      full = __builtin_fma(w, p01 * p23, full);
+      full = cfma(w, p01 * p23, full);
       const T wl0 = w * lo0, wl1 = w * lo1, wl2 = w * lo2, wl3 = w * lo3;
       loo[0] += wl0;
       loo[1] += wl1;
       loo[2] += wl2;
       loo[3] += wl3;
-      kb[0] = __builtin_fma(wl0, K[0], kb[0]);
-      kb[1] = __builtin_fma(wl1, K[1], kb[1]);
-      kb[2] = __builtin_fma(wl2, K[2], kb[2]);
-      kb[3] = __builtin_fma(wl3, K[3], kb[3]);
+      kb[0] = cfma(wl0, K[0], kb[0]);
+      kb[1] = cfma(wl1, K[1], kb[1]);
+      kb[2] = cfma(wl2, K[2], kb[2]);
+      kb[3] = cfma(wl3, K[3], kb[3]);
     }
     const T php = pv * hl;
-    value = __builtin_fma(php, full, value);
-    curv = __builtin_fma(hl, full, curv);
+    value = cfma(php, full, value);
+    curv = cfma(hl, full, curv);
 #pragma unroll
     for (int i = 0; i < 4; ++i) {
-      Q[i] = __builtin_fma(php, loo[i], Q[i]);
-      cur[i] = __builtin_fma(php, kb[i], cur[i]);
+      Q[i] = cfma(php, loo[i], Q[i]);
+      cur[i] = cfma(php, kb[i], cur[i]);
     }
     // vertex bin boundary
     if (nv == x1 && jv < h - 1) {
       const int a = jidx(0, jv);
-      J[a] = __builtin_fma(g, curv * idv, J[a]);
+      J[a] = cfma(g, curv * idv, J[a]);
       curv = T(0);
       ++jv;
       nv = jv + 1 < h ? T(jv + 1) * dv : hv;
@@ -100,7 +100,7 @@ __device__ T hist_side_jac(const HistLds<T>& L, int ev, const int (&en)[4], cons
       if (hist_cursor_step(c[i], L, en[i], rev, x1, big)) {
         if (jo >= 0 && jo < h) {
           const int a = jidx(1 + i, jo);
-          J[a] = __builtin_fma(g, cur[i], J[a]);
+          J[a] = cfma(g, cur[i], J[a]);
         }
         cur[i] = Q[i];
       }
@@ -110,7 +110,7 @@ __device__ T hist_side_jac(const HistLds<T>& L, int ev, const int (&en)[4], cons
   // close the open bins; bins above the end see the whole range below them
   {
     const int a = jidx(0, jv);
-    J[a] = __builtin_fma(g, curv * idv, J[a]);
+    J[a] = cfma(g, curv * idv, J[a]);
   }
 #pragma unroll
   for (int i = 0; i < 4; ++i) {
@@ -118,11 +118,11 @@ __device__ T hist_side_jac(const HistLds<T>& L, int ev, const int (&en)[4], cons
     int j = c[i].j;
     if (j >= 0 && j < h) {
       const int a = jidx(1 + i, j);
-      J[a] = __builtin_fma(g, cur[i], J[a]);
+      J[a] = cfma(g, cur[i], J[a]);
     }
     for (int k = (j < 0 ? 0 : j + 1); k < h; ++k) {
       const int a = jidx(1 + i, k);
-      J[a] = __builtin_fma(g, Q[i], J[a]);
+      J[a] = cfma(g, Q[i], J[a]);
     }
   }
   return value;
@@ -146,7 +146,7 @@ __device__ __forceinline__ void tile_bwd_hist(const FieldPtrs<T>& f, int ty0, in
   stage<T, G::PY, G::PX, NT>(par, f.params, 2 + h, f.ps, f.rs, f.H, f.W, ty0 - 2, tx0 - 2, tid);
   for (int i = tid; i < 5 * h * G::EJ; i += NT) J[i] = T(0);
   __syncthreads();
-  hist_stage_sums<T, G::EP, NT>(par, h, tid);
+  hist_stage_sums<T, NT>(par, G::EP, h, tid);
   __syncthreads();
   const HistLds<T> L{par, G::EP, h};
   for (int i = tid; i < G::EJ; i += NT) {

@@ -42,12 +42,12 @@ __device__ __forceinline__ void stage(T* lds, const T* g, int np, int64_t ps, in
 }
 
 template <typename T>
-__device__ __forceinline__ bool valid_range(T lo, T hi) {
+CP_HD bool valid_range(T lo, T hi) {
   const T d = hi - lo;
   return d > T(0) && d < T(3.0e38) && (lo - lo) == T(0);
 }
 template <typename T>
-__device__ __forceinline__ bool valid_epa(T m, T w) {
+CP_HD bool valid_epa(T m, T w) {
   return w > T(0) && w < T(3.0e38) && (m - m) == T(0);
 }
 
@@ -55,7 +55,7 @@ __device__ __forceinline__ bool valid_epa(T m, T w) {
 // per-vertex evaluation from LDS (e = centre, en = e/n/w/s LDS indices)
 // ---------------------------------------------------------------------------
 template <typename T, int MODEL>
-__device__ __forceinline__ void vertex_fwd_ue(const T* L, int E, int e, const int (&en)[4], const bool (&pres)[4],
+CP_HD void vertex_fwd_ue(const T* L, int E, int e, const int (&en)[4], const bool (&pres)[4],
                                               T& pmin, T& pmax) {
   const T p0 = L[e], p1 = L[E + e];
   T q0[4], q1[4];
@@ -106,7 +106,7 @@ __device__ __forceinline__ void vertex_fwd_ue(const T* L, int E, int e, const in
 // Jacobian of one stencil, weighted by the upstream gradients:
 // jac[slot*2 + q] = gmin dP_min/dtheta_q(slot) + gmax dP_max/dtheta_q(slot)
 template <typename T, int MODEL>
-__device__ __forceinline__ void vertex_jac_ue(const T* L, int E, int e, const int (&en)[4], const bool (&pres)[4],
+CP_HD void vertex_jac_ue(const T* L, int E, int e, const int (&en)[4], const bool (&pres)[4],
                                               T gmin, T gmax, T (&jac)[10], T& pmin, T& pmax) {
   const T p0 = L[e], p1 = L[E + e];
   T q0[4], q1[4];
@@ -216,8 +216,8 @@ __device__ __forceinline__ void tile_fwd_ue(const FieldPtrs<T>& f, int ty0, int 
 }
 
 // FP64 suffix / prefix sums and validity of every staged histogram.
-template <typename T, int E, int NT>
-__device__ __forceinline__ void hist_stage_sums(T* lds, int h, int tid) {
+template <typename T, int NT>
+CP_HD void hist_stage_sums(T* lds, int E, int h, int tid) {
   for (int e = tid; e < E; e += NT) {
     const T lo = lds[e], hi = lds[E + e];
     bool ok = valid_range(lo, hi);
@@ -245,7 +245,7 @@ __device__ __forceinline__ void tile_fwd_hist(const FieldPtrs<T>& f, int ty0, in
   const int h = f.nb;
   stage<T, EY, EX, NT>(lds, f.params, 2 + h, f.ps, f.rs, f.H, f.W, ty0 - 1, tx0 - 1, tid);
   __syncthreads();
-  hist_stage_sums<T, E, NT>(lds, h, tid);
+  hist_stage_sums<T, NT>(lds, E, h, tid);
   __syncthreads();
   const int lx = tid % TX, ly = tid / TX;
   const int x = tx0 + lx, y = ty0 + ly;

@@ -2,8 +2,10 @@
 element by element on the same seeded inputs.
 
 Tolerances: probabilities 1e-6 absolute in FP32 and 1e-12 in FP64; gradients
-|d| <= 2e-5 (1 + |g|) in FP32 and 1e-10 (1 + |g|) in FP64 (the adjoint sums
-five stencil Jacobians whose entries scale like 1/width); Monte Carlo: raw
+|d| <= 1e-5 (1 + |g|) + 5e-7 S in FP32 and 1e-10 (1 + |g|) + 1e-13 S in FP64,
+where S is the sum of the magnitudes of the ten terms the adjoint adds (five
+stencils, two sides): the gradient is a sum whose terms scale like 1/width
+and cancel, so its rounding error is relative to S, not to g; Monte Carlo: raw
 Philox words bit-identical, conditional estimator within 1e-6, hit counts
 equal up to samples whose decision margin is below the oracle's ambiguity
 threshold; histogram bins (an integer decision) identical.
@@ -203,8 +205,17 @@ def test_fit_fp64_and_many_members():
 # ----------------------------------------------------------------------------
 # adjoint
 # ----------------------------------------------------------------------------
-def grad_tol(ref, dtype):
-    return (2e-5 if dtype == torch.float32 else 1e-10) * (1 + np.abs(ref))
+def grad_tol(ref, S, dtype):
+    if dtype == torch.float32:
+        return 1e-5 * (1 + np.abs(ref)) + 5e-7 * S
+    return 1e-10 * (1 + np.abs(ref)) + 1e-13 * S
+
+
+def assert_grad(g, ref, S, dtype, what="grad"):
+    d = np.abs(g - ref)
+    tol = grad_tol(ref, S, dtype)
+    i = int(np.argmax(d / tol))
+    assert np.all(d <= tol), f"{what}: worst |d|/tol {d.flat[i] / tol.flat[i]:.3g} (|d| {d.flat[i]:.3e}, g {ref.flat[i]:.4g}, S {S.flat[i]:.3g})"
 
 
 @pytest.mark.parametrize("model", [U, E, HST])
@@ -218,9 +229,8 @@ def test_backward_parity(model, dtype):
     gmin, gmax = workloads.upstream(1, H, W, np.float64)
     f = cp.field_of(pt, model, nb if model == HST else 0)
     g = host(cp.backward(pt, dev(gmin, dtype), dev(gmax, dtype), f))
-    ref = oracle.grad(model, host(pt), host(dev(gmin, dtype)), host(dev(gmax, dtype)))
-    d = np.abs(g - ref)
-    assert np.all(d <= grad_tol(ref, dtype)), f"max rel {np.max(d / (1 + np.abs(ref))):.3e}"
+    args = (model, host(pt), host(dev(gmin, dtype)), host(dev(gmax, dtype)))
+    assert_grad(g, oracle.grad(*args), oracle.grad(*args, absolute=True), dtype)
 
 
 @pytest.mark.parametrize("model", [U, E, HST])
@@ -231,9 +241,8 @@ def test_backward_fitted_fields(model):
     gmin, gmax = workloads.upstream(2, H, W)
     f = cp.field_of(params, model, 10 if model == HST else 0)
     g = host(cp.backward(params, dev(gmin, torch.float32), dev(gmax, torch.float32), f))
-    ref = oracle.grad(model, host(params), gmin.astype(np.float64), gmax.astype(np.float64))
-    d = np.abs(g - ref)
-    assert np.all(d <= grad_tol(ref, torch.float32)), f"max rel {np.max(d / (1 + np.abs(ref))):.3e}"
+    args = (model, host(params), gmin.astype(np.float64), gmax.astype(np.float64))
+    assert_grad(g, oracle.grad(*args), oracle.grad(*args, absolute=True), torch.float32)
 
 
 def test_autograd_function_matches_backward():
@@ -275,10 +284,9 @@ def test_full_size_2048_sampled(model, n):
     assert_close(host(pmin).ravel()[idx], rmin, 1e-6, "P_min")
     assert_close(host(pmax).ravel()[idx], rmax, 1e-6, "P_max")
     gi = idx[: max(64, n // 16)]
-    ref = oracle.grad_at(model, ph, gmin.astype(np.float64), gmax.astype(np.float64), gi)
+    args = (model, ph, gmin.astype(np.float64), gmax.astype(np.float64), gi)
     g = host(grad).reshape(ph.shape[0], -1)[:, gi].T
-    d = np.abs(g - ref)
-    assert np.all(d <= grad_tol(ref, torch.float32)), f"max rel {np.max(d / (1 + np.abs(ref))):.3e}"
+    assert_grad(g, oracle.grad_at(*args), oracle.grad_at(*args, absolute=True), torch.float32)
     # the fit itself, at the same vertices
     rfit = oracle.fit(model, mem[:, :64, :].astype(np.float64), nbins=10 if model == HST else 0, single=True)
     gfit = ph[:, :64, :]
