@@ -25,7 +25,9 @@ cp_status_t device_fail(hipError_t e, const char* what) {
   return CP_EDEVICE;
 }
 
-cp_status_t check_desc(const cp_field_desc_t* d, cp::Field& f) {
+// `sampling`: the call draws Monte Carlo samples (forward / backward of the
+// Gaussian model); the fit does not use nsamples / estimator.
+cp_status_t check_desc(const cp_field_desc_t* d, cp::Field& f, bool sampling = true) {
   if (!d) return fail(CP_EINVAL, "descriptor is NULL");
   if (d->height < 1 || d->width < 1) return fail(CP_EINVAL, "height and width must be >= 1");
   if (d->model < CP_UNIFORM || d->model > CP_MVGAUSS) return fail(CP_EINVAL, "unknown model");
@@ -37,8 +39,9 @@ cp_status_t check_desc(const cp_field_desc_t* d, cp::Field& f) {
     return fail(CP_EINVAL, "nbins must be in 1..32");
   if (d->model == CP_MVGAUSS) {
     if (d->dtype != CP_F32) return fail(CP_EUNSUPPORTED, "the Gaussian model samples in FP32 only");
-    if (d->nsamples < 1) return fail(CP_EINVAL, "nsamples must be >= 1");
-    if (d->estimator != CP_MC_CONDITIONAL && d->estimator != CP_MC_HIT) return fail(CP_EINVAL, "unknown estimator");
+    if (sampling && d->nsamples < 1) return fail(CP_EINVAL, "nsamples must be >= 1");
+    if (sampling && d->estimator != CP_MC_CONDITIONAL && d->estimator != CP_MC_HIT)
+      return fail(CP_EINVAL, "unknown estimator");
   }
   f.H = d->height;
   f.W = d->width;
@@ -96,7 +99,7 @@ const char* cp_last_error(void) { return g_last.c_str(); }
 cp_status_t cpu_fit_params(const cp_field_desc_t* desc, const void* members, int32_t n_members,
                            const cp_fit_opts_t* opts, void* params, void* stream) {
   cp::Field f;
-  cp_status_t s = check_desc(desc, f);
+  cp_status_t s = check_desc(desc, f, false);
   if (s != CP_OK) return s;
   if (!members || !params) return fail(CP_EINVAL, "members / params is NULL");
   if (n_members < 1) return fail(CP_EINVAL, "n_members must be >= 1");

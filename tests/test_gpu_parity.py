@@ -199,7 +199,8 @@ def test_fit_fp64_and_many_members():
     for model in (U, E, HST):
         got = host(cp.fit(dev(mem, torch.float64), model, nbins=6 if model == HST else 0))
         ref = oracle.fit(model, mem, nbins=6 if model == HST else 0, single=False)
-        np.testing.assert_allclose(got, ref, rtol=1e-13, atol=1e-15)
+        # 40-term FP64 sums in different orders: rounding ~ M * 2^-53 * max|x|
+        np.testing.assert_allclose(got, ref, rtol=1e-12, atol=2e-14)
 
 
 # ----------------------------------------------------------------------------
