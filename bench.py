@@ -143,6 +143,12 @@ def main():
     value = S * S / (ms * 1e-3)
     print(f"[bench] step {ms:.3f} ms", file=sys.stderr, flush=True)
     if args.profile_only:
+        # a plain copy of known size (256 MiB read + 256 MiB written): the
+        # reference that scales the HBM byte counters of the kernels above
+        src = torch.ones(64 << 20, dtype=torch.float32, device=dev)
+        dst = torch.empty_like(src)
+        dst.copy_(src)
+        torch.cuda.synchronize()
         return
 
     def timed(fn, reps):
@@ -235,7 +241,45 @@ def more_detail(cp, workloads, torch, dev, S, reps):
                             "fwd_vertices_per_s": n * n / (t_rb * 1e-3),
                             "fwd_bwd_vertices_per_s": n * n / ((t_rb + t_bwd) * 1e-3),
                             "samples_per_s_conditional": n * n * 4096 / (t_rb * 1e-3)}
+    del params, grad
+    res["batched_64_fields"] = batched_detail(cp, workloads, torch, dev)
     return res
+
+
+def batched_detail(cp, workloads, torch, dev):
+    """64 fields, sides round(2^U[7,11]), models cycling uniform /
+    Epanechnikov / histogram(10), each fitted from a 20-member ensemble:
+    forward + adjoint as one persistent launch, as a replayed graph, and as
+    one forward and one adjoint launch per field."""
+    t0 = time.time()
+    fields, params, pmin, pmax, gmin, gmax, grad = [], [], [], [], [], [], []
+    for side, model, seed in workloads.batched_layout(0):
+        gen = workloads.mixture_ensemble if model == 2 else workloads.smooth_ensemble
+        mem = torch.as_tensor(gen(seed, side, side), device=dev)
+        p = cp.fit(mem, model, nbins=10 if model == 2 else 0)
+        del mem
+        fields.append(cp.field_of(p, model, 10 if model == 2 else 0))
+        params.append(p)
+        pmin.append(torch.empty((side, side), device=dev))
+        pmax.append(torch.empty((side, side), device=dev))
+        a, b = workloads.upstream(seed, side, side)
+        gmin.append(torch.as_tensor(a, device=dev))
+        gmax.append(torch.as_tensor(b, device=dev))
+        grad.append(torch.empty_like(p))
+    nv = sum(f.height * f.width for f in fields)
+    print(f"[bench] batched inputs ({nv / 1e6:.1f} M vertices) in {time.time() - t0:.1f}s", file=sys.stderr,
+          flush=True)
+    out = {"fields": len(fields), "vertices": nv}
+    for name, kw in (("per_field", dict(per_field=True)), ("persistent", dict()), ("graph", dict(graph=True))):
+        ms = _timed(torch, lambda: cp.batched(fields, params, pmin, pmax, gmin, gmax, grad, **kw), 5)
+        out[name + "_fwd_bwd_ms"] = ms
+        out[name + "_fwd_bwd_vertices_per_s"] = nv / (ms * 1e-3)
+    for name, kw in (("per_field", dict(per_field=True)), ("graph", dict(graph=True))):
+        ms = _timed(torch, lambda: cp.batched(fields, params, pmin, pmax, **kw), 5)
+        out[name + "_fwd_ms"] = ms
+        out[name + "_fwd_vertices_per_s"] = nv / (ms * 1e-3)
+    out["speedup_fwd_bwd_graph_vs_per_field"] = out["per_field_fwd_bwd_ms"] / out["graph_fwd_bwd_ms"]
+    return out
 
 
 def _timed(torch, fn, reps):

@@ -5,6 +5,7 @@
 
 #include <climits>
 #include <cstdio>
+#include <mutex>
 #include <string>
 #include <vector>
 
@@ -65,6 +66,36 @@ int n_params(int model, int nb) {
   if (model == CP_HISTOGRAM) return 2 + nb;
   if (model == CP_MVGAUSS) return 16;
   return 2;
+}
+
+namespace {
+std::mutex g_ws_mu;
+void* g_ws = nullptr;
+size_t g_ws_bytes = 0;
+}  // namespace
+
+hipError_t workspace(size_t bytes, void** out) {
+  std::lock_guard<std::mutex> lk(g_ws_mu);
+  if (bytes > g_ws_bytes) {
+    if (g_ws) {
+      hipError_t e = hipFree(g_ws);  // waits for work that may still use it
+      if (e != hipSuccess) return e;
+      g_ws = nullptr;
+      g_ws_bytes = 0;
+    }
+    hipError_t e = hipMalloc(&g_ws, bytes);
+    if (e != hipSuccess) return e;
+    g_ws_bytes = bytes;
+  }
+  *out = g_ws;
+  return hipSuccess;
+}
+
+void workspace_release() {
+  std::lock_guard<std::mutex> lk(g_ws_mu);
+  if (g_ws) (void)hipFree(g_ws);
+  g_ws = nullptr;
+  g_ws_bytes = 0;
 }
 }  // namespace cp
 
@@ -184,7 +215,7 @@ cp_status_t cp_prob_batched(int32_t n, const cp_field_desc_t* descs, const void*
 
 cp_status_t cp_release(void) {
   cp::batched_release();
-  cp::mvg_release();
+  cp::workspace_release();
   return CP_OK;
 }
 

@@ -1,5 +1,5 @@
 // cp_batched.hip -- many fields of uneven size and mixed closed-form models
-// in one persistent launch.
+// in one persistent launch per pass.
 //
 // Small fields under-fill 256 CUs when launched one by one (a 128^2 field is
 // 64 forward tiles); the batched form flattens every field into tiles, deals
@@ -7,8 +7,14 @@
 // over a per-vertex cost model, and lets each block walk its own list.  The
 // tile lists depend only on the shapes, so they are built and uploaded once
 // per shape signature; the field table (data pointers) is refreshed only when
-// a pointer changes.  With CP_BATCH_GRAPH the launch is captured once per
+// a pointer changes.  With CP_BATCH_GRAPH the launches are captured once per
 // signature into a HIP graph and replayed.
+//
+// Forward-only and adjoint plans use separate kernel instantiations (each
+// carries only the register budget of its own tile routines).  Histogram
+// adjoint tiles write their per-stencil Jacobians to a workspace owned by the
+// plan, and a second persistent launch gathers them; forward values are
+// written by the adjoint tiles when both are requested.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -28,20 +34,47 @@ namespace cp {
 namespace {
 
 constexpr int kNT = 256;
-constexpr int kBwdF32 = 30, kBwdF64 = 14, kBwdHist = 14;  // adjoint tile edges
+constexpr int kBwdF32 = 30, kBwdF64 = 14;  // uniform / Epanechnikov adjoint tile edges
+constexpr int kGatherChunk = 256;          // histogram gather: vertices per tile
 constexpr size_t kMaxLds = 160 * 1024;
 
+enum { KIND_FWD = 0, KIND_BWD = 1, KIND_GATHER = 2 };
+enum { PASS_FWD = 0, PASS_BWD = 1, PASS_GATHER = 2 };
+
 struct BatchTile {
-  int field, ty0, tx0, kind;  // kind 0 = forward tile, 1 = adjoint (fused) tile
+  int field, ty0, tx0, kind;  // gather tiles: ty0 = first flat vertex index
 };
 
 template <typename T>
 struct BatchField {
   FieldPtrs<T> p;
+  T* J;  // histogram adjoint workspace ([5][h][H][W]) or null
   int model;
 };
 
+// histogram gather over vertices [i0, i0 + n) of one field (flat y*W + x)
 template <typename T>
+__device__ __forceinline__ void hist_gather_chunk(const FieldPtrs<T>& f, const T* __restrict__ J, int64_t i0,
+                                                  int tid) {
+  const int64_t plane = (int64_t)f.H * f.W;
+  const int64_t id = i0 + tid;
+  if (id >= plane) return;
+  const int y = (int)(id / f.W), x = (int)(id - (int64_t)y * f.W);
+  const int h = f.nb;
+  const int64_t at = (int64_t)y * f.rs + x;
+  f.grad[at] = T(0);
+  f.grad[f.ps + at] = T(0);
+  for (int k = 0; k < h; ++k) {
+    T g = J[(int64_t)(0 * h + k) * plane + id];
+    if (x + 1 < f.W) g += J[(int64_t)(3 * h + k) * plane + id + 1];
+    if (x > 0) g += J[(int64_t)(1 * h + k) * plane + id - 1];
+    if (y > 0) g += J[(int64_t)(4 * h + k) * plane + id - f.W];
+    if (y + 1 < f.H) g += J[(int64_t)(2 * h + k) * plane + id + f.W];
+    f.grad[(int64_t)(2 + k) * f.ps + at] = g;
+  }
+}
+
+template <typename T, int PASS>
 __global__ __launch_bounds__(kNT) void k_batched(const BatchField<T>* __restrict__ fields,
                                                  const BatchTile* __restrict__ tiles, const int* __restrict__ start) {
   extern __shared__ __align__(16) unsigned char smem[];
@@ -52,58 +85,69 @@ __global__ __launch_bounds__(kNT) void k_batched(const BatchField<T>* __restrict
   for (int t = start[b]; t < t1; ++t) {
     const BatchTile tl = tiles[t];
     const BatchField<T> F = fields[tl.field];
-    if (tl.kind == 0) {
+    if (PASS == PASS_FWD) {
       if (F.model == CP_UNIFORM)
         tile_fwd_ue<T, CP_UNIFORM, 4>(F.p, tl.ty0, tl.tx0, lds, tid);
       else if (F.model == CP_EPANECHNIKOV)
         tile_fwd_ue<T, CP_EPANECHNIKOV, 4>(F.p, tl.ty0, tl.tx0, lds, tid);
       else
         tile_fwd_hist<T, 4>(F.p, tl.ty0, tl.tx0, lds, tid);
-    } else {
+    } else if (PASS == PASS_BWD) {
       constexpr int OB = sizeof(T) == 4 ? kBwdF32 : kBwdF64;
       if (F.model == CP_UNIFORM)
         tile_bwd_ue<T, CP_UNIFORM, OB, OB, kNT>(F.p, tl.ty0, tl.tx0, lds, tid);
       else if (F.model == CP_EPANECHNIKOV)
         tile_bwd_ue<T, CP_EPANECHNIKOV, OB, OB, kNT>(F.p, tl.ty0, tl.tx0, lds, tid);
       else
-        tile_bwd_hist<T, kBwdHist, kBwdHist, kNT>(F.p, tl.ty0, tl.tx0, lds, tid);
+        tile_hist_sweep<T, 4>(F.p, tl.ty0, tl.tx0, lds, tid, F.J);
+    } else {
+      hist_gather_chunk<T>(F.p, F.J, tl.ty0, tid);
     }
   }
 }
 
-// relative cost per vertex (forward, adjoint) by model, used for balancing
+// Relative cost per vertex (forward, adjoint), measured on MI355X with the
+// per-field kernels at 2048^2 (uniform forward = 1); histograms scale with
+// the number of bin edges.
 double vertex_cost(int model, int nb, bool bwd) {
-  if (model == CP_UNIFORM) return bwd ? 3.0 : 1.0;
-  if (model == CP_EPANECHNIKOV) return bwd ? 10.0 : 3.5;
-  return (bwd ? 12.0 : 4.0) * (nb + 1);
+  if (model == CP_UNIFORM) return bwd ? 2.0 : 1.0;
+  if (model == CP_EPANECHNIKOV) return bwd ? 4.3 : 1.9;
+  return (bwd ? 5.6 : 2.3) * (nb + 1);
 }
 
 size_t tile_lds_bytes(int model, int nb, bool bwd, size_t el) {
-  if (!bwd) {
-    if (model == CP_HISTOGRAM) return el * (size_t)hist_planes(nb) * (kFwdTX + 2) * 6;
-    return el * 2 * (kFwdTX + 2) * 6;
-  }
-  if (model == CP_HISTOGRAM) return el * hist_bwd_lds_elems<kBwdHist, kBwdHist>(nb);
+  if (model == CP_HISTOGRAM) return el * (size_t)hist_planes(nb) * (kFwdTX + 2) * 6;
+  if (!bwd) return el * 2 * (kFwdTX + 2) * 6;
   if (el == 4) return el * bwd_ue_lds_elems<kBwdF32, kBwdF32>();
   return el * bwd_ue_lds_elems<kBwdF64, kBwdF64>();
 }
 
-struct Plan {
-  int dtype = 0, grid = 0;
+struct Pass {
+  int grid = 0;
   size_t lds = 0;
   int* d_start = nullptr;
   BatchTile* d_tiles = nullptr;
+};
+
+struct Plan {
+  int dtype = 0;
+  bool bwd = false;
+  Pass main, gather;  // gather.grid == 0: no histogram adjoint
   void* d_fields = nullptr;
-  size_t field_bytes = 0;
+  void* d_ws = nullptr;             // histogram Jacobians of all fields
+  std::vector<size_t> ws_offset;    // bytes, per field (SIZE_MAX: none)
   std::vector<unsigned char> host_fields;  // last uploaded field table
   hipGraphExec_t exec = nullptr;
   hipGraph_t graph = nullptr;
   ~Plan() {
     if (exec) (void)hipGraphExecDestroy(exec);
     if (graph) (void)hipGraphDestroy(graph);
-    if (d_start) (void)hipFree(d_start);
-    if (d_tiles) (void)hipFree(d_tiles);
+    for (Pass* p : {&main, &gather}) {
+      if (p->d_start) (void)hipFree(p->d_start);
+      if (p->d_tiles) (void)hipFree(p->d_tiles);
+    }
     if (d_fields) (void)hipFree(d_fields);
+    if (d_ws) (void)hipFree(d_ws);
   }
 };
 
@@ -111,62 +155,34 @@ std::mutex g_mu;
 std::map<std::vector<int64_t>, std::unique_ptr<Plan>> g_plans;
 int g_num_cu = 0;
 
-template <typename T>
-hipError_t occupancy(size_t lds, int* blocks) {
-  return hipOccupancyMaxActiveBlocksPerMultiprocessor(blocks, reinterpret_cast<const void*>(k_batched<T>), kNT,
-                                                      lds);
+template <typename T, int PASS>
+hipError_t prepare_kernel(size_t lds, int* per_cu) {
+  const void* k = reinterpret_cast<const void*>(k_batched<T, PASS>);
+  if (lds > 65536) {
+    hipError_t e = hipFuncSetAttribute(k, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+    if (e != hipSuccess) return e;
+  }
+  return hipOccupancyMaxActiveBlocksPerMultiprocessor(per_cu, k, kNT, lds);
 }
 
-template <typename T>
-hipError_t set_lds(size_t lds) {
-  if (lds <= 65536) return hipSuccess;
-  return hipFuncSetAttribute(reinterpret_cast<const void*>(k_batched<T>), hipFuncAttributeMaxDynamicSharedMemorySize,
-                             (int)lds);
+hipError_t prepare(int dtype, int pass, size_t lds, int* per_cu) {
+  if (dtype == CP_F64) {
+    if (pass == PASS_FWD) return prepare_kernel<double, PASS_FWD>(lds, per_cu);
+    if (pass == PASS_BWD) return prepare_kernel<double, PASS_BWD>(lds, per_cu);
+    return prepare_kernel<double, PASS_GATHER>(lds, per_cu);
+  }
+  if (pass == PASS_FWD) return prepare_kernel<float, PASS_FWD>(lds, per_cu);
+  if (pass == PASS_BWD) return prepare_kernel<float, PASS_BWD>(lds, per_cu);
+  return prepare_kernel<float, PASS_GATHER>(lds, per_cu);
 }
 
-cp_status_t build_plan(int n, const Field* fs, bool fwd, bool bwd, Plan& P, const char** why) {
-  const size_t el = fs[0].dtype == CP_F64 ? 8 : 4;
-  P.dtype = fs[0].dtype;
-  std::vector<BatchTile> tiles;
-  std::vector<double> cost;
-  size_t lds = 0;
-  for (int i = 0; i < n; ++i) {
-    const Field& f = fs[i];
-    const bool adj = bwd;  // adjoint tiles also write P when requested
-    int ox, oy;
-    if (adj) {
-      ox = oy = f.model == CP_HISTOGRAM ? kBwdHist : (el == 4 ? kBwdF32 : kBwdF64);
-    } else {
-      ox = kFwdTX;
-      oy = 4;
-    }
-    lds = std::max(lds, tile_lds_bytes(f.model, f.nb, adj, el));
-    const double c = vertex_cost(f.model, f.nb, adj) * ox * oy;
-    for (int ty = 0; ty < f.H; ty += oy)
-      for (int tx = 0; tx < f.W; tx += ox) {
-        tiles.push_back(BatchTile{i, ty, tx, adj ? 1 : 0});
-        cost.push_back(c);
-      }
-  }
-  (void)fwd;
-  if (lds > kMaxLds) {
-    *why = "batched: staged planes exceed the LDS of a workgroup (too many bins for this dtype)";
-    return CP_EUNSUPPORTED;
-  }
-  hipError_t e = el == 4 ? set_lds<float>(lds) : set_lds<double>(lds);
-  if (e != hipSuccess) return CP_EDEVICE;
+// Deal tiles to resident blocks (longest processing time first) and upload.
+cp_status_t build_pass(const std::vector<BatchTile>& tiles, const std::vector<double>& cost, int dtype, int pass,
+                       size_t lds, Pass& P) {
   int per_cu = 0;
-  e = el == 4 ? occupancy<float>(lds, &per_cu) : occupancy<double>(lds, &per_cu);
-  if (e != hipSuccess) return CP_EDEVICE;
-  if (g_num_cu == 0) {
-    int dev = 0;
-    if (hipGetDevice(&dev) != hipSuccess) return CP_EDEVICE;
-    if (hipDeviceGetAttribute(&g_num_cu, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess)
-      return CP_EDEVICE;
-  }
+  if (prepare(dtype, pass, lds, &per_cu) != hipSuccess) return CP_EDEVICE;
   per_cu = std::max(per_cu, 1);
   const int grid = std::max(1, std::min<int>((int)tiles.size(), g_num_cu * per_cu));
-  // longest-processing-time: biggest tiles first, each to the least-loaded block
   std::vector<int> order(tiles.size());
   for (size_t i = 0; i < order.size(); ++i) order[i] = (int)i;
   std::stable_sort(order.begin(), order.end(), [&](int a, int b) { return cost[a] > cost[b]; });
@@ -185,17 +201,14 @@ cp_status_t build_plan(int n, const Field* fs, bool fwd, bool bwd, Plan& P, cons
   flat.reserve(tiles.size());
   for (int b = 0; b < grid; ++b) {
     start[b] = (int)flat.size();
-    // walk a block's tiles in field/row order for locality
-    std::sort(lists[b].begin(), lists[b].end());
+    std::sort(lists[b].begin(), lists[b].end());  // field / row order within a block
     for (int t : lists[b]) flat.push_back(tiles[t]);
   }
   start[grid] = (int)flat.size();
   P.grid = grid;
   P.lds = lds;
-  P.field_bytes = (el == 4 ? sizeof(BatchField<float>) : sizeof(BatchField<double>)) * (size_t)n;
   if (hipMalloc(&P.d_start, sizeof(int) * start.size()) != hipSuccess) return CP_ENOMEM;
   if (hipMalloc(&P.d_tiles, sizeof(BatchTile) * std::max<size_t>(flat.size(), 1)) != hipSuccess) return CP_ENOMEM;
-  if (hipMalloc(&P.d_fields, P.field_bytes) != hipSuccess) return CP_ENOMEM;
   if (hipMemcpy(P.d_start, start.data(), sizeof(int) * start.size(), hipMemcpyHostToDevice) != hipSuccess)
     return CP_EDEVICE;
   if (!flat.empty() &&
@@ -204,10 +217,63 @@ cp_status_t build_plan(int n, const Field* fs, bool fwd, bool bwd, Plan& P, cons
   return CP_OK;
 }
 
+cp_status_t build_plan(int n, const Field* fs, bool bwd, Plan& P, const char** why) {
+  const size_t el = fs[0].dtype == CP_F64 ? 8 : 4;
+  P.dtype = fs[0].dtype;
+  P.bwd = bwd;
+  if (g_num_cu == 0) {
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess) return CP_EDEVICE;
+    if (hipDeviceGetAttribute(&g_num_cu, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess)
+      return CP_EDEVICE;
+  }
+  std::vector<BatchTile> tiles, gtiles;
+  std::vector<double> cost, gcost;
+  size_t lds = 0, ws = 0;
+  P.ws_offset.assign(n, SIZE_MAX);
+  for (int i = 0; i < n; ++i) {
+    const Field& f = fs[i];
+    int ox = kFwdTX, oy = 4;
+    if (bwd && f.model != CP_HISTOGRAM) ox = oy = el == 4 ? kBwdF32 : kBwdF64;
+    lds = std::max(lds, tile_lds_bytes(f.model, f.nb, bwd, el));
+    const double c = vertex_cost(f.model, f.nb, bwd) * ox * oy;
+    for (int ty = 0; ty < f.H; ty += oy)
+      for (int tx = 0; tx < f.W; tx += ox) {
+        tiles.push_back(BatchTile{i, ty, tx, bwd ? KIND_BWD : KIND_FWD});
+        cost.push_back(c);
+      }
+    if (bwd && f.model == CP_HISTOGRAM) {
+      const int64_t plane = (int64_t)f.H * f.W;
+      P.ws_offset[i] = ws;
+      ws += el * (size_t)5 * f.nb * plane;
+      ws = (ws + 255) / 256 * 256;
+      for (int64_t v = 0; v < plane; v += kGatherChunk) {
+        gtiles.push_back(BatchTile{i, (int)v, 0, KIND_GATHER});
+        gcost.push_back(1.0);
+      }
+    }
+  }
+  if (lds > kMaxLds) {
+    *why = "batched: staged planes exceed the LDS of a workgroup (too many bins for this dtype)";
+    return CP_EUNSUPPORTED;
+  }
+  cp_status_t s = build_pass(tiles, cost, P.dtype, bwd ? PASS_BWD : PASS_FWD, lds, P.main);
+  if (s != CP_OK) return s;
+  if (!gtiles.empty()) {
+    s = build_pass(gtiles, gcost, P.dtype, PASS_GATHER, 0, P.gather);
+    if (s != CP_OK) return s;
+    if (hipMalloc(&P.d_ws, ws) != hipSuccess) return CP_ENOMEM;
+  }
+  P.host_fields.clear();
+  const size_t fb = (el == 4 ? sizeof(BatchField<float>) : sizeof(BatchField<double>)) * (size_t)n;
+  if (hipMalloc(&P.d_fields, fb) != hipSuccess) return CP_ENOMEM;
+  return CP_OK;
+}
+
 template <typename T>
-void fill_fields(int n, const Field* fs, const void* const* params, void* const* pmin, void* const* pmax,
-                 const void* const* gmin, const void* const* gmax, void* const* grad, bool fwd, bool bwd,
-                 std::vector<unsigned char>& out) {
+void fill_fields(int n, const Field* fs, const Plan& P, const void* const* params, void* const* pmin,
+                 void* const* pmax, const void* const* gmin, const void* const* gmax, void* const* grad, bool fwd,
+                 bool bwd, std::vector<unsigned char>& out) {
   out.assign(sizeof(BatchField<T>) * (size_t)n, 0);
   BatchField<T>* bf = reinterpret_cast<BatchField<T>*>(out.data());
   for (int i = 0; i < n; ++i) {
@@ -226,17 +292,29 @@ void fill_fields(int n, const Field* fs, const void* const* params, void* const*
     p.ps = f.plane();
     bf[i].p = p;
     bf[i].model = f.model;
+    bf[i].J = P.ws_offset[i] == SIZE_MAX ? nullptr
+                                         : reinterpret_cast<T*>(static_cast<unsigned char*>(P.d_ws) + P.ws_offset[i]);
   }
 }
 
-hipError_t launch(const Plan& P, hipStream_t st) {
-  if (P.dtype == CP_F64)
-    hipLaunchKernelGGL(k_batched<double>, dim3(P.grid), dim3(kNT), P.lds, st,
-                       static_cast<const BatchField<double>*>(P.d_fields), P.d_tiles, P.d_start);
+template <typename T>
+hipError_t launch_typed(const Plan& P, hipStream_t st) {
+  const auto* F = static_cast<const BatchField<T>*>(P.d_fields);
+  if (P.bwd)
+    hipLaunchKernelGGL((k_batched<T, PASS_BWD>), dim3(P.main.grid), dim3(kNT), P.main.lds, st, F, P.main.d_tiles,
+                       P.main.d_start);
   else
-    hipLaunchKernelGGL(k_batched<float>, dim3(P.grid), dim3(kNT), P.lds, st,
-                       static_cast<const BatchField<float>*>(P.d_fields), P.d_tiles, P.d_start);
+    hipLaunchKernelGGL((k_batched<T, PASS_FWD>), dim3(P.main.grid), dim3(kNT), P.main.lds, st, F, P.main.d_tiles,
+                       P.main.d_start);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess || P.gather.grid == 0) return e;
+  hipLaunchKernelGGL((k_batched<T, PASS_GATHER>), dim3(P.gather.grid), dim3(kNT), 0, st, F, P.gather.d_tiles,
+                     P.gather.d_start);
   return hipGetLastError();
+}
+
+hipError_t launch(const Plan& P, hipStream_t st) {
+  return P.dtype == CP_F64 ? launch_typed<double>(P, st) : launch_typed<float>(P, st);
 }
 
 }  // namespace
@@ -248,11 +326,8 @@ cp_status_t batched(int n, const Field* fs, const void* const* params, void* con
   if (flags & CP_BATCH_PER_FIELD) {
     for (int i = 0; i < n; ++i) {
       hipError_t e = hipSuccess;
-      if (fwd && !bwd) e = cf_forward(fs[i], params[i], pmin[i], pmax[i], st);
-      if (bwd) {
-        if (fwd) e = cf_forward(fs[i], params[i], pmin[i], pmax[i], st);
-        if (e == hipSuccess) e = cf_backward(fs[i], params[i], gmin[i], gmax[i], grad[i], st);
-      }
+      if (fwd) e = cf_forward(fs[i], params[i], pmin[i], pmax[i], st);
+      if (bwd && e == hipSuccess) e = cf_backward(fs[i], params[i], gmin[i], gmax[i], grad[i], st);
       if (e != hipSuccess) {
         *why = "batched: per-field launch failed";
         return CP_EDEVICE;
@@ -278,16 +353,16 @@ cp_status_t batched(int n, const Field* fs, const void* const* params, void* con
   auto it = g_plans.find(key);
   if (it == g_plans.end()) {
     auto P = std::make_unique<Plan>();
-    cp_status_t s = build_plan(n, fs, fwd, bwd, *P, why);
+    cp_status_t s = build_plan(n, fs, bwd, *P, why);
     if (s != CP_OK) return s;
     it = g_plans.emplace(key, std::move(P)).first;
   }
   Plan& P = *it->second;
   std::vector<unsigned char> table;
   if (P.dtype == CP_F64)
-    fill_fields<double>(n, fs, params, pmin, pmax, gmin, gmax, grad, fwd, bwd, table);
+    fill_fields<double>(n, fs, P, params, pmin, pmax, gmin, gmax, grad, fwd, bwd, table);
   else
-    fill_fields<float>(n, fs, params, pmin, pmax, gmin, gmax, grad, fwd, bwd, table);
+    fill_fields<float>(n, fs, P, params, pmin, pmax, gmin, gmax, grad, fwd, bwd, table);
   if (table != P.host_fields) {
     // pageable source: the copy is staged before the call returns, so the
     // host vector may be reused at once

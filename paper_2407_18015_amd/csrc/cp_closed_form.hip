@@ -36,12 +36,35 @@ __global__ __launch_bounds__(256) void k_bwd_ue(FieldPtrs<T> f, int tiles_x, int
   tile_bwd_ue<T, MODEL, OX, OY, 256>(f, (t / tiles_x) * OY, (t % tiles_x) * OX, lds, threadIdx.x);
 }
 
-template <typename T, int OX, int OY, int NT>
-__global__ __launch_bounds__(NT) void k_bwd_hist(FieldPtrs<T> f, int tiles_x, int ntiles) {
+// histogram adjoint, pass 1: per-stencil Jacobians into the workspace
+template <typename T, int TY>
+__global__ __launch_bounds__(kFwdTX* TY) void k_hist_sweep(FieldPtrs<T> f, int tiles_x, int ntiles, T* J) {
   extern __shared__ __align__(16) unsigned char smem[];
   T* lds = reinterpret_cast<T*>(smem);
   const int t = xcd_tile(blockIdx.x, ntiles);
-  tile_bwd_hist<T, OX, OY, NT>(f, (t / tiles_x) * OY, (t % tiles_x) * OX, lds, threadIdx.x);
+  tile_hist_sweep<T, TY>(f, (t / tiles_x) * TY, (t % tiles_x) * kFwdTX, lds, threadIdx.x, J);
+}
+
+// histogram adjoint, pass 2: every mass of u gathers its own stencil's entry
+// and the entries of its four neighbours' stencils that refer to u
+template <typename T>
+__global__ __launch_bounds__(256) void k_hist_gather(FieldPtrs<T> f, const T* __restrict__ J) {
+  const int64_t id = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  const int64_t plane = (int64_t)f.H * f.W;
+  if (id >= plane) return;
+  const int y = (int)(id / f.W), x = (int)(id - (int64_t)y * f.W);
+  const int h = f.nb;
+  const int64_t at = (int64_t)y * f.rs + x;
+  f.grad[at] = T(0);
+  f.grad[f.ps + at] = T(0);
+  for (int k = 0; k < h; ++k) {
+    T g = J[(int64_t)(0 * h + k) * plane + id];
+    if (x + 1 < f.W) g += J[(int64_t)(3 * h + k) * plane + id + 1];
+    if (x > 0) g += J[(int64_t)(1 * h + k) * plane + id - 1];
+    if (y > 0) g += J[(int64_t)(4 * h + k) * plane + id - f.W];
+    if (y + 1 < f.H) g += J[(int64_t)(2 * h + k) * plane + id + f.W];
+    f.grad[(int64_t)(2 + k) * f.ps + at] = g;
+  }
 }
 
 // ---------------------------------------------------------------------------
@@ -122,13 +145,22 @@ static hipError_t launch_bwd_ue(const FieldPtrs<T>& p, int model, hipStream_t st
   return hipGetLastError();
 }
 
-template <typename T, int OX, int OY, int NT>
+template <typename T, int TY>
 static hipError_t launch_bwd_hist(const FieldPtrs<T>& p, hipStream_t st) {
-  const int tx = cdiv(p.W, OX), ty = cdiv(p.H, OY), n = tx * ty;
-  const size_t lds = sizeof(T) * hist_bwd_lds_elems<OX, OY>(p.nb);
-  hipError_t e = allow_lds(k_bwd_hist<T, OX, OY, NT>, lds);
+  const int tx = cdiv(p.W, kFwdTX), ty = cdiv(p.H, TY), n = tx * ty;
+  const int64_t plane = (int64_t)p.H * p.W;
+  void* ws = nullptr;
+  hipError_t e = workspace(sizeof(T) * (size_t)5 * p.nb * plane, &ws);
   if (e != hipSuccess) return e;
-  hipLaunchKernelGGL((k_bwd_hist<T, OX, OY, NT>), dim3(n), dim3(NT), lds, st, p, tx, n);
+  T* J = static_cast<T*>(ws);
+  const size_t lds = sizeof(T) * (size_t)hist_planes(p.nb) * (kFwdTX + 2) * (TY + 2);
+  e = allow_lds(k_hist_sweep<T, TY>, lds);
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL((k_hist_sweep<T, TY>), dim3(n), dim3(kFwdTX * TY), lds, st, p, tx, n, J);
+  e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(k_hist_gather<T>, dim3((unsigned)((plane + 255) / 256)), dim3(256), 0, st, p,
+                     static_cast<const T*>(J));
   return hipGetLastError();
 }
 
@@ -144,10 +176,11 @@ static hipError_t bwd_typed(const Field& f, const void* params, const void* gmin
     else
       return launch_bwd_ue<T, 14, 14>(p, f.model, st);
   }
-  // 16x16 stencils (one per thread) when the staged planes fit, else 8x8
-  if (sizeof(T) * hist_bwd_lds_elems<14, 14>(f.nb) <= kMaxLds) return launch_bwd_hist<T, 14, 14, 256>(p, st);
-  if (sizeof(T) * hist_bwd_lds_elems<6, 6>(f.nb) <= kMaxLds) return launch_bwd_hist<T, 6, 6, 64>(p, st);
-  return hipErrorInvalidValue;
+  // sweep tiles as in the forward; the Jacobians go through the workspace
+  const size_t per_row = sizeof(T) * (size_t)hist_planes(f.nb) * (kFwdTX + 2);
+  if (per_row * 6 <= 64 * 1024) return launch_bwd_hist<T, 4>(p, st);
+  if (per_row * 4 <= kMaxLds) return launch_bwd_hist<T, 2>(p, st);
+  return launch_bwd_hist<T, 1>(p, st);
 }
 
 hipError_t cf_backward(const Field& f, const void* params, const void* gmin, const void* gmax, void* grad,

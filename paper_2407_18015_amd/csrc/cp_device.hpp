@@ -31,6 +31,21 @@ CP_HD double cfma<double>(double a, double b, double c) {
   return __builtin_fma(a, b, c);
 }
 
+// Reciprocal: the hardware v_rcp_f32 (1 ulp) in FP32 device code, exact
+// division otherwise.  Parameters are reciprocated once per vertex.
+template <typename T>
+CP_HD T crcp(T x) {
+  return T(1) / x;
+}
+template <>
+CP_HD float crcp<float>(float x) {
+#if defined(__HIP_DEVICE_COMPILE__)
+  return __builtin_amdgcn_rcpf(x);
+#else
+  return 1.0f / x;
+#endif
+}
+
 // ---------------------------------------------------------------------------
 // Gauss-Legendre rules on [-1, 1]; an N-point rule integrates polynomials of
 // degree <= 2N-1 exactly.
@@ -144,7 +159,7 @@ CP_HD void sort4(T (&k)[4], T (&p)[4][P], int (&tag)[4]) {
 // ===========================================================================
 template <typename T>
 struct UniSide {
-  T Lv;
+  T Lv, iLv;
   T c[4];      // sorted clamped start points
   T b[4];      // matching upper ends
   T iL[4];     // matching 1/(b - a)
@@ -154,9 +169,10 @@ struct UniSide {
 };
 
 template <typename T>
-CP_HD void uni_setup(UniSide<T>& s, T Lv, const T (&a)[4], const T (&b)[4],
-                                          const T (&iL)[4], const bool (&pres)[4]) {
+CP_HD void uni_setup(UniSide<T>& s, T Lv, T iLv, const T (&a)[4], const T (&b)[4], const T (&iL)[4],
+                     const bool (&pres)[4]) {
   s.Lv = Lv;
+  s.iLv = iLv;
   T bmin = Lv;
 #pragma unroll
   for (int i = 0; i < 4; ++i)
@@ -171,7 +187,7 @@ CP_HD void uni_setup(UniSide<T>& s, T Lv, const T (&a)[4], const T (&b)[4],
     // active on a non-empty piece); finite stand-ins keep empty pieces finite
     key[i] = pres[i] ? tclamp(a[i], T(0), bmin) : bmin;
     pay[i][0] = pres[i] ? b[i] : T(3) * Lv;
-    pay[i][1] = pres[i] ? iL[i] : T(1) / Lv;
+    pay[i][1] = pres[i] ? iL[i] : iLv;
     s.tag[i] = i;
   }
   sort4<T, 2>(key, pay, s.tag);
@@ -213,7 +229,7 @@ CP_HD T uni_side_value(const UniSide<T>& s) {
   acc += uni_piece<T, 2, 2>(s, s.c[1], s.c[2]);
   acc += uni_piece<T, 3, 2>(s, s.c[2], s.c[3]);
   acc += uni_piece<T, 4, 3>(s, s.c[3], s.bmin);
-  return acc / s.Lv;
+  return acc * s.iLv;
 }
 
 // Local derivatives of one side:  f(Lv, a_i, b_i) = (1/Lv) int_0^{b_min} prod S_i
@@ -280,7 +296,7 @@ CP_HD void uni_side_grad(const UniSide<T>& s, UniGrad<T>& g) {
   act[2] = act[3] + I[3];
   act[1] = act[2] + I[2];
   act[0] = act[1] + I[1];
-  const T iLv = T(1) / s.Lv;
+  const T iLv = s.iLv;
   const T f = (act[0] + I[0]) * iLv;
   g.f = f;
   // product of the survival factors at x = Lv (zero unless b_min = Lv)
@@ -327,10 +343,10 @@ struct EpaSide {
 };
 
 template <typename T>
-CP_HD void epa_setup(EpaSide<T>& s, T wv, const T (&d)[4], const T (&w)[4],
-                                          const bool (&pres)[4]) {
+CP_HD void epa_setup(EpaSide<T>& s, T wv, T iwv, const T (&d)[4], const T (&w)[4], const T (&iw)[4],
+                     const bool (&pres)[4]) {
   s.wv = wv;
-  s.iwv = T(1) / wv;
+  s.iwv = iwv;
   T bmin = wv;
 #pragma unroll
   for (int i = 0; i < 4; ++i)
@@ -343,7 +359,7 @@ CP_HD void epa_setup(EpaSide<T>& s, T wv, const T (&d)[4], const T (&w)[4],
   for (int i = 0; i < 4; ++i) {
     key[i] = pres[i] ? tclamp(d[i] - w[i], -wv, bmin) : bmin;
     pay[i][0] = pres[i] ? d[i] : T(3) * wv;
-    pay[i][1] = pres[i] ? T(1) / w[i] : s.iwv;
+    pay[i][1] = pres[i] ? iw[i] : s.iwv;
     s.tag[i] = i;
   }
   sort4<T, 2>(key, pay, s.tag);
@@ -363,16 +379,24 @@ CP_HD T epa_cdf4(const EpaSide<T>& s, T x) {
   return o * o * (T(2) - t);
 }
 
+// 4 S(u) = u^3 - 3u + 2 in Horner form: three fused multiply-adds.  On a
+// piece where the factor has started, u is in [-1, 1] and the rounding error
+// is at most a few ulp of 3 in absolute terms.
+template <typename T>
+CP_HD T epa_s4(T u) {
+  return cfma(cfma(u, u, T(-3)), u, T(2));
+}
+
 // integral over [l, r] of (1 - t^2) prod_{i<K} 4 S_i   (unscaled)
 template <typename T, int K, int N>
 CP_HD T epa_piece(const EpaSide<T>& s, T l, T r) {
   const T mid = (l + r) * T(0.5), hl = (r - l) * T(0.5);
   const T av = mid * s.iwv, bv = hl * s.iwv;
-  T aq[K], bq[K];
+  T au[K], bu[K];
 #pragma unroll
   for (int i = 0; i < K; ++i) {
-    aq[i] = T(1) - (mid - s.d[i]) * s.iw[i];  // q = 1 - u = aq - bq x
-    bq[i] = hl * s.iw[i];
+    au[i] = (mid - s.d[i]) * s.iw[i];  // u = au + bu x
+    bu[i] = hl * s.iw[i];
   }
   T sum = T(0);
 #pragma unroll
@@ -381,10 +405,7 @@ CP_HD T epa_piece(const EpaSide<T>& s, T l, T r) {
     const T t = cfma(bv, x, av);
     T prod = cfma(-t, t, T(1));
 #pragma unroll
-    for (int i = 0; i < K; ++i) {
-      const T q = cfma(-bq[i], x, aq[i]);
-      prod *= q * q * (T(3) - q);
-    }
+    for (int i = 0; i < K; ++i) prod *= epa_s4(cfma(bu[i], x, au[i]));
     sum = cfma(T(GL<N>::w[j]), prod, sum);
   }
   return sum * hl;
@@ -419,11 +440,11 @@ template <typename T, int K, int N>
 CP_HD void epa_piece_grad(const EpaSide<T>& s, T l, T r, T& full, T (&gd)[4], T (&gw)[4], T (&gx)[4]) {
   const T mid = (l + r) * T(0.5), hl = (r - l) * T(0.5);
   const T av = mid * s.iwv, bv = hl * s.iwv;
-  T aq[K], bq[K];
+  T au[K], bu[K];
 #pragma unroll
   for (int i = 0; i < K; ++i) {
-    aq[i] = T(1) - (mid - s.d[i]) * s.iw[i];
-    bq[i] = hl * s.iw[i];
+    au[i] = (mid - s.d[i]) * s.iw[i];  // u = au + bu x
+    bu[i] = hl * s.iw[i];
   }
   T sf = T(0), sd[K], sww[K], sxx[K];
 #pragma unroll
@@ -433,13 +454,13 @@ CP_HD void epa_piece_grad(const EpaSide<T>& s, T l, T r, T& full, T (&gd)[4], T 
     const T x = T(GL<N>::x[j]);
     const T wj = T(GL<N>::w[j]);
     const T t = cfma(bv, x, av);
-    const T pv = cfma(-t, t, T(1));  // 4 wv/3 * pdf_v
-    const T xl = cfma(hl, x, mid);   // node in the vertex frame
-    T q[K], S[K], pre[K + 1], suf[K + 1];
+    const T wpv = wj * cfma(-t, t, T(1));  // weight * 4 wv/3 * pdf_v
+    const T xl = cfma(hl, x, mid);         // node in the vertex frame
+    T u[K], S[K], pre[K + 1], suf[K + 1];
 #pragma unroll
     for (int i = 0; i < K; ++i) {
-      q[i] = cfma(-bq[i], x, aq[i]);
-      S[i] = q[i] * q[i] * (T(3) - q[i]);  // 4 S_i
+      u[i] = cfma(bu[i], x, au[i]);
+      S[i] = epa_s4(u[i]);  // 4 S_i
     }
     pre[0] = T(1);
 #pragma unroll
@@ -447,14 +468,13 @@ CP_HD void epa_piece_grad(const EpaSide<T>& s, T l, T r, T& full, T (&gd)[4], T 
     suf[K] = T(1);
 #pragma unroll
     for (int i = K - 1; i >= 0; --i) suf[i] = suf[i + 1] * S[i];
-    sf = cfma(wj * pv, pre[K], sf);
+    sf = cfma(wpv, pre[K], sf);
 #pragma unroll
     for (int i = 0; i < K; ++i) {
-      // (4 w_i / 3) p_i = 1 - u^2 = q (2 - q); u = 1 - q
-      const T pi = q[i] * (T(2) - q[i]);
-      const T lw = wj * pv * pi * pre[i] * suf[i + 1];
+      // (4 w_i / 3) p_i = 1 - u^2
+      const T lw = wpv * (cfma(-u[i], u[i], T(1)) * (pre[i] * suf[i + 1]));
       sd[i] += lw;
-      sww[i] = cfma(lw, T(1) - q[i], sww[i]);
+      sww[i] = cfma(lw, u[i], sww[i]);
       sxx[i] = cfma(lw, xl, sxx[i]);
     }
   }

@@ -17,6 +17,8 @@
 // registers), statistics are accumulated in FP64.
 #include <hip/hip_runtime.h>
 
+#include <cmath>
+
 #include "cp_internal.hpp"
 
 namespace cp {
@@ -78,7 +80,8 @@ struct FitArgs {
   void* params;
   int M, H, W, nb, ddof;
   int64_t rs, ps;
-  double bw, eps;
+  double wscale;  // bw * M^(-1/5) / sqrt(M - ddof): Epanechnikov w = wscale * sqrt(sum of squares)
+  double eps;
 };
 
 // Uniform / Epanechnikov / histogram.  MM: members held in registers
@@ -97,7 +100,22 @@ __global__ __launch_bounds__(kFitTX* kFitTY) void k_fit(FitArgs a) {
   T v[MM > 0 ? MM : 1];
   T mn, mx;
   double s1 = 0.0, s2 = 0.0, shift;
-  if (MM > 0) {
+  if (MODEL != CP_HISTOGRAM) {
+    // one streaming pass: min, max and shifted sums
+    mn = mx = mem[at];
+    shift = (double)mn;
+#pragma unroll 4
+    for (int k = 0; k < M; ++k) {
+      const T xk = mem[(int64_t)k * a.ps + at];
+      mn = xk < mn ? xk : mn;
+      mx = xk > mx ? xk : mx;
+      if (MODEL == CP_EPANECHNIKOV) {
+        const double d = (double)xk - shift;
+        s1 += d;
+        s2 = fma(d, d, s2);
+      }
+    }
+  } else if (MM > 0) {
 #pragma unroll
     for (int k = 0; k < (MM > 0 ? MM : 1); ++k)
       if (k < M) v[k] = mem[(int64_t)k * a.ps + at];
@@ -109,15 +127,6 @@ __global__ __launch_bounds__(kFitTX* kFitTY) void k_fit(FitArgs a) {
         mn = v[k] < mn ? v[k] : mn;
         mx = v[k] > mx ? v[k] : mx;
       }
-    if (MODEL == CP_EPANECHNIKOV) {
-#pragma unroll
-      for (int k = 0; k < (MM > 0 ? MM : 1); ++k)
-        if (k < M) {
-          const double d = (double)v[k] - shift;
-          s1 += d;
-          s2 = fma(d, d, s2);
-        }
-    }
   } else {
     mn = mx = mem[at];
     shift = (double)mn;
@@ -149,7 +158,7 @@ __global__ __launch_bounds__(kFitTX* kFitTY) void k_fit(FitArgs a) {
       w = a.eps * fmax(1.0, fabs(mean));
     } else {
       const double ss = fmax(s2 - s1 * s1 / (double)M, 0.0);
-      w = a.bw * sqrt(ss / (double)(M - a.ddof)) * pow((double)M, -0.2);
+      w = a.wscale * sqrt(ss);
     }
     par[at] = (T)mean;
     par[a.ps + at] = (T)w;
@@ -267,7 +276,9 @@ __global__ __launch_bounds__(256) void k_fit_mvg(FitArgs a, double jitter) {
 template <typename T, int MODEL>
 hipError_t launch_fit(const FitArgs& a, hipStream_t st) {
   dim3 grid((a.W + kFitTX - 1) / kFitTX, (a.H + kFitTY - 1) / kFitTY);
-  if (a.M <= 8)
+  if (MODEL != CP_HISTOGRAM)
+    hipLaunchKernelGGL((k_fit<T, MODEL, 0>), grid, dim3(kFitTX * kFitTY), 0, st, a);
+  else if (a.M <= 8)
     hipLaunchKernelGGL((k_fit<T, MODEL, 8>), grid, dim3(kFitTX * kFitTY), 0, st, a);
   else if (a.M <= kMaxRegMembers)
     hipLaunchKernelGGL((k_fit<T, MODEL, kMaxRegMembers>), grid, dim3(kFitTX * kFitTY), 0, st, a);
@@ -297,7 +308,7 @@ hipError_t fit_params(const Field& f, const void* members, int M, int ddof, doub
   a.ddof = ddof;
   a.rs = f.rs;
   a.ps = f.plane();
-  a.bw = bw;
+  a.wscale = M - ddof > 0 ? bw * std::pow((double)M, -0.2) / std::sqrt((double)(M - ddof)) : 0.0;
   a.eps = eps;
   if (f.model == CP_MVGAUSS) {
     dim3 grid((a.W + kFitTX - 1) / kFitTX, (a.H + kFitTY - 1) / kFitTY);

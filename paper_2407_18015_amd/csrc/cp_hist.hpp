@@ -13,54 +13,67 @@
 // cancellation occurs.
 //
 // Staged per vertex in LDS (planes of the extended tile, E vertices each):
-//   0 lo, 1 hi, 2..h+1 masses, h+2..2h+2 suffix sums T_j = sum_{i>=j} m_i,
-//   2h+3..3h+3 prefix sums P_j = sum_{i<j} m_i, 3h+4 validity (1 or 0).
-// Suffix and prefix sums are formed in FP64 and rounded once.
+//   0 lo, 1 hi, 2..h+1 masses.  An invalid histogram (lo >= hi, non-finite,
+// negative mass) is marked by lo = NaN while staging.  Each cursor carries
+// the survival value at its next edge as a running FP64 sum of masses, which
+// is exact for FP32 masses.
 #pragma once
 
 #include "cp_device.hpp"
 
 namespace cp {
 
-__host__ __device__ constexpr int hist_planes(int h) { return 3 * h + 5; }
+__host__ __device__ constexpr int hist_planes(int h) { return h + 2; }
 
 template <typename T>
 struct HistLds {
   const T* base;
   int E;  // vertices per plane (extended tile)
   int h;
+  T ih;   // 1 / h
   // mass j of vertex e; `rev` reads the histogram of -X (bins reversed)
   CP_HD T mass(int e, int j, bool rev) const {
     const int p = rev ? (1 + h - j) : (2 + j);
     return base[p * E + e];
   }
-  // survival at edge j: sum of masses of bins >= j (of X or of -X)
-  CP_HD T tail(int e, int j, bool rev) const {
-    const int p = rev ? (3 + 3 * h - j) : (2 + h + j);
-    return base[p * E + e];
-  }
-  CP_HD bool valid(int e) const { return base[(4 + 3 * h) * E + e] != T(0); }
+  CP_HD bool valid(int e) const { return base[e] == base[e]; }
 };
+
+// Validity marking of every staged histogram (lo := NaN when invalid).
+template <typename T, int NT>
+CP_HD void hist_stage_validity(T* lds, int E, int h, int tid) {
+  for (int e = tid; e < E; e += NT) {
+    const T lo = lds[e], hi = lds[E + e];
+    const T d = hi - lo;
+    bool ok = d > T(0) && d < T(3.0e38) && (lo - lo) == T(0);
+    for (int j = 0; j < h; ++j) {
+      const T m = lds[(2 + j) * E + e];
+      ok = ok && m >= T(0) && m < T(3.0e38);
+    }
+    if (!ok) lds[e] = __builtin_nan("");
+  }
+}
 
 // Integral over [0,1] of prod_{i<4} (f0_i (1-t) + f1_i t)
 template <typename T>
 CP_HD T bern4(const T (&f0)[4], const T (&f1)[4]) {
   T b0 = f0[0], b1 = f1[0];
   T c0 = b0 * f0[1], c1 = cfma(b0, f1[1], b1 * f0[1]), c2 = b1 * f1[1];
-  T d0 = c0 * f0[2], d1 = cfma(c0, f1[2], c1 * f0[2]), d2 = cfma(c1, f1[2], c2 * f0[2]),
-    d3 = c2 * f1[2];
+  T d0 = c0 * f0[2], d1 = cfma(c0, f1[2], c1 * f0[2]), d2 = cfma(c1, f1[2], c2 * f0[2]), d3 = c2 * f1[2];
   T e0 = d0 * f0[3], e1 = cfma(d0, f1[3], d1 * f0[3]), e2 = cfma(d1, f1[3], d2 * f0[3]),
     e3 = cfma(d2, f1[3], d3 * f0[3]), e4 = d3 * f1[3];
   return (e0 + e4) * T(0.2) + (e1 + e3) * T(0.05) + e2 * T(1.0 / 30.0);
 }
 
 // State of one neighbour histogram during the sweep: on the current bin,
-// S(x) = snx + slope * (nxt - x); nxt is the next edge to cross.
+// S(x) = snx + slope * (nxt - x); nxt is the next edge to cross and snx the
+// survival there (sum of the masses above it).
 template <typename T>
 struct HistCursor {
-  int j;  // current bin (-1 below the range)
+  int j;  // current bin (-1 below the range, h after the range / absent)
   T lo, hi, d, id;
   T nxt, snx, slope;
+  double snxd;
 };
 
 template <typename T>
@@ -70,52 +83,61 @@ CP_HD T hist_edge(const HistCursor<T>& c, int j, int h) {
 
 // Position the cursor of neighbour e (local range [lo, hi]) at x = 0.
 template <typename T>
-CP_HD void hist_cursor_init(HistCursor<T>& c, const HistLds<T>& L, int e, bool rev,
-                                                 T lo, T hi, bool present, T big) {
+CP_HD void hist_cursor_init(HistCursor<T>& c, const HistLds<T>& L, int e, bool rev, T lo, T hi, bool present,
+                            T big) {
   const int h = L.h;
   c.lo = lo;
   c.hi = hi;
-  c.d = (hi - lo) / T(h);
-  c.id = T(h) / (hi - lo);
+  c.d = (hi - lo) * L.ih;
+  c.id = T(h) * crcp(hi - lo);
+  c.slope = T(0);
   if (!present) {
     c.j = h;
     c.nxt = big;
     c.snx = T(1);
-    c.slope = T(0);
+    c.snxd = 1.0;
     return;
   }
-  if (!(lo < T(0))) {
-    c.j = -1;
-    c.nxt = lo;
-    c.snx = L.tail(e, 0, rev);
-    c.slope = T(0);
-    return;
+  int j = -1;
+  if (lo < T(0)) {
+    j = (int)(-lo * c.id);
+    j = j < 0 ? 0 : (j > h - 1 ? h - 1 : j);
+    if (j + 1 < h && !(hist_edge(c, j + 1, h) > T(0))) ++j;
+    if (j > 0 && hist_edge(c, j, h) > T(0)) --j;
   }
-  int j = (int)(-lo * c.id);
-  j = j < 0 ? 0 : (j > h - 1 ? h - 1 : j);
-  if (j + 1 < h && !(hist_edge(c, j + 1, h) > T(0))) ++j;
-  if (j > 0 && hist_edge(c, j, h) > T(0)) --j;
+  // survival at the next edge: sum of the masses above bin j (all of them
+  // below the range), and the slope of the current bin
+  double tail = 0.0;
+  T mj = T(0);
+  for (int i = 0; i < h; ++i) {
+    const T m = L.mass(e, i, rev);
+    tail += i > j ? (double)m : 0.0;
+    mj = i == j ? m : mj;
+  }
   c.j = j;
-  c.nxt = hist_edge(c, j + 1, h);
-  c.snx = L.tail(e, j + 1, rev);
-  c.slope = L.mass(e, j, rev) * c.id;
+  c.nxt = j < 0 ? lo : hist_edge(c, j + 1, h);
+  c.snxd = tail;
+  c.snx = (T)tail;
+  c.slope = mj * c.id;
 }
 
 // Cross the edge at x1 if it is this cursor's next edge.
 template <typename T>
-CP_HD bool hist_cursor_step(HistCursor<T>& c, const HistLds<T>& L, int e, bool rev,
-                                                 T x1, T big) {
+CP_HD bool hist_cursor_step(HistCursor<T>& c, const HistLds<T>& L, int e, bool rev, T x1, T big) {
   const int h = L.h;
   if (!(c.nxt == x1)) return false;
   if (c.j < h - 1) {
     c.j += 1;
     c.nxt = hist_edge(c, c.j + 1, h);
-    c.snx = L.tail(e, c.j + 1, rev);
-    c.slope = L.mass(e, c.j, rev) * c.id;
+    const T m = L.mass(e, c.j, rev);
+    c.snxd -= (double)m;
+    c.snx = (T)c.snxd;
+    c.slope = m * c.id;
   } else {  // passed the upper end: S = 0 from here on
     c.j = h;
     c.nxt = big;
     c.snx = T(0);
+    c.snxd = 0.0;
     c.slope = T(0);
   }
   return true;
@@ -125,8 +147,8 @@ CP_HD bool hist_cursor_step(HistCursor<T>& c, const HistLds<T>& L, int e, bool r
 // pdf_v prod S_n.  Vertex local range [0, hv]; neighbour local ranges
 // [lo_i, hi_i] (already reflected for the max side).
 template <typename T>
-__host__ __device__ T hist_side_value(const HistLds<T>& L, int ev, const int (&en)[4], const bool (&pres)[4], bool rev,
-                             T hv, const T (&lo)[4], const T (&hi)[4]) {
+__host__ __device__ T hist_side_value(const HistLds<T>& L, int ev, const int (&en)[4], const bool (&pres)[4],
+                                      bool rev, T hv, const T (&lo)[4], const T (&hi)[4]) {
   const int h = L.h;
   T bmin = hv;
 #pragma unroll
@@ -134,7 +156,7 @@ __host__ __device__ T hist_side_value(const HistLds<T>& L, int ev, const int (&e
     if (pres[i]) bmin = tmin(bmin, hi[i]);
   if (!(bmin > T(0))) return T(0);
   const T big = hv + hv + T(1);  // beyond every edge the sweep can reach
-  const T dv = hv / T(h), idv = T(h) / hv;
+  const T dv = hv * L.ih, idv = T(h) * crcp(hv);
   int jv = 0;
   T nv = h > 1 ? dv : hv;
   T pv = L.mass(ev, 0, rev) * idv;

@@ -37,7 +37,11 @@ hipError_t mvg_forward(const Field& f, const double* params, float* pmin, float*
 hipError_t mvg_backward(const Field& f, const double* params, const float* gmin, const float* gmax,
                         double* grad, hipStream_t st);
 hipError_t philox_raw(int64_t n, const uint32_t* ctr, uint64_t seed, uint32_t* out, hipStream_t st);
-void mvg_release();
+
+// Library-owned device workspace (per-stencil adjoint partials), grown on
+// demand, shared by the adjoints that gather through memory.
+hipError_t workspace(size_t bytes, void** out);
+void workspace_release();
 
 // batched persistent launch
 cp_status_t batched(int n, const Field* fields, const void* const* params, void* const* pmin,

@@ -19,8 +19,6 @@
 // its pathwise derivative.  Maxima use Phi((c - max_n x_n) / L44).
 #include <hip/hip_runtime.h>
 
-#include <mutex>
-
 #include "cp_internal.hpp"
 
 namespace cp {
@@ -276,36 +274,7 @@ MvgArgs make_args(const Field& f, const double* params) {
   return a;
 }
 
-// Library-owned workspace for the mean-plane partials (grown on demand).
-std::mutex g_ws_mu;
-void* g_ws = nullptr;
-size_t g_ws_bytes = 0;
-
-hipError_t workspace(size_t bytes, void** out) {
-  std::lock_guard<std::mutex> lk(g_ws_mu);
-  if (bytes > g_ws_bytes) {
-    if (g_ws) {
-      hipError_t e = hipFree(g_ws);
-      if (e != hipSuccess) return e;
-      g_ws = nullptr;
-      g_ws_bytes = 0;
-    }
-    hipError_t e = hipMalloc(&g_ws, bytes);
-    if (e != hipSuccess) return e;
-    g_ws_bytes = bytes;
-  }
-  *out = g_ws;
-  return hipSuccess;
-}
-
 }  // namespace
-
-void mvg_release() {
-  std::lock_guard<std::mutex> lk(g_ws_mu);
-  if (g_ws) (void)hipFree(g_ws);
-  g_ws = nullptr;
-  g_ws_bytes = 0;
-}
 
 hipError_t mvg_forward(const Field& f, const double* params, float* pmin, float* pmax, hipStream_t st) {
   MvgArgs a = make_args(f, params);

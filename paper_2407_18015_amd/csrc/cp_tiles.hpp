@@ -71,34 +71,38 @@ CP_HD void vertex_fwd_ue(const T* L, int E, int e, const int (&en)[4], const boo
     return;
   }
   if (MODEL == CP_UNIFORM) {
-    const T Lv = p1 - p0;
+    const T Lv = p1 - p0, iLv = crcp(Lv);
     T a[4], b[4], iL[4];
     UniSide<T> s;
 #pragma unroll
     for (int i = 0; i < 4; ++i) {
       a[i] = q0[i] - p0;
       b[i] = q1[i] - p0;
-      iL[i] = T(1) / (q1[i] - q0[i]);
+      iL[i] = crcp(q1[i] - q0[i]);
     }
-    uni_setup(s, Lv, a, b, iL, pres);
+    uni_setup(s, Lv, iLv, a, b, iL, pres);
     pmin = uni_side_value(s);
 #pragma unroll
     for (int i = 0; i < 4; ++i) {
       a[i] = p1 - q1[i];
       b[i] = p1 - q0[i];
     }
-    uni_setup(s, Lv, a, b, iL, pres);
+    uni_setup(s, Lv, iLv, a, b, iL, pres);
     pmax = uni_side_value(s);
   } else {
-    T d[4];
+    T d[4], iw[4];
+    const T iwv = crcp(p1);
     EpaSide<T> s;
 #pragma unroll
-    for (int i = 0; i < 4; ++i) d[i] = q0[i] - p0;
-    epa_setup(s, p1, d, q1, pres);
+    for (int i = 0; i < 4; ++i) {
+      d[i] = q0[i] - p0;
+      iw[i] = crcp(q1[i]);
+    }
+    epa_setup(s, p1, iwv, d, q1, iw, pres);
     pmin = epa_side_value(s);
 #pragma unroll
     for (int i = 0; i < 4; ++i) d[i] = p0 - q0[i];
-    epa_setup(s, p1, d, q1, pres);
+    epa_setup(s, p1, iwv, d, q1, iw, pres);
     pmax = epa_side_value(s);
   }
 }
@@ -124,7 +128,7 @@ CP_HD void vertex_jac_ue(const T* L, int E, int e, const int (&en)[4], const boo
     return;
   }
   if (MODEL == CP_UNIFORM) {
-    const T Lv = p1 - p0;
+    const T Lv = p1 - p0, iLv = crcp(Lv);
     T a[4], b[4], iL[4];
     UniSide<T> s;
     UniGrad<T> g, r;
@@ -132,16 +136,16 @@ CP_HD void vertex_jac_ue(const T* L, int E, int e, const int (&en)[4], const boo
     for (int i = 0; i < 4; ++i) {
       a[i] = q0[i] - p0;
       b[i] = q1[i] - p0;
-      iL[i] = T(1) / (q1[i] - q0[i]);
+      iL[i] = crcp(q1[i] - q0[i]);
     }
-    uni_setup(s, Lv, a, b, iL, pres);
+    uni_setup(s, Lv, iLv, a, b, iL, pres);
     uni_side_grad(s, g);
 #pragma unroll
     for (int i = 0; i < 4; ++i) {
       a[i] = p1 - q1[i];
       b[i] = p1 - q0[i];
     }
-    uni_setup(s, Lv, a, b, iL, pres);
+    uni_setup(s, Lv, iLv, a, b, iL, pres);
     uni_side_grad(s, r);
     T sg = T(0), sr = T(0);
 #pragma unroll
@@ -161,16 +165,20 @@ CP_HD void vertex_jac_ue(const T* L, int E, int e, const int (&en)[4], const boo
       jac[3 + 2 * i] = gmin * g.db[i] - gmax * r.da[i];
     }
   } else {
-    T d[4];
+    T d[4], iw[4];
+    const T iwv = crcp(p1);
     EpaSide<T> s;
     EpaGrad<T> g, r;
 #pragma unroll
-    for (int i = 0; i < 4; ++i) d[i] = q0[i] - p0;
-    epa_setup(s, p1, d, q1, pres);
+    for (int i = 0; i < 4; ++i) {
+      d[i] = q0[i] - p0;
+      iw[i] = crcp(q1[i]);
+    }
+    epa_setup(s, p1, iwv, d, q1, iw, pres);
     epa_side_grad(s, g);
 #pragma unroll
     for (int i = 0; i < 4; ++i) d[i] = p0 - q0[i];
-    epa_setup(s, p1, d, q1, pres);
+    epa_setup(s, p1, iwv, d, q1, iw, pres);
     epa_side_grad(s, r);
     T sg = T(0), sr = T(0);
 #pragma unroll
@@ -215,42 +223,18 @@ __device__ __forceinline__ void tile_fwd_ue(const FieldPtrs<T>& f, int ty0, int 
   __syncthreads();
 }
 
-// FP64 suffix / prefix sums and validity of every staged histogram.
-template <typename T, int NT>
-CP_HD void hist_stage_sums(T* lds, int E, int h, int tid) {
-  for (int e = tid; e < E; e += NT) {
-    const T lo = lds[e], hi = lds[E + e];
-    bool ok = valid_range(lo, hi);
-    double run = 0.0;
-    lds[(3 + 2 * h) * E + e] = T(0);  // P_0
-    for (int j = 0; j < h; ++j) {
-      const T m = lds[(2 + j) * E + e];
-      ok = ok && (m >= T(0)) && (m < T(3.0e38));
-      run += (double)m;
-      lds[(4 + 2 * h + j) * E + e] = T(run);  // P_{j+1}
-    }
-    double suf = 0.0;
-    lds[(2 + 2 * h) * E + e] = T(0);  // T_h
-    for (int j = h - 1; j >= 0; --j) {
-      suf += (double)lds[(2 + j) * E + e];
-      lds[(2 + h + j) * E + e] = T(suf);  // T_j
-    }
-    lds[(4 + 3 * h) * E + e] = ok ? T(1) : T(0);
-  }
-}
-
 template <typename T, int TY>
 __device__ __forceinline__ void tile_fwd_hist(const FieldPtrs<T>& f, int ty0, int tx0, T* lds, int tid) {
   constexpr int TX = kFwdTX, EX = TX + 2, EY = TY + 2, E = EX * EY, NT = TX * TY;
   const int h = f.nb;
   stage<T, EY, EX, NT>(lds, f.params, 2 + h, f.ps, f.rs, f.H, f.W, ty0 - 1, tx0 - 1, tid);
   __syncthreads();
-  hist_stage_sums<T, NT>(lds, E, h, tid);
+  hist_stage_validity<T, NT>(lds, E, h, tid);
   __syncthreads();
   const int lx = tid % TX, ly = tid / TX;
   const int x = tx0 + lx, y = ty0 + ly;
   if (x < f.W && y < f.H) {
-    const HistLds<T> L{lds, E, h};
+    const HistLds<T> L{lds, E, h, T(1) / T(h)};
     const int e = (ly + 1) * EX + lx + 1;
     const int en[4] = {e + 1, e - EX, e - 1, e + EX};
     const bool pres[4] = {x + 1 < f.W, y > 0, x > 0, y + 1 < f.H};
