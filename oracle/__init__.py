@@ -55,6 +55,7 @@ def _load():
         "or_forward": (i32, [i32, i32, i32, i32, P, P, P]),
         "or_forward_at": (i32, [i32, i32, i32, i32, P, i64, P, P, P]),
         "or_jacobian_at": (i32, [i32, i32, i32, i32, P, i64, P, P, P]),
+        "or_saddle_at": (i32, [i32, i32, i32, i32, P, i64, P, P, P]),
         "or_grad_at": (i32, [i32, i32, i32, i32, P, P, P, i64, P, P, i32]),
         "or_grad": (i32, [i32, i32, i32, i32, P, P, P, P, i32]),
         "or_fit": (i32, [i32, i32, P, i32, i32, i32, i32, i32, f64, f64, P]),
@@ -113,6 +114,25 @@ def forward_at(model: int, params, idx) -> tuple[np.ndarray, np.ndarray]:
     _check(_load().or_forward_at(model, H, W, nb, _ptr(params), idx.size, _ptr(idx), _ptr(pmin),
                                  _ptr(pmax)), "forward_at")
     return pmin, pmax
+
+
+def saddle_at(model: int, params, idx) -> tuple[np.ndarray, np.ndarray]:
+    """Saddle terms (t1, t2) at flat vertex indices; P_saddle = t1 + t2
+    (interior vertices; boundary vertices give 0)."""
+    params, H, W, nb = _grid(params, model)
+    idx = np.ascontiguousarray(idx, dtype=np.int64)
+    t1 = np.empty(idx.size); t2 = np.empty(idx.size)
+    _check(_load().or_saddle_at(model, H, W, nb, _ptr(params), idx.size, _ptr(idx), _ptr(t1), _ptr(t2)),
+           "saddle_at")
+    return t1, t2
+
+
+def saddle(model: int, params) -> np.ndarray:
+    """P_saddle = t1 + t2 for every vertex: [H][W]."""
+    params = _f64(params)
+    _, H, W = params.shape
+    t1, t2 = saddle_at(model, params, np.arange(H * W))
+    return (t1 + t2).reshape(H, W)
 
 
 def jacobian_at(model: int, params, idx) -> tuple[np.ndarray, np.ndarray]:

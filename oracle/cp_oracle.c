@@ -441,6 +441,54 @@ static void cf_vertex(const grid_t* g, int y, int x, double* pmin, double* pmax,
   *pmax = smax;
 }
 
+/*
+ * Saddle probability (Eq. 2 in 1-D, Eq. 4 on the 4-neighbour stencil):
+ *   t1 = Pr[X_v < X_e, X_v > X_n, X_v < X_w, X_v > X_s]
+ *      = integral pdf_v S_e F_n S_w F_s dx      (independence, Sec. 3)
+ *   t2 = the same with every inequality reversed
+ *      = integral pdf_v F_e S_n F_w S_s dx
+ * Defined on interior vertices only: the alternating pattern needs the full
+ * ring of four neighbours; a boundary vertex gets 0.
+ */
+static void cf_saddle_vertex(const grid_t* g, int y, int x, double* t1, double* t2) {
+  *t1 = *t2 = 0.0;
+  if (y < 1 || y > g->H - 2 || x < 1 || x > g->W - 2) return;
+  dist_t ds[NSLOT];
+  for (int s = 0; s < NSLOT; ++s) grid_dist(g, y + SLOT_DY[s], x + SLOT_DX[s], &ds[s]);
+  const dist_t* v = &ds[0];
+  double bp[MAXBREAK];
+  int nbp = breakpoints(ds, NSLOT, v->lo, v->hi, bp);
+  /* slot 1 = e, 2 = n, 3 = w, 4 = s */
+  const int kind1[NSLOT] = {0, K_SURV, K_CDF, K_SURV, K_CDF};
+  const int kind2[NSLOT] = {0, K_CDF, K_SURV, K_CDF, K_SURV};
+  for (int i = 0; i + 1 < nbp; ++i) {
+    double c = 0.5 * (bp[i] + bp[i + 1]), h = 0.5 * (bp[i + 1] - bp[i]);
+    if (!(h > 0.0)) continue;
+    poly_t pdf, a, b, f;
+    d_poly(v, K_PDF, -1, c, h, &pdf);
+    a = pdf;
+    b = pdf;
+    for (int k = 1; k < NSLOT; ++k) {
+      d_poly(&ds[k], kind1[k], -1, c, h, &f);
+      p_mul(&a, &a, &f);
+      d_poly(&ds[k], kind2[k], -1, c, h, &f);
+      p_mul(&b, &b, &f);
+    }
+    *t1 += p_integrate(&a, h);
+    *t2 += p_integrate(&b, h);
+  }
+}
+
+int or_saddle_at(int model, int H, int W, int nb, const double* params, int64_t nidx, const int64_t* idx,
+                 double* t1, double* t2) {
+  if (H < 1 || W < 1 || model < OR_UNIFORM || model > OR_HISTOGRAM) return 1;
+  if (model == OR_HISTOGRAM && (nb < 1 || nb > MAXNB)) return 1;
+  grid_t g = {model, H, W, nb, params};
+#pragma omp parallel for schedule(dynamic, 16)
+  for (int64_t i = 0; i < nidx; ++i) cf_saddle_vertex(&g, (int)(idx[i] / W), (int)(idx[i] % W), &t1[i], &t2[i]);
+  return 0;
+}
+
 /* ------------------------------------------------------------------------ */
 /* public closed-form entry points                                            */
 /* ------------------------------------------------------------------------ */

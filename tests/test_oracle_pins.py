@@ -669,3 +669,91 @@ def test_mvg_fit_against_numpy():
             for c in range(r + 1):
                 assert par[1 + k, y, x] == pytest.approx(L[r, c], abs=1e-12)
                 k += 1
+
+
+# ----------------------------------------------------------------------------
+# saddle probability (Eq. 2, Eq. 4)
+# ----------------------------------------------------------------------------
+def saddle_centre(model, grid):
+    t1, t2 = oracle.saddle_at(model, grid, [4])
+    return t1[0], t2[0]
+
+
+@pytest.mark.parametrize("model,par", [(U, (0.0, 1.0)), (E, (0.3, 0.01)), (HST, (0.0, 1.0, 0.1, 0.2, 0.3, 0.4))])
+def test_saddle_iid_is_one_fifteenth(model, par):
+    """Identical independent values: t1 = int F^2 S^2 dF = int_0^1 u^2 (1-u)^2 du
+    = 1/30, and t2 likewise, so P_saddle = 1/15 (by exchangeability every one
+    of the 5! orders is equally likely and 4 of them put v between e,w and
+    n,s in each alternating way)."""
+    g = np.broadcast_to(np.array(par)[:, None, None], (len(par), 5, 6)).copy()
+    ps = oracle.saddle(model, g)
+    np.testing.assert_allclose(ps[1:-1, 1:-1], 1 / 15, atol=1e-14)
+    assert np.all(ps[0, :] == 0) and np.all(ps[:, 0] == 0) and np.all(ps[-1, :] == 0) and np.all(ps[:, -1] == 0)
+
+
+def test_saddle_disjoint_supports():
+    """e, w entirely above v and n, s entirely below: a certain saddle of the
+    first kind (t1 = 1, t2 = 0)."""
+    d = {"v": (0.0, 1.0), "e": (2.0, 3.0), "w": (1.5, 4.0), "n": (-2.0, -1.0), "s": (-3.0, -0.5)}
+    t1, t2 = saddle_centre(U, stencil_grid(U, d))
+    assert t1 == pytest.approx(1.0, abs=1e-15) and t2 == 0.0
+    d["n"] = (3.0, 4.0)  # now n is above v as well: impossible
+    t1, t2 = saddle_centre(U, stencil_grid(U, d))
+    assert t1 == 0.0 and t2 == 0.0
+
+
+@pytest.mark.parametrize("model", [U, E, HST])
+def test_saddle_against_scipy_quadrature(model):
+    rng = np.random.default_rng(71 + model)
+    nb = 4
+    for _ in range(8):
+        d = random_stencil(model, rng, nb)
+        t1, t2 = saddle_centre(model, stencil_grid(model, d, nb if model == HST else 0))
+        dv, pts = scipy_dist(model, d["v"])
+        dist = {}
+        allpts = list(pts)
+        for k in "enws":
+            dist[k], p = scipy_dist(model, d[k])
+            allpts += p
+        lo, hi = pts[0], pts[-1]
+        inner = sorted({p for p in allpts if lo < p < hi})
+        kw = dict(points=inner or None, limit=400, epsabs=1e-14, epsrel=1e-12)
+        f1 = lambda x: dv.pdf(x) * dist["e"].sf(x) * dist["n"].cdf(x) * dist["w"].sf(x) * dist["s"].cdf(x)
+        f2 = lambda x: dv.pdf(x) * dist["e"].cdf(x) * dist["n"].sf(x) * dist["w"].cdf(x) * dist["s"].sf(x)
+        assert t1 == pytest.approx(integrate.quad(f1, lo, hi, **kw)[0], abs=2e-10)
+        assert t2 == pytest.approx(integrate.quad(f2, lo, hi, **kw)[0], abs=2e-10)
+
+
+@pytest.mark.parametrize("model", [U, E, HST])
+def test_saddle_brute_force_monte_carlo(model):
+    rng = np.random.default_rng(17 + model)
+    nb = 3
+    d = SURVEY_STENCILS.get(model) or {
+        "v": (0, 1, 0.5, 0.25, 0.25), "e": (-0.5, 0.5, 1 / 3, 1 / 3, 1 / 3),
+        "n": (0.25, 1.25, 0.1, 0.6, 0.3), "w": (0.5, 2.0, 0.2, 0.3, 0.5), "s": (0.1, 0.9, 0.2, 0.2, 0.6)}
+    t1, t2 = saddle_centre(model, stencil_grid(model, d, nb if model == HST else 0))
+    N, chunks, c1, c2 = 1_000_000, 4, 0, 0
+    for _ in range(chunks):
+        xs = {k: sample(model, d[k], N, rng) for k in POS}
+        v = xs["v"]
+        c1 += int(np.count_nonzero((v < xs["e"]) & (v > xs["n"]) & (v < xs["w"]) & (v > xs["s"])))
+        c2 += int(np.count_nonzero((v > xs["e"]) & (v < xs["n"]) & (v > xs["w"]) & (v < xs["s"])))
+    n = N * chunks
+    for p, c in ((t1, c1), (t2, c2)):
+        se = math.sqrt(max(p * (1 - p), 1e-12) / n)
+        assert abs(c / n - p) < 4 * se, (p, c / n, se)
+
+
+@pytest.mark.parametrize("model", [U, E, HST])
+def test_saddle_negation_and_classes(model):
+    """Negating every value swaps the two saddle terms (Sec. 4.1.3); minimum,
+    maximum and saddle are disjoint events, so their probabilities sum to at
+    most 1."""
+    par = workloads.random_params(model, 6, 9, 11, nbins=4, width=0.05)
+    idx = np.arange(9 * 11)
+    t1, t2 = oracle.saddle_at(model, par, idx)
+    n1, n2 = oracle.saddle_at(model, negate(model, par), idx)
+    np.testing.assert_allclose(t1, n2, atol=1e-13)
+    np.testing.assert_allclose(t2, n1, atol=1e-13)
+    pmin, pmax = oracle.forward(model, par)
+    assert np.all(pmin.ravel() + pmax.ravel() + t1 + t2 <= 1 + 1e-12)
