@@ -142,6 +142,31 @@ cp_status_t cp_prob_forward(const cp_field_desc_t* desc, const void* params, voi
 cp_status_t cp_prob_backward(const cp_field_desc_t* desc, const void* params, const void* g_min,
                              const void* g_max, void* grad_params, void* stream);
 
+/*
+ * Classification of every vertex into minimum, maximum, saddle or regular
+ * point, for the closed-form models (uniform, Epanechnikov, histogram).
+ * Besides P_min and P_max (as cp_prob_forward), the saddle probability of
+ * Eq. 2 (one dimension) / Eq. 4 (the 4-neighbour stencil): with independent
+ * vertex values (Sec. 3) and S = 1 - CDF, F = CDF of a neighbour,
+ *     t1 = Pr[X_v < X_e, X_v > X_n, X_v < X_w, X_v > X_s]
+ *        = integral pdf_v(x) S_e(x) F_n(x) S_w(x) F_s(x) dx,
+ *     t2 = Pr[X_v > X_e, X_v < X_n, X_v > X_w, X_v < X_s]
+ *        = integral pdf_v(x) F_e(x) S_n(x) F_w(x) S_s(x) dx,
+ *     P_saddle = t1 + t2,
+ * integrated exactly over the pieces of [max(a_v, a of the F neighbours),
+ * min(b_v, b of the S neighbours)] (Task 1 of Sec. 4.1.1 with mixed
+ * factors), and P_regular = 1 - P_min - P_max - P_saddle.  The saddle
+ * pattern needs all four neighbours, so P_saddle = 0 on the grid boundary.
+ *   params     [n_param][H][row_stride]
+ *   p_min, p_max, p_saddle, p_regular  [H][row_stride] outputs
+ *   terms      [2][H][row_stride] output: t1, t2
+ * Every output pointer may be NULL (then it is not written); at least one
+ * must be given.  A vertex with an invalid distribution in its stencil gets
+ * NaN in every output.  CP_MVGAUSS: CP_EUNSUPPORTED.
+ */
+cp_status_t cp_prob_classify(const cp_field_desc_t* desc, const void* params, void* p_min, void* p_max,
+                             void* p_saddle, void* p_regular, void* terms, void* stream);
+
 /* cp_prob_batched flags */
 #define CP_BATCH_FWD 1u       /* write p_min / p_max */
 #define CP_BATCH_BWD 2u       /* write grad_params (needs g_min / g_max) */

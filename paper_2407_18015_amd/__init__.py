@@ -3,15 +3,15 @@
 Implements the method of Athawale et al., "Uncertainty Visualization of
 Critical Points of 2D Scalar Fields for Parametric and Nonparametric
 Probabilistic Models" (arXiv 2407.18015): per-vertex probability of being a
-local minimum / maximum on the 4-neighbour stencil for uniform, Epanechnikov
-and histogram models (closed form), and a correlated Gaussian over the
+local minimum / maximum (and saddle / regular point) on the 4-neighbour
+stencil for uniform, Epanechnikov and histogram models (closed form), and a correlated Gaussian over the
 stencil (Monte Carlo), with fitting from ensemble members, adjoints and a
 batched persistent launch.  All computation runs in the HIP library
 ``libcpcrit.so`` behind the C ABI of ``include/cpcrit.h``.
 """
 from . import _lib
-from .ops import (CPProb, Field, backward, batched, critical_point_probability, field_of, fit, forward,
-                  n_params, philox)
+from .ops import (CPProb, Field, backward, batched, classify, critical_point_probability, field_of, fit,
+                  forward, n_params, philox)
 
-__all__ = ["CPProb", "Field", "backward", "batched", "critical_point_probability", "field_of", "fit", "forward",
-           "n_params", "philox", "_lib"]
+__all__ = ["CPProb", "Field", "backward", "batched", "classify", "critical_point_probability", "field_of", "fit",
+           "forward", "n_params", "philox", "_lib"]

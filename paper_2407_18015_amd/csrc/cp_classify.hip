@@ -1,0 +1,172 @@
+// cp_classify.hip -- classification probabilities of every vertex: P_min,
+// P_max (Eq. 3 and its negation), P_saddle = t1 + t2 (Eq. 4) and
+// P_regular = 1 - P_min - P_max - P_saddle, in one pass over the parameters.
+// Tiles of 64 x TY vertices stage their parameters plus a one-vertex halo in
+// LDS, as the forward kernels do; every requested output is written from the
+// same staged stencil.
+#include <hip/hip_runtime.h>
+
+#include "cp_internal.hpp"
+#include "cp_saddle.hpp"
+#include "cp_tiles.hpp"
+
+namespace cp {
+
+template <typename T>
+struct ClassPtrs {
+  const T* params;
+  T* pmin;
+  T* pmax;
+  T* psad;
+  T* preg;
+  T* terms;  // [2][H][rs]: t1, t2
+  int H, W, nb;
+  int64_t rs, ps;
+};
+
+template <typename T>
+__device__ __forceinline__ void class_store(const ClassPtrs<T>& f, int y, int x, T pmin, T pmax, T t1, T t2) {
+  const int64_t at = (int64_t)y * f.rs + x;
+  const T ps = t1 + t2;
+  if (f.pmin) f.pmin[at] = pmin;
+  if (f.pmax) f.pmax[at] = pmax;
+  if (f.psad) f.psad[at] = ps;
+  if (f.terms) {
+    f.terms[at] = t1;
+    f.terms[f.ps + at] = t2;
+  }
+  if (f.preg) f.preg[at] = T(1) - pmin - pmax - ps;
+}
+
+template <typename T, int MODEL, int TY>
+__global__ __launch_bounds__(kFwdTX* TY) void k_classify_ue(ClassPtrs<T> f, int tiles_x, int ntiles) {
+  constexpr int TX = kFwdTX, EX = TX + 2, EY = TY + 2, E = EX * EY, NT = TX * TY;
+  __shared__ T lds[2 * E];
+  const int t = xcd_tile(blockIdx.x, ntiles);
+  const int ty0 = (t / tiles_x) * TY, tx0 = (t % tiles_x) * TX, tid = threadIdx.x;
+  stage<T, EY, EX, NT>(lds, f.params, 2, f.ps, f.rs, f.H, f.W, ty0 - 1, tx0 - 1, tid);
+  __syncthreads();
+  const int lx = tid % TX, ly = tid / TX;
+  const int x = tx0 + lx, y = ty0 + ly;
+  if (x >= f.W || y >= f.H) return;
+  const int e = (ly + 1) * EX + lx + 1;
+  const int en[4] = {e + 1, e - EX, e - 1, e + EX};
+  const bool pres[4] = {x + 1 < f.W, y > 0, x > 0, y + 1 < f.H};
+  const bool mm = f.pmin || f.pmax || f.preg;
+  const bool sad = f.psad || f.terms || f.preg;
+  T pmin = T(0), pmax = T(0), t1 = T(0), t2 = T(0);
+  if (!stencil_valid_ue<T, MODEL>(lds, E, e, en, pres)) {
+    pmin = pmax = t1 = t2 = qnan<T>();
+  } else {
+    if (mm) vertex_fwd_ue<T, MODEL>(lds, E, e, en, pres, pmin, pmax);
+    // the alternating pattern needs all four neighbours: 0 on the boundary
+    if (sad && pres[0] && pres[1] && pres[2] && pres[3]) vertex_saddle_ue<T, MODEL>(lds, E, e, en, t1, t2);
+  }
+  class_store(f, y, x, pmin, pmax, t1, t2);
+}
+
+template <typename T, int TY>
+__global__ __launch_bounds__(kFwdTX* TY) void k_classify_hist(ClassPtrs<T> f, int tiles_x, int ntiles) {
+  constexpr int TX = kFwdTX, EX = TX + 2, EY = TY + 2, E = EX * EY, NT = TX * TY;
+  extern __shared__ __align__(16) unsigned char smem[];
+  T* lds = reinterpret_cast<T*>(smem);
+  const int t = xcd_tile(blockIdx.x, ntiles);
+  const int ty0 = (t / tiles_x) * TY, tx0 = (t % tiles_x) * TX, tid = threadIdx.x;
+  const int h = f.nb;
+  stage<T, EY, EX, NT>(lds, f.params, 2 + h, f.ps, f.rs, f.H, f.W, ty0 - 1, tx0 - 1, tid);
+  __syncthreads();
+  hist_stage_validity<T, NT>(lds, E, h, tid);
+  __syncthreads();
+  const int lx = tid % TX, ly = tid / TX;
+  const int x = tx0 + lx, y = ty0 + ly;
+  if (x >= f.W || y >= f.H) return;
+  const HistLds<T> L{lds, E, h, T(1) / T(h)};
+  const int e = (ly + 1) * EX + lx + 1;
+  const int en[4] = {e + 1, e - EX, e - 1, e + EX};
+  const bool pres[4] = {x + 1 < f.W, y > 0, x > 0, y + 1 < f.H};
+  bool ok = L.valid(e);
+#pragma unroll
+  for (int i = 0; i < 4; ++i) ok = ok && (!pres[i] || L.valid(en[i]));
+  const bool mm = f.pmin || f.pmax || f.preg;
+  const bool sad = f.psad || f.terms || f.preg;
+  T pmin = T(0), pmax = T(0), t1 = T(0), t2 = T(0);
+  if (!ok) {
+    pmin = pmax = t1 = t2 = qnan<T>();
+  } else {
+    if (mm) {
+      const T lov = lds[e], hiv = lds[E + e];
+      T lo[4], hi[4];
+#pragma unroll
+      for (int i = 0; i < 4; ++i) {
+        lo[i] = lds[en[i]] - lov;
+        hi[i] = lds[E + en[i]] - lov;
+      }
+      pmin = hist_side_value(L, e, en, pres, false, hiv - lov, lo, hi);
+#pragma unroll
+      for (int i = 0; i < 4; ++i) {
+        lo[i] = hiv - lds[E + en[i]];
+        hi[i] = hiv - lds[en[i]];
+      }
+      pmax = hist_side_value(L, e, en, pres, true, hiv - lov, lo, hi);
+    }
+    if (sad && pres[0] && pres[1] && pres[2] && pres[3]) vertex_saddle_hist(L, e, en, t1, t2);
+  }
+  class_store(f, y, x, pmin, pmax, t1, t2);
+}
+
+// ---------------------------------------------------------------------------
+// launcher
+// ---------------------------------------------------------------------------
+static int cdiv_c(int a, int b) { return (a + b - 1) / b; }
+
+template <typename T, int TY>
+static hipError_t launch_classify_hist(const ClassPtrs<T>& p, hipStream_t st) {
+  const int tx = cdiv_c(p.W, kFwdTX), ty = cdiv_c(p.H, TY), n = tx * ty;
+  const size_t lds = sizeof(T) * (size_t)hist_planes(p.nb) * (kFwdTX + 2) * (TY + 2);
+  if (lds > 65536) {
+    hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(k_classify_hist<T, TY>),
+                                       hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+    if (e != hipSuccess) return e;
+  }
+  hipLaunchKernelGGL((k_classify_hist<T, TY>), dim3(n), dim3(kFwdTX * TY), lds, st, p, tx, n);
+  return hipGetLastError();
+}
+
+template <typename T>
+static hipError_t classify_typed(const Field& f, const void* params, void* pmin, void* pmax, void* psad,
+                                 void* preg, void* terms, hipStream_t st) {
+  ClassPtrs<T> p;
+  p.params = static_cast<const T*>(params);
+  p.pmin = static_cast<T*>(pmin);
+  p.pmax = static_cast<T*>(pmax);
+  p.psad = static_cast<T*>(psad);
+  p.preg = static_cast<T*>(preg);
+  p.terms = static_cast<T*>(terms);
+  p.H = f.H;
+  p.W = f.W;
+  p.nb = f.nb;
+  p.rs = f.rs;
+  p.ps = f.plane();
+  constexpr int TY = 4;
+  const int tx = cdiv_c(f.W, kFwdTX), ty = cdiv_c(f.H, TY), n = tx * ty;
+  if (f.model == CP_UNIFORM) {
+    hipLaunchKernelGGL((k_classify_ue<T, CP_UNIFORM, TY>), dim3(n), dim3(kFwdTX * TY), 0, st, p, tx, n);
+    return hipGetLastError();
+  }
+  if (f.model == CP_EPANECHNIKOV) {
+    hipLaunchKernelGGL((k_classify_ue<T, CP_EPANECHNIKOV, TY>), dim3(n), dim3(kFwdTX * TY), 0, st, p, tx, n);
+    return hipGetLastError();
+  }
+  const size_t per_row = sizeof(T) * (size_t)hist_planes(f.nb) * (kFwdTX + 2);
+  if (per_row * 6 <= 64 * 1024) return launch_classify_hist<T, 4>(p, st);
+  if (per_row * 4 <= 160 * 1024) return launch_classify_hist<T, 2>(p, st);
+  return launch_classify_hist<T, 1>(p, st);
+}
+
+hipError_t cf_classify(const Field& f, const void* params, void* pmin, void* pmax, void* psad, void* preg,
+                       void* terms, hipStream_t st) {
+  if (f.dtype == CP_F64) return classify_typed<double>(f, params, pmin, pmax, psad, preg, terms, st);
+  return classify_typed<float>(f, params, pmin, pmax, psad, preg, terms, st);
+}
+
+}  // namespace cp

@@ -133,6 +133,27 @@ def backward(params: torch.Tensor, gmin: torch.Tensor, gmax: torch.Tensor, f: Fi
     return grad
 
 
+def classify(params: torch.Tensor, f: Field, outputs=("min", "max", "saddle", "regular"),
+             terms: bool = False) -> dict:
+    """cp_prob_classify: the requested subset of P_min, P_max, P_saddle and
+    P_regular (each [H, W]) and, with terms=True, the saddle terms [2, H, W]
+    (t1, t2).  Returns a dict keyed by "min", "max", "saddle", "regular",
+    "terms"."""
+    _planes(params, f.height, f.width, f.param_dtype, "params", f.row_stride)
+    if params.shape[0] != f.n_param:
+        raise ValueError(f"params needs {f.n_param} planes")
+    names = set(outputs)
+    if not names <= {"min", "max", "saddle", "regular"}:
+        raise ValueError(f"unknown outputs {sorted(names)}")
+    out = {k: torch.empty((f.height, f.width), dtype=f.out_dtype, device=params.device) for k in sorted(names)}
+    if terms:
+        out["terms"] = torch.empty((2, f.height, f.width), dtype=f.out_dtype, device=params.device)
+    L.check(L.cp_prob_classify(f.desc(), _ptr(params), _ptr(out.get("min")), _ptr(out.get("max")),
+                               _ptr(out.get("saddle")), _ptr(out.get("regular")), _ptr(out.get("terms")),
+                               _stream(params)))
+    return out
+
+
 def batched(fields: list[Field], params: list[torch.Tensor], pmin=None, pmax=None, gmin=None, gmax=None,
             grad=None, graph: bool = False, per_field: bool = False) -> None:
     """cp_prob_batched over caller-allocated outputs (lists of tensors)."""

@@ -116,6 +116,16 @@ def test_batched_validation():
                              None) == L.CP_EINVAL
 
 
+def test_classify_validation():
+    lib = L.load()
+    assert lib.cp_prob_classify(desc(), None, FAKE, FAKE, FAKE, FAKE, FAKE, None) == L.CP_EINVAL
+    assert lib.cp_prob_classify(desc(), FAKE, None, None, None, None, None, None) == L.CP_EINVAL
+    assert lib.cp_prob_classify(desc(height=0), FAKE, FAKE, None, None, None, None, None) == L.CP_EINVAL
+    assert lib.cp_prob_classify(desc(model=L.CP_MVGAUSS, nsamples=4), FAKE, FAKE, None, None, None, None,
+                                None) == L.CP_EUNSUPPORTED
+    assert lib.cp_last_error().decode() != ""
+
+
 def test_status_strings():
     lib = L.load()
     for s in range(6):

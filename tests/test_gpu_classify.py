@@ -1,0 +1,204 @@
+"""GPU parity of cp_prob_classify (minimum, maximum, saddle and regular
+probabilities, Eq. 3 and Eq. 4) against the FP64 oracle, through the C ABI.
+
+Tolerances as for the forward: 1e-6 absolute in FP32, 1e-12 in FP64 for
+P_min, P_max and each saddle term; P_regular is a sum of four such values,
+so 4x that.
+"""
+import sys
+
+import numpy as np
+import pytest
+import torch
+
+import oracle
+import workloads
+import paper_2407_18015_amd as cp
+from paper_2407_18015_amd import _lib as L
+
+pytestmark = pytest.mark.gpu
+
+U, E, HST = 0, 1, 2
+NAMES = {U: "uniform", E: "epanechnikov", HST: "histogram"}
+TOL = {torch.float32: 1e-6, torch.float64: 1e-12}
+
+
+@pytest.fixture(scope="module", autouse=True)
+def device():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    L.load()
+    return torch.device("cuda:0")
+
+
+def note(*a):
+    print("[case]", *a, flush=True)
+    sys.stdout.flush()
+
+
+def dev(a, dtype):
+    return torch.as_tensor(np.ascontiguousarray(a), dtype=dtype, device="cuda")
+
+
+def host(t):
+    torch.cuda.synchronize()
+    return t.detach().cpu().numpy().astype(np.float64)
+
+
+def close(got, ref, atol, what):
+    assert np.array_equal(np.isfinite(got), np.isfinite(ref)), f"{what}: NaN pattern differs"
+    d = np.abs(got - ref)
+    if d.size:
+        i = int(np.nanargmax(d))
+        assert np.nanmax(d) <= atol, f"{what}: max |diff| {np.nanmax(d):.3e} at flat {i} (got {got.flat[i]}, ref {ref.flat[i]})"
+
+
+def reference(model, p):
+    """Oracle P_min, P_max, t1, t2, P_regular on every vertex of p."""
+    _, H, W = p.shape
+    pmin, pmax = oracle.forward(model, p)
+    t1, t2 = oracle.saddle_at(model, p, np.arange(H * W))
+    t1 = t1.reshape(H, W)
+    t2 = t2.reshape(H, W)
+    return pmin, pmax, t1, t2, 1.0 - pmin - pmax - (t1 + t2)
+
+
+def check_all(model, pt, nbins, tol, what):
+    f = cp.field_of(pt, model, nbins)
+    out = cp.classify(pt, f, terms=True)
+    rmin, rmax, r1, r2, rreg = reference(model, host(pt))
+    close(host(out["min"]), rmin, tol, f"{what} P_min")
+    close(host(out["max"]), rmax, tol, f"{what} P_max")
+    close(host(out["terms"][0]), r1, tol, f"{what} t1")
+    close(host(out["terms"][1]), r2, tol, f"{what} t2")
+    close(host(out["saddle"]), r1 + r2, 2 * tol, f"{what} P_saddle")
+    close(host(out["regular"]), rreg, 4 * tol, f"{what} P_regular")
+    return out
+
+
+@pytest.mark.parametrize("model", [U, E, HST])
+@pytest.mark.parametrize("dtype", [torch.float32, torch.float64])
+def test_classify_random_fields_ragged(model, dtype):
+    """131x197 (several 64x4 tiles, ragged in both directions)."""
+    note("classify", NAMES[model], dtype, "131x197")
+    p = workloads.random_params(model, 41 + model, 131, 197, nbins=7, width=0.06)
+    check_all(model, dev(p, dtype), 7 if model == HST else 0, TOL[dtype], NAMES[model])
+
+
+@pytest.mark.parametrize("model", [U, E, HST])
+def test_classify_wide_overlap(model):
+    """Wide distributions: most stencils overlap fully, so every piece of the
+    saddle range is populated."""
+    note("classify wide", NAMES[model])
+    p = workloads.random_params(model, 61 + model, 70, 90, nbins=5, width=0.5)
+    check_all(model, dev(p, torch.float32), 5 if model == HST else 0, 1e-6, NAMES[model])
+
+
+@pytest.mark.parametrize("model", [U, E, HST])
+def test_classify_fitted_fields(model):
+    """Parameters fitted on the GPU from the seeded ensembles."""
+    note("classify fitted", NAMES[model], "160x210")
+    mem = workloads.mixture_ensemble(5, 160, 210) if model == HST else workloads.smooth_ensemble(5, 160, 210)
+    params = cp.fit(dev(mem, torch.float32), model, nbins=10 if model == HST else 0)
+    check_all(model, params, 10 if model == HST else 0, 1e-6, NAMES[model])
+
+
+@pytest.mark.parametrize("model", [U, E, HST])
+def test_classify_min_max_equal_forward(model):
+    """The classification's P_min / P_max are those of cp_prob_forward, bit
+    for bit (same per-vertex evaluation)."""
+    note("classify == forward", NAMES[model])
+    p = workloads.random_params(model, 3, 100, 150, nbins=6, width=0.08)
+    pt = dev(p, torch.float32)
+    f = cp.field_of(pt, model, 6 if model == HST else 0)
+    pmin, pmax = cp.forward(pt, f)
+    out = cp.classify(pt, f, outputs=("min", "max"))
+    assert torch.equal(out["min"], pmin) and torch.equal(out["max"], pmax)
+
+
+@pytest.mark.parametrize("model", [U, E, HST])
+def test_classify_output_subsets(model):
+    """Any subset of outputs gives the same values as the full call."""
+    note("classify subsets", NAMES[model])
+    p = workloads.random_params(model, 8, 67, 70, nbins=4, width=0.1)
+    pt = dev(p, torch.float64)
+    f = cp.field_of(pt, model, 4 if model == HST else 0)
+    full = cp.classify(pt, f, terms=True)
+    only_sad = cp.classify(pt, f, outputs=("saddle",))
+    only_terms = cp.classify(pt, f, outputs=(), terms=True)
+    only_reg = cp.classify(pt, f, outputs=("regular",))
+    assert torch.equal(only_sad["saddle"], full["saddle"])
+    assert torch.equal(only_terms["terms"], full["terms"])
+    assert torch.equal(only_reg["regular"], full["regular"])
+
+
+@pytest.mark.parametrize("shape", [(1, 1), (1, 9), (9, 1), (2, 2), (3, 3), (3, 67), (67, 3), (5, 64), (4, 65)])
+@pytest.mark.parametrize("model", [U, E, HST])
+def test_classify_edge_shapes(model, shape):
+    """Small and thin grids: saddle 0 on the boundary, 1x1 is a certain
+    minimum and maximum (no neighbours)."""
+    note("classify edge shape", NAMES[model], shape)
+    H, W = shape
+    p = workloads.random_params(model, 19, H, W, nbins=3, width=0.3)
+    out = check_all(model, dev(p, torch.float64), 3 if model == HST else 0, 1e-12, NAMES[model])
+    sad = host(out["saddle"])
+    assert np.all(sad[0, :] == 0) and np.all(sad[-1, :] == 0) and np.all(sad[:, 0] == 0) and np.all(sad[:, -1] == 0)
+
+
+@pytest.mark.parametrize("model", [U, E, HST])
+def test_classify_invalid_vertex_gives_nan(model):
+    """An invalid distribution makes every output of each stencil that holds it
+    NaN, and nothing else."""
+    note("classify invalid", NAMES[model])
+    H, W = 9, 12
+    p = workloads.random_params(model, 23, H, W, nbins=3, width=0.1)
+    p[1, 4, 5] = -1.0 if model == E else p[0, 4, 5] - 1.0  # w <= 0 / hi < lo
+    f = cp.field_of(dev(p, torch.float32), model, 3 if model == HST else 0)
+    out = cp.classify(dev(p, torch.float32), f, terms=True)
+    bad = np.zeros((H, W), bool)
+    for dy, dx in ((0, 0), (0, 1), (-1, 0), (0, -1), (1, 0)):
+        bad[4 + dy, 5 + dx] = True
+    for k in ("min", "max", "saddle", "regular"):
+        got = host(out[k])
+        assert np.array_equal(np.isnan(got), bad), k
+    assert np.array_equal(np.isnan(host(out["terms"])), np.stack([bad, bad]))
+
+
+def test_classify_rejects_bad_calls():
+    p = dev(workloads.random_params(U, 1, 8, 8), torch.float32)
+    f = cp.field_of(p, U)
+    with pytest.raises(L.CPError):  # no output requested
+        cp.classify(p, f, outputs=())
+    g = cp.Field(8, 8, L.CP_MVGAUSS)
+    mvg = torch.zeros((16, 8, 8), dtype=torch.float64, device="cuda")
+    with pytest.raises(L.CPError) as ei:
+        cp.classify(mvg, g)
+    assert ei.value.status == L.CP_EUNSUPPORTED
+
+
+def test_classify_full_size_epanechnikov_sampled():
+    """2048 x 2048 Epanechnikov (the fitted 20-member workload) at the launch
+    configuration the benchmark uses: 4096 sampled vertices (boundary rows and
+    columns included) against the oracle one by one, and P_min + P_max +
+    P_saddle + P_regular = 1 everywhere."""
+    note("classify 2048^2 epanechnikov sampled")
+    H = W = 2048
+    mem = workloads.smooth_ensemble(0, H, W)
+    params = cp.fit(dev(mem, torch.float32), E)
+    del mem
+    f = cp.field_of(params, E)
+    out = cp.classify(params, f, terms=True)
+    rng = np.random.default_rng(5)
+    idx = rng.choice(H * W, 4000, replace=False)
+    edge = np.concatenate([np.arange(0, W, 37), (H - 1) * W + np.arange(0, W, 41),
+                           np.arange(0, H, 43) * W, np.arange(0, H, 47) * W + W - 1])
+    idx = np.unique(np.concatenate([idx, edge]))
+    ph = host(params)
+    t1, t2 = oracle.saddle_at(E, ph, idx)
+    rmin, rmax = oracle.forward_at(E, ph, idx)
+    close(host(out["terms"][0]).ravel()[idx], t1, 1e-6, "t1")
+    close(host(out["terms"][1]).ravel()[idx], t2, 1e-6, "t2")
+    close(host(out["min"]).ravel()[idx], rmin, 1e-6, "P_min")
+    close(host(out["max"]).ravel()[idx], rmax, 1e-6, "P_max")
+    total = out["min"] + out["max"] + out["saddle"] + out["regular"]
+    assert torch.allclose(total, torch.ones_like(total), atol=1e-6, rtol=0)

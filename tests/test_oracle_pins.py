@@ -757,3 +757,35 @@ def test_saddle_negation_and_classes(model):
     np.testing.assert_allclose(t2, n1, atol=1e-13)
     pmin, pmax = oracle.forward(model, par)
     assert np.all(pmin.ravel() + pmax.ravel() + t1 + t2 <= 1 + 1e-12)
+
+
+@pytest.mark.parametrize("model", [U, E, HST])
+def test_classification_brute_force_monte_carlo(model):
+    """The four classes (minimum, maximum, saddle of either kind, regular)
+    partition the outcomes of one draw of the stencil; P_regular is the rest,
+    1 - P_min - P_max - P_saddle.  All four against the sampled frequencies."""
+    rng = np.random.default_rng(29 + model)
+    nb = 3
+    d = random_stencil(model, rng, nb)
+    g = stencil_grid(model, d, nb if model == HST else 0)
+    pmin, pmax = oracle.forward_at(model, g, [4])
+    t1, t2 = saddle_centre(model, g)
+    probs = {"min": pmin[0], "max": pmax[0], "saddle": t1 + t2}
+    probs["regular"] = 1.0 - probs["min"] - probs["max"] - probs["saddle"]
+    N, chunks = 1_000_000, 3
+    counts = dict.fromkeys(probs, 0)
+    for _ in range(chunks):
+        xs = {k: sample(model, d[k], N, rng) for k in POS}
+        v, e, n, w, s = (xs[k] for k in "venws")
+        is_min = (v < e) & (v < n) & (v < w) & (v < s)
+        is_max = (v > e) & (v > n) & (v > w) & (v > s)
+        is_sad = ((v < e) & (v > n) & (v < w) & (v > s)) | ((v > e) & (v < n) & (v > w) & (v < s))
+        counts["min"] += int(np.count_nonzero(is_min))
+        counts["max"] += int(np.count_nonzero(is_max))
+        counts["saddle"] += int(np.count_nonzero(is_sad))
+        counts["regular"] += int(np.count_nonzero(~(is_min | is_max | is_sad)))
+    n_all = N * chunks
+    assert sum(counts.values()) == n_all
+    for k, p in probs.items():
+        se = math.sqrt(max(p * (1 - p), 1e-12) / n_all)
+        assert abs(counts[k] / n_all - p) < 4 * se, (k, p, counts[k] / n_all, se)
