@@ -166,6 +166,8 @@ def main():
     t_fit = timed(lambda: cp.fit(mem, E, out=params), reps)
     t_fwd = timed(lambda: cp.forward(params, f, pmin, pmax), reps)
     t_bwd = timed(lambda: cp.backward(params, gmin, gmax, f, grad), reps)
+    t_cls = timed(lambda: cp.classify(params, f), reps)
+    t_sad = timed(lambda: cp.classify(params, f, outputs=("saddle",)), reps)
     ph = params.cpu().numpy()
     fl_fwd, fl_bwd, counts = epa_flops(ph)
     roof = {"bound": "alu", "kernel": "adjoint, Epanechnikov FP32 (k_bwd_ue)", "achieved": fl_bwd / (t_bwd * 1e-3) / 1e12,
@@ -179,6 +181,7 @@ def main():
             "fwd_bwd_vertices_per_s": S * S / ((t_fwd + t_bwd) * 1e-3),
             "fwd_tflops": fl_fwd / (t_fwd * 1e-3) / 1e12, "bwd_tflops": fl_bwd / (t_bwd * 1e-3) / 1e12,
             "fit_hbm_gbs": (20 * 4 + 8) * S * S / (t_fit * 1e-3) / 1e9,
+            "classify_ms": t_cls, "saddle_ms": t_sad,
             "pieces_by_started_neighbours": counts.tolist(),
         }
     }
@@ -221,7 +224,10 @@ def more_detail(cp, workloads, torch, dev, S, reps):
         grad = torch.empty_like(params)
         tf = _timed(torch, lambda: cp.forward(params, f, a, b), reps)
         tb = _timed(torch, lambda: cp.backward(params, g1, g2, f, grad), max(3, reps // 2))
-        res[name] = {"fwd_ms": tf, "bwd_ms": tb, "fwd_vertices_per_s": S * S / (tf * 1e-3),
+        tc = _timed(torch, lambda: cp.classify(params, f), reps)
+        ts = _timed(torch, lambda: cp.classify(params, f, outputs=("saddle",)), reps)
+        res[name] = {"fwd_ms": tf, "bwd_ms": tb, "classify_ms": tc, "saddle_ms": ts,
+                     "fwd_vertices_per_s": S * S / (tf * 1e-3),
                      "fwd_bwd_vertices_per_s": S * S / ((tf + tb) * 1e-3)}
         del params, grad
     # multivariate Gaussian 1024^2, 4096 samples

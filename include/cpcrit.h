@@ -117,6 +117,22 @@ cp_status_t cpu_fit_params(const cp_field_desc_t* desc, const void* members, int
                            const cp_fit_opts_t* opts, void* params, void* stream);
 
 /*
+ * Uniform model of a field reconstructed by an error-bounded lossy compressor
+ * (Sec. 5.3, climate data): each vertex value lies in
+ *     [d' - eb/2, d' + eb/2],
+ * d' the decompressed value, and with no knowledge of the error distribution
+ * it is modelled as uniform on that range.
+ *   desc->model  CP_UNIFORM (else CP_EUNSUPPORTED)
+ *   decompressed [H][row_stride], desc->dtype
+ *   eb           the bound in data units (a relative bound is converted by the
+ *                caller), > 0 and finite, else CP_EDOMAIN
+ *   params       output [2][H][row_stride]: lo = d' - h, hi = d' + h with
+ *                h = eb/2 rounded to desc->dtype, each end rounded once
+ */
+cp_status_t cp_fit_error_bound(const cp_field_desc_t* desc, const void* decompressed, double eb, void* params,
+                               void* stream);
+
+/*
  * Forward: P_min and P_max of every vertex (Eq. 3 and its negation).
  *   params  [n_param][H][row_stride] (layout above)
  *   p_min, p_max  [H][row_stride] outputs

@@ -185,6 +185,22 @@ def fit(model: int, members, nbins: int = 0, single: bool = False, ddof: int = 1
     return out
 
 
+def fit_error_bound(decompressed, eb: float, single: bool = False) -> np.ndarray:
+    """Uniform model of an error-bounded lossy reconstruction (Sec. 5.3,
+    climate data): every value lies in [d' - eb/2, d' + eb/2] around the
+    decompressed value d'.  single=True: both ends are FP32 values, each the
+    FP32 rounding of the exact difference / sum (FP32 inputs and eb/2
+    rounded to FP32)."""
+    if single:
+        d = np.asarray(decompressed, dtype=np.float32)
+        h = np.float32(eb * 0.5)
+        out = np.stack([d - h, d + h]).astype(np.float64)
+    else:
+        d = _f64(decompressed)
+        out = np.stack([d - eb * 0.5, d + eb * 0.5])
+    return out
+
+
 def philox4x32_10(counter, key) -> np.ndarray:
     c = np.ascontiguousarray(counter, dtype=np.uint32)
     k = np.ascontiguousarray(key, dtype=np.uint32)

@@ -18,7 +18,7 @@ CP_F32, CP_F64 = 0, 1
 CP_MC_CONDITIONAL, CP_MC_HIT = 0, 1
 CP_BATCH_FWD, CP_BATCH_BWD, CP_BATCH_GRAPH, CP_BATCH_PER_FIELD = 1, 2, 4, 8
 
-EXPORTS = ["cpu_fit_params", "cp_prob_forward", "cp_prob_backward", "cp_prob_classify", "cp_prob_batched",
+EXPORTS = ["cpu_fit_params", "cp_fit_error_bound", "cp_prob_forward", "cp_prob_backward", "cp_prob_classify", "cp_prob_batched",
            "cp_n_params", "cp_status_string", "cp_last_error", "cp_release", "cp_philox4x32_10", "cp_gauss_legendre"]
 
 
@@ -58,6 +58,7 @@ def load() -> ctypes.CDLL:
     PP = ctypes.POINTER(ctypes.c_void_p)
     sigs = {
         "cpu_fit_params": (i32, [D, P, i32, O, P, P]),
+        "cp_fit_error_bound": (i32, [D, P, ctypes.c_double, P, P]),
         "cp_prob_forward": (i32, [D, P, P, P, P]),
         "cp_prob_backward": (i32, [D, P, P, P, P, P]),
         "cp_prob_classify": (i32, [D, P, P, P, P, P, P, P]),

@@ -150,6 +150,21 @@ cp_status_t cpu_fit_params(const cp_field_desc_t* desc, const void* members, int
   return CP_OK;
 }
 
+cp_status_t cp_fit_error_bound(const cp_field_desc_t* desc, const void* decompressed, double eb, void* params,
+                               void* stream) {
+  cp::Field f;
+  cp_status_t s = check_desc(desc, f, false);
+  if (s != CP_OK) return s;
+  if (f.model != CP_UNIFORM) return fail(CP_EUNSUPPORTED, "error-bound fit: the model is uniform");
+  if (!decompressed || !params) return fail(CP_EINVAL, "decompressed / params is NULL");
+  if (!(eb > 0.0) || !(eb < 1e300)) return fail(CP_EDOMAIN, "eb must be positive and finite");
+  if (f.dtype == CP_F32 && !((float)(eb * 0.5) > 0.0f && (float)(eb * 0.5) < 3.0e38f))
+    return fail(CP_EDOMAIN, "eb / 2 is not a positive finite FP32 value");
+  hipError_t e = cp::fit_error_bound(f, decompressed, eb, params, static_cast<hipStream_t>(stream));
+  if (e != hipSuccess) return device_fail(e, "error-bound fit launch");
+  return CP_OK;
+}
+
 cp_status_t cp_prob_forward(const cp_field_desc_t* desc, const void* params, void* p_min, void* p_max,
                             void* stream) {
   cp::Field f;

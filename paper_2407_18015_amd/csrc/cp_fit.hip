@@ -296,6 +296,37 @@ hipError_t fit_typed(const FitArgs& a, int model, hipStream_t st) {
 
 }  // namespace
 
+// ---------------------------------------------------------------------------
+// uniform model of an error-bounded reconstruction (Sec. 5.3, climate data):
+// [d' - eb/2, d' + eb/2], each end rounded once in the field's precision
+// ---------------------------------------------------------------------------
+template <typename T>
+__global__ __launch_bounds__(256) void k_fit_error_bound(const T* __restrict__ d, T half, T* __restrict__ params,
+                                                         int H, int W, int64_t rs, int64_t ps) {
+  const int64_t n = (int64_t)H * W;
+  for (int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x; i < n; i += (int64_t)gridDim.x * 256) {
+    const int y = (int)(i / W), x = (int)(i - (int64_t)y * W);
+    const int64_t at = (int64_t)y * rs + x;
+    const T v = d[at];
+    params[at] = v - half;
+    params[ps + at] = v + half;
+  }
+}
+
+hipError_t fit_error_bound(const Field& f, const void* decompressed, double eb, void* params, hipStream_t st) {
+  const int64_t n = (int64_t)f.H * f.W;
+  const int blocks = (int)std::min<int64_t>((n + 255) / 256, 256 * 16);
+  if (f.dtype == CP_F64)
+    hipLaunchKernelGGL(k_fit_error_bound<double>, dim3(blocks), dim3(256), 0, st,
+                       static_cast<const double*>(decompressed), eb * 0.5, static_cast<double*>(params), f.H, f.W,
+                       f.rs, f.plane());
+  else
+    hipLaunchKernelGGL(k_fit_error_bound<float>, dim3(blocks), dim3(256), 0, st,
+                       static_cast<const float*>(decompressed), (float)(eb * 0.5), static_cast<float*>(params),
+                       f.H, f.W, f.rs, f.plane());
+  return hipGetLastError();
+}
+
 hipError_t fit_params(const Field& f, const void* members, int M, int ddof, double bw, double jitter, double eps,
                       void* params, hipStream_t st) {
   FitArgs a;

@@ -35,6 +35,7 @@ hipError_t cf_classify(const Field& f, const void* params, void* pmin, void* pma
 // fitting from members
 hipError_t fit_params(const Field& f, const void* members, int M, int ddof, double bw, double jitter,
                       double eps, void* params, hipStream_t st);
+hipError_t fit_error_bound(const Field& f, const void* decompressed, double eb, void* params, hipStream_t st);
 
 // multivariate Gaussian
 hipError_t mvg_forward(const Field& f, const double* params, float* pmin, float* pmax, hipStream_t st);

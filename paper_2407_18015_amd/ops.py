@@ -105,6 +105,19 @@ def fit(members: torch.Tensor, model, nbins: int = 0, ddof: int = 1, bw_factor: 
     return out
 
 
+def fit_error_bound(decompressed: torch.Tensor, eb: float, out: torch.Tensor | None = None) -> torch.Tensor:
+    """cp_fit_error_bound: uniform parameters [2, H, W] = d' -/+ eb/2 of an
+    error-bounded reconstruction d' [H, W]."""
+    H, W = decompressed.shape
+    f = Field(H, W, L.CP_UNIFORM, decompressed.dtype)
+    _planes(decompressed, H, W, decompressed.dtype, "decompressed")
+    if out is None:
+        out = torch.empty((2, H, W), dtype=decompressed.dtype, device=decompressed.device)
+    _planes(out, H, W, decompressed.dtype, "params")
+    L.check(L.cp_fit_error_bound(f.desc(), _ptr(decompressed), float(eb), _ptr(out), _stream(decompressed)))
+    return out
+
+
 def forward(params: torch.Tensor, f: Field, pmin: torch.Tensor | None = None, pmax: torch.Tensor | None = None):
     """cp_prob_forward: (P_min, P_max) of every vertex."""
     _planes(params, f.height, f.width, f.param_dtype, "params", f.row_stride)

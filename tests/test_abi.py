@@ -126,6 +126,14 @@ def test_classify_validation():
     assert lib.cp_last_error().decode() != ""
 
 
+def test_error_bound_fit_validation():
+    lib = L.load()
+    assert lib.cp_fit_error_bound(desc(), None, 1.0, FAKE, None) == L.CP_EINVAL
+    assert lib.cp_fit_error_bound(desc(model=L.CP_EPANECHNIKOV), FAKE, 1.0, FAKE, None) == L.CP_EUNSUPPORTED
+    for eb in (0.0, -1.0, float("nan"), float("inf"), 1e39):
+        assert lib.cp_fit_error_bound(desc(), FAKE, eb, FAKE, None) == L.CP_EDOMAIN
+
+
 def test_status_strings():
     lib = L.load()
     for s in range(6):

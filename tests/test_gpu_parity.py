@@ -454,3 +454,33 @@ def test_batched_per_field_mode():
     for i, (f, p) in enumerate(fl):
         a, b = cp.forward(p, f)
         assert torch.equal(a, pmin[i]) and torch.equal(b, pmax[i])
+
+
+# ----------------------------------------------------------------------------
+# error-bound uniform model (Sec. 5.3, climate data)
+# ----------------------------------------------------------------------------
+@pytest.mark.parametrize("dtype", [torch.float32, torch.float64])
+def test_fit_error_bound_bit_exact_and_forward(dtype):
+    """240 x 960 (the climate grid's shape): the ends are bit-identical to the
+    oracle's, and the probabilities of the resulting uniform field match."""
+    note("error-bound fit", dtype)
+    H, W = 240, 960
+    d = workloads.smooth_ensemble(4, H, W)[0]
+    eb = 1e-3 * float(d.max() - d.min())
+    dt = dev(d, dtype)
+    par = cp.fit_error_bound(dt, eb)
+    ref = oracle.fit_error_bound(host(dt), eb, single=dtype == torch.float32)
+    assert np.array_equal(host(par), ref)
+    pmin, pmax = gpu_forward(par, U)
+    rmin, rmax = oracle.forward(U, ref)
+    tol = 1e-6 if dtype == torch.float32 else 1e-12
+    assert_close(host(pmin), rmin, tol, "P_min")
+    assert_close(host(pmax), rmax, tol, "P_max")
+
+
+def test_fit_error_bound_rejects_bad_bound():
+    d = dev(np.zeros((4, 4)), torch.float32)
+    for eb in (0.0, -1.0, float("nan"), float("inf")):
+        with pytest.raises(L.CPError) as ei:
+            cp.fit_error_bound(d, eb)
+        assert ei.value.status == L.CP_EDOMAIN

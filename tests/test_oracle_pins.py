@@ -789,3 +789,48 @@ def test_classification_brute_force_monte_carlo(model):
     for k, p in probs.items():
         se = math.sqrt(max(p * (1 - p), 1e-12) / n_all)
         assert abs(counts[k] / n_all - p) < 4 * se, (k, p, counts[k] / n_all, se)
+
+
+# ----------------------------------------------------------------------------
+# error-bound uniform model (Sec. 5.3, climate data)
+# ----------------------------------------------------------------------------
+def test_error_bound_single_close_neighbour():
+    """Decompressed centre 0, eb = 1: a neighbour at distance delta < eb gives
+    Pr[X_v < X_n] = 1 - (1 - delta)^2 / 2 (two unit-width uniforms); the
+    other three neighbours lie more than eb above and never interfere."""
+    for delta in (0.0, 0.25, 0.6, 0.999):
+        d = np.full((3, 3), 5.0)
+        d[1, 1] = 0.0
+        d[1, 2] = delta
+        par = oracle.fit_error_bound(d, 1.0)
+        pmin, _ = oracle.forward_at(U, par, [4])
+        assert pmin[0] == pytest.approx(1 - (1 - delta) ** 2 / 2, abs=1e-14)
+
+
+def test_error_bound_certain_and_equal():
+    """Gaps larger than eb give the classical min/max (P in {0, 1}); equal
+    decompressed values give identical independent ranges, P = 1/5."""
+    d = np.array([[3.0, 2.0, 3.0], [2.0, 0.0, 2.5], [3.0, 1.1, 3.0]])
+    par = oracle.fit_error_bound(d, 1.0)
+    pmin, pmax = oracle.forward_at(U, par, [4])
+    assert pmin[0] == 1.0 and pmax[0] == 0.0
+    par = oracle.fit_error_bound(np.full((3, 3), 0.7), 0.01)
+    pmin, pmax = oracle.forward_at(U, par, [4])
+    assert pmin[0] == pytest.approx(0.2, abs=1e-13) and pmax[0] == pytest.approx(0.2, abs=1e-13)
+
+
+def test_error_bound_fp32_ends_are_rounded_once():
+    """In FP32 each end is the correctly rounded d' -/+ eb/2."""
+    from fractions import Fraction
+    rng = np.random.default_rng(3)
+    d = rng.uniform(-100, 100, 257).astype(np.float32)
+    eb = 1e-3
+    par = oracle.fit_error_bound(d[None, :], eb, single=True)
+    h = Fraction(float(np.float32(eb * 0.5)))
+    for i in range(d.size):
+        lo_exact = Fraction(float(d[i])) - h
+        hi_exact = Fraction(float(d[i])) + h
+        assert par[0, 0, i] == float(np.float32(float(lo_exact))) or abs(
+            Fraction(par[0, 0, i]) - lo_exact) <= abs(Fraction(float(np.float32(float(lo_exact)))) - lo_exact)
+        assert par[1, 0, i] == float(np.float32(float(hi_exact))) or abs(
+            Fraction(par[1, 0, i]) - hi_exact) <= abs(Fraction(float(np.float32(float(hi_exact)))) - hi_exact)
