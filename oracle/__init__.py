@@ -21,7 +21,7 @@ _HERE = os.path.dirname(os.path.abspath(__file__))
 _SRC = os.path.join(_HERE, "cp_oracle.c")
 _LIB = os.path.join(_HERE, "libcp_oracle.so")
 
-UNIFORM, EPANECHNIKOV, HISTOGRAM, MVG = 0, 1, 2, 3
+UNIFORM, EPANECHNIKOV, HISTOGRAM, MVG, GAUSSIAN = 0, 1, 2, 3, 4
 NSLOT = 5  # stencil slots: 0 = v, 1 = e (x+1), 2 = n (y-1), 3 = w (x-1), 4 = s (y+1)
 SLOT_OFFSETS = ((0, 0), (0, 1), (-1, 0), (0, -1), (1, 0))  # (dy, dx)
 
@@ -56,6 +56,7 @@ def _load():
         "or_forward_at": (i32, [i32, i32, i32, i32, P, i64, P, P, P]),
         "or_jacobian_at": (i32, [i32, i32, i32, i32, P, i64, P, P, P]),
         "or_saddle_at": (i32, [i32, i32, i32, i32, P, i64, P, P, P]),
+        "or_gauss_at": (i32, [i32, i32, P, i64, P, P]),
         "or_grad_at": (i32, [i32, i32, i32, i32, P, P, P, i64, P, P, i32]),
         "or_grad": (i32, [i32, i32, i32, i32, P, P, P, P, i32]),
         "or_fit": (i32, [i32, i32, P, i32, i32, i32, i32, i32, f64, f64, P]),
@@ -183,6 +184,25 @@ def fit(model: int, members, nbins: int = 0, single: bool = False, ddof: int = 1
     _check(_load().or_fit(model, int(single), _ptr(members), M, H, W, nbins, ddof, bw, eps, _ptr(out)),
            "fit")
     return out
+
+
+def gauss_at(params, idx) -> np.ndarray:
+    """Independent Gaussian model, params [2][H][W] = (mu, sigma): returns
+    [n][4] = (P_min, P_max, t1, t2) at flat vertex indices (saddle terms 0
+    off the interior)."""
+    params = _f64(params)
+    _, H, W = params.shape
+    idx = np.ascontiguousarray(idx, dtype=np.int64)
+    out = np.empty((idx.size, 4))
+    _check(_load().or_gauss_at(H, W, _ptr(params), idx.size, _ptr(idx), _ptr(out)), "gauss_at")
+    return out
+
+
+def gauss(params) -> np.ndarray:
+    """[4][H][W] = (P_min, P_max, t1, t2) of every vertex (independent Gaussian)."""
+    params = _f64(params)
+    _, H, W = params.shape
+    return gauss_at(params, np.arange(H * W)).T.reshape(4, H, W).copy()
 
 
 def fit_error_bound(decompressed, eb: float, single: bool = False) -> np.ndarray:

@@ -32,6 +32,11 @@
  *                 (unconstrained), so S(x) = integral_x^inf pdf, which equals
  *                 sum(masses) below the range; P is multilinear in the masses
  *                 exactly as in the h^5 sum of Eq. 5.
+ *   independent Gaussian  N(mu, sigma^2) per vertex (the parametric
+ *                 comparison model of Sec. 5.2, fitted from the member mean
+ *                 and standard deviation).  No closed form exists (Sec. 4.3),
+ *                 so the 1-D integral is evaluated by adaptive quadrature to
+ *                 ~1e-15 (see gauss_* below).
  *   multivariate Gaussian over the 5-point stencil, Monte Carlo (Sec. 5.2,
  *                 5.3; prior work the paper compares against): Philox4x32-10
  *                 counters, Box-Muller normals, hit-count and conditional
@@ -47,6 +52,7 @@
  *   uniform      (lo, hi)
  *   Epanechnikov (m, w)
  *   histogram    (lo, hi, mass_0 .. mass_{nb-1})   -- lo/hi not differentiated
+ *   Gaussian     (mu, sigma)
  *   mvg          (mu, L_00, L_10, L_11, L_20, ... L_44) lower-triangular
  *                Cholesky factor over the variable order (e, n, w, s, v)
  */
@@ -55,7 +61,7 @@
 #include <stdlib.h>
 #include <string.h>
 
-enum { OR_UNIFORM = 0, OR_EPANECHNIKOV = 1, OR_HISTOGRAM = 2, OR_MVG = 3 };
+enum { OR_UNIFORM = 0, OR_EPANECHNIKOV = 1, OR_HISTOGRAM = 2, OR_MVG = 3, OR_GAUSSIAN = 4 };
 
 #define NSLOT 5
 #define PCOEF 16 /* degree <= 15: pdf (2) + four cubic survival factors (12) */
@@ -612,7 +618,7 @@ int or_grad(int model, int H, int W, int nb, const double* params, const double*
 int or_fit(int model, int single, const double* members, int M, int H, int W, int nb, int ddof,
            double bw, double eps, double* params) {
   if (H < 1 || W < 1 || M < 1) return 1;
-  if (model < OR_UNIFORM || model > OR_HISTOGRAM) return 1;
+  if (model < OR_UNIFORM || model > OR_GAUSSIAN || model == OR_MVG) return 1;
   if (model == OR_HISTOGRAM && (nb < 1 || nb > MAXNB)) return 1;
   int64_t n = (int64_t)H * W;
 #pragma omp parallel for schedule(static)
@@ -639,7 +645,8 @@ int or_fit(int model, int single, const double* members, int M, int H, int W, in
     if (model == OR_UNIFORM) {
       params[i] = lo;
       params[n + i] = hi;
-    } else if (model == OR_EPANECHNIKOV) {
+    } else if (model == OR_EPANECHNIKOV || model == OR_GAUSSIAN) {
+      /* Epanechnikov half-width bw * sd * M^(-1/5); Gaussian sigma = sd */
       double mean = sum / (double)M, ss = 0.0;
       for (int k = 0; k < M; ++k) {
         double dk = members[(int64_t)k * n + i] - mean;
@@ -650,7 +657,7 @@ int or_fit(int model, int single, const double* members, int M, int H, int W, in
         w = eps * fmax(1.0, fabs(mean));
       } else {
         double sd = sqrt(ss / (double)(M - ddof));
-        w = bw * sd * pow((double)M, -0.2);
+        w = model == OR_GAUSSIAN ? sd : bw * sd * pow((double)M, -0.2);
       }
       params[i] = mean;
       params[n + i] = w;
@@ -957,5 +964,160 @@ int or_mvg_grad_at(const double* params, int H, int W, int ns, uint64_t seed, ui
         for (int k = 0; k < 15; ++k) o[1 + k] += gmin[at] * r.dl_min[k] + gmax[at] * r.dl_max[k];
     }
   }
+  return 0;
+}
+
+/* ------------------------------------------------------------------------ */
+/* independent Gaussian model                                                 */
+/* ------------------------------------------------------------------------ */
+/*
+ * With X_i ~ N(mu_i, sigma_i^2) independent, the four classification
+ * probabilities of an interior vertex are 1-D integrals (Eq. 3, Eq. 4):
+ *   P_min = int pdf_v S_e S_n S_w S_s,  P_max = int pdf_v F_e F_n F_w F_s,
+ *   t1 = int pdf_v S_e F_n S_w F_s,     t2 = int pdf_v F_e S_n F_w S_s,
+ * S = 1 - CDF, F = CDF, evaluated with erfc so that both tails keep full
+ * relative precision.  The integrals have no closed form; they are taken over
+ * mu_v -/+ 12 sigma_v (the rest of pdf_v weighs < 1e-32), split at
+ * mu_i + k sigma_i (k = 0, +-1, +-2, +-4, +-8) of the five distributions, and
+ * each piece is refined by bisection until a 20-point and a 40-point
+ * Gauss-Legendre rule agree to 1e-16 absolute (plus 1e-14 relative).
+ * The Gauss-Legendre nodes are computed here by Newton's method on the
+ * Legendre polynomial.  Absent neighbours contribute the factor 1; the
+ * saddle terms are 0 unless all four neighbours exist.
+ */
+#define GQ_MAXN 40
+static double gq_x[2][GQ_MAXN], gq_w[2][GQ_MAXN];
+static const int gq_n[2] = {20, 40};
+static int gq_ready = 0;
+
+static void gq_init(void) {
+  for (int r = 0; r < 2; ++r) {
+    int n = gq_n[r];
+    for (int i = 0; i < n; ++i) {
+      double x = cos(M_PI * (i + 0.75) / (n + 0.5)), dp = 1.0;
+      for (int it = 0; it < 100; ++it) {
+        double p0 = 1.0, p1 = x;
+        for (int k = 2; k <= n; ++k) {
+          double p2 = ((2.0 * k - 1.0) * x * p1 - (k - 1.0) * p0) / k;
+          p0 = p1;
+          p1 = p2;
+        }
+        dp = n * (x * p1 - p0) / (x * x - 1.0);
+        double dx = p1 / dp;
+        x -= dx;
+        if (fabs(dx) < 1e-17) break;
+      }
+      double p0 = 1.0, p1 = x;
+      for (int k = 2; k <= n; ++k) {
+        double p2 = ((2.0 * k - 1.0) * x * p1 - (k - 1.0) * p0) / k;
+        p0 = p1;
+        p1 = p2;
+      }
+      dp = n * (x * p1 - p0) / (x * x - 1.0);
+      gq_x[r][i] = x;
+      gq_w[r][i] = 2.0 / ((1.0 - x * x) * dp * dp);
+    }
+  }
+  gq_ready = 1;
+}
+
+typedef struct {
+  double mu[NSLOT], sg[NSLOT];
+  int pres[NSLOT];
+} gstencil_t;
+
+static double g_surv(double x, double mu, double sg) { return 0.5 * erfc((x - mu) / (sg * M_SQRT2)); }
+static double g_cdf(double x, double mu, double sg) { return 0.5 * erfc((mu - x) / (sg * M_SQRT2)); }
+
+/* the four integrands at x: out = (min, max, t1, t2) */
+static void g_integrands(const gstencil_t* g, double x, double out[4]) {
+  double z = (x - g->mu[0]) / g->sg[0];
+  double pdf = exp(-0.5 * z * z) / (g->sg[0] * sqrt(2.0 * M_PI));
+  double smin = pdf, smax = pdf, a = pdf, b = pdf;
+  for (int k = 1; k < NSLOT; ++k) {
+    if (!g->pres[k]) continue;
+    double S = g_surv(x, g->mu[k], g->sg[k]), F = g_cdf(x, g->mu[k], g->sg[k]);
+    smin *= S;
+    smax *= F;
+    /* slots 1 = e, 2 = n, 3 = w, 4 = s: t1 takes S for e, w and F for n, s */
+    a *= (k == 1 || k == 3) ? S : F;
+    b *= (k == 1 || k == 3) ? F : S;
+  }
+  out[0] = smin;
+  out[1] = smax;
+  out[2] = a;
+  out[3] = b;
+}
+
+static void g_rule(const gstencil_t* g, int r, double lo, double hi, double out[4]) {
+  double c = 0.5 * (lo + hi), h = 0.5 * (hi - lo), f[4];
+  out[0] = out[1] = out[2] = out[3] = 0.0;
+  for (int i = 0; i < gq_n[r]; ++i) {
+    g_integrands(g, c + h * gq_x[r][i], f);
+    for (int q = 0; q < 4; ++q) out[q] += gq_w[r][i] * f[q];
+  }
+  for (int q = 0; q < 4; ++q) out[q] *= h;
+}
+
+static void g_adapt(const gstencil_t* g, double lo, double hi, int depth, double acc[4]) {
+  double a[4], b[4];
+  g_rule(g, 0, lo, hi, a);
+  g_rule(g, 1, lo, hi, b);
+  int ok = 1;
+  for (int q = 0; q < 4; ++q)
+    if (fabs(a[q] - b[q]) > 1e-16 + 1e-14 * fabs(b[q])) ok = 0;
+  if (ok || depth >= 50) {
+    for (int q = 0; q < 4; ++q) acc[q] += b[q];
+    return;
+  }
+  double m = 0.5 * (lo + hi);
+  g_adapt(g, lo, m, depth + 1, acc);
+  g_adapt(g, m, hi, depth + 1, acc);
+}
+
+static void gauss_vertex(const grid_t* gr, int y, int x, double out[4]) {
+  gstencil_t g;
+  int64_t plane = (int64_t)gr->H * gr->W;
+  for (int s = 0; s < NSLOT; ++s) {
+    int yy = y + SLOT_DY[s], xx = x + SLOT_DX[s];
+    g.pres[s] = yy >= 0 && yy < gr->H && xx >= 0 && xx < gr->W;
+    g.mu[s] = g.sg[s] = 1.0;
+    if (g.pres[s]) {
+      int64_t at = (int64_t)yy * gr->W + xx;
+      g.mu[s] = gr->par[at];
+      g.sg[s] = gr->par[plane + at];
+    }
+  }
+  const double ks[9] = {-8, -4, -2, -1, 0, 1, 2, 4, 8};
+  double lo = g.mu[0] - 12.0 * g.sg[0], hi = g.mu[0] + 12.0 * g.sg[0];
+  double bp[2 + NSLOT * 9];
+  int nbp = 0;
+  bp[nbp++] = lo;
+  bp[nbp++] = hi;
+  for (int s = 0; s < NSLOT; ++s) {
+    if (!g.pres[s]) continue;
+    for (int k = 0; k < 9; ++k) {
+      double p = g.mu[s] + ks[k] * g.sg[s];
+      if (p > lo && p < hi) bp[nbp++] = p;
+    }
+  }
+  qsort(bp, nbp, sizeof(double), cmp_double);
+  double acc[4] = {0, 0, 0, 0};
+  for (int i = 0; i + 1 < nbp; ++i)
+    if (bp[i + 1] > bp[i]) g_adapt(&g, bp[i], bp[i + 1], 0, acc);
+  int interior = g.pres[1] && g.pres[2] && g.pres[3] && g.pres[4];
+  out[0] = acc[0];
+  out[1] = acc[1];
+  out[2] = interior ? acc[2] : 0.0;
+  out[3] = interior ? acc[3] : 0.0;
+}
+
+/* out [nidx][4] = (P_min, P_max, t1, t2) at flat indices idx */
+int or_gauss_at(int H, int W, const double* params, int64_t nidx, const int64_t* idx, double* out) {
+  if (H < 1 || W < 1) return 1;
+  if (!gq_ready) gq_init();
+  grid_t g = {OR_GAUSSIAN, H, W, 0, params};
+#pragma omp parallel for schedule(dynamic, 16)
+  for (int64_t i = 0; i < nidx; ++i) gauss_vertex(&g, (int)(idx[i] / W), (int)(idx[i] % W), &out[4 * i]);
   return 0;
 }

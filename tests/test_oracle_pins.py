@@ -834,3 +834,146 @@ def test_error_bound_fp32_ends_are_rounded_once():
             Fraction(par[0, 0, i]) - lo_exact) <= abs(Fraction(float(np.float32(float(lo_exact)))) - lo_exact)
         assert par[1, 0, i] == float(np.float32(float(hi_exact))) or abs(
             Fraction(par[1, 0, i]) - hi_exact) <= abs(Fraction(float(np.float32(float(hi_exact)))) - hi_exact)
+
+
+# ----------------------------------------------------------------------------
+# independent Gaussian model (the parametric comparison model of Sec. 5.2)
+# ----------------------------------------------------------------------------
+G = oracle.GAUSSIAN
+
+
+def gauss_grid(vals):
+    """3x3 (mu, sigma) grid with the given stencil; other cells far away."""
+    par = np.zeros((2, 3, 3))
+    par[0] = 50.0
+    par[1] = 1.0
+    for k, (m, s) in vals.items():
+        par[0][POS[k]] = m
+        par[1][POS[k]] = s
+    return par
+
+
+def random_gauss_stencil(rng):
+    sig = 10 ** rng.uniform(-2, 0.3, 5) if rng.random() < 0.5 else 10 ** rng.uniform(-0.3, 0.3, 5)
+    mu = rng.normal(0, 1, 5) * (0.4 if rng.random() < 0.7 else 3)
+    return {k: (mu[i], sig[i]) for i, k in enumerate("venws")}
+
+
+def test_gauss_iid_values():
+    """Identical independent Gaussians: every ordering of the five values is
+    equally likely, so P_min = P_max = 1/5 and t1 = t2 = 1/30 (4 of 120)."""
+    for m, s in ((0.0, 1.0), (3.5, 0.01), (-200.0, 7.0)):
+        r = oracle.gauss_at(gauss_grid({k: (m, s) for k in "venws"}), [4])[0]
+        np.testing.assert_allclose(r, [0.2, 0.2, 1 / 30, 1 / 30], atol=1e-14)
+
+
+def test_gauss_single_neighbour_closed_form():
+    """1x2 grid: each vertex has one neighbour, and Pr[X_v < X_n] =
+    Phi((mu_n - mu_v) / sqrt(sigma_v^2 + sigma_n^2))."""
+    from scipy import special
+    rng = np.random.default_rng(4)
+    for _ in range(20):
+        mu = rng.normal(0, 1, 2)
+        sg = 10 ** rng.uniform(-2, 0.5, 2)
+        p = np.array([[mu], [sg]]).reshape(2, 1, 2)
+        r = oracle.gauss_at(p, [0, 1])
+        z = (mu[1] - mu[0]) / math.hypot(sg[0], sg[1])
+        assert r[0, 0] == pytest.approx(special.ndtr(z), abs=1e-14)
+        assert r[0, 1] == pytest.approx(special.ndtr(-z), abs=1e-14)
+        assert r[1, 0] == pytest.approx(special.ndtr(-z), abs=1e-14)
+        assert r[0, 2] == 0.0 and r[0, 3] == 0.0
+
+
+def test_gauss_corner_bivariate_orthant():
+    """Corner vertex (0,0) with neighbours e, s: (X_e - X_v, X_s - X_v) is
+    bivariate normal with covariance [[s_v^2 + s_e^2, s_v^2], [s_v^2,
+    s_v^2 + s_s^2]]; P_min is its positive orthant (scipy's bivariate normal
+    CDF)."""
+    rng = np.random.default_rng(8)
+    for _ in range(10):
+        mu = rng.normal(0, 0.5, 3)
+        sg = 10 ** rng.uniform(-1, 0.3, 3)
+        p = np.zeros((2, 2, 2))
+        p[1] = 1.0
+        p[0, 0, 0], p[0, 0, 1], p[0, 1, 0] = mu  # v, e, s
+        p[1, 0, 0], p[1, 0, 1], p[1, 1, 0] = sg
+        r = oracle.gauss_at(p, [0])[0]
+        dm = np.array([mu[1] - mu[0], mu[2] - mu[0]])
+        C = np.array([[sg[0] ** 2 + sg[1] ** 2, sg[0] ** 2], [sg[0] ** 2, sg[0] ** 2 + sg[2] ** 2]])
+        # Pr[D > 0] = Pr[-D < 0] with -D ~ N(-dm, C)
+        ref = stats.multivariate_normal.cdf(np.zeros(2), -dm, C, abseps=1e-12, releps=1e-12)
+        assert r[0] == pytest.approx(ref, abs=1e-9)
+
+
+def test_gauss_against_scipy_quadrature():
+    """Interior stencils with mixed scales: all four integrals against scipy's
+    adaptive quadrature of scipy.stats densities and tails."""
+    rng = np.random.default_rng(12)
+    for _ in range(12):
+        d = random_gauss_stencil(rng)
+        r = oracle.gauss_at(gauss_grid(d), [4])[0]
+        dv = stats.norm(*d["v"])
+        nb = {k: stats.norm(*d[k]) for k in "enws"}
+        pts = sorted(m + c * s for m, s in d.values() for c in (-3, 0, 3))
+        lo, hi = d["v"][0] - 12 * d["v"][1], d["v"][0] + 12 * d["v"][1]
+        inner = [p for p in pts if lo < p < hi]
+        kw = dict(points=inner or None, limit=500, epsabs=1e-14, epsrel=1e-12)
+        fs = [
+            lambda x: dv.pdf(x) * np.prod([nb[k].sf(x) for k in "enws"]),
+            lambda x: dv.pdf(x) * np.prod([nb[k].cdf(x) for k in "enws"]),
+            lambda x: dv.pdf(x) * nb["e"].sf(x) * nb["n"].cdf(x) * nb["w"].sf(x) * nb["s"].cdf(x),
+            lambda x: dv.pdf(x) * nb["e"].cdf(x) * nb["n"].sf(x) * nb["w"].cdf(x) * nb["s"].sf(x),
+        ]
+        for q in range(4):
+            assert r[q] == pytest.approx(integrate.quad(fs[q], lo, hi, **kw)[0], abs=1e-11), q
+
+
+def test_gauss_brute_force_monte_carlo():
+    rng = np.random.default_rng(31)
+    d = {"v": (0.0, 0.3), "e": (0.2, 0.5), "n": (-0.1, 0.2), "w": (0.05, 0.3), "s": (-0.3, 0.4)}
+    r = oracle.gauss_at(gauss_grid(d), [4])[0]
+    N, chunks = 1_000_000, 3
+    c = np.zeros(4)
+    for _ in range(chunks):
+        x = {k: rng.normal(m, s, N) for k, (m, s) in d.items()}
+        v, e, n, w, s = (x[k] for k in "venws")
+        c += [np.count_nonzero((v < e) & (v < n) & (v < w) & (v < s)),
+              np.count_nonzero((v > e) & (v > n) & (v > w) & (v > s)),
+              np.count_nonzero((v < e) & (v > n) & (v < w) & (v > s)),
+              np.count_nonzero((v > e) & (v < n) & (v > w) & (v < s))]
+    n_all = N * chunks
+    for q in range(4):
+        se = math.sqrt(r[q] * (1 - r[q]) / n_all)
+        assert abs(c[q] / n_all - r[q]) < 4 * se, (q, r[q], c[q] / n_all)
+
+
+def test_gauss_negation_and_invariance():
+    """Negating every value swaps P_min/P_max and t1/t2 (Sec. 4.1.2, 4.1.3);
+    an affine change of units a X + b (a > 0) changes nothing."""
+    rng = np.random.default_rng(2)
+    par = np.stack([rng.normal(0, 0.1, (7, 9)), 10 ** rng.uniform(-2, -0.5, (7, 9))])
+    r = oracle.gauss(par)
+    neg = oracle.gauss(np.stack([-par[0], par[1]]))
+    np.testing.assert_allclose(r[[1, 0, 3, 2]], neg, atol=1e-13)
+    aff = oracle.gauss(np.stack([3.0 * par[0] + 17.0, 3.0 * par[1]]))
+    np.testing.assert_allclose(r, aff, atol=1e-12)
+    assert np.all(r.sum(0) <= 1 + 1e-12)
+
+
+def test_gauss_equals_diagonal_multivariate_model():
+    """The multivariate Gaussian model with a diagonal covariance is the
+    independent model: its conditional Monte Carlo estimate (a separate
+    oracle routine, Philox samples) agrees within 4 standard errors."""
+    means = [0.1, -0.2, 0.3, 0.05, 0.0]  # e, n, w, s, v
+    sig = [0.3, 0.5, 0.4, 0.2, 0.35]
+    r = oracle.gauss_at(gauss_grid({k: (means[i], sig[i]) for i, k in enumerate("enwsv")}), [4])[0]
+    est, _ = oracle.mvg_forward_at(mvg_grid(mu_plane(means), np.diag(sig)), [4], 1 << 15, seed=777)
+    for got, p in ((est[0, 2], r[0]), (est[0, 3], r[1])):
+        assert abs(got - p) < 4 * math.sqrt(p * (1 - p) / (1 << 15)), (got, p)
+
+
+def test_gauss_fit_against_numpy():
+    mem = workloads.smooth_ensemble(2, 9, 13)
+    par = oracle.fit(G, mem.astype(np.float64))
+    np.testing.assert_allclose(par[0], mem.astype(np.float64).mean(0), rtol=1e-14, atol=1e-15)
+    np.testing.assert_allclose(par[1], mem.astype(np.float64).std(0, ddof=1), rtol=1e-12)
