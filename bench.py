@@ -230,6 +230,15 @@ def more_detail(cp, workloads, torch, dev, S, reps):
                      "fwd_vertices_per_s": S * S / (tf * 1e-3),
                      "fwd_bwd_vertices_per_s": S * S / ((tf + tb) * 1e-3)}
         del params, grad
+    # independent Gaussian at S^2 (deterministic quadrature: forward = all four classes)
+    mem = torch.as_tensor(workloads.smooth_ensemble(1, S, S), device=dev)
+    params = cp.fit(mem, "gaussian")
+    del mem
+    f = cp.field_of(params, "gaussian")
+    a, b = torch.empty((S, S), device=dev), torch.empty((S, S), device=dev)
+    tf = _timed(torch, lambda: cp.forward(params, f, a, b), reps)
+    res["gaussian_2048"] = {"fwd_ms": tf, "fwd_vertices_per_s": S * S / (tf * 1e-3)}
+    del params
     # multivariate Gaussian 1024^2, 4096 samples
     n = 1024
     mem = torch.as_tensor(workloads.correlated_ensemble(0, n, n), device=dev)

@@ -48,6 +48,13 @@
  *                                                       on [m-w, m+w]
  *  CP_HISTOGRAM     2 + nbins planes: lo, hi, mass_0..  nbins equal-width bins on
  *                                                       [lo,hi]; pdf mass_j/Delta
+ *  CP_GAUSSIAN      2 planes: mu, sigma                  independent N(mu, sigma^2)
+ *                   (the parametric comparison model of Sec. 5.2).  No closed
+ *                   form exists; the 1-D integrals are evaluated by a fixed
+ *                   composite Gauss-Legendre rule on panels cut at multiples of
+ *                   every sigma of the stencil, accurate to ~1e-8 (FP32) and
+ *                   ~1e-14 (FP64) absolute.  Forward and classification only:
+ *                   cp_prob_backward and cp_prob_batched return CP_EUNSUPPORTED.
  *  CP_MVGAUSS       16 FP64 planes: mean, then the packed lower-triangular
  *                   Cholesky factor L (row-major: L00, L10, L11, L20, ...,
  *                   L44) of the covariance of (e, n, w, s, v) at that vertex.
@@ -71,7 +78,13 @@ typedef enum {
   CP_EUNSUPPORTED = 5  /* model x dtype x operation not provided */
 } cp_status_t;
 
-typedef enum { CP_UNIFORM = 0, CP_EPANECHNIKOV = 1, CP_HISTOGRAM = 2, CP_MVGAUSS = 3 } cp_model_t;
+typedef enum {
+  CP_UNIFORM = 0,
+  CP_EPANECHNIKOV = 1,
+  CP_HISTOGRAM = 2,
+  CP_MVGAUSS = 3,  /* correlated Gaussian over the stencil, Monte Carlo */
+  CP_GAUSSIAN = 4  /* independent Gaussian per vertex, deterministic quadrature */
+} cp_model_t;
 typedef enum { CP_F32 = 0, CP_F64 = 1 } cp_dtype_t;
 
 /* Monte Carlo estimator of the multivariate Gaussian model */
@@ -104,7 +117,8 @@ typedef struct {
 /*
  * Fit the per-vertex model of desc->model from ensemble members
  * (Sec. 5.1 and 5.2: uniform range = member min/max; Epanechnikov from the
- * member mean and standard deviation; Sec. 4.4: histogram with nbins bins
+ * member mean and standard deviation; independent Gaussian: mu = mean,
+ * sigma = std(ddof); Sec. 4.4: histogram with nbins bins
  * over the member range, mass = count / M, a member at relative position t
  * falls in bin floor(t * nbins) computed in desc->dtype, the maximum in the
  * last bin; Sec. 5.2/5.3: multivariate Gaussian from the member covariance of
@@ -160,7 +174,8 @@ cp_status_t cp_prob_backward(const cp_field_desc_t* desc, const void* params, co
 
 /*
  * Classification of every vertex into minimum, maximum, saddle or regular
- * point, for the closed-form models (uniform, Epanechnikov, histogram).
+ * point, for the closed-form models (uniform, Epanechnikov, histogram) and
+ * the independent Gaussian.
  * Besides P_min and P_max (as cp_prob_forward), the saddle probability of
  * Eq. 2 (one dimension) / Eq. 4 (the 4-neighbour stencil): with independent
  * vertex values (Sec. 3) and S = 1 - CDF, F = CDF of a neighbour,
@@ -171,7 +186,8 @@ cp_status_t cp_prob_backward(const cp_field_desc_t* desc, const void* params, co
  *     P_saddle = t1 + t2,
  * integrated exactly over the pieces of [max(a_v, a of the F neighbours),
  * min(b_v, b of the S neighbours)] (Task 1 of Sec. 4.1.1 with mixed
- * factors), and P_regular = 1 - P_min - P_max - P_saddle.  The saddle
+ * factors; CP_GAUSSIAN: by the quadrature described with its layout), and
+ * P_regular = 1 - P_min - P_max - P_saddle.  The saddle
  * pattern needs all four neighbours, so P_saddle = 0 on the grid boundary.
  *   params     [n_param][H][row_stride]
  *   p_min, p_max, p_saddle, p_regular  [H][row_stride] outputs
@@ -225,7 +241,7 @@ cp_status_t cp_philox4x32_10(int64_t n, const uint32_t* counters, uint64_t seed,
 
 /*
  * Gauss-Legendre rule the closed-form kernels use for an n-point piece
- * (n in {1, 2, 3, 5, 6, 8}): host copies of the device tables, for checking.
+ * (n in {1, 2, 3, 5, 6, 8, 10}): host copies of the device tables, for checking.
  * Returns CP_EINVAL for other n.
  */
 cp_status_t cp_gauss_legendre(int32_t n, double* nodes, double* weights);

@@ -13,7 +13,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(HERE, "libcpcrit.so")
 
 CP_OK, CP_EINVAL, CP_EDOMAIN, CP_ENOMEM, CP_EDEVICE, CP_EUNSUPPORTED = range(6)
-CP_UNIFORM, CP_EPANECHNIKOV, CP_HISTOGRAM, CP_MVGAUSS = range(4)
+CP_UNIFORM, CP_EPANECHNIKOV, CP_HISTOGRAM, CP_MVGAUSS, CP_GAUSSIAN = range(5)
 CP_F32, CP_F64 = 0, 1
 CP_MC_CONDITIONAL, CP_MC_HIT = 0, 1
 CP_BATCH_FWD, CP_BATCH_BWD, CP_BATCH_GRAPH, CP_BATCH_PER_FIELD = 1, 2, 4, 8

@@ -31,7 +31,7 @@ cp_status_t device_fail(hipError_t e, const char* what) {
 cp_status_t check_desc(const cp_field_desc_t* d, cp::Field& f, bool sampling = true) {
   if (!d) return fail(CP_EINVAL, "descriptor is NULL");
   if (d->height < 1 || d->width < 1) return fail(CP_EINVAL, "height and width must be >= 1");
-  if (d->model < CP_UNIFORM || d->model > CP_MVGAUSS) return fail(CP_EINVAL, "unknown model");
+  if (d->model < CP_UNIFORM || d->model > CP_GAUSSIAN) return fail(CP_EINVAL, "unknown model");
   if (d->dtype != CP_F32 && d->dtype != CP_F64) return fail(CP_EINVAL, "unknown dtype");
   const int64_t rs = d->row_stride == 0 ? d->width : d->row_stride;
   if (rs < d->width) return fail(CP_EINVAL, "row_stride is smaller than width");
@@ -102,7 +102,7 @@ void workspace_release() {
 extern "C" {
 
 int32_t cp_n_params(int32_t model, int32_t nbins) {
-  if (model < CP_UNIFORM || model > CP_MVGAUSS) return -1;
+  if (model < CP_UNIFORM || model > CP_GAUSSIAN) return -1;
   if (model == CP_HISTOGRAM && (nbins < 1 || nbins > cp::kMaxBins)) return -1;
   return cp::n_params(model, nbins);
 }
@@ -140,7 +140,7 @@ cp_status_t cpu_fit_params(const cp_field_desc_t* desc, const void* members, int
   if (!(o.bw_factor > 0.0)) return fail(CP_EDOMAIN, "bw_factor must be > 0");
   if (!(o.cov_jitter >= 0.0)) return fail(CP_EDOMAIN, "cov_jitter must be >= 0");
   double eps = o.degenerate_eps > 0.0 ? o.degenerate_eps : (f.dtype == CP_F64 ? 0x1p-30 : 0x1p-20);
-  if (f.model == CP_EPANECHNIKOV && n_members > 1 && n_members - o.ddof < 1)
+  if ((f.model == CP_EPANECHNIKOV || f.model == CP_GAUSSIAN) && n_members > 1 && n_members - o.ddof < 1)
     return fail(CP_EDOMAIN, "n_members - ddof must be >= 1");
   if (f.model == CP_MVGAUSS && (n_members < 2 || n_members - o.ddof < 1))
     return fail(CP_EDOMAIN, "the Gaussian fit needs n_members >= 2 and n_members - ddof >= 1");
@@ -188,6 +188,7 @@ cp_status_t cp_prob_backward(const cp_field_desc_t* desc, const void* params, co
   cp_status_t s = check_desc(desc, f);
   if (s != CP_OK) return s;
   if (!params || !g_min || !g_max || !grad_params) return fail(CP_EINVAL, "a backward argument is NULL");
+  if (f.model == CP_GAUSSIAN) return fail(CP_EUNSUPPORTED, "backward: no adjoint for the independent Gaussian");
   hipStream_t st = static_cast<hipStream_t>(stream);
   hipError_t e;
   if (f.model == CP_MVGAUSS)
@@ -229,7 +230,8 @@ cp_status_t cp_prob_batched(int32_t n, const cp_field_desc_t* descs, const void*
   for (int i = 0; i < n; ++i) {
     cp_status_t s = check_desc(&descs[i], fs[i]);
     if (s != CP_OK) return s;
-    if (fs[i].model == CP_MVGAUSS) return fail(CP_EUNSUPPORTED, "batched: Gaussian fields are not accepted");
+    if (fs[i].model == CP_MVGAUSS || fs[i].model == CP_GAUSSIAN)
+      return fail(CP_EUNSUPPORTED, "batched: Gaussian fields are not accepted");
     if (fs[i].dtype != fs[0].dtype) return fail(CP_EINVAL, "batched: all fields must share one dtype");
     if (!params[i] || (fwd && (!p_min[i] || !p_max[i])) ||
         (bwd && (!g_min[i] || !g_max[i] || !grad_params[i])))

@@ -6,6 +6,7 @@
 // same staged stencil.
 #include <hip/hip_runtime.h>
 
+#include "cp_gauss.hpp"
 #include "cp_internal.hpp"
 #include "cp_saddle.hpp"
 #include "cp_tiles.hpp"
@@ -57,6 +58,18 @@ __global__ __launch_bounds__(kFwdTX* TY) void k_classify_ue(ClassPtrs<T> f, int 
   T pmin = T(0), pmax = T(0), t1 = T(0), t2 = T(0);
   if (!stencil_valid_ue<T, MODEL>(lds, E, e, en, pres)) {
     pmin = pmax = t1 = t2 = qnan<T>();
+  } else if constexpr (MODEL == CP_GAUSSIAN) {
+    T mn[4], sn[4], o[4];
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+      mn[i] = pres[i] ? lds[en[i]] : T(0);
+      sn[i] = pres[i] ? lds[E + en[i]] : T(1);
+    }
+    gauss_vertex<T>(lds[e], lds[E + e], mn, sn, pres, o);
+    pmin = o[0];
+    pmax = o[1];
+    t1 = o[2];
+    t2 = o[3];
   } else {
     if (mm) vertex_fwd_ue<T, MODEL>(lds, E, e, en, pres, pmin, pmax);
     // the alternating pattern needs all four neighbours: 0 on the boundary
@@ -155,6 +168,10 @@ static hipError_t classify_typed(const Field& f, const void* params, void* pmin,
   }
   if (f.model == CP_EPANECHNIKOV) {
     hipLaunchKernelGGL((k_classify_ue<T, CP_EPANECHNIKOV, TY>), dim3(n), dim3(kFwdTX * TY), 0, st, p, tx, n);
+    return hipGetLastError();
+  }
+  if (f.model == CP_GAUSSIAN) {
+    hipLaunchKernelGGL((k_classify_ue<T, CP_GAUSSIAN, TY>), dim3(n), dim3(kFwdTX * TY), 0, st, p, tx, n);
     return hipGetLastError();
   }
   const size_t per_row = sizeof(T) * (size_t)hist_planes(f.nb) * (kFwdTX + 2);

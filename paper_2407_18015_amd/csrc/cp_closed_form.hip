@@ -131,6 +131,8 @@ static hipError_t fwd_typed(const Field& f, const void* params, void* pmin, void
 }
 
 hipError_t cf_forward(const Field& f, const void* params, void* pmin, void* pmax, hipStream_t st) {
+  // the Gaussian sweep yields all four classification integrals at once
+  if (f.model == CP_GAUSSIAN) return cf_classify(f, params, pmin, pmax, nullptr, nullptr, nullptr, st);
   if (f.dtype == CP_F64) return fwd_typed<double>(f, params, pmin, pmax, st);
   return fwd_typed<float>(f, params, pmin, pmax, st);
 }
@@ -204,6 +206,7 @@ bool gl_table(int n, double* x, double* w) {
     CP_GL_CASE(5)
     CP_GL_CASE(6)
     CP_GL_CASE(8)
+    CP_GL_CASE(10)
 #undef CP_GL_CASE
     default:
       return false;

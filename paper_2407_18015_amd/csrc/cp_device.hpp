@@ -96,6 +96,17 @@ struct GL<8> {
                                   0.36268378337836198297, 0.31370664587788728734,
                                   0.22238103445337447054, 0.10122853629037625915};
 };
+template <>
+struct GL<10> {
+  static constexpr double x[10] = {-0.97390652851717172008, -0.86506336668898451073, -0.67940956829902440623,
+                                   -0.43339539412924719080, -0.14887433898163121088, 0.14887433898163121088,
+                                   0.43339539412924719080,  0.67940956829902440623,  0.86506336668898451073,
+                                   0.97390652851717172008};
+  static constexpr double w[10] = {0.066671344308688137594, 0.14945134915058059315, 0.21908636251598204400,
+                                   0.26926671930999635509,  0.29552422471475287017, 0.29552422471475287017,
+                                   0.26926671930999635509,  0.21908636251598204400, 0.14945134915058059315,
+                                   0.066671344308688137594};
+};
 
 // ---------------------------------------------------------------------------
 // small helpers

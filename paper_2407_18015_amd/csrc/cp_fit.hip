@@ -4,13 +4,14 @@
 // histograms, Sec. 5.2/5.3 for the multivariate Gaussian):
 //   uniform       lo = min, hi = max of the members
 //   Epanechnikov  m = mean, w = bw * std(ddof) * M^(-1/5)
+//   Gaussian      mu = mean, sigma = std(ddof) (independent per vertex)
 //   histogram     lo = min, hi = max, nbins equal-width bins, mass = count/M;
 //                 bin of x = floor(((x - lo) / (hi - lo)) * nbins), computed in
 //                 the field's precision with every operation rounded once,
 //                 the maximum in the last bin
 //   degenerate    all members equal: lo/hi = x -/+ eps*max(1,|x|), Epanechnikov
-//                 w = eps*max(1,|m|)
-//   Gaussian      mean plane; covariance of (e, n, w, s, v) over members with
+//                 w (Gaussian sigma) = eps*max(1,|m|)
+//   multivariate  mean plane; covariance of (e, n, w, s, v) over members with
 //                 `ddof`, + jitter on the diagonal, FP64 Cholesky; absent
 //                 neighbours get identity rows.
 // The kernels are HBM-bound: every member value is read once (held in
@@ -290,7 +291,7 @@ hipError_t launch_fit(const FitArgs& a, hipStream_t st) {
 template <typename T>
 hipError_t fit_typed(const FitArgs& a, int model, hipStream_t st) {
   if (model == CP_UNIFORM) return launch_fit<T, CP_UNIFORM>(a, st);
-  if (model == CP_EPANECHNIKOV) return launch_fit<T, CP_EPANECHNIKOV>(a, st);
+  if (model == CP_EPANECHNIKOV || model == CP_GAUSSIAN) return launch_fit<T, CP_EPANECHNIKOV>(a, st);
   return launch_fit<T, CP_HISTOGRAM>(a, st);
 }
 
@@ -339,7 +340,10 @@ hipError_t fit_params(const Field& f, const void* members, int M, int ddof, doub
   a.ddof = ddof;
   a.rs = f.rs;
   a.ps = f.plane();
+  // Epanechnikov half-width bw * sd * M^(-1/5); Gaussian sigma = sd; both as
+  // wscale * sqrt(sum of squared deviations)
   a.wscale = M - ddof > 0 ? bw * std::pow((double)M, -0.2) / std::sqrt((double)(M - ddof)) : 0.0;
+  if (f.model == CP_GAUSSIAN) a.wscale = M - ddof > 0 ? 1.0 / std::sqrt((double)(M - ddof)) : 0.0;
   a.eps = eps;
   if (f.model == CP_MVGAUSS) {
     dim3 grid((a.W + kFitTX - 1) / kFitTX, (a.H + kFitTY - 1) / kFitTY);

@@ -1,0 +1,133 @@
+// cp_gauss.hpp -- independent Gaussian model (the parametric comparison
+// model of Sec. 5.2: per-vertex N(mu, sigma^2) from the member mean and
+// standard deviation).
+//
+// The paper notes that the Gaussian has no closed form (Sec. 4.3) and samples
+// it by Monte Carlo.  Here the 1-D integrals of Eq. 3 / Eq. 4,
+//   P_min = int phi_v S_e S_n S_w S_s,  P_max = int phi_v F_e F_n F_w F_s,
+//   t1 = int phi_v S_e F_n S_w F_s,     t2 = int phi_v F_e S_n F_w S_s,
+// are evaluated deterministically in one sweep.  Coordinates are in units of
+// the vertex: t = (x - mu_v) / sigma_v, so phi_v dt is the standard normal
+// and neighbour n enters through z_n = (t - d_n) r_n with
+// d_n = (mu_n - mu_v) / sigma_v and r_n = sigma_v / sigma_n.
+// The sweep covers t in [-C, C] (the rest of phi weighs 2e-9 for C = 6 and
+// 1.3e-17 for C = 8.5) and cuts it at the points d_n + c_k / r_n of every
+// neighbour and c_k of the vertex, c_k running over K fixed multiples of the
+// standard deviation in [-C, C].  Every panel therefore spans at most
+// ~2 (FP32) or ~1.5 (FP64) standard deviations of every distribution that
+// varies on it, and a fixed Gauss-Legendre rule of N nodes integrates it to
+// ~1e-8 (FP32: C = 6, c = 0, +-2, +-4, +-6, N = 6) or ~1e-14 (FP64:
+// C = 8.5, c = 0, +-1.5, +-3, +-4.5, +-6, +-8.5, N = 10) absolute over the
+// whole integral.  S and F come from one erfc of |z|, so both tails keep full
+// relative precision.  The cuts are merged on the fly by one cursor per
+// distribution (each sequence is already sorted), as in the histogram sweep.
+#pragma once
+
+#include <cmath>
+
+#include "cp_device.hpp"
+
+namespace cp {
+
+template <typename T>
+struct GaussRule;
+template <>
+struct GaussRule<float> {
+  static constexpr int K = 7, N = 6;
+  static constexpr float c[7] = {-6.f, -4.f, -2.f, 0.f, 2.f, 4.f, 6.f};
+};
+template <>
+struct GaussRule<double> {
+  static constexpr int K = 11, N = 10;
+  static constexpr double c[11] = {-8.5, -6.0, -4.5, -3.0, -1.5, 0.0, 1.5, 3.0, 4.5, 6.0, 8.5};
+};
+
+CP_HD float gerfc(float x) { return erfcf(x); }
+CP_HD double gerfc(double x) { return erfc(x); }
+CP_HD float gexp(float x) { return expf(x); }
+CP_HD double gexp(double x) { return exp(x); }
+
+// out = (P_min, P_max, t1, t2) of a vertex with valid parameters; neighbour
+// order e, n, w, s; absent neighbours contribute 1; the saddle terms are
+// computed only when `interior` (all four present) and are 0 otherwise.
+template <typename T>
+CP_HD void gauss_vertex(T mv, T sv, const T (&mn)[4], const T (&sn)[4], const bool (&pres)[4], T (&out)[4]) {
+  using R = GaussRule<T>;
+  constexpr int K = R::K, N = R::N;
+  constexpr T C = R::c[K - 1];
+  const T big = T(4) * C;  // beyond every panel end
+  const T isv = crcp(sv);
+  T d[4], s[4], r[4], nx[4];
+  int k[4];
+#pragma unroll
+  for (int n = 0; n < 4; ++n) {
+    d[n] = (mn[n] - mv) * isv;
+    s[n] = sn[n] * isv;
+    r[n] = sv * crcp(sn[n]);
+    k[n] = 0;
+    nx[n] = pres[n] ? cfma(T(R::c[0]), s[n], d[n]) : big;
+    // skip the cuts at or below the window start
+    for (int q = 0; q < K && pres[n] && !(nx[n] > -C); ++q) {
+      k[n] += 1;
+      nx[n] = k[n] < K ? cfma(T(R::c[k[n]]), s[n], d[n]) : big;
+    }
+  }
+  int kv = 1;
+  T nv = T(R::c[1]);
+  T x0 = -C;
+  T acc[4] = {T(0), T(0), T(0), T(0)};
+  constexpr T rs2 = T(0.70710678118654752440);
+  for (int it = 0; it < 5 * K; ++it) {
+    if (!(x0 < C)) break;
+    T x1 = nv;
+#pragma unroll
+    for (int n = 0; n < 4; ++n) x1 = tmin(x1, nx[n]);
+    const T mid = (x0 + x1) * T(0.5), hl = (x1 - x0) * T(0.5);
+    T p[4] = {T(0), T(0), T(0), T(0)};
+#pragma unroll
+    for (int j = 0; j < N; ++j) {
+      const T t = cfma(hl, T(GL<N>::x[j]), mid);
+      const T phi = T(GL<N>::w[j]) * gexp(T(-0.5) * t * t);
+      T q0 = phi, q1 = phi, q2 = phi, q3 = phi;
+#pragma unroll
+      for (int n = 0; n < 4; ++n) {
+        if (!pres[n]) continue;
+        const T z = (t - d[n]) * r[n];
+        const T e = T(0.5) * gerfc(fabs(z) * rs2);
+        const T S = z > T(0) ? e : T(1) - e;
+        const T F = z > T(0) ? T(1) - e : e;
+        q0 *= S;
+        q1 *= F;
+        // e, w (n = 0, 2) take S in t1 and F in t2; n, s the reverse
+        q2 *= (n & 1) ? F : S;
+        q3 *= (n & 1) ? S : F;
+      }
+      p[0] += q0;
+      p[1] += q1;
+      p[2] += q2;
+      p[3] += q3;
+    }
+#pragma unroll
+    for (int q = 0; q < 4; ++q) acc[q] = cfma(p[q], hl, acc[q]);
+    // advance every cursor that sits at x1
+    if (nv == x1) {
+      kv += 1;
+      nv = kv < K ? T(R::c[kv]) : big;
+    }
+#pragma unroll
+    for (int n = 0; n < 4; ++n)
+      if (nx[n] == x1) {
+        k[n] += 1;
+        nx[n] = k[n] < K ? cfma(T(R::c[k[n]]), s[n], d[n]) : big;
+      }
+    x0 = x1;
+  }
+  constexpr T inv_sqrt_2pi = T(0.39894228040143267794);
+  const bool interior = pres[0] && pres[1] && pres[2] && pres[3];
+  out[0] = acc[0] * inv_sqrt_2pi;
+  out[1] = acc[1] * inv_sqrt_2pi;
+  out[2] = interior ? acc[2] * inv_sqrt_2pi : T(0);
+  out[3] = interior ? acc[3] * inv_sqrt_2pi : T(0);
+}
+
+}  // namespace cp

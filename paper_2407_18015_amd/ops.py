@@ -14,7 +14,7 @@ import torch
 from . import _lib as L
 
 MODELS = {"uniform": L.CP_UNIFORM, "epanechnikov": L.CP_EPANECHNIKOV, "histogram": L.CP_HISTOGRAM,
-          "mvg": L.CP_MVGAUSS}
+          "mvg": L.CP_MVGAUSS, "gaussian": L.CP_GAUSSIAN}
 
 
 def model_id(model) -> int:

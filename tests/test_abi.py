@@ -36,7 +36,7 @@ def test_struct_layouts_match_header():
     assert ctypes.sizeof(L.cp_fit_opts_t) == 32
 
 
-@pytest.mark.parametrize("n", [1, 2, 3, 5, 6, 8])
+@pytest.mark.parametrize("n", [1, 2, 3, 5, 6, 8, 10])
 def test_gauss_legendre_tables(n):
     """The device rules against numpy's Gauss-Legendre (Golub-Welsch)."""
     x, w = L.cp_gauss_legendre(n)

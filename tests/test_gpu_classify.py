@@ -3,7 +3,8 @@ probabilities, Eq. 3 and Eq. 4) against the FP64 oracle, through the C ABI.
 
 Tolerances as for the forward: 1e-6 absolute in FP32, 1e-12 in FP64 for
 P_min, P_max and each saddle term; P_regular is a sum of four such values,
-so 4x that.
+so 4x that.  The independent Gaussian model (no closed form) is held to the
+same tolerances: its quadrature error is ~1e-8 (FP32) and ~1e-14 (FP64).
 """
 import sys
 
@@ -202,3 +203,103 @@ def test_classify_full_size_epanechnikov_sampled():
     close(host(out["max"]).ravel()[idx], rmax, 1e-6, "P_max")
     total = out["min"] + out["max"] + out["saddle"] + out["regular"]
     assert torch.allclose(total, torch.ones_like(total), atol=1e-6, rtol=0)
+
+
+# ----------------------------------------------------------------------------
+# independent Gaussian (deterministic quadrature; tolerances as above)
+# ----------------------------------------------------------------------------
+G = L.CP_GAUSSIAN
+
+
+def gauss_params(seed, H, W, mixed=True):
+    rng = np.random.default_rng(seed)
+    mu = rng.normal(0, 0.05, (H, W))
+    sg = 10 ** rng.uniform(-3, -0.5, (H, W)) if mixed else np.full((H, W), 0.02) * 10 ** rng.uniform(-0.2, 0.2, (H, W))
+    return np.stack([mu, sg])
+
+
+def gauss_ref(p):
+    r = oracle.gauss(p)
+    return r[0], r[1], r[2], r[3], 1.0 - r[0] - r[1] - r[2] - r[3]
+
+
+@pytest.mark.parametrize("mixed", [True, False])
+@pytest.mark.parametrize("dtype", [torch.float32, torch.float64])
+def test_gaussian_classify_ragged(dtype, mixed):
+    """131x197, sigmas spanning 2.5 decades (mixed) or nearly equal."""
+    note("gaussian classify", dtype, "mixed" if mixed else "equal")
+    pt = dev(gauss_params(3 + mixed, 131, 197, mixed), dtype)
+    out = cp.classify(pt, cp.field_of(pt, G), terms=True)
+    rmin, rmax, r1, r2, rreg = gauss_ref(host(pt))
+    tol = TOL[dtype]
+    close(host(out["min"]), rmin, tol, "P_min")
+    close(host(out["max"]), rmax, tol, "P_max")
+    close(host(out["terms"][0]), r1, tol, "t1")
+    close(host(out["terms"][1]), r2, tol, "t2")
+    close(host(out["regular"]), rreg, 4 * tol, "P_regular")
+
+
+def test_gaussian_fit_and_forward():
+    """GPU fit (mean, std with ddof = 1) against the oracle's, then the
+    forward of the fitted field; forward equals the classification's P_min /
+    P_max bit for bit."""
+    note("gaussian fit + forward 160x210")
+    mem = workloads.smooth_ensemble(6, 160, 210)
+    params = cp.fit(dev(mem, torch.float32), G)
+    ref = oracle.fit(G, mem.astype(np.float64))
+    np.testing.assert_allclose(host(params)[0], ref[0], rtol=0, atol=2e-7 * (1 + np.abs(ref[0]).max()))
+    np.testing.assert_allclose(host(params)[1], ref[1], rtol=5e-7)
+    f = cp.field_of(params, G)
+    pmin, pmax = cp.forward(params, f)
+    rmin, rmax, _, _, _ = gauss_ref(host(params))
+    close(host(pmin), rmin, 1e-6, "P_min")
+    close(host(pmax), rmax, 1e-6, "P_max")
+    out = cp.classify(params, f, outputs=("min", "max"))
+    assert torch.equal(out["min"], pmin) and torch.equal(out["max"], pmax)
+
+
+@pytest.mark.parametrize("shape", [(1, 1), (1, 2), (2, 1), (2, 2), (3, 3), (3, 67), (67, 3), (4, 65)])
+def test_gaussian_edge_shapes(shape):
+    note("gaussian edge shape", shape)
+    H, W = shape
+    pt = dev(gauss_params(9, H, W), torch.float64)
+    out = cp.classify(pt, cp.field_of(pt, G), terms=True)
+    rmin, rmax, r1, r2, _ = gauss_ref(host(pt))
+    close(host(out["min"]), rmin, 1e-12, "P_min")
+    close(host(out["max"]), rmax, 1e-12, "P_max")
+    close(host(out["terms"][0]), r1, 1e-12, "t1")
+    close(host(out["terms"][1]), r2, 1e-12, "t2")
+
+
+def test_gaussian_invalid_and_unsupported():
+    H, W = 9, 12
+    p = gauss_params(1, H, W)
+    p[1, 4, 5] = 0.0  # sigma must be > 0
+    pt = dev(p, torch.float32)
+    f = cp.field_of(pt, G)
+    out = cp.classify(pt, f)
+    bad = np.zeros((H, W), bool)
+    for dy, dx in ((0, 0), (0, 1), (-1, 0), (0, -1), (1, 0)):
+        bad[4 + dy, 5 + dx] = True
+    assert np.array_equal(np.isnan(host(out["min"])), bad)
+    g = torch.zeros((H, W), device="cuda")
+    with pytest.raises(L.CPError) as ei:
+        cp.backward(pt, g, g, f)
+    assert ei.value.status == L.CP_EUNSUPPORTED
+
+
+def test_gaussian_full_size_sampled():
+    """2048 x 2048 fitted from the 20-member ensemble, FP32: 3000 sampled
+    vertices against the oracle."""
+    note("gaussian 2048^2 sampled")
+    H = W = 2048
+    mem = workloads.smooth_ensemble(0, H, W)
+    params = cp.fit(dev(mem, torch.float32), G)
+    del mem
+    out = cp.classify(params, cp.field_of(params, G), terms=True)
+    idx = np.random.default_rng(8).choice(H * W, 3000, replace=False)
+    ref = oracle.gauss_at(host(params), idx)
+    close(host(out["min"]).ravel()[idx], ref[:, 0], 1e-6, "P_min")
+    close(host(out["max"]).ravel()[idx], ref[:, 1], 1e-6, "P_max")
+    close(host(out["terms"][0]).ravel()[idx], ref[:, 2], 1e-6, "t1")
+    close(host(out["terms"][1]).ravel()[idx], ref[:, 3], 1e-6, "t2")
