@@ -25,7 +25,43 @@ import numpy as np
 
 METRIC = "vertex-probabilities/s (fwd, fwd+bwd) per model; batched vs plain at 1e-6 abs err"
 UNIT = "vertex-probabilities/s"
-PEAK_FP32_VALU = 157.3e12  # FLOP/s, MI355X dense vector FP32 (packed issue)
+# FP32 vector peak reachable without packed FP32 (v_pk_* is not generated on
+# this platform): 256 CUs x 64 lanes x 2 FLOP (FMA) x 2.4 GHz.  The published
+# 157.3 TFLOP/s counts the packed two-wide FMA.
+PEAK_FP32_VALU = 256 * 64 * 2 * 2.4e9
+PEAK_FP32_PACKED = 157.3e12
+
+# HBM bytes of one launch of the Epanechnikov FP32 adjoint at 2048^2, from
+# two rocprofv3 --pmc passes (FETCH_SIZE, WRITE_SIZE, KiB per dispatch) over
+# `bench.py --profile-only`, each scaled by the same counter on a plain
+# 256 MiB copy (FETCH_SIZE read 128 MiB: x2; WRITE_SIZE 256 MiB: x1).  They
+# describe the kernel built from the sources fingerprinted here and are
+# reported as null once any of them changes.
+ADJOINT_PMC = {
+    "fetch_kib": 33287.5, "write_kib": 32777.5, "fetch_scale": 2.0, "write_scale": 1.0, "grid": [2048, 2048],
+    "sources": ["paper_2407_18015_amd/csrc/cp_closed_form.hip", "paper_2407_18015_amd/csrc/cp_tiles.hpp",
+                "paper_2407_18015_amd/csrc/cp_device.hpp", "paper_2407_18015_amd/csrc/cp_hist.hpp",
+                "paper_2407_18015_amd/csrc/cp_hist_bwd.hpp", "paper_2407_18015_amd/csrc/cp_internal.hpp",
+                "include/cpcrit.h"],
+    "sha256": "2c35347c17dcfe47ca6f860e1cb4e3e1c20240fcdff550b60f8e62ec9ee93249",
+}
+
+
+def sources_sha256(paths) -> str:
+    import hashlib
+    h = hashlib.sha256()
+    root = os.path.dirname(os.path.abspath(__file__))
+    for p in paths:
+        with open(os.path.join(root, p), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()
+
+
+def adjoint_traffic(size: int = 2048):
+    m = ADJOINT_PMC
+    if [size, size] != m["grid"] or sources_sha256(m["sources"]) != m["sha256"]:
+        return None
+    return (m["fetch_kib"] * m["fetch_scale"] + m["write_kib"] * m["write_scale"]) * 1024
 
 
 def parse():
@@ -42,7 +78,9 @@ def parse():
 
 
 # ----------------------------------------------------------------------------
-# algorithmic work of the Epanechnikov kernels (roofline)
+# algorithmic work of the Epanechnikov kernels: FLOPs per non-empty piece with
+# k started neighbours at the exact quadrature order (FMA = 2); redundant work
+# (empty pieces, halo ring, masked lanes) is not counted
 # ----------------------------------------------------------------------------
 GL_NODES = {1: 3, 2: 5, 3: 6, 4: 8}  # exact rule for a piece with k started neighbours
 
@@ -100,8 +138,9 @@ def epa_flops(params: np.ndarray):
 def main():
     args = parse()
     if args.gpus != 1:
-        print("bench.py measures one GPU: this build has no multi-GPU path (fields shard by rows or by "
-              "field with no communication; see DESIGN.md).  Run with --gpus 1.", file=sys.stderr)
+        print("bench.py measures one GPU: there is no multi-GPU path (a field shards by rows with a "
+              "one- or two-row halo, a batch by field with no communication).  Run with --gpus 1.",
+              file=sys.stderr)
         sys.exit(2)
     import torch
 
@@ -133,15 +172,24 @@ def main():
     for _ in range(args.warmup):
         step()
     torch.cuda.synchronize()
-    ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-    ev0.record()
-    for _ in range(args.steps):
-        step()
-    ev1.record()
+    # timed region: K steps, each stage bracketed by HIP events on the stream
+    # the kernels run on (torch's current stream), so per-kernel durations are
+    # measured inside the step sequence (cold caches after the member reads)
+    evs = [[torch.cuda.Event(enable_timing=True) for _ in range(4)] for _ in range(args.steps)]
+    for e in evs:
+        e[0].record()
+        cp.fit(mem, E, out=params)
+        e[1].record()
+        cp.forward(params, f, pmin, pmax)
+        e[2].record()
+        cp.backward(params, gmin, gmax, f, grad)
+        e[3].record()
     torch.cuda.synchronize()
-    ms = ev0.elapsed_time(ev1) / args.steps
+    ms = evs[0][0].elapsed_time(evs[-1][3]) / args.steps
+    t_fit, t_fwd, t_bwd = (sum(e[k].elapsed_time(e[k + 1]) for e in evs) / args.steps for k in range(3))
     value = S * S / (ms * 1e-3)
-    print(f"[bench] step {ms:.3f} ms", file=sys.stderr, flush=True)
+    print(f"[bench] step {ms:.3f} ms (fit {t_fit * 1e3:.1f} us, forward {t_fwd * 1e3:.1f} us, "
+          f"adjoint {t_bwd * 1e3:.1f} us)", file=sys.stderr, flush=True)
     if args.profile_only:
         # a plain copy of known size (256 MiB read + 256 MiB written): the
         # reference that scales the HBM byte counters of the kernels above
@@ -163,17 +211,17 @@ def main():
         return a.elapsed_time(b) / reps
 
     reps = max(5, args.steps)
-    t_fit = timed(lambda: cp.fit(mem, E, out=params), reps)
-    t_fwd = timed(lambda: cp.forward(params, f, pmin, pmax), reps)
-    t_bwd = timed(lambda: cp.backward(params, gmin, gmax, f, grad), reps)
     t_cls = timed(lambda: cp.classify(params, f), reps)
     t_sad = timed(lambda: cp.classify(params, f, outputs=("saddle",)), reps)
     ph = params.cpu().numpy()
     fl_fwd, fl_bwd, counts = epa_flops(ph)
-    roof = {"bound": "alu", "kernel": "adjoint, Epanechnikov FP32 (k_bwd_ue)", "achieved": fl_bwd / (t_bwd * 1e-3) / 1e12,
-            "peak": PEAK_FP32_VALU / 1e12, "unit": "TFLOP/s",
-            "frac": fl_bwd / (t_bwd * 1e-3) / PEAK_FP32_VALU, "traffic": None,
-            "algorithmic_flops_per_launch": fl_bwd}
+    achieved = fl_bwd / (t_bwd * 1e-3)
+    roof = {"bound": "alu", "kernel": "adjoint, Epanechnikov FP32 (k_bwd_ue<float,1,30,30>)",
+            "achieved": achieved / 1e12, "peak": PEAK_FP32_VALU / 1e12, "unit": "TFLOP/s",
+            "frac": achieved / PEAK_FP32_VALU, "traffic": adjoint_traffic(S),
+            "algorithmic_flops_per_launch": fl_bwd, "launch_us": t_bwd * 1e3,
+            "peak_packed": PEAK_FP32_PACKED / 1e12, "frac_packed": achieved / PEAK_FP32_PACKED,
+            "algorithmic_bytes_per_launch": 24 * S * S}
     detail = {
         "epanechnikov_2048": {
             "fit_ms": t_fit, "fwd_ms": t_fwd, "bwd_ms": t_bwd,

@@ -212,8 +212,11 @@ cp_status_t cp_prob_classify(const cp_field_desc_t* desc, const void* params, vo
  * CP_BATCH_FWD, g_min/g_max/grad_params unless CP_BATCH_BWD.  Results equal
  * those of cp_prob_forward / cp_prob_backward on each field.  The graph cache
  * is keyed by the field shapes; each call refreshes the descriptor table
- * (pointers may change between calls).  Multivariate Gaussian fields are not
- * accepted here (CP_EUNSUPPORTED).
+ * (pointers may change between calls).  Calls with the same shapes share one
+ * plan, including its device-side tile queue: they must not execute
+ * concurrently (e.g. on two streams without ordering between them).
+ * Gaussian fields (CP_MVGAUSS, CP_GAUSSIAN) are not accepted here
+ * (CP_EUNSUPPORTED).
  */
 cp_status_t cp_prob_batched(int32_t n, const cp_field_desc_t* descs, const void* const* params,
                             void* const* p_min, void* const* p_max, const void* const* g_min,

@@ -89,6 +89,14 @@ def cpu_fit_params(desc, members, n_members, opts, params, stream) -> int:
                                  params, stream)
 
 
+def cp_fit_error_bound(desc, decompressed, eb, params, stream) -> int:
+    return load().cp_fit_error_bound(ctypes.byref(desc), decompressed, eb, params, stream)
+
+
+def cp_prob_classify(desc, params, p_min, p_max, p_saddle, p_regular, terms, stream) -> int:
+    return load().cp_prob_classify(ctypes.byref(desc), params, p_min, p_max, p_saddle, p_regular, terms, stream)
+
+
 def cp_prob_forward(desc, params, p_min, p_max, stream) -> int:
     return load().cp_prob_forward(ctypes.byref(desc), params, p_min, p_max, stream)
 

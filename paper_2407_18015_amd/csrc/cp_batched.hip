@@ -2,19 +2,24 @@
 // in one persistent launch per pass.
 //
 // Small fields under-fill 256 CUs when launched one by one (a 128^2 field is
-// 64 forward tiles); the batched form flattens every field into tiles, deals
-// the tiles to a grid of resident blocks by a longest-processing-time rule
-// over a per-vertex cost model, and lets each block walk its own list.  The
-// tile lists depend only on the shapes, so they are built and uploaded once
-// per shape signature; the field table (data pointers) is refreshed only when
-// a pointer changes.  With CP_BATCH_GRAPH the launches are captured once per
+// 64 forward tiles); the batched form flattens every field into tiles, orders
+// them by a per-vertex cost model (most expensive first, then field and row
+// order) and lets a grid of resident blocks take them from a device-side
+// queue: block after block claims the next tile with one atomic, so blocks
+// that draw cheap tiles simply take more of them.  The last block to leave
+// resets the queue, so every launch (and every graph replay) starts from a
+// zeroed counter without a memset.  The tile lists depend only on the
+// shapes, so they are built and uploaded once per shape signature; the field
+// table (data pointers) is refreshed only when a pointer changes.  With CP_BATCH_GRAPH the launches are captured once per
 // signature into a HIP graph and replayed.
 //
-// Forward-only and adjoint plans use separate kernel instantiations (each
-// carries only the register budget of its own tile routines).  Histogram
-// adjoint tiles write their per-stencil Jacobians to a workspace owned by the
-// plan, and a second persistent launch gathers them; forward values are
-// written by the adjoint tiles when both are requested.
+// Every pass is its own kernel instantiation and persistent launch: histogram
+// tiles and uniform / Epanechnikov tiles run in separate passes, so each
+// carries only the registers and LDS of its own tile routine (the latency-
+// bound histogram sweep keeps the occupancy of its per-field kernel).
+// Histogram adjoint tiles write their per-stencil Jacobians to a workspace
+// owned by the plan, and a last pass gathers them; forward values are written
+// by the adjoint tiles when both are requested.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -22,7 +27,6 @@
 #include <map>
 #include <memory>
 #include <mutex>
-#include <queue>
 #include <vector>
 
 #include "cp_hist_bwd.hpp"
@@ -38,11 +42,10 @@ constexpr int kBwdF32 = 30, kBwdF64 = 14;  // uniform / Epanechnikov adjoint til
 constexpr int kGatherChunk = 256;          // histogram gather: vertices per tile
 constexpr size_t kMaxLds = 160 * 1024;
 
-enum { KIND_FWD = 0, KIND_BWD = 1, KIND_GATHER = 2 };
-enum { PASS_FWD = 0, PASS_BWD = 1, PASS_GATHER = 2 };
+enum { PASS_FWD_UE = 0, PASS_FWD_HIST = 1, PASS_BWD_UE = 2, PASS_BWD_HIST = 3, PASS_GATHER = 4, NPASS = 5 };
 
 struct BatchTile {
-  int field, ty0, tx0, kind;  // gather tiles: ty0 = first flat vertex index
+  int field, ty0, tx0, pad;  // gather tiles: ty0 = first flat vertex index
 };
 
 template <typename T>
@@ -74,34 +77,69 @@ __device__ __forceinline__ void hist_gather_chunk(const FieldPtrs<T>& f, const T
   }
 }
 
+// The FP32 histogram forward pass keeps the 5 waves per SIMD of its per-field
+// kernel (the tile loop would otherwise push it one register over).
 template <typename T, int PASS>
-__global__ __launch_bounds__(kNT) void k_batched(const BatchField<T>* __restrict__ fields,
-                                                 const BatchTile* __restrict__ tiles, const int* __restrict__ start) {
+constexpr int batched_min_waves() {
+  return sizeof(T) == 4 && PASS == PASS_FWD_HIST ? 5 : 1;
+}
+
+// Tiles are claimed in chunks of `chunk` consecutive entries (neighbouring
+// tiles of one field, so halo lines are reused in the claiming CU's L2).
+// queue[0]: next unclaimed chunk; queue[1]: blocks that have left.  The claim
+// of the next chunk is issued before the current one is processed, so its
+// latency overlaps the tile's own loads.  Every block leaves once the counter
+// has passed the last chunk (the loop ends for all).
+template <typename T, int PASS>
+__global__ __launch_bounds__(kNT, (batched_min_waves<T, PASS>())) void k_batched(
+    const BatchField<T>* __restrict__ fields, const BatchTile* __restrict__ tiles, int ntiles, int chunk,
+    int* queue) {
   extern __shared__ __align__(16) unsigned char smem[];
+  __shared__ int claimed;
   T* lds = reinterpret_cast<T*>(smem);
   const int tid = threadIdx.x;
-  const int b = blockIdx.x;
-  const int t1 = start[b + 1];
-  for (int t = start[b]; t < t1; ++t) {
-    const BatchTile tl = tiles[t];
-    const BatchField<T> F = fields[tl.field];
-    if (PASS == PASS_FWD) {
-      if (F.model == CP_UNIFORM)
-        tile_fwd_ue<T, CP_UNIFORM, 4>(F.p, tl.ty0, tl.tx0, lds, tid);
-      else if (F.model == CP_EPANECHNIKOV)
-        tile_fwd_ue<T, CP_EPANECHNIKOV, 4>(F.p, tl.ty0, tl.tx0, lds, tid);
-      else
+  constexpr int OB = sizeof(T) == 4 ? kBwdF32 : kBwdF64;
+  const int nchunks = (ntiles + chunk - 1) / chunk;
+  if (tid == 0) claimed = atomicAdd(&queue[0], 1);
+  __syncthreads();
+  int c = claimed;
+  __syncthreads();  // every thread has read `claimed` before it is rewritten
+  while (c < nchunks) {
+    int ahead = 0;
+    if (tid == 0) ahead = atomicAdd(&queue[0], 1);
+    const int t1 = min(ntiles, (c + 1) * chunk);
+    for (int t = c * chunk; t < t1; ++t) {
+      const BatchTile tl = tiles[t];
+      const BatchField<T> F = fields[tl.field];
+      if (PASS == PASS_FWD_UE) {
+        if (F.model == CP_UNIFORM)
+          tile_fwd_ue<T, CP_UNIFORM, 4>(F.p, tl.ty0, tl.tx0, lds, tid);
+        else
+          tile_fwd_ue<T, CP_EPANECHNIKOV, 4>(F.p, tl.ty0, tl.tx0, lds, tid);
+      } else if (PASS == PASS_FWD_HIST) {
         tile_fwd_hist<T, 4>(F.p, tl.ty0, tl.tx0, lds, tid);
-    } else if (PASS == PASS_BWD) {
-      constexpr int OB = sizeof(T) == 4 ? kBwdF32 : kBwdF64;
-      if (F.model == CP_UNIFORM)
-        tile_bwd_ue<T, CP_UNIFORM, OB, OB, kNT>(F.p, tl.ty0, tl.tx0, lds, tid);
-      else if (F.model == CP_EPANECHNIKOV)
-        tile_bwd_ue<T, CP_EPANECHNIKOV, OB, OB, kNT>(F.p, tl.ty0, tl.tx0, lds, tid);
-      else
+      } else if (PASS == PASS_BWD_UE) {
+        if (F.model == CP_UNIFORM)
+          tile_bwd_ue<T, CP_UNIFORM, OB, OB, kNT>(F.p, tl.ty0, tl.tx0, lds, tid);
+        else
+          tile_bwd_ue<T, CP_EPANECHNIKOV, OB, OB, kNT>(F.p, tl.ty0, tl.tx0, lds, tid);
+      } else if (PASS == PASS_BWD_HIST) {
         tile_hist_sweep<T, 4>(F.p, tl.ty0, tl.tx0, lds, tid, F.J);
-    } else {
-      hist_gather_chunk<T>(F.p, F.J, tl.ty0, tid);
+      } else {
+        hist_gather_chunk<T>(F.p, F.J, tl.ty0, tid);
+      }
+    }
+    if (tid == 0) claimed = ahead;
+    __syncthreads();
+    c = claimed;
+    __syncthreads();
+  }
+  if (tid == 0) {
+    __threadfence();
+    // the last block out has seen every claim: reset the queue for the next launch
+    if (atomicAdd(&queue[1], 1) == (int)gridDim.x - 1) {
+      atomicExch(&queue[0], 0);
+      atomicExch(&queue[1], 0);
     }
   }
 }
@@ -123,16 +161,19 @@ size_t tile_lds_bytes(int model, int nb, bool bwd, size_t el) {
 }
 
 struct Pass {
+  int kind = 0;
   int grid = 0;
   size_t lds = 0;
-  int* d_start = nullptr;
+  int ntiles = 0;
+  int chunk = 1;
+  int* d_queue = nullptr;  // 2 counters, zero between launches
   BatchTile* d_tiles = nullptr;
 };
 
 struct Plan {
   int dtype = 0;
   bool bwd = false;
-  Pass main, gather;  // gather.grid == 0: no histogram adjoint
+  std::vector<Pass> passes;  // launched in this order
   void* d_fields = nullptr;
   void* d_ws = nullptr;             // histogram Jacobians of all fields
   std::vector<size_t> ws_offset;    // bytes, per field (SIZE_MAX: none)
@@ -142,9 +183,9 @@ struct Plan {
   ~Plan() {
     if (exec) (void)hipGraphExecDestroy(exec);
     if (graph) (void)hipGraphDestroy(graph);
-    for (Pass* p : {&main, &gather}) {
-      if (p->d_start) (void)hipFree(p->d_start);
-      if (p->d_tiles) (void)hipFree(p->d_tiles);
+    for (Pass& p : passes) {
+      if (p.d_queue) (void)hipFree(p.d_queue);
+      if (p.d_tiles) (void)hipFree(p.d_tiles);
     }
     if (d_fields) (void)hipFree(d_fields);
     if (d_ws) (void)hipFree(d_ws);
@@ -165,18 +206,28 @@ hipError_t prepare_kernel(size_t lds, int* per_cu) {
   return hipOccupancyMaxActiveBlocksPerMultiprocessor(per_cu, k, kNT, lds);
 }
 
-hipError_t prepare(int dtype, int pass, size_t lds, int* per_cu) {
-  if (dtype == CP_F64) {
-    if (pass == PASS_FWD) return prepare_kernel<double, PASS_FWD>(lds, per_cu);
-    if (pass == PASS_BWD) return prepare_kernel<double, PASS_BWD>(lds, per_cu);
-    return prepare_kernel<double, PASS_GATHER>(lds, per_cu);
+template <typename T>
+hipError_t prepare_typed(int pass, size_t lds, int* per_cu) {
+  switch (pass) {
+    case PASS_FWD_UE:
+      return prepare_kernel<T, PASS_FWD_UE>(lds, per_cu);
+    case PASS_FWD_HIST:
+      return prepare_kernel<T, PASS_FWD_HIST>(lds, per_cu);
+    case PASS_BWD_UE:
+      return prepare_kernel<T, PASS_BWD_UE>(lds, per_cu);
+    case PASS_BWD_HIST:
+      return prepare_kernel<T, PASS_BWD_HIST>(lds, per_cu);
+    default:
+      return prepare_kernel<T, PASS_GATHER>(lds, per_cu);
   }
-  if (pass == PASS_FWD) return prepare_kernel<float, PASS_FWD>(lds, per_cu);
-  if (pass == PASS_BWD) return prepare_kernel<float, PASS_BWD>(lds, per_cu);
-  return prepare_kernel<float, PASS_GATHER>(lds, per_cu);
 }
 
-// Deal tiles to resident blocks (longest processing time first) and upload.
+hipError_t prepare(int dtype, int pass, size_t lds, int* per_cu) {
+  return dtype == CP_F64 ? prepare_typed<double>(pass, lds, per_cu) : prepare_typed<float>(pass, lds, per_cu);
+}
+
+// Order the tiles (most expensive first; field / row order among equals),
+// size the resident grid and upload.
 cp_status_t build_pass(const std::vector<BatchTile>& tiles, const std::vector<double>& cost, int dtype, int pass,
                        size_t lds, Pass& P) {
   int per_cu = 0;
@@ -186,31 +237,18 @@ cp_status_t build_pass(const std::vector<BatchTile>& tiles, const std::vector<do
   std::vector<int> order(tiles.size());
   for (size_t i = 0; i < order.size(); ++i) order[i] = (int)i;
   std::stable_sort(order.begin(), order.end(), [&](int a, int b) { return cost[a] > cost[b]; });
-  using Item = std::pair<double, int>;
-  std::priority_queue<Item, std::vector<Item>, std::greater<Item>> heap;
-  for (int b = 0; b < grid; ++b) heap.push({0.0, b});
-  std::vector<std::vector<int>> lists(grid);
-  for (int t : order) {
-    Item it = heap.top();
-    heap.pop();
-    lists[it.second].push_back(t);
-    heap.push({it.first + cost[t], it.second});
-  }
-  std::vector<int> start(grid + 1, 0);
   std::vector<BatchTile> flat;
   flat.reserve(tiles.size());
-  for (int b = 0; b < grid; ++b) {
-    start[b] = (int)flat.size();
-    std::sort(lists[b].begin(), lists[b].end());  // field / row order within a block
-    for (int t : lists[b]) flat.push_back(tiles[t]);
-  }
-  start[grid] = (int)flat.size();
+  for (int t : order) flat.push_back(tiles[t]);
+  P.kind = pass;
   P.grid = grid;
   P.lds = lds;
-  if (hipMalloc(&P.d_start, sizeof(int) * start.size()) != hipSuccess) return CP_ENOMEM;
+  P.ntiles = (int)flat.size();
+  // cheap tiles are claimed several at a time
+  P.chunk = pass == PASS_FWD_UE || pass == PASS_GATHER ? 4 : 1;
+  if (hipMalloc(&P.d_queue, 2 * sizeof(int)) != hipSuccess) return CP_ENOMEM;
+  if (hipMemset(P.d_queue, 0, 2 * sizeof(int)) != hipSuccess) return CP_EDEVICE;
   if (hipMalloc(&P.d_tiles, sizeof(BatchTile) * std::max<size_t>(flat.size(), 1)) != hipSuccess) return CP_ENOMEM;
-  if (hipMemcpy(P.d_start, start.data(), sizeof(int) * start.size(), hipMemcpyHostToDevice) != hipSuccess)
-    return CP_EDEVICE;
   if (!flat.empty() &&
       hipMemcpy(P.d_tiles, flat.data(), sizeof(BatchTile) * flat.size(), hipMemcpyHostToDevice) != hipSuccess)
     return CP_EDEVICE;
@@ -227,43 +265,48 @@ cp_status_t build_plan(int n, const Field* fs, bool bwd, Plan& P, const char** w
     if (hipDeviceGetAttribute(&g_num_cu, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess)
       return CP_EDEVICE;
   }
-  std::vector<BatchTile> tiles, gtiles;
-  std::vector<double> cost, gcost;
-  size_t lds = 0, ws = 0;
+  std::vector<BatchTile> tiles[NPASS];
+  std::vector<double> cost[NPASS];
+  size_t lds[NPASS] = {0, 0, 0, 0, 0}, ws = 0;
   P.ws_offset.assign(n, SIZE_MAX);
   for (int i = 0; i < n; ++i) {
     const Field& f = fs[i];
+    const bool hist = f.model == CP_HISTOGRAM;
+    const int pass = bwd ? (hist ? PASS_BWD_HIST : PASS_BWD_UE) : (hist ? PASS_FWD_HIST : PASS_FWD_UE);
     int ox = kFwdTX, oy = 4;
-    if (bwd && f.model != CP_HISTOGRAM) ox = oy = el == 4 ? kBwdF32 : kBwdF64;
-    lds = std::max(lds, tile_lds_bytes(f.model, f.nb, bwd, el));
+    if (pass == PASS_BWD_UE) ox = oy = el == 4 ? kBwdF32 : kBwdF64;
+    lds[pass] = std::max(lds[pass], tile_lds_bytes(f.model, f.nb, bwd, el));
     const double c = vertex_cost(f.model, f.nb, bwd) * ox * oy;
-    for (int ty = 0; ty < f.H; ty += oy)
-      for (int tx = 0; tx < f.W; tx += ox) {
-        tiles.push_back(BatchTile{i, ty, tx, bwd ? KIND_BWD : KIND_FWD});
-        cost.push_back(c);
+    // columns of tiles (a claimed chunk stacks vertically and shares halo rows)
+    for (int tx = 0; tx < f.W; tx += ox)
+      for (int ty = 0; ty < f.H; ty += oy) {
+        tiles[pass].push_back(BatchTile{i, ty, tx, 0});
+        cost[pass].push_back(c);
       }
-    if (bwd && f.model == CP_HISTOGRAM) {
+    if (pass == PASS_BWD_HIST) {
       const int64_t plane = (int64_t)f.H * f.W;
       P.ws_offset[i] = ws;
       ws += el * (size_t)5 * f.nb * plane;
       ws = (ws + 255) / 256 * 256;
       for (int64_t v = 0; v < plane; v += kGatherChunk) {
-        gtiles.push_back(BatchTile{i, (int)v, 0, KIND_GATHER});
-        gcost.push_back(1.0);
+        tiles[PASS_GATHER].push_back(BatchTile{i, (int)v, 0, 0});
+        cost[PASS_GATHER].push_back(1.0);
       }
     }
   }
-  if (lds > kMaxLds) {
-    *why = "batched: staged planes exceed the LDS of a workgroup (too many bins for this dtype)";
-    return CP_EUNSUPPORTED;
-  }
-  cp_status_t s = build_pass(tiles, cost, P.dtype, bwd ? PASS_BWD : PASS_FWD, lds, P.main);
-  if (s != CP_OK) return s;
-  if (!gtiles.empty()) {
-    s = build_pass(gtiles, gcost, P.dtype, PASS_GATHER, 0, P.gather);
+  for (int q = 0; q < NPASS; ++q)
+    if (lds[q] > kMaxLds) {
+      *why = "batched: staged planes exceed the LDS of a workgroup (too many bins for this dtype)";
+      return CP_EUNSUPPORTED;
+    }
+  // histogram passes first (the longest), the gather last (it reads their Jacobians)
+  for (int q : {PASS_FWD_HIST, PASS_BWD_HIST, PASS_FWD_UE, PASS_BWD_UE, PASS_GATHER}) {
+    if (tiles[q].empty()) continue;
+    P.passes.emplace_back();
+    cp_status_t s = build_pass(tiles[q], cost[q], P.dtype, q, lds[q], P.passes.back());
     if (s != CP_OK) return s;
-    if (hipMalloc(&P.d_ws, ws) != hipSuccess) return CP_ENOMEM;
   }
+  if (ws > 0 && hipMalloc(&P.d_ws, ws) != hipSuccess) return CP_ENOMEM;
   P.host_fields.clear();
   const size_t fb = (el == 4 ? sizeof(BatchField<float>) : sizeof(BatchField<double>)) * (size_t)n;
   if (hipMalloc(&P.d_fields, fb) != hipSuccess) return CP_ENOMEM;
@@ -300,17 +343,28 @@ void fill_fields(int n, const Field* fs, const Plan& P, const void* const* param
 template <typename T>
 hipError_t launch_typed(const Plan& P, hipStream_t st) {
   const auto* F = static_cast<const BatchField<T>*>(P.d_fields);
-  if (P.bwd)
-    hipLaunchKernelGGL((k_batched<T, PASS_BWD>), dim3(P.main.grid), dim3(kNT), P.main.lds, st, F, P.main.d_tiles,
-                       P.main.d_start);
-  else
-    hipLaunchKernelGGL((k_batched<T, PASS_FWD>), dim3(P.main.grid), dim3(kNT), P.main.lds, st, F, P.main.d_tiles,
-                       P.main.d_start);
-  hipError_t e = hipGetLastError();
-  if (e != hipSuccess || P.gather.grid == 0) return e;
-  hipLaunchKernelGGL((k_batched<T, PASS_GATHER>), dim3(P.gather.grid), dim3(kNT), 0, st, F, P.gather.d_tiles,
-                     P.gather.d_start);
-  return hipGetLastError();
+  for (const Pass& q : P.passes) {
+    const dim3 g(q.grid), b(kNT);
+    switch (q.kind) {
+      case PASS_FWD_UE:
+        hipLaunchKernelGGL((k_batched<T, PASS_FWD_UE>), g, b, q.lds, st, F, q.d_tiles, q.ntiles, q.chunk, q.d_queue);
+        break;
+      case PASS_FWD_HIST:
+        hipLaunchKernelGGL((k_batched<T, PASS_FWD_HIST>), g, b, q.lds, st, F, q.d_tiles, q.ntiles, q.chunk, q.d_queue);
+        break;
+      case PASS_BWD_UE:
+        hipLaunchKernelGGL((k_batched<T, PASS_BWD_UE>), g, b, q.lds, st, F, q.d_tiles, q.ntiles, q.chunk, q.d_queue);
+        break;
+      case PASS_BWD_HIST:
+        hipLaunchKernelGGL((k_batched<T, PASS_BWD_HIST>), g, b, q.lds, st, F, q.d_tiles, q.ntiles, q.chunk, q.d_queue);
+        break;
+      default:
+        hipLaunchKernelGGL((k_batched<T, PASS_GATHER>), g, b, q.lds, st, F, q.d_tiles, q.ntiles, q.chunk, q.d_queue);
+    }
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+  }
+  return hipSuccess;
 }
 
 hipError_t launch(const Plan& P, hipStream_t st) {

@@ -134,6 +134,17 @@ def test_error_bound_fit_validation():
         assert lib.cp_fit_error_bound(desc(), FAKE, eb, FAKE, None) == L.CP_EDOMAIN
 
 
+def test_binding_covers_every_call_of_the_torch_layer():
+    """Every L.<name> the torch layer calls exists in the binding module."""
+    import re
+    src = open(os.path.join(ROOT, "paper_2407_18015_amd", "ops.py")).read()
+    for name in set(re.findall(r"\bL\.(cp\w+)\(", src)):
+        assert callable(getattr(L, name, None)), name
+    for name in L.EXPORTS:
+        if name not in ("cp_status_string", "cp_last_error"):
+            assert callable(getattr(L, name, None)), name
+
+
 def test_status_strings():
     lib = L.load()
     for s in range(6):

@@ -386,7 +386,7 @@ def test_batched_forward_equals_per_field(graph):
     params = [p for _, p in fl]
     pmin = [torch.empty((f.height, f.width), device="cuda") for f in fields]
     pmax = [torch.empty((f.height, f.width), device="cuda") for f in fields]
-    for rep in range(3 if graph else 1):
+    for rep in range(3):
         for t in pmin + pmax:
             t.fill_(-1.0)
         cp.batched(fields, params, pmin=pmin, pmax=pmax, graph=graph)
@@ -424,6 +424,37 @@ def test_batched_forward_backward(graph):
         f, p = fl[i]
         r = oracle.forward(f.model, host(p))
         assert_close(host(pmin[i]), r[0], 1e-6, "oracle P_min")
+
+
+@pytest.mark.parametrize("graph", [False, True])
+def test_batched_many_tiles_back_to_back(graph):
+    """24 fields of 2^U[7,10] per side (tens of thousands of tiles, far more
+    than resident blocks, so every block claims many tiles from the queue);
+    four launches back to back without synchronising (each must start from
+    the queue reset by the previous one), then forward and adjoint equal the
+    per-field launches bit for bit."""
+    note("batched many tiles graph", graph)
+    fl = batched_fields(7, n=24, lo=7.0, hi=10.0)
+    fields = [f for f, _ in fl]
+    params = [p for _, p in fl]
+    nt = sum((f.height + 3) // 4 * ((f.width + 63) // 64) for f in fields)
+    assert nt > 10000, nt
+    pmin = [torch.full((f.height, f.width), -1.0, device="cuda") for f in fields]
+    pmax = [torch.full((f.height, f.width), -1.0, device="cuda") for f in fields]
+    for _ in range(4):
+        cp.batched(fields, params, pmin=pmin, pmax=pmax, graph=graph)
+    torch.cuda.synchronize()
+    for i, (f, p) in enumerate(fl):
+        a, b = cp.forward(p, f)
+        assert torch.equal(a, pmin[i]) and torch.equal(b, pmax[i]), i
+    gmin = [dev(workloads.upstream(i, f.height, f.width)[0], torch.float32) for i, f in enumerate(fields)]
+    gmax = [dev(workloads.upstream(i, f.height, f.width)[1], torch.float32) for i, f in enumerate(fields)]
+    grad = [torch.full_like(p, -1.0) for p in params]
+    for _ in range(3):
+        cp.batched(fields, params, None, None, gmin, gmax, grad, graph=graph)
+    torch.cuda.synchronize()
+    for i, (f, p) in enumerate(fl):
+        assert torch.equal(cp.backward(p, gmin[i], gmax[i], f), grad[i]), i
 
 
 def test_batched_pointer_refresh():

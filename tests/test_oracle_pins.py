@@ -198,7 +198,7 @@ def sample(model, par, n, rng):
     return lo + (b + rng.random(n)) * (hi - lo) / len(mass)
 
 
-SURVEY_STENCILS = {
+MIXED_STENCILS = {
     # (v, e, n, w, s)
     U: {"v": (0, 1), "e": (-0.5, 0.5), "n": (0.25, 1.25), "w": (0.5, 2.0), "s": (0.1, 0.9)},
     E: {"v": (0, 1), "e": (0.5, 1), "n": (-0.25, 0.75), "w": (1 / 3, 0.5), "s": (0.1, 2.0)},
@@ -212,7 +212,7 @@ def test_brute_force_monte_carlo(model):
     oracle within 4 binomial standard errors."""
     rng = np.random.default_rng(7 + model)
     nb = 3
-    d = SURVEY_STENCILS.get(model) or {
+    d = MIXED_STENCILS.get(model) or {
         "v": (0, 1, 0.5, 0.25, 0.25), "e": (-0.5, 0.5, 1 / 3, 1 / 3, 1 / 3),
         "n": (0.25, 1.25, 0.1, 0.6, 0.3), "w": (0.5, 2.0, 0.2, 0.3, 0.5), "s": (0.1, 0.9, 0.2, 0.2, 0.6)}
     pmin, pmax = centre(model, stencil_grid(model, d, nb if model == HST else 0))
@@ -728,7 +728,7 @@ def test_saddle_against_scipy_quadrature(model):
 def test_saddle_brute_force_monte_carlo(model):
     rng = np.random.default_rng(17 + model)
     nb = 3
-    d = SURVEY_STENCILS.get(model) or {
+    d = MIXED_STENCILS.get(model) or {
         "v": (0, 1, 0.5, 0.25, 0.25), "e": (-0.5, 0.5, 1 / 3, 1 / 3, 1 / 3),
         "n": (0.25, 1.25, 0.1, 0.6, 0.3), "w": (0.5, 2.0, 0.2, 0.3, 0.5), "s": (0.1, 0.9, 0.2, 0.2, 0.6)}
     t1, t2 = saddle_centre(model, stencil_grid(model, d, nb if model == HST else 0))
