@@ -43,17 +43,23 @@ ADJOINT_PMC = {
                 "paper_2407_18015_amd/csrc/cp_device.hpp", "paper_2407_18015_amd/csrc/cp_hist.hpp",
                 "paper_2407_18015_amd/csrc/cp_hist_bwd.hpp", "paper_2407_18015_amd/csrc/cp_internal.hpp",
                 "include/cpcrit.h"],
-    "sha256": "2c35347c17dcfe47ca6f860e1cb4e3e1c20240fcdff550b60f8e62ec9ee93249",
+    "sha256": "6b6294e04a1d24523b62d5a7223284a4b67bf6b50ff4a8fd2a1e296bac834df2",
 }
 
 
 def sources_sha256(paths) -> str:
+    """Fingerprint of the code in C/C++ sources: comments and whitespace are
+    dropped, so documentation edits do not count as a kernel change."""
     import hashlib
+    import re
     h = hashlib.sha256()
     root = os.path.dirname(os.path.abspath(__file__))
     for p in paths:
-        with open(os.path.join(root, p), "rb") as fh:
-            h.update(fh.read())
+        with open(os.path.join(root, p)) as fh:
+            text = fh.read()
+        text = re.sub(r"/\*.*?\*/", " ", text, flags=re.S)
+        text = re.sub(r"//[^\n]*", " ", text)
+        h.update(" ".join(text.split()).encode())
     return h.hexdigest()
 
 
