@@ -57,6 +57,8 @@ def _load():
         "or_jacobian_at": (i32, [i32, i32, i32, i32, P, i64, P, P, P]),
         "or_saddle_at": (i32, [i32, i32, i32, i32, P, i64, P, P, P]),
         "or_gauss_at": (i32, [i32, i32, P, i64, P, P]),
+        "or_semi_at": (i32, [i32, i32, i32, P, i32, ctypes.c_uint64, ctypes.c_uint32, i64, P, P]),
+        "or_semi_samples": (i32, [i32, i32, i32, P, i32, i32, i32, ctypes.c_uint64, ctypes.c_uint32, P]),
         "or_grad_at": (i32, [i32, i32, i32, i32, P, P, P, i64, P, P, i32]),
         "or_grad": (i32, [i32, i32, i32, i32, P, P, P, P, i32]),
         "or_fit": (i32, [i32, i32, P, i32, i32, i32, i32, i32, f64, f64, P]),
@@ -203,6 +205,27 @@ def gauss(params) -> np.ndarray:
     params = _f64(params)
     _, H, W = params.shape
     return gauss_at(params, np.arange(H * W)).T.reshape(4, H, W).copy()
+
+
+def semi_at(params, idx, nsamples: int, seed: int, field_id: int = 0) -> np.ndarray:
+    """Semianalytical histogram estimator (Sec. 4.4.2), params [2+h][H][W]:
+    [n][4] = (P_min, P_max, t1, t2) estimates from `nsamples` Philox samples
+    of each vertex histogram (saddle terms 0 off the interior)."""
+    params, H, W, nb = _grid(params, HISTOGRAM)
+    idx = np.ascontiguousarray(idx, dtype=np.int64)
+    out = np.empty((idx.size, 4))
+    _check(_load().or_semi_at(H, W, nb, _ptr(params), nsamples, seed, field_id, idx.size, _ptr(idx), _ptr(out)),
+           "semi_at")
+    return out
+
+
+def semi_samples(params, y: int, x: int, nsamples: int, seed: int, field_id: int = 0) -> np.ndarray:
+    """The sample positions the semianalytical estimator draws at (y, x)."""
+    params, H, W, nb = _grid(params, HISTOGRAM)
+    out = np.empty(nsamples)
+    _check(_load().or_semi_samples(H, W, nb, _ptr(params), y, x, nsamples, seed, field_id, _ptr(out)),
+           "semi_samples")
+    return out
 
 
 def fit_error_bound(decompressed, eb: float, single: bool = False) -> np.ndarray:

@@ -1121,3 +1121,116 @@ int or_gauss_at(int H, int W, const double* params, int64_t nidx, const int64_t*
   for (int64_t i = 0; i < nidx; ++i) gauss_vertex(&g, (int)(idx[i] / W), (int)(idx[i] % W), &out[4 * i]);
   return 0;
 }
+
+/* ------------------------------------------------------------------------ */
+/* semianalytical histogram estimator (Sec. 4.4.2)                            */
+/* ------------------------------------------------------------------------ */
+/*
+ * c samples x_i are drawn from the vertex histogram; for each sample the
+ * probabilities that the neighbours lie above / below it are closed-form
+ * (bin lookup plus the masses of the later / earlier bins), and their
+ * products are averaged:
+ *   P_min ~ T (1/c) sum_i prod_n S_n(x_i),   P_max ~ T (1/c) sum_i prod_n F_n(x_i),
+ *   t1 ~ T (1/c) sum_i S_e F_n S_w F_s(x_i), t2 likewise with S and F swapped,
+ * T = sum of the vertex masses (1 for a normalised histogram; with it the
+ * expectation equals the closed-form integral of Eq. 3 / Eq. 4 for
+ * unnormalised masses too).
+ * Sampling: sample i uses word (i mod 4) of Philox4x32-10 with counter
+ * (i / 4, y*W + x, field_id, 2) under key seed, u = ((word >> 8) + 1/2) 2^-24;
+ * r = u T; with C_k = m_0 + ... + m_{k-1}, the bin is
+ * j = #{k in 1..h-1 : C_k <= r}, the position in it
+ * f = (r - C_j) / m_j clamped to [0, 1] (0 when m_j = 0), and
+ * x = lo + Delta (j + f): the inverse of the histogram CDF.
+ */
+static void semi_vertex(const grid_t* g, int y, int x, int ns, uint64_t seed, uint32_t field_id, double out[4]) {
+  out[0] = out[1] = out[2] = out[3] = 0.0;
+  dist_t ds[NSLOT];
+  int pres[NSLOT];
+  for (int s = 0; s < NSLOT; ++s) {
+    int yy = y + SLOT_DY[s], xx = x + SLOT_DX[s];
+    pres[s] = yy >= 0 && yy < g->H && xx >= 0 && xx < g->W;
+    if (pres[s]) grid_dist(g, yy, xx, &ds[s]);
+  }
+  const dist_t* v = &ds[0];
+  int h = v->nb;
+  double C[MAXNB + 1];
+  C[0] = 0.0;
+  for (int k = 0; k < h; ++k) C[k + 1] = C[k] + d_mass(v, k);
+  double T = C[h];
+  uint32_t key[2] = {(uint32_t)seed, (uint32_t)(seed >> 32)};
+  uint32_t at = (uint32_t)((int64_t)y * g->W + x);
+  int interior = pres[1] && pres[2] && pres[3] && pres[4];
+  double acc[4] = {0, 0, 0, 0};
+  uint32_t words[4];
+  for (int i = 0; i < ns; ++i) {
+    if (i % 4 == 0) {
+      uint32_t ctr[4] = {(uint32_t)(i / 4), at, field_id, 2u};
+      or_philox4x32_10(ctr, key, words);
+    }
+    double r = u24(words[i % 4]) * T;
+    int j = 0;
+    for (int k = 1; k < h; ++k) j += C[k] <= r;
+    double mj = d_mass(v, j), f = 0.0;
+    if (mj > 0.0) {
+      f = (r - C[j]) / mj;
+      f = f < 0.0 ? 0.0 : (f > 1.0 ? 1.0 : f);
+    }
+    double xs = v->lo + v->delta * ((double)j + f);
+    double pmin = 1.0, pmax = 1.0, a = 1.0, b = 1.0;
+    for (int k = 1; k < NSLOT; ++k) {
+      if (!pres[k]) continue;
+      double S = d_point(&ds[k], K_SURV, xs), F = d_point(&ds[k], K_CDF, xs);
+      pmin *= S;
+      pmax *= F;
+      a *= (k == 1 || k == 3) ? S : F;
+      b *= (k == 1 || k == 3) ? F : S;
+    }
+    acc[0] += pmin;
+    acc[1] += pmax;
+    acc[2] += a;
+    acc[3] += b;
+  }
+  for (int q = 0; q < 4; ++q) out[q] = ns > 0 ? T * acc[q] / (double)ns : 0.0;
+  if (!interior) out[2] = out[3] = 0.0;
+}
+
+/* out [nidx][4] = (P_min, P_max, t1, t2) estimates at flat indices idx */
+int or_semi_at(int H, int W, int nb, const double* params, int ns, uint64_t seed, uint32_t field_id, int64_t nidx,
+               const int64_t* idx, double* out) {
+  if (H < 1 || W < 1 || nb < 1 || nb > MAXNB || ns < 0) return 1;
+  grid_t g = {OR_HISTOGRAM, H, W, nb, params};
+#pragma omp parallel for schedule(dynamic, 16)
+  for (int64_t i = 0; i < nidx; ++i)
+    semi_vertex(&g, (int)(idx[i] / W), (int)(idx[i] % W), ns, seed, field_id, &out[4 * i]);
+  return 0;
+}
+
+/* the first ns sample positions of vertex (y, x) (for checking the sampler) */
+int or_semi_samples(int H, int W, int nb, const double* params, int y, int x, int ns, uint64_t seed,
+                    uint32_t field_id, double* xs) {
+  if (H < 1 || W < 1 || nb < 1 || nb > MAXNB || ns < 0 || y < 0 || y >= H || x < 0 || x >= W) return 1;
+  grid_t g = {OR_HISTOGRAM, H, W, nb, params};
+  dist_t v;
+  grid_dist(&g, y, x, &v);
+  double C[MAXNB + 1];
+  C[0] = 0.0;
+  for (int k = 0; k < nb; ++k) C[k + 1] = C[k] + d_mass(&v, k);
+  uint32_t key[2] = {(uint32_t)seed, (uint32_t)(seed >> 32)};
+  uint32_t words[4];
+  for (int i = 0; i < ns; ++i) {
+    if (i % 4 == 0) {
+      uint32_t ctr[4] = {(uint32_t)(i / 4), (uint32_t)((int64_t)y * W + x), field_id, 2u};
+      or_philox4x32_10(ctr, key, words);
+    }
+    double r = u24(words[i % 4]) * C[nb];
+    int j = 0;
+    for (int k = 1; k < nb; ++k) j += C[k] <= r;
+    double mj = d_mass(&v, j), f = 0.0;
+    if (mj > 0.0) {
+      f = (r - C[j]) / mj;
+      f = f < 0.0 ? 0.0 : (f > 1.0 ? 1.0 : f);
+    }
+    xs[i] = v.lo + v.delta * ((double)j + f);
+  }
+  return 0;
+}

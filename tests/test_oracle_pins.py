@@ -977,3 +977,71 @@ def test_gauss_fit_against_numpy():
     par = oracle.fit(G, mem.astype(np.float64))
     np.testing.assert_allclose(par[0], mem.astype(np.float64).mean(0), rtol=1e-14, atol=1e-15)
     np.testing.assert_allclose(par[1], mem.astype(np.float64).std(0, ddof=1), rtol=1e-12)
+
+
+# ----------------------------------------------------------------------------
+# semianalytical histogram estimator (Sec. 4.4.2)
+# ----------------------------------------------------------------------------
+def test_semi_sampler_is_the_inverse_histogram_cdf():
+    """The estimator's sample positions are the histogram's inverse CDF at
+    the Philox uniforms ((word >> 8) + 1/2) 2^-24 of counter
+    (i // 4, y*W + x, field_id, 2): recomputed with numpy's piecewise-linear
+    interpolation of the cumulative masses."""
+    par = workloads.random_params(HST, 5, 4, 5, nbins=7, width=0.1)
+    y, x, ns, seed, fid = 2, 3, 64, 0x1234_5678_9ABC, 7
+    xs = oracle.semi_samples(par, y, x, ns, seed, fid)
+    lo, hi, m = par[0, y, x], par[1, y, x], par[2:, y, x]
+    C = np.concatenate([[0.0], np.cumsum(m)])
+    edges = lo + (hi - lo) * np.arange(len(m) + 1) / len(m)
+    key = np.array([seed & 0xFFFFFFFF, seed >> 32], dtype=np.uint32)
+    for i in range(ns):
+        w = oracle.philox4x32_10([i // 4, y * 5 + x, fid, 2], key)[i % 4]
+        u = ((int(w) >> 8) + 0.5) / 2.0 ** 24
+        assert xs[i] == pytest.approx(np.interp(u * C[-1], C, edges), abs=1e-13)
+
+
+def test_semi_samples_follow_the_histogram():
+    """Kolmogorov-Smirnov: 20000 samples against the histogram CDF."""
+    par = workloads.random_params(HST, 9, 3, 3, nbins=5, width=0.2)
+    xs = oracle.semi_samples(par, 1, 1, 20000, seed=3)
+    lo, hi, m = par[0, 1, 1], par[1, 1, 1], par[2:, 1, 1]
+    C = np.concatenate([[0.0], np.cumsum(m)]) / m.sum()
+    edges = lo + (hi - lo) * np.arange(len(m) + 1) / len(m)
+    assert stats.kstest(xs, lambda t: np.interp(t, edges, C)).pvalue > 1e-3
+
+
+def test_semi_point_mass_vertex():
+    """A vertex histogram of width 1e-12 puts every sample at x0, so each
+    estimate is the product of the neighbours' tails at x0 (numpy
+    interpolation of their cumulative masses)."""
+    par = workloads.random_params(HST, 11, 3, 3, nbins=4, width=0.2)
+    x0 = par[0, 1, 1] + 0.3 * (par[1, 1, 1] - par[0, 1, 1])
+    par[0, 1, 1], par[1, 1, 1] = x0, x0 + 1e-12
+    est = oracle.semi_at(par, [4], 64, seed=1)[0]
+    S, F = {}, {}
+    for k in "enws":
+        yy, xx = POS[k]
+        lo, hi, m = par[0, yy, xx], par[1, yy, xx], par[2:, yy, xx]
+        edges = lo + (hi - lo) * np.arange(len(m) + 1) / len(m)
+        F[k] = np.interp(x0, edges, np.concatenate([[0.0], np.cumsum(m)]))
+        S[k] = m.sum() - F[k]
+    T = par[2:, 1, 1].sum()
+    ref = [T * np.prod([S[k] for k in "enws"]), T * np.prod([F[k] for k in "enws"]),
+           T * S["e"] * F["n"] * S["w"] * F["s"], T * F["e"] * S["n"] * F["w"] * S["s"]]
+    np.testing.assert_allclose(est, ref, atol=1e-9)
+
+
+@pytest.mark.parametrize("seed", [0, 1])
+def test_semi_estimates_are_unbiased(seed):
+    """2^15 samples per vertex: every estimate lies within 4 standard errors
+    of the closed-form value (Eq. 3, Eq. 4) of the same histograms (each
+    sample's product lies in [0, 1], so its variance is at most p(1 - p))."""
+    par = workloads.random_params(HST, 20 + seed, 6, 7, nbins=6, width=0.08)
+    idx = np.arange(6 * 7)
+    ns = 1 << 15
+    est = oracle.semi_at(par, idx, ns, seed=seed + 5)
+    pmin, pmax = oracle.forward_at(HST, par, idx)
+    t1, t2 = oracle.saddle_at(HST, par, idx)
+    for q, ref in enumerate((pmin, pmax, t1, t2)):
+        se = np.sqrt(np.clip(ref * (1 - ref), 1e-12, None) / ns)
+        assert np.all(np.abs(est[:, q] - ref) <= 4 * se + 1e-12), q
