@@ -283,6 +283,12 @@ def more_detail(cp, workloads, torch, dev, S, reps):
         res[name] = {"fwd_ms": tf, "bwd_ms": tb, "classify_ms": tc, "saddle_ms": ts,
                      "fwd_vertices_per_s": S * S / (tf * 1e-3),
                      "fwd_bwd_vertices_per_s": S * S / ((tf + tb) * 1e-3)}
+        if model == 2:
+            # semianalytical estimator (Sec. 4.4.2), 1000 samples per vertex
+            fs = cp.field_of(params, model, nb, nsamples=1000, seed=1)
+            tsa = _timed(torch, lambda: cp.semianalytical(params, fs, terms=True), max(3, reps // 4))
+            res[name]["semianalytical_1000_ms"] = tsa
+            res[name]["semianalytical_1000_samples_per_s"] = S * S * 1000 / (tsa * 1e-3)
         del params, grad
     # independent Gaussian at S^2 (deterministic quadrature: forward = all four classes)
     mem = torch.as_tensor(workloads.smooth_ensemble(1, S, S), device=dev)

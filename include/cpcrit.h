@@ -199,6 +199,28 @@ cp_status_t cp_prob_backward(const cp_field_desc_t* desc, const void* params, co
 cp_status_t cp_prob_classify(const cp_field_desc_t* desc, const void* params, void* p_min, void* p_max,
                              void* p_saddle, void* p_regular, void* terms, void* stream);
 
+/*
+ * Semianalytical histogram estimator (Sec. 4.4.2): desc->nsamples samples c
+ * are drawn from each vertex histogram by its inverse CDF; for each sample the
+ * probabilities that the neighbours lie above / below it are closed-form
+ * (bin lookup plus cumulative masses), and their products are averaged:
+ *     P_min ~ T (1/c) sum_i prod_n S_n(x_i),  P_max ~ T (1/c) sum_i prod_n F_n(x_i),
+ *     t1, t2 (Eq. 4) likewise with mixed S / F factors (0 on the boundary),
+ * T = the vertex's total mass, so the expectation is the closed-form value of
+ * cp_prob_forward / cp_prob_classify.  Sample i of vertex (y, x) uses word
+ * i mod 4 of Philox4x32-10 with counter (i / 4, y*W + x, desc->field_id, 2)
+ * under key desc->seed; u = ((word >> 8) + 1/2) 2^-24, r = u T, bin
+ * j = #{k in 1..h-1 : m_0 + ... + m_{k-1} <= r}, x = lo + Delta (j + f) with
+ * f = (r - m_0 - ... - m_{j-1}) / m_j clamped to [0, 1] (0 for an empty bin).
+ *   desc->model   CP_HISTOGRAM (else CP_EUNSUPPORTED); desc->nsamples >= 1
+ *   params        [2 + nbins][H][row_stride]
+ *   p_min, p_max  [H][row_stride] outputs; terms [2][H][row_stride] (t1, t2)
+ * Any output may be NULL; at least one must be given.  Invalid histograms in
+ * a stencil give NaN in its outputs.
+ */
+cp_status_t cp_prob_semianalytical(const cp_field_desc_t* desc, const void* params, void* p_min, void* p_max,
+                                   void* terms, void* stream);
+
 /* cp_prob_batched flags */
 #define CP_BATCH_FWD 1u       /* write p_min / p_max */
 #define CP_BATCH_BWD 2u       /* write grad_params (needs g_min / g_max) */

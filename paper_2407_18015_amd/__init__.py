@@ -11,7 +11,7 @@ batched persistent launch.  All computation runs in the HIP library
 """
 from . import _lib
 from .ops import (CPProb, Field, backward, batched, classify, critical_point_probability, field_of, fit,
-                  fit_error_bound, forward, n_params, philox)
+                  fit_error_bound, forward, n_params, philox, semianalytical)
 
 __all__ = ["CPProb", "Field", "backward", "batched", "classify", "critical_point_probability", "field_of", "fit",
-           "fit_error_bound", "forward", "n_params", "philox", "_lib"]
+           "fit_error_bound", "forward", "n_params", "philox", "semianalytical", "_lib"]

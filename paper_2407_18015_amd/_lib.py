@@ -18,7 +18,8 @@ CP_F32, CP_F64 = 0, 1
 CP_MC_CONDITIONAL, CP_MC_HIT = 0, 1
 CP_BATCH_FWD, CP_BATCH_BWD, CP_BATCH_GRAPH, CP_BATCH_PER_FIELD = 1, 2, 4, 8
 
-EXPORTS = ["cpu_fit_params", "cp_fit_error_bound", "cp_prob_forward", "cp_prob_backward", "cp_prob_classify", "cp_prob_batched",
+EXPORTS = ["cpu_fit_params", "cp_fit_error_bound", "cp_prob_forward", "cp_prob_backward", "cp_prob_classify", "cp_prob_semianalytical",
+           "cp_prob_batched",
            "cp_n_params", "cp_status_string", "cp_last_error", "cp_release", "cp_philox4x32_10", "cp_gauss_legendre"]
 
 
@@ -62,6 +63,7 @@ def load() -> ctypes.CDLL:
         "cp_prob_forward": (i32, [D, P, P, P, P]),
         "cp_prob_backward": (i32, [D, P, P, P, P, P]),
         "cp_prob_classify": (i32, [D, P, P, P, P, P, P, P]),
+        "cp_prob_semianalytical": (i32, [D, P, P, P, P, P]),
         "cp_prob_batched": (i32, [i32, D, PP, PP, PP, PP, PP, PP, u32, P]),
         "cp_n_params": (i32, [i32, i32]),
         "cp_status_string": (ctypes.c_char_p, [i32]),
@@ -95,6 +97,10 @@ def cp_fit_error_bound(desc, decompressed, eb, params, stream) -> int:
 
 def cp_prob_classify(desc, params, p_min, p_max, p_saddle, p_regular, terms, stream) -> int:
     return load().cp_prob_classify(ctypes.byref(desc), params, p_min, p_max, p_saddle, p_regular, terms, stream)
+
+
+def cp_prob_semianalytical(desc, params, p_min, p_max, terms, stream) -> int:
+    return load().cp_prob_semianalytical(ctypes.byref(desc), params, p_min, p_max, terms, stream)
 
 
 def cp_prob_forward(desc, params, p_min, p_max, stream) -> int:

@@ -18,7 +18,7 @@ BUILD = os.path.join(HERE, "_build")
 LIB = os.path.join(HERE, "libcpcrit.so")
 ARCH = os.environ.get("CPCRIT_ARCH", "gfx950")
 
-SOURCES = ["cp_api.cpp", "cp_closed_form.hip", "cp_fit.hip", "cp_mvg.hip", "cp_batched.hip", "cp_classify.hip"]
+SOURCES = ["cp_api.cpp", "cp_closed_form.hip", "cp_fit.hip", "cp_mvg.hip", "cp_batched.hip", "cp_classify.hip", "cp_semi.hip"]
 
 COMMON = ["-O3", "-std=c++17", "-fPIC", f"--offload-arch={ARCH}",
           "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",

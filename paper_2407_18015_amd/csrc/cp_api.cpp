@@ -216,6 +216,20 @@ cp_status_t cp_prob_classify(const cp_field_desc_t* desc, const void* params, vo
   return CP_OK;
 }
 
+cp_status_t cp_prob_semianalytical(const cp_field_desc_t* desc, const void* params, void* p_min, void* p_max,
+                                   void* terms, void* stream) {
+  cp::Field f;
+  cp_status_t s = check_desc(desc, f, false);
+  if (s != CP_OK) return s;
+  if (f.model != CP_HISTOGRAM) return fail(CP_EUNSUPPORTED, "semianalytical: histogram model only");
+  if (desc->nsamples < 1) return fail(CP_EINVAL, "nsamples must be >= 1");
+  if (!params) return fail(CP_EINVAL, "params is NULL");
+  if (!p_min && !p_max && !terms) return fail(CP_EINVAL, "no output requested");
+  hipError_t e = cp::semi_forward(f, params, p_min, p_max, terms, static_cast<hipStream_t>(stream));
+  if (e != hipSuccess) return device_fail(e, "semianalytical launch");
+  return CP_OK;
+}
+
 cp_status_t cp_prob_batched(int32_t n, const cp_field_desc_t* descs, const void* const* params, void* const* p_min,
                             void* const* p_max, const void* const* g_min, const void* const* g_max,
                             void* const* grad_params, uint32_t flags, void* stream) {

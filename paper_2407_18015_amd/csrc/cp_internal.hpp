@@ -32,6 +32,9 @@ hipError_t cf_backward(const Field& f, const void* params, const void* gmin, con
 hipError_t cf_classify(const Field& f, const void* params, void* pmin, void* pmax, void* psad, void* preg,
                        void* terms, hipStream_t st);
 
+// semianalytical histogram estimator; any output may be null
+hipError_t semi_forward(const Field& f, const void* params, void* pmin, void* pmax, void* terms, hipStream_t st);
+
 // fitting from members
 hipError_t fit_params(const Field& f, const void* members, int M, int ddof, double bw, double jitter,
                       double eps, void* params, hipStream_t st);

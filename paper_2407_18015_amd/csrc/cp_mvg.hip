@@ -20,30 +20,13 @@
 #include <hip/hip_runtime.h>
 
 #include "cp_internal.hpp"
+#include "cp_philox.hpp"
 
 namespace cp {
 
 namespace {
 
-constexpr uint32_t kM0 = 0xD2511F53u, kM1 = 0xCD9E8D57u;
-constexpr uint32_t kW0 = 0x9E3779B9u, kW1 = 0xBB67AE85u;
-
-__device__ __forceinline__ void philox(uint32_t c[4], uint32_t k0, uint32_t k1) {
-#pragma unroll
-  for (int r = 0; r < 10; ++r) {
-    const uint32_t hi0 = __umulhi(kM0, c[0]), lo0 = kM0 * c[0];
-    const uint32_t hi1 = __umulhi(kM1, c[2]), lo1 = kM1 * c[2];
-    const uint32_t n0 = hi1 ^ c[1] ^ k0, n2 = hi0 ^ c[3] ^ k1;
-    c[0] = n0;
-    c[1] = lo1;
-    c[2] = n2;
-    c[3] = lo0;
-    k0 += kW0;
-    k1 += kW1;
-  }
-}
-
-__device__ __forceinline__ float u24(uint32_t r) { return ((float)(r >> 8) + 0.5f) * 5.9604644775390625e-8f; }
+__device__ __forceinline__ float u24(uint32_t r) { return u24_of<float>(r); }
 
 __device__ __forceinline__ void box_muller(float u0, float u1, float& z0, float& z1) {
   const float rad = sqrtf(-2.0f * logf(u0));

@@ -1,0 +1,195 @@
+// cp_semi.hip -- semianalytical histogram estimator (Sec. 4.4.2).
+//
+// c samples are drawn from each vertex histogram; for each sample the
+// probability that a neighbour lies above (below) it is closed-form: the
+// neighbour's bin is found by one multiply, and the masses of the earlier
+// bins come from cumulative sums prepared once per staged vertex (the paper's
+// prefix-sum step), so the work per sample does not grow with the number of
+// bins except for locating the sample's own bin.  The products are averaged:
+//   P_min ~ T (1/c) sum_i prod_n S_n(x_i),   P_max ~ T (1/c) sum_i prod_n F_n(x_i),
+//   t1 ~ T (1/c) sum_i S_e F_n S_w F_s(x_i), t2 with S and F exchanged,
+// T = the vertex's total mass.  Sample i of vertex (y, x) uses word i mod 4 of
+// Philox4x32-10 with counter (i / 4, y*W + x, field_id, 2) under key seed,
+// u = ((word >> 8) + 1/2) 2^-24, r = u T, bin j = #{k in 1..h-1 : C_k <= r}
+// (C_k = m_0 + ... + m_{k-1}), f = (r - C_j) / m_j clamped to [0, 1] (0 for an
+// empty bin), x = lo + Delta (j + f): the inverse of the histogram CDF.
+//
+// Tiles of 64 x TY vertices stage lo, hi and the masses with a one-vertex
+// halo (as the closed-form forward does) and add h planes of cumulative
+// masses (FP64 running sums rounded once); one thread per vertex loops over
+// its samples, sums in FP64.  Positions are vertex-local (origin lo_v), so
+// FP32 errors are relative to the widths.
+#include <hip/hip_runtime.h>
+
+#include "cp_hist.hpp"
+#include "cp_internal.hpp"
+#include "cp_philox.hpp"
+#include "cp_tiles.hpp"
+
+namespace cp {
+
+namespace {
+
+template <typename T>
+struct SemiArgs {
+  const T* params;
+  T* pmin;
+  T* pmax;
+  T* terms;  // [2][H][rs]: t1, t2
+  int H, W, nb, ns;
+  int64_t rs, ps;
+  uint32_t k0, k1, fid;
+};
+
+template <typename T>
+__device__ __forceinline__ T clamp01(T v) {
+  return v < T(0) ? T(0) : (v > T(1) ? T(1) : v);
+}
+
+template <typename T, int TY>
+__global__ __launch_bounds__(kFwdTX* TY) void k_semi(SemiArgs<T> a, int tiles_x, int ntiles) {
+  constexpr int TX = kFwdTX, EX = TX + 2, EY = TY + 2, E = EX * EY, NT = TX * TY;
+  extern __shared__ __align__(16) unsigned char smem[];
+  T* lds = reinterpret_cast<T*>(smem);
+  const int t = xcd_tile(blockIdx.x, ntiles);
+  const int ty0 = (t / tiles_x) * TY, tx0 = (t % tiles_x) * TX, tid = threadIdx.x;
+  const int h = a.nb;
+  stage<T, EY, EX, NT>(lds, a.params, 2 + h, a.ps, a.rs, a.H, a.W, ty0 - 1, tx0 - 1, tid);
+  __syncthreads();
+  hist_stage_validity<T, NT>(lds, E, h, tid);
+  // cumulative masses: plane k - 1 of `cum` holds C_k, k = 1..h (C_h = T)
+  T* cum = lds + (size_t)(2 + h) * E;
+  for (int e = tid; e < E; e += NT) {
+    double c = 0.0;
+    for (int k = 0; k < h; ++k) {
+      c += (double)lds[(2 + k) * E + e];
+      cum[k * E + e] = (T)c;
+    }
+  }
+  __syncthreads();
+  const int lx = tid % TX, ly = tid / TX;
+  const int x = tx0 + lx, y = ty0 + ly;
+  if (x >= a.W || y >= a.H) return;
+  const HistLds<T> L{lds, E, h, T(1) / T(h)};
+  const int e = (ly + 1) * EX + lx + 1;
+  const int en[4] = {e + 1, e - EX, e - 1, e + EX};
+  const bool pres[4] = {x + 1 < a.W, y > 0, x > 0, y + 1 < a.H};
+  bool ok = L.valid(e);
+#pragma unroll
+  for (int i = 0; i < 4; ++i) ok = ok && (!pres[i] || L.valid(en[i]));
+  T out[4] = {qnan<T>(), qnan<T>(), qnan<T>(), qnan<T>()};
+  if (ok) {
+    const T lov = lds[e];
+    const T dv = (lds[E + e] - lov) * L.ih;
+    const T Tv = cum[(h - 1) * E + e];
+    T lo[4], id[4], tot[4];
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+      lo[i] = lds[en[i]] - lov;
+      id[i] = T(h) * crcp(lds[E + en[i]] - lds[en[i]]);
+      tot[i] = cum[(h - 1) * E + en[i]];
+    }
+    double acc[4] = {0.0, 0.0, 0.0, 0.0};
+    const uint32_t at = (uint32_t)((int64_t)y * a.W + x);
+    uint32_t w[4] = {0u, 0u, 0u, 0u};
+    for (int i = 0; i < a.ns; ++i) {
+      if ((i & 3) == 0) {
+        w[0] = (uint32_t)(i >> 2);
+        w[1] = at;
+        w[2] = a.fid;
+        w[3] = 2u;
+        philox(w, a.k0, a.k1);
+      }
+      const T r = u24_of<T>(w[i & 3]) * Tv;
+      int j = 0;
+      for (int k = 1; k < h; ++k) j += cum[(k - 1) * E + e] <= r ? 1 : 0;
+      const T mj = lds[(2 + j) * E + e];
+      const T cj = j > 0 ? cum[(j - 1) * E + e] : T(0);
+      const T f = mj > T(0) ? clamp01((r - cj) / mj) : T(0);
+      const T xs = dv * (T(j) + f);
+      T S[4], F[4];
+#pragma unroll
+      for (int n = 0; n < 4; ++n) {
+        S[n] = T(1);
+        F[n] = T(1);
+        if (!pres[n]) continue;
+        const T z = (xs - lo[n]) * id[n];
+        if (!(z > T(0))) {
+          S[n] = tot[n];
+          F[n] = T(0);
+        } else if (!(z < T(h))) {
+          S[n] = T(0);
+          F[n] = tot[n];
+        } else {
+          const int k = min((int)z, h - 1);
+          const T below = k > 0 ? cum[(k - 1) * E + en[n]] : T(0);
+          F[n] = cfma(lds[(2 + k) * E + en[n]], z - T(k), below);
+          S[n] = tot[n] - F[n];
+        }
+      }
+      acc[0] += (double)(S[0] * S[1] * S[2] * S[3]);
+      acc[1] += (double)(F[0] * F[1] * F[2] * F[3]);
+      acc[2] += (double)(S[0] * F[1] * S[2] * F[3]);
+      acc[3] += (double)(F[0] * S[1] * F[2] * S[3]);
+    }
+    const double sc = (double)Tv / (double)a.ns;
+#pragma unroll
+    for (int q = 0; q < 4; ++q) out[q] = (T)(acc[q] * sc);
+    // the alternating pattern needs all four neighbours
+    if (!(pres[0] && pres[1] && pres[2] && pres[3])) out[2] = out[3] = T(0);
+  }
+  const int64_t o = (int64_t)y * a.rs + x;
+  if (a.pmin) a.pmin[o] = out[0];
+  if (a.pmax) a.pmax[o] = out[1];
+  if (a.terms) {
+    a.terms[o] = out[2];
+    a.terms[a.ps + o] = out[3];
+  }
+}
+
+int cdiv_s(int p, int q) { return (p + q - 1) / q; }
+
+template <typename T, int TY>
+hipError_t launch_semi(const SemiArgs<T>& a, hipStream_t st) {
+  const int tx = cdiv_s(a.W, kFwdTX), ty = cdiv_s(a.H, TY), n = tx * ty;
+  const size_t lds = sizeof(T) * (size_t)(2 + 2 * a.nb) * (kFwdTX + 2) * (TY + 2);
+  if (lds > 65536) {
+    hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(k_semi<T, TY>),
+                                       hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+    if (e != hipSuccess) return e;
+  }
+  hipLaunchKernelGGL((k_semi<T, TY>), dim3(n), dim3(kFwdTX * TY), lds, st, a, tx, n);
+  return hipGetLastError();
+}
+
+template <typename T>
+hipError_t semi_typed(const Field& f, const void* params, void* pmin, void* pmax, void* terms, hipStream_t st) {
+  SemiArgs<T> a;
+  a.params = static_cast<const T*>(params);
+  a.pmin = static_cast<T*>(pmin);
+  a.pmax = static_cast<T*>(pmax);
+  a.terms = static_cast<T*>(terms);
+  a.H = f.H;
+  a.W = f.W;
+  a.nb = f.nb;
+  a.ns = f.ns;
+  a.rs = f.rs;
+  a.ps = f.plane();
+  a.k0 = (uint32_t)f.seed;
+  a.k1 = (uint32_t)(f.seed >> 32);
+  a.fid = f.fid;
+  // tile height: the staged and cumulative planes must fit the LDS
+  const size_t per_row = sizeof(T) * (size_t)(2 + 2 * f.nb) * (kFwdTX + 2);
+  if (per_row * 6 <= 64 * 1024) return launch_semi<T, 4>(a, st);
+  if (per_row * 4 <= 160 * 1024) return launch_semi<T, 2>(a, st);
+  return launch_semi<T, 1>(a, st);
+}
+
+}  // namespace
+
+hipError_t semi_forward(const Field& f, const void* params, void* pmin, void* pmax, void* terms, hipStream_t st) {
+  if (f.dtype == CP_F64) return semi_typed<double>(f, params, pmin, pmax, terms, st);
+  return semi_typed<float>(f, params, pmin, pmax, terms, st);
+}
+
+}  // namespace cp

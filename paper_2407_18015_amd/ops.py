@@ -167,6 +167,22 @@ def classify(params: torch.Tensor, f: Field, outputs=("min", "max", "saddle", "r
     return out
 
 
+def semianalytical(params: torch.Tensor, f: Field, terms: bool = False) -> dict:
+    """cp_prob_semianalytical: Monte Carlo over the vertex histogram with
+    closed-form neighbour tails (f.nsamples samples, Philox key f.seed,
+    counter word f.field_id).  Returns {"min", "max"} ([H, W]) and, with
+    terms=True, "terms" ([2, H, W]: t1, t2)."""
+    _planes(params, f.height, f.width, f.param_dtype, "params", f.row_stride)
+    if params.shape[0] != f.n_param:
+        raise ValueError(f"params needs {f.n_param} planes")
+    out = {k: torch.empty((f.height, f.width), dtype=f.out_dtype, device=params.device) for k in ("min", "max")}
+    if terms:
+        out["terms"] = torch.empty((2, f.height, f.width), dtype=f.out_dtype, device=params.device)
+    L.check(L.cp_prob_semianalytical(f.desc(), _ptr(params), _ptr(out["min"]), _ptr(out["max"]),
+                                     _ptr(out.get("terms")), _stream(params)))
+    return out
+
+
 def batched(fields: list[Field], params: list[torch.Tensor], pmin=None, pmax=None, gmin=None, gmax=None,
             grad=None, graph: bool = False, per_field: bool = False) -> None:
     """cp_prob_batched over caller-allocated outputs (lists of tensors)."""

@@ -145,6 +145,16 @@ def test_binding_covers_every_call_of_the_torch_layer():
             assert callable(getattr(L, name, None)), name
 
 
+def test_semianalytical_validation():
+    lib = L.load()
+    h = dict(model=L.CP_HISTOGRAM, nbins=4, nsamples=8)
+    assert lib.cp_prob_semianalytical(desc(**h), None, FAKE, FAKE, None, None) == L.CP_EINVAL
+    assert lib.cp_prob_semianalytical(desc(**h), FAKE, None, None, None, None) == L.CP_EINVAL
+    assert lib.cp_prob_semianalytical(desc(model=L.CP_HISTOGRAM, nbins=4, nsamples=0), FAKE, FAKE, FAKE, None,
+                                      None) == L.CP_EINVAL
+    assert lib.cp_prob_semianalytical(desc(), FAKE, FAKE, FAKE, None, None) == L.CP_EUNSUPPORTED
+
+
 def test_status_strings():
     lib = L.load()
     for s in range(6):
