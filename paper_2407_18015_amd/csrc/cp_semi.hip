@@ -17,8 +17,11 @@
 // Tiles of 64 x TY vertices stage lo, hi and the masses with a one-vertex
 // halo (as the closed-form forward does) and add h planes of cumulative
 // masses (FP64 running sums rounded once); one thread per vertex loops over
-// its samples, sums in FP64.  Positions are vertex-local (origin lo_v), so
-// FP32 errors are relative to the widths.
+// its samples.  Sample positions and neighbour tails are computed in FP64
+// for both dtypes, in vertex-local coordinates: in FP32 a position carries
+// an error of one unit in the last place of the distribution width, which
+// is h units of a bin, and the neighbour's tail inherits it for every
+// sample alike; FP64 arithmetic costs the same issue rate as FP32 here.
 #include <hip/hip_runtime.h>
 
 #include "cp_hist.hpp"
@@ -79,15 +82,16 @@ __global__ __launch_bounds__(kFwdTX* TY) void k_semi(SemiArgs<T> a, int tiles_x,
   for (int i = 0; i < 4; ++i) ok = ok && (!pres[i] || L.valid(en[i]));
   T out[4] = {qnan<T>(), qnan<T>(), qnan<T>(), qnan<T>()};
   if (ok) {
-    const T lov = lds[e];
-    const T dv = (lds[E + e] - lov) * L.ih;
+    using A = double;
+    const A lov = (A)lds[e];
+    const A dv = ((A)lds[E + e] - lov) / A(h);
     const T Tv = cum[(h - 1) * E + e];
-    T lo[4], id[4], tot[4];
+    A lo[4], id[4], tot[4];
 #pragma unroll
     for (int i = 0; i < 4; ++i) {
-      lo[i] = lds[en[i]] - lov;
-      id[i] = T(h) * crcp(lds[E + en[i]] - lds[en[i]]);
-      tot[i] = cum[(h - 1) * E + en[i]];
+      lo[i] = (A)lds[en[i]] - lov;
+      id[i] = A(h) / ((A)lds[E + en[i]] - (A)lds[en[i]]);
+      tot[i] = (A)cum[(h - 1) * E + en[i]];
     }
     double acc[4] = {0.0, 0.0, 0.0, 0.0};
     const uint32_t at = (uint32_t)((int64_t)y * a.W + x);
@@ -100,37 +104,37 @@ __global__ __launch_bounds__(kFwdTX* TY) void k_semi(SemiArgs<T> a, int tiles_x,
         w[3] = 2u;
         philox(w, a.k0, a.k1);
       }
-      const T r = u24_of<T>(w[i & 3]) * Tv;
+      const A r = u24_of<A>(w[i & 3]) * (A)Tv;
       int j = 0;
-      for (int k = 1; k < h; ++k) j += cum[(k - 1) * E + e] <= r ? 1 : 0;
-      const T mj = lds[(2 + j) * E + e];
-      const T cj = j > 0 ? cum[(j - 1) * E + e] : T(0);
-      const T f = mj > T(0) ? clamp01((r - cj) / mj) : T(0);
-      const T xs = dv * (T(j) + f);
-      T S[4], F[4];
+      for (int k = 1; k < h; ++k) j += (A)cum[(k - 1) * E + e] <= r ? 1 : 0;
+      const A mj = (A)lds[(2 + j) * E + e];
+      const A cj = j > 0 ? (A)cum[(j - 1) * E + e] : A(0);
+      const A f = mj > A(0) ? clamp01((r - cj) / mj) : A(0);
+      const A xs = dv * (A(j) + f);
+      A S[4], F[4];
 #pragma unroll
       for (int n = 0; n < 4; ++n) {
-        S[n] = T(1);
-        F[n] = T(1);
+        S[n] = A(1);
+        F[n] = A(1);
         if (!pres[n]) continue;
-        const T z = (xs - lo[n]) * id[n];
-        if (!(z > T(0))) {
+        const A z = (xs - lo[n]) * id[n];
+        if (!(z > A(0))) {
           S[n] = tot[n];
-          F[n] = T(0);
-        } else if (!(z < T(h))) {
-          S[n] = T(0);
+          F[n] = A(0);
+        } else if (!(z < A(h))) {
+          S[n] = A(0);
           F[n] = tot[n];
         } else {
           const int k = min((int)z, h - 1);
-          const T below = k > 0 ? cum[(k - 1) * E + en[n]] : T(0);
-          F[n] = cfma(lds[(2 + k) * E + en[n]], z - T(k), below);
+          const A below = k > 0 ? (A)cum[(k - 1) * E + en[n]] : A(0);
+          F[n] = fma((A)lds[(2 + k) * E + en[n]], z - A(k), below);
           S[n] = tot[n] - F[n];
         }
       }
-      acc[0] += (double)(S[0] * S[1] * S[2] * S[3]);
-      acc[1] += (double)(F[0] * F[1] * F[2] * F[3]);
-      acc[2] += (double)(S[0] * F[1] * S[2] * F[3]);
-      acc[3] += (double)(F[0] * S[1] * F[2] * S[3]);
+      acc[0] += S[0] * S[1] * S[2] * S[3];
+      acc[1] += F[0] * F[1] * F[2] * F[3];
+      acc[2] += S[0] * F[1] * S[2] * F[3];
+      acc[3] += F[0] * S[1] * F[2] * S[3];
     }
     const double sc = (double)Tv / (double)a.ns;
 #pragma unroll
