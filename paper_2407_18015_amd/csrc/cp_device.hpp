@@ -347,13 +347,15 @@ CP_HD void uni_side_grad(const UniSide<T>& s, UniGrad<T>& g) {
 template <typename T>
 struct EpaSide {
   T wv, iwv;
-  T c[4], d[4], iw[4];
+  T c[4], d[4], iw[4], w[4];
   int tag[4];
   T bmin;
   bool empty;
 };
 
-template <typename T>
+// WW: also carry the neighbour half-widths through the sort (the adjoint
+// needs them; the forward does not).
+template <typename T, bool WW = false>
 CP_HD void epa_setup(EpaSide<T>& s, T wv, T iwv, const T (&d)[4], const T (&w)[4], const T (&iw)[4],
                      const bool (&pres)[4]) {
   s.wv = wv;
@@ -364,21 +366,24 @@ CP_HD void epa_setup(EpaSide<T>& s, T wv, T iwv, const T (&d)[4], const T (&w)[4
     if (pres[i]) bmin = tmin(bmin, d[i] + w[i]);
   s.bmin = bmin;
   s.empty = !(bmin > -wv);
+  constexpr int P = WW ? 3 : 2;
   T key[4];
-  T pay[4][2];
+  T pay[4][P];
 #pragma unroll
   for (int i = 0; i < 4; ++i) {
     key[i] = pres[i] ? tclamp(d[i] - w[i], -wv, bmin) : bmin;
     pay[i][0] = pres[i] ? d[i] : T(3) * wv;
     pay[i][1] = pres[i] ? iw[i] : s.iwv;
+    if constexpr (WW) pay[i][2] = pres[i] ? w[i] : wv;
     s.tag[i] = i;
   }
-  sort4<T, 2>(key, pay, s.tag);
+  sort4<T, P>(key, pay, s.tag);
 #pragma unroll
   for (int i = 0; i < 4; ++i) {
     s.c[i] = key[i];
     s.d[i] = pay[i][0];
     s.iw[i] = pay[i][1];
+    if constexpr (WW) s.w[i] = pay[i][2];
   }
 }
 
@@ -437,18 +442,20 @@ CP_HD T epa_side_value(const EpaSide<T>& s) {
 // Local derivatives of one side, f(wv, d_i, w_i):
 //   df/dd_i = int p_v p_i prod_{k!=i} S_k          (dS/dm = pdf)
 //   df/dw_i = int p_v u_i p_i prod_{k!=i} S_k      (dS/dw = u pdf)
-//   df/dwv  = -(1/wv) sum_i int x p_v p_i prod_{k!=i} S_k
+//   df/dwv  = -(1/wv) sum_i (d_i df/dd_i + w_i df/dw_i)
 // The last line is the scale invariance of P about the vertex centre
-// (wv df/dwv + sum_i (d_i df/dd_i + w_i df/dw_i) = 0); integrating
-// dpdf_v/dwv directly would cancel (its integral over the support is 0).
+// (wv df/dwv + sum_i (d_i df/dd_i + w_i df/dw_i) = 0): it equals
+// -(1/wv) sum_i int x p_v p_i prod_{k!=i} S_k, since x = d_i + w_i u_i, and
+// avoids integrating dpdf_v/dwv, whose integral over the support is 0 and
+// cancels.  WF: also return f itself (the fused forward).
 template <typename T>
 struct EpaGrad {
   T f, dwv;
   T dd[4], dw[4];  // by neighbour index
 };
 
-template <typename T, int K, int N>
-CP_HD void epa_piece_grad(const EpaSide<T>& s, T l, T r, T& full, T (&gd)[4], T (&gw)[4], T (&gx)[4]) {
+template <typename T, int K, int N, bool WF>
+CP_HD void epa_piece_grad(const EpaSide<T>& s, T l, T r, T& full, T (&gd)[4], T (&gw)[4]) {
   const T mid = (l + r) * T(0.5), hl = (r - l) * T(0.5);
   const T av = mid * s.iwv, bv = hl * s.iwv;
   T au[K], bu[K];
@@ -457,85 +464,83 @@ CP_HD void epa_piece_grad(const EpaSide<T>& s, T l, T r, T& full, T (&gd)[4], T 
     au[i] = (mid - s.d[i]) * s.iw[i];  // u = au + bu x
     bu[i] = hl * s.iw[i];
   }
-  T sf = T(0), sd[K], sww[K], sxx[K];
+  T sf = T(0), sd[K], sww[K];
 #pragma unroll
-  for (int i = 0; i < K; ++i) sd[i] = sww[i] = sxx[i] = T(0);
+  for (int i = 0; i < K; ++i) sd[i] = sww[i] = T(0);
 #pragma unroll
   for (int j = 0; j < N; ++j) {
     const T x = T(GL<N>::x[j]);
-    const T wj = T(GL<N>::w[j]);
     const T t = cfma(bv, x, av);
-    const T wpv = wj * cfma(-t, t, T(1));  // weight * 4 wv/3 * pdf_v
-    const T xl = cfma(hl, x, mid);         // node in the vertex frame
     T u[K], S[K], pre[K + 1], suf[K + 1];
 #pragma unroll
     for (int i = 0; i < K; ++i) {
       u[i] = cfma(bu[i], x, au[i]);
       S[i] = epa_s4(u[i]);  // 4 S_i
     }
-    pre[0] = T(1);
+    // prefix products carry the node weight and the vertex pdf
+    // (weight * 4 wv/3 * pdf_v = w_j (1 - t^2))
+    pre[0] = T(GL<N>::w[j]) * cfma(-t, t, T(1));
 #pragma unroll
     for (int i = 0; i < K; ++i) pre[i + 1] = pre[i] * S[i];
     suf[K] = T(1);
 #pragma unroll
     for (int i = K - 1; i >= 0; --i) suf[i] = suf[i + 1] * S[i];
-    sf = cfma(wpv, pre[K], sf);
+    if (WF) sf += pre[K];
 #pragma unroll
     for (int i = 0; i < K; ++i) {
       // (4 w_i / 3) p_i = 1 - u^2
-      const T lw = wpv * (cfma(-u[i], u[i], T(1)) * (pre[i] * suf[i + 1]));
+      const T lw = cfma(-u[i], u[i], T(1)) * (pre[i] * suf[i + 1]);
       sd[i] += lw;
       sww[i] = cfma(lw, u[i], sww[i]);
-      sxx[i] = cfma(lw, xl, sxx[i]);
     }
   }
-  full += sf * hl;
+  if (WF) full += sf * hl;
 #pragma unroll
   for (int i = 0; i < K; ++i) {
     gd[i] += sd[i] * hl;
     gw[i] += sww[i] * hl;
-    gx[i] += sxx[i] * hl;
   }
 }
 
-template <typename T>
+template <typename T, bool WF = true>
 CP_HD void epa_side_grad(const EpaSide<T>& s, EpaGrad<T>& g) {
   g.f = g.dwv = T(0);
 #pragma unroll
   for (int i = 0; i < 4; ++i) g.dd[i] = g.dw[i] = T(0);
   if (s.empty) return;
   T F[5] = {T(0), T(0), T(0), T(0), T(0)};
-  T gd[5][4], gw[5][4], gx[5][4];
+  T gd[5][4], gw[5][4];
 #pragma unroll
   for (int k = 0; k < 5; ++k)
 #pragma unroll
-    for (int i = 0; i < 4; ++i) gd[k][i] = gw[k][i] = gx[k][i] = T(0);
-  epa_piece_grad<T, 1, 3>(s, s.c[0], s.c[1], F[1], gd[1], gw[1], gx[1]);
-  epa_piece_grad<T, 2, 5>(s, s.c[1], s.c[2], F[2], gd[2], gw[2], gx[2]);
-  epa_piece_grad<T, 3, 6>(s, s.c[2], s.c[3], F[3], gd[3], gw[3], gx[3]);
-  epa_piece_grad<T, 4, 8>(s, s.c[3], s.bmin, F[4], gd[4], gw[4], gx[4]);
+    for (int i = 0; i < 4; ++i) gd[k][i] = gw[k][i] = T(0);
+  epa_piece_grad<T, 1, 3, WF>(s, s.c[0], s.c[1], F[1], gd[1], gw[1]);
+  epa_piece_grad<T, 2, 5, WF>(s, s.c[1], s.c[2], F[2], gd[2], gw[2]);
+  epa_piece_grad<T, 3, 6, WF>(s, s.c[2], s.c[3], F[3], gd[3], gw[3]);
+  epa_piece_grad<T, 4, 8, WF>(s, s.c[3], s.bmin, F[4], gd[4], gw[4]);
   const T kv = T(0.75) * s.iwv;
   const T sc[5] = {T(1), T(0.25), T(0.0625), T(0.015625), T(0.00390625)};
-  T f = epa_cdf4(s, s.c[0]) * T(0.25);
+  if (WF) {
+    T f = epa_cdf4(s, s.c[0]) * T(0.25);
 #pragma unroll
-  for (int k = 1; k < 5; ++k) f += kv * sc[k] * F[k];
-  g.f = f;
+    for (int k = 1; k < 5; ++k) f += kv * sc[k] * F[k];
+    g.f = f;
+  }
   // neighbour terms: slot i collects pieces k > i; p_i carries 3/(4 w_i) and
   // the other factors 4^-(k-1)
   T xsum = T(0);
 #pragma unroll
   for (int i = 0; i < 4; ++i) {
-    T ad = T(0), aw = T(0), ax = T(0);
+    T ad = T(0), aw = T(0);
 #pragma unroll
     for (int k = i + 1; k < 5; ++k) {
       ad += sc[k - 1] * gd[k][i];
       aw += sc[k - 1] * gw[k][i];
-      ax += sc[k - 1] * gx[k][i];
     }
     const T ki = T(0.75) * s.iw[i] * kv;
     const T dd = ki * ad;
     const T dw = ki * aw;
-    xsum += ki * ax;
+    xsum = cfma(s.d[i], dd, cfma(s.w[i], dw, xsum));
     const int t = s.tag[i];
 #pragma unroll
     for (int n = 0; n < 4; ++n) {

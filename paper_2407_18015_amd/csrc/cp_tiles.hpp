@@ -109,7 +109,8 @@ CP_HD void vertex_fwd_ue(const T* L, int E, int e, const int (&en)[4], const boo
 
 // Jacobian of one stencil, weighted by the upstream gradients:
 // jac[slot*2 + q] = gmin dP_min/dtheta_q(slot) + gmax dP_max/dtheta_q(slot)
-template <typename T, int MODEL>
+// WF: also return P_min, P_max (the Epanechnikov adjoint skips them otherwise).
+template <typename T, int MODEL, bool WF = true>
 CP_HD void vertex_jac_ue(const T* L, int E, int e, const int (&en)[4], const bool (&pres)[4],
                                               T gmin, T gmax, T (&jac)[10], T& pmin, T& pmax) {
   const T p0 = L[e], p1 = L[E + e];
@@ -174,12 +175,12 @@ CP_HD void vertex_jac_ue(const T* L, int E, int e, const int (&en)[4], const boo
       d[i] = q0[i] - p0;
       iw[i] = crcp(q1[i]);
     }
-    epa_setup(s, p1, iwv, d, q1, iw, pres);
-    epa_side_grad(s, g);
+    epa_setup<T, true>(s, p1, iwv, d, q1, iw, pres);
+    epa_side_grad<T, WF>(s, g);
 #pragma unroll
     for (int i = 0; i < 4; ++i) d[i] = p0 - q0[i];
-    epa_setup(s, p1, iwv, d, q1, iw, pres);
-    epa_side_grad(s, r);
+    epa_setup<T, true>(s, p1, iwv, d, q1, iw, pres);
+    epa_side_grad<T, WF>(s, r);
     T sg = T(0), sr = T(0);
 #pragma unroll
     for (int i = 0; i < 4; ++i) {
@@ -278,8 +279,8 @@ struct BwdGeom {
   static constexpr int PX = OX + 4, PY = OY + 4, EP = PX * PY;  // parameters
 };
 
-template <typename T, int MODEL, int OX, int OY, int NT>
-__device__ __forceinline__ void tile_bwd_ue(const FieldPtrs<T>& f, int ty0, int tx0, T* lds, int tid) {
+template <typename T, int MODEL, int OX, int OY, int NT, bool WF>
+__device__ __forceinline__ void tile_bwd_ue_impl(const FieldPtrs<T>& f, int ty0, int tx0, T* lds, int tid) {
   using G = BwdGeom<OX, OY>;
   T* par = lds;
   T* J = lds + 2 * G::EP;
@@ -297,9 +298,9 @@ __device__ __forceinline__ void tile_bwd_ue(const FieldPtrs<T>& f, int ty0, int 
       const bool pres[4] = {gx + 1 < f.W, gy > 0, gx > 0, gy + 1 < f.H};
       const int64_t at = (int64_t)gy * f.rs + gx;
       T pmin, pmax;
-      vertex_jac_ue<T, MODEL>(par, G::EP, e, en, pres, f.gmin[at], f.gmax[at], jac, pmin, pmax);
-      // fused forward: the adjoint evaluates the probabilities anyway
-      if (f.pmin && ey >= 1 && ey <= OY && ex >= 1 && ex <= OX) {
+      vertex_jac_ue<T, MODEL, WF>(par, G::EP, e, en, pres, f.gmin[at], f.gmax[at], jac, pmin, pmax);
+      // fused forward: the adjoint evaluates the probabilities as well
+      if (WF && ey >= 1 && ey <= OY && ex >= 1 && ex <= OX) {
         f.pmin[at] = pmin;
         f.pmax[at] = pmax;
       }
@@ -324,6 +325,14 @@ __device__ __forceinline__ void tile_bwd_ue(const FieldPtrs<T>& f, int ty0, int 
     }
   }
   __syncthreads();
+}
+
+template <typename T, int MODEL, int OX, int OY, int NT>
+__device__ __forceinline__ void tile_bwd_ue(const FieldPtrs<T>& f, int ty0, int tx0, T* lds, int tid) {
+  if (f.pmin)
+    tile_bwd_ue_impl<T, MODEL, OX, OY, NT, true>(f, ty0, tx0, lds, tid);
+  else
+    tile_bwd_ue_impl<T, MODEL, OX, OY, NT, false>(f, ty0, tx0, lds, tid);
 }
 
 template <int OX, int OY>
