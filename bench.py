@@ -35,37 +35,25 @@ PEAK_FP32_PACKED = 157.3e12
 # two rocprofv3 --pmc passes (FETCH_SIZE, WRITE_SIZE, KiB per dispatch) over
 # `bench.py --profile-only`, each scaled by the same counter on a plain
 # 256 MiB copy (FETCH_SIZE read 128 MiB: x2; WRITE_SIZE 256 MiB: x1).  They
-# describe the kernel built from the sources fingerprinted here (the files
-# that define its code; declarations elsewhere do not enter it) and are
-# reported as null once any of them changes.
+# describe the machine code whose instruction hash is recorded here (the
+# build writes every closed-form kernel's hash to libcpcrit.isa.json) and are
+# reported as null once the built kernel differs.
 ADJOINT_PMC = {
     "fetch_kib": 33281.4, "write_kib": 32777.6, "fetch_scale": 2.0, "write_scale": 1.0, "grid": [2048, 2048],
-    "sources": ["paper_2407_18015_amd/csrc/cp_closed_form.hip", "paper_2407_18015_amd/csrc/cp_tiles.hpp",
-                "paper_2407_18015_amd/csrc/cp_device.hpp", "paper_2407_18015_amd/csrc/cp_hist.hpp",
-                "paper_2407_18015_amd/csrc/cp_hist_bwd.hpp"],
-    "sha256": "b2ccd41affe69cc73a8c7835018608019ebd38f8b98f026272c890d787de99a9",
+    "kernel": "_ZN2cp8k_bwd_ueIfLi1ELi30ELi30EEEvNS_9FieldPtrsIT_EEii",
+    "isa_sha256": "c4b89f5c04316e192c3eb06f64edfbad4092277d242c766a670a1f06a7fc203f",
 }
-
-
-def sources_sha256(paths) -> str:
-    """Fingerprint of the code in C/C++ sources: comments and whitespace are
-    dropped, so documentation edits do not count as a kernel change."""
-    import hashlib
-    import re
-    h = hashlib.sha256()
-    root = os.path.dirname(os.path.abspath(__file__))
-    for p in paths:
-        with open(os.path.join(root, p)) as fh:
-            text = fh.read()
-        text = re.sub(r"/\*.*?\*/", " ", text, flags=re.S)
-        text = re.sub(r"//[^\n]*", " ", text)
-        h.update(" ".join(text.split()).encode())
-    return h.hexdigest()
 
 
 def adjoint_traffic(size: int = 2048):
     m = ADJOINT_PMC
-    if [size, size] != m["grid"] or sources_sha256(m["sources"]) != m["sha256"]:
+    path = os.path.join(os.path.dirname(os.path.abspath(__file__)), "paper_2407_18015_amd", "libcpcrit.isa.json")
+    try:
+        with open(path) as fh:
+            built = json.load(fh).get(m["kernel"])
+    except (OSError, ValueError):
+        built = None
+    if [size, size] != m["grid"] or built != m["isa_sha256"]:
         return None
     return (m["fetch_kib"] * m["fetch_scale"] + m["write_kib"] * m["write_scale"]) * 1024
 

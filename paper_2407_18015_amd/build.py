@@ -2,12 +2,18 @@
 
 Every source under csrc/ is compiled to an object in _build/ (in parallel),
 then linked into paper_2407_18015_amd/libcpcrit.so.  Packed FP32 instructions
-are disabled for all device code.
+are disabled for all device code.  The device assembly of the closed-form
+kernels is also emitted, and a SHA-256 of each kernel's instructions is
+written to libcpcrit.isa.json: measurements taken on a kernel (hardware
+counters) can then be tied to the exact machine code they describe.
 """
 from __future__ import annotations
 
 import concurrent.futures as cf
+import hashlib
+import json
 import os
+import re
 import shutil
 import subprocess
 
@@ -16,6 +22,8 @@ ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 BUILD = os.path.join(HERE, "_build")
 LIB = os.path.join(HERE, "libcpcrit.so")
+ISA_JSON = os.path.join(HERE, "libcpcrit.isa.json")
+ISA_SOURCES = ["cp_closed_form.hip"]
 ARCH = os.environ.get("CPCRIT_ARCH", "gfx950")
 
 SOURCES = ["cp_api.cpp", "cp_closed_form.hip", "cp_fit.hip", "cp_mvg.hip", "cp_batched.hip", "cp_classify.hip", "cp_semi.hip"]
@@ -43,11 +51,38 @@ def _compile(src: str) -> str:
     return obj
 
 
+def _isa(src: str) -> dict:
+    """Device assembly of one source; {kernel symbol: sha256 of its instructions}."""
+    asm = os.path.join(BUILD, os.path.splitext(src)[0] + ".s")
+    cmd = [_hipcc(), *COMMON, "--offload-device-only", "-S", os.path.join(CSRC, src), "-o", asm]
+    r = subprocess.run(cmd, capture_output=True, text=True)
+    if r.returncode != 0:
+        raise RuntimeError(f"hipcc -S failed on {src}:\n{r.stderr[-6000:]}")
+    text = open(asm).read()
+    out = {}
+    for m in re.finditer(r"^(_Z\w+):", text, flags=re.M):
+        name = m.group(1)
+        end = text.find(".Lfunc_end", m.end())
+        body = text[m.end():end if end > 0 else len(text)]
+        lines = [ln.split(";")[0].strip() for ln in body.splitlines()]
+        # branch labels carry the function's index in the file: keep the local part
+        code = "\n".join(re.sub(r"\.LBB\d+_(\d+)", r".LBB_\1", ln) for ln in lines
+                         if ln and not ln.startswith("."))
+        out[name] = hashlib.sha256(code.encode()).hexdigest()
+    return out
+
+
 def build(jobs: int | None = None) -> str:
     os.makedirs(BUILD, exist_ok=True)
-    jobs = jobs or min(len(SOURCES), max(1, (os.cpu_count() or 4)))
+    jobs = jobs or min(len(SOURCES) + len(ISA_SOURCES), max(1, (os.cpu_count() or 4)))
     with cf.ThreadPoolExecutor(jobs) as ex:
+        isa = [ex.submit(_isa, s) for s in ISA_SOURCES]
         objs = list(ex.map(_compile, SOURCES))
+        hashes = {}
+        for fut in isa:
+            hashes.update(fut.result())
+    with open(ISA_JSON, "w") as fh:
+        json.dump(hashes, fh, indent=1, sort_keys=True)
     tmp = LIB + ".tmp"
     cmd = [_hipcc(), "-shared", "-fPIC", f"--offload-arch={ARCH}", "-o", tmp, *objs]
     r = subprocess.run(cmd, capture_output=True, text=True)

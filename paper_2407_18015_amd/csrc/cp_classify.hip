@@ -89,11 +89,13 @@ __global__ __launch_bounds__(kFwdTX* TY) void k_classify_hist(ClassPtrs<T> f, in
   stage<T, EY, EX, NT>(lds, f.params, 2 + h, f.ps, f.rs, f.H, f.W, ty0 - 1, tx0 - 1, tid);
   __syncthreads();
   hist_stage_validity<T, NT>(lds, E, h, tid);
+  hist_stage_suffix<T, NT>(lds, E, h, tid);
   __syncthreads();
   const int lx = tid % TX, ly = tid / TX;
   const int x = tx0 + lx, y = ty0 + ly;
   if (x >= f.W || y >= f.H) return;
   const HistLds<T> L{lds, E, h, T(1) / T(h)};
+  const HistSuf<T> U{lds, E, h};
   const int e = (ly + 1) * EX + lx + 1;
   const int en[4] = {e + 1, e - EX, e - 1, e + EX};
   const bool pres[4] = {x + 1 < f.W, y > 0, x > 0, y + 1 < f.H};
@@ -114,15 +116,9 @@ __global__ __launch_bounds__(kFwdTX* TY) void k_classify_hist(ClassPtrs<T> f, in
         lo[i] = lds[en[i]] - lov;
         hi[i] = lds[E + en[i]] - lov;
       }
-      pmin = hist_side_value(L, e, en, pres, false, hiv - lov, lo, hi);
-#pragma unroll
-      for (int i = 0; i < 4; ++i) {
-        lo[i] = hiv - lds[E + en[i]];
-        hi[i] = hiv - lds[en[i]];
-      }
-      pmax = hist_side_value(L, e, en, pres, true, hiv - lov, lo, hi);
+      hist_vertex_minmax(U, e, en, pres, hiv - lov, lo, hi, pmin, pmax);
     }
-    if (sad && pres[0] && pres[1] && pres[2] && pres[3]) vertex_saddle_hist(L, e, en, t1, t2);
+    if (sad && pres[0] && pres[1] && pres[2] && pres[3]) vertex_saddle_hist(U, e, en, t1, t2);
   }
   class_store(f, y, x, pmin, pmax, t1, t2);
 }

@@ -143,51 +143,158 @@ CP_HD bool hist_cursor_step(HistCursor<T>& c, const HistLds<T>& L, int e, bool r
   return true;
 }
 
-// One side (min; the max is the min of -X): integral over [0, bmin] of
-// pdf_v prod S_n.  Vertex local range [0, hv]; neighbour local ranges
-// [lo_i, hi_i] (already reflected for the max side).
+}  // namespace cp
+
+// ---------------------------------------------------------------------------
+// Forward in one sweep: P_min and P_max of a vertex share the merged edges
+// of the five histograms over the vertex range [0, hv], with F = T - S for
+// every neighbour.  The staged masses are first replaced, per staged vertex,
+// by their suffix sums U_j = m_j + ... + m_{h-1} (FP64 sums rounded once), so
+// a neighbour's survival at an edge is one LDS read and crossing an edge
+// costs one read, whatever the number of bins.
+// ---------------------------------------------------------------------------
+namespace cp {
+
+// masses (planes 2..h+1) -> suffix sums U_0 .. U_{h-1}; U_0 = total mass
+template <typename T, int NT>
+CP_HD void hist_stage_suffix(T* lds, int E, int h, int tid) {
+  for (int e = tid; e < E; e += NT) {
+    double acc = 0.0;
+    for (int j = h - 1; j >= 0; --j) {
+      acc += (double)lds[(2 + j) * E + e];
+      lds[(2 + j) * E + e] = (T)acc;
+    }
+  }
+}
+
 template <typename T>
-__host__ __device__ T hist_side_value(const HistLds<T>& L, int ev, const int (&en)[4], const bool (&pres)[4],
-                                      bool rev, T hv, const T (&lo)[4], const T (&hi)[4]) {
+struct HistSuf {
+  const T* base;
+  int E, h;
+  // U_j of vertex e (U_h = 0)
+  CP_HD T U(int e, int j) const { return j >= h ? T(0) : base[(2 + j) * E + e]; }
+};
+
+// One neighbour in the vertex frame: survival S(x) = snx + slope (nxt - x)
+// on the current bin; F = tot - S.
+template <typename T>
+struct SufCursor {
+  int j;  // -1 below the range, h above it
+  T lo, d, id, nxt, snx, slope, tot;
+};
+
+template <typename T>
+CP_HD void suf_cursor_init(SufCursor<T>& c, const HistSuf<T>& L, int e, T lo, T hi, bool present, T big) {
   const int h = L.h;
-  T bmin = hv;
-#pragma unroll
-  for (int i = 0; i < 4; ++i)
-    if (pres[i]) bmin = tmin(bmin, hi[i]);
-  if (!(bmin > T(0))) return T(0);
-  const T big = hv + hv + T(1);  // beyond every edge the sweep can reach
-  const T dv = hv * L.ih, idv = T(h) * crcp(hv);
+  c.lo = lo;
+  c.d = (hi - lo) * (T(1) / T(h));
+  c.id = T(h) * crcp(hi - lo);
+  if (!present) {  // constant factor 1 in both products
+    c.j = h;
+    c.nxt = big;
+    c.snx = T(1);
+    c.slope = T(0);
+    c.tot = T(2);
+    return;
+  }
+  c.tot = L.U(e, 0);
+  if (!(lo < T(0))) {  // range starts at or after x = 0
+    c.j = -1;
+    c.nxt = lo;
+    c.snx = c.tot;
+    c.slope = T(0);
+    return;
+  }
+  int j = (int)(-lo * c.id);
+  j = j < 0 ? 0 : (j > h - 1 ? h - 1 : j);
+  const auto edge = [&](int k) { return k >= h ? hi : cfma(T(k), c.d, lo); };
+  if (j + 1 < h && !(edge(j + 1) > T(0))) ++j;
+  if (j > 0 && edge(j) > T(0)) --j;
+  c.j = j;
+  c.nxt = edge(j + 1);
+  const T uj = L.U(e, j);
+  c.snx = L.U(e, j + 1);
+  c.slope = (uj - c.snx) * c.id;
+  if (!(hi > T(0))) {  // the whole range lies below x = 0
+    c.j = h;
+    c.nxt = big;
+    c.snx = T(0);
+    c.slope = T(0);
+  }
+}
+
+template <typename T>
+CP_HD void suf_cursor_step(SufCursor<T>& c, const HistSuf<T>& L, int e, T hi, T x1, T big) {
+  const int h = L.h;
+  if (!(c.nxt == x1)) return;
+  if (c.j < h - 1) {
+    c.j += 1;
+    const T prev = c.snx;
+    c.snx = L.U(e, c.j + 1);
+    c.slope = (prev - c.snx) * c.id;
+    c.nxt = c.j + 1 >= h ? hi : cfma(T(c.j + 1), c.d, c.lo);
+  } else {
+    c.j = h;
+    c.nxt = big;
+    c.snx = T(0);
+    c.slope = T(0);
+  }
+}
+
+// P_min and P_max of vertex ev; neighbour ranges [lo_i, hi_i] in the vertex
+// frame (origin at the vertex lower end), vertex range [0, hv].
+template <typename T>
+__host__ __device__ void hist_vertex_minmax(const HistSuf<T>& L, int ev, const int (&en)[4], const bool (&pres)[4],
+                                            T hv, const T (&lo)[4], const T (&hi)[4], T& pmin, T& pmax) {
+  const int h = L.h;
+  const T big = hv + hv + T(1);
+  const T dv = hv * (T(1) / T(h)), idv = T(h) * crcp(hv);
   int jv = 0;
   T nv = h > 1 ? dv : hv;
-  T pv = L.mass(ev, 0, rev) * idv;
-  HistCursor<T> c[4];
+  T uv = L.U(ev, 1);
+  T pv = (L.U(ev, 0) - uv) * idv;
+  SufCursor<T> c[4];
 #pragma unroll
-  for (int i = 0; i < 4; ++i) hist_cursor_init(c[i], L, en[i], rev, lo[i], hi[i], pres[i], big);
-  T f0[4], f1[4];
+  for (int i = 0; i < 4; ++i) suf_cursor_init(c[i], L, en[i], lo[i], hi[i], pres[i], big);
+  T s0[4], f0[4], s1[4], f1[4];
 #pragma unroll
-  for (int i = 0; i < 4; ++i) f0[i] = cfma(c[i].slope, c[i].nxt, c[i].snx);
-  T x0 = T(0), acc = T(0);
+  for (int i = 0; i < 4; ++i) {
+    s0[i] = cfma(c[i].slope, c[i].nxt, c[i].snx);
+    f0[i] = c[i].tot - s0[i];
+  }
+  T x0 = T(0), amin = T(0), amax = T(0);
   const int maxit = 5 * (h + 1) + 2;  // every step crosses at least one edge
   for (int it = 0; it < maxit; ++it) {
-    if (!(x0 < bmin)) break;
-    T x1 = tmin(nv, bmin);
+    if (!(x0 < hv)) break;
+    T x1 = nv;
 #pragma unroll
     for (int i = 0; i < 4; ++i) x1 = tmin(x1, c[i].nxt);
 #pragma unroll
-    for (int i = 0; i < 4; ++i) f1[i] = cfma(c[i].slope, c[i].nxt - x1, c[i].snx);
-    acc = cfma(pv * (x1 - x0), bern4(f0, f1), acc);
-    if (nv == x1 && jv < h - 1) {
+    for (int i = 0; i < 4; ++i) {
+      s1[i] = cfma(c[i].slope, c[i].nxt - x1, c[i].snx);
+      f1[i] = c[i].tot - s1[i];
+    }
+    const T wgt = pv * (x1 - x0);
+    amin = cfma(wgt, bern4(s0, s1), amin);
+    amax = cfma(wgt, bern4(f0, f1), amax);
+    if (nv == x1) {
       ++jv;
+      const T un = L.U(ev, jv + 1);
+      pv = (uv - un) * idv;
+      uv = un;
       nv = jv + 1 < h ? T(jv + 1) * dv : hv;
-      pv = L.mass(ev, jv, rev) * idv;
     }
 #pragma unroll
-    for (int i = 0; i < 4; ++i) hist_cursor_step(c[i], L, en[i], rev, x1, big);
+    for (int i = 0; i < 4; ++i) suf_cursor_step(c[i], L, en[i], hi[i], x1, big);
 #pragma unroll
-    for (int i = 0; i < 4; ++i) f0[i] = f1[i];
+    for (int i = 0; i < 4; ++i) {
+      s0[i] = s1[i];
+      f0[i] = f1[i];
+    }
     x0 = x1;
   }
-  return acc;
+  pmin = amin;
+  pmax = amax;
 }
 
 }  // namespace cp

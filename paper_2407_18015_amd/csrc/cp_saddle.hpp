@@ -116,12 +116,12 @@ CP_HD T epa_saddle_term(int term, T wv, T iwv, const T (&d)[4], const T (&w)[4],
 }
 
 // ---------------------------------------------------------------------------
-// histogram: sweep from a_max^alt to b_min^alt with five cursors (the vertex
-// carries its density as the cursor slope); F = total - S.
+// histogram: sweep from a_max^alt to b_min^alt with five cursors over the
+// staged suffix sums (the vertex cursor's slope is its density); F = T - S.
 // Local frame: origin at the vertex lower end, vertex [0, hv].
 // ---------------------------------------------------------------------------
 template <typename T>
-__host__ __device__ T hist_saddle_term(int term, const HistLds<T>& L, int ev, const int (&en)[4], T hv,
+__host__ __device__ T hist_saddle_term(int term, const HistSuf<T>& L, int ev, const int (&en)[4], T hv,
                                        const T (&lo)[4], const T (&hi)[4]) {
   const int h = L.h;
   T a = T(0), b = hv;
@@ -135,20 +135,17 @@ __host__ __device__ T hist_saddle_term(int term, const HistLds<T>& L, int ev, co
   if (!(b > a)) return T(0);
   const T end = b - a;
   const T big = (hv - a) + (hv - a) + T(1);
-  HistCursor<T> cv, c[4];
-  T tot[4];
-  hist_cursor_init(cv, L, ev, false, -a, hv - a, true, big);
+  SufCursor<T> cv, c[4];
+  T hs[4];
+  suf_cursor_init(cv, L, ev, -a, hv - a, true, big);
 #pragma unroll
   for (int i = 0; i < 4; ++i) {
-    hist_cursor_init(c[i], L, en[i], false, lo[i] - a, hi[i] - a, true, big);
-    // total mass of neighbour i (the survival before its range)
-    double t = 0.0;
-    for (int k = 0; k < h; ++k) t += (double)L.mass(en[i], k, false);
-    tot[i] = (T)t;
+    hs[i] = hi[i] - a;
+    suf_cursor_init(c[i], L, en[i], lo[i] - a, hs[i], true, big);
   }
-  auto val = [&](const HistCursor<T>& q, int i, T x) {
-    const T s = cfma(q.slope, q.nxt - x, q.snx);
-    return saddle_is_cdf(term, i) ? tot[i] - s : s;
+  auto val = [&](const SufCursor<T>& q, int i, T x) {
+    const T sv = cfma(q.slope, q.nxt - x, q.snx);
+    return saddle_is_cdf(term, i) ? q.tot - sv : sv;
   };
   T f0[4], f1[4];
 #pragma unroll
@@ -163,9 +160,9 @@ __host__ __device__ T hist_saddle_term(int term, const HistLds<T>& L, int ev, co
 #pragma unroll
     for (int i = 0; i < 4; ++i) f1[i] = val(c[i], i, x1);
     acc = cfma(cv.slope * (x1 - x0), bern4(f0, f1), acc);
-    hist_cursor_step(cv, L, ev, false, x1, big);
+    suf_cursor_step(cv, L, ev, hv - a, x1, big);
 #pragma unroll
-    for (int i = 0; i < 4; ++i) hist_cursor_step(c[i], L, en[i], false, x1, big);
+    for (int i = 0; i < 4; ++i) suf_cursor_step(c[i], L, en[i], hs[i], x1, big);
 #pragma unroll
     for (int i = 0; i < 4; ++i) f0[i] = f1[i];
     x0 = x1;
@@ -215,9 +212,10 @@ CP_HD void vertex_saddle_ue(const T* L, int E, int e, const int (&en)[4], T& t1,
   }
 }
 
-// Histogram saddle terms of an interior vertex (validity checked by the caller).
+// Histogram saddle terms of an interior vertex (validity checked by the
+// caller; the staged masses already replaced by their suffix sums).
 template <typename T>
-__host__ __device__ void vertex_saddle_hist(const HistLds<T>& L, int e, const int (&en)[4], T& t1, T& t2) {
+__host__ __device__ void vertex_saddle_hist(const HistSuf<T>& L, int e, const int (&en)[4], T& t1, T& t2) {
   const int E = L.E;
   const T lov = L.base[e], hv = L.base[E + e] - lov;
   T lo[4], hi[4];

@@ -230,12 +230,15 @@ __device__ __forceinline__ void tile_fwd_hist(const FieldPtrs<T>& f, int ty0, in
   const int h = f.nb;
   stage<T, EY, EX, NT>(lds, f.params, 2 + h, f.ps, f.rs, f.H, f.W, ty0 - 1, tx0 - 1, tid);
   __syncthreads();
+  // validity, then masses -> suffix sums (the same thread owns each staged vertex)
   hist_stage_validity<T, NT>(lds, E, h, tid);
+  hist_stage_suffix<T, NT>(lds, E, h, tid);
   __syncthreads();
   const int lx = tid % TX, ly = tid / TX;
   const int x = tx0 + lx, y = ty0 + ly;
   if (x < f.W && y < f.H) {
     const HistLds<T> L{lds, E, h, T(1) / T(h)};
+    const HistSuf<T> U{lds, E, h};
     const int e = (ly + 1) * EX + lx + 1;
     const int en[4] = {e + 1, e - EX, e - 1, e + EX};
     const bool pres[4] = {x + 1 < f.W, y > 0, x > 0, y + 1 < f.H};
@@ -251,13 +254,7 @@ __device__ __forceinline__ void tile_fwd_hist(const FieldPtrs<T>& f, int ty0, in
         lo[i] = lds[en[i]] - lov;
         hi[i] = lds[E + en[i]] - lov;
       }
-      pmin = hist_side_value(L, e, en, pres, false, hiv - lov, lo, hi);
-#pragma unroll
-      for (int i = 0; i < 4; ++i) {
-        lo[i] = hiv - lds[E + en[i]];
-        hi[i] = hiv - lds[en[i]];
-      }
-      pmax = hist_side_value(L, e, en, pres, true, hiv - lov, lo, hi);
+      hist_vertex_minmax(U, e, en, pres, hiv - lov, lo, hi, pmin, pmax);
     }
     f.pmin[(int64_t)y * f.rs + x] = pmin;
     f.pmax[(int64_t)y * f.rs + x] = pmax;
