@@ -14,9 +14,9 @@
 //
 // Staged per vertex in LDS (planes of the extended tile, E vertices each):
 //   0 lo, 1 hi, 2..h+1 masses.  An invalid histogram (lo >= hi, non-finite,
-// negative mass) is marked by lo = NaN while staging.  Each cursor carries
-// the survival value at its next edge as a running FP64 sum of masses, which
-// is exact for FP32 masses.
+// negative mass) is marked by lo = NaN while staging.  The sweeps then
+// replace the masses by their suffix sums U_j = m_j + ... + m_{h-1} (FP64
+// sums rounded once), so the survival at an edge is one read.
 #pragma once
 
 #include "cp_device.hpp"
@@ -63,84 +63,6 @@ CP_HD T bern4(const T (&f0)[4], const T (&f1)[4]) {
   T e0 = d0 * f0[3], e1 = cfma(d0, f1[3], d1 * f0[3]), e2 = cfma(d1, f1[3], d2 * f0[3]),
     e3 = cfma(d2, f1[3], d3 * f0[3]), e4 = d3 * f1[3];
   return (e0 + e4) * T(0.2) + (e1 + e3) * T(0.05) + e2 * T(1.0 / 30.0);
-}
-
-// State of one neighbour histogram during the sweep: on the current bin,
-// S(x) = snx + slope * (nxt - x); nxt is the next edge to cross and snx the
-// survival there (sum of the masses above it).
-template <typename T>
-struct HistCursor {
-  int j;  // current bin (-1 below the range, h after the range / absent)
-  T lo, hi, d, id;
-  T nxt, snx, slope;
-  double snxd;
-};
-
-template <typename T>
-CP_HD T hist_edge(const HistCursor<T>& c, int j, int h) {
-  return j >= h ? c.hi : cfma(T(j), c.d, c.lo);
-}
-
-// Position the cursor of neighbour e (local range [lo, hi]) at x = 0.
-template <typename T>
-CP_HD void hist_cursor_init(HistCursor<T>& c, const HistLds<T>& L, int e, bool rev, T lo, T hi, bool present,
-                            T big) {
-  const int h = L.h;
-  c.lo = lo;
-  c.hi = hi;
-  c.d = (hi - lo) * L.ih;
-  c.id = T(h) * crcp(hi - lo);
-  c.slope = T(0);
-  if (!present) {
-    c.j = h;
-    c.nxt = big;
-    c.snx = T(1);
-    c.snxd = 1.0;
-    return;
-  }
-  int j = -1;
-  if (lo < T(0)) {
-    j = (int)(-lo * c.id);
-    j = j < 0 ? 0 : (j > h - 1 ? h - 1 : j);
-    if (j + 1 < h && !(hist_edge(c, j + 1, h) > T(0))) ++j;
-    if (j > 0 && hist_edge(c, j, h) > T(0)) --j;
-  }
-  // survival at the next edge: sum of the masses above bin j (all of them
-  // below the range), and the slope of the current bin
-  double tail = 0.0;
-  T mj = T(0);
-  for (int i = 0; i < h; ++i) {
-    const T m = L.mass(e, i, rev);
-    tail += i > j ? (double)m : 0.0;
-    mj = i == j ? m : mj;
-  }
-  c.j = j;
-  c.nxt = j < 0 ? lo : hist_edge(c, j + 1, h);
-  c.snxd = tail;
-  c.snx = (T)tail;
-  c.slope = mj * c.id;
-}
-
-// Cross the edge at x1 if it is this cursor's next edge.
-template <typename T>
-CP_HD bool hist_cursor_step(HistCursor<T>& c, const HistLds<T>& L, int e, bool rev, T x1, T big) {
-  const int h = L.h;
-  if (!(c.nxt == x1)) return false;
-  if (c.j < h - 1) {
-    c.j += 1;
-    c.nxt = hist_edge(c, c.j + 1, h);
-    const T m = L.mass(e, c.j, rev);
-    c.snxd -= (double)m;
-    c.snx = (T)c.snxd;
-    c.slope = m * c.id;
-  } else {  // passed the upper end: S = 0 from here on
-    c.j = h;
-    c.nxt = big;
-    c.snx = T(0);
-    c.snxd = 0.0;
-    c.slope = T(0);
-  }
-  return true;
 }
 
 }  // namespace cp
