@@ -72,9 +72,18 @@ def parse():
 
 
 # ----------------------------------------------------------------------------
-# algorithmic work of the Epanechnikov kernels: FLOPs per non-empty piece with
-# k started neighbours at the exact quadrature order (FMA = 2); redundant work
-# (empty pieces, halo ring, masked lanes) is not counted
+# algorithmic work of the Epanechnikov kernels: FLOPs of the kernels'
+# formulation per non-empty piece with k started neighbours at the exact
+# quadrature order n_k (FMA = 2); redundant work (empty pieces, halo ring,
+# masked lanes, sorting) is not counted.
+#   forward piece k:  setup 6 + 3k; per node 6 + 7k (node, vertex pdf, per
+#                     factor u, 4 S(u) and the product); 3 to accumulate.
+#                     Piece 0 (vertex CDF in closed form): 6.
+#   adjoint piece k:  setup 6 + 3k; per node 4 + 15k (node, weight x pdf,
+#                     per factor u, 4 S(u), prefix / suffix products, the
+#                     leave-one-out product times (1 - u^2), two moments);
+#                     4k to accumulate.  Piece 0 needs no adjoint work.
+#                     Per vertex 8 for the gather of the five stencils.
 # ----------------------------------------------------------------------------
 GL_NODES = {1: 3, 2: 5, 3: 6, 4: 8}  # exact rule for a piece with k started neighbours
 
@@ -82,13 +91,13 @@ GL_NODES = {1: 3, 2: 5, 3: 6, 4: 8}  # exact rule for a piece with k started nei
 def flops_fwd_piece(k):
     if k == 0:
         return 6
-    return 8 + 4 * k + GL_NODES[k] * (6 + 6 * k)
+    return 9 + 3 * k + GL_NODES[k] * (6 + 7 * k)
 
 
 def flops_bwd_piece(k):
     if k == 0:
-        return 10
-    return 10 + 8 * k + GL_NODES[k] * (10 + 18 * k)
+        return 0
+    return 6 + 7 * k + GL_NODES[k] * (4 + 15 * k)
 
 
 def epa_piece_counts(params: np.ndarray) -> np.ndarray:

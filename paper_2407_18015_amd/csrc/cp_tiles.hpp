@@ -110,18 +110,15 @@ CP_HD void vertex_fwd_ue(const T* L, int E, int e, const int (&en)[4], const boo
 // Jacobian of one stencil, weighted by the upstream gradients:
 // jac[slot*2 + q] = gmin dP_min/dtheta_q(slot) + gmax dP_max/dtheta_q(slot)
 // WF: also return P_min, P_max (the Epanechnikov adjoint skips them otherwise).
+// The stencil's parameters are passed by value: (p0, p1) of the vertex and
+// (q0[i], q1[i]) of neighbour i (e, n, w, s), read only where pres[i].
 template <typename T, int MODEL, bool WF = true>
-CP_HD void vertex_jac_ue(const T* L, int E, int e, const int (&en)[4], const bool (&pres)[4],
-                                              T gmin, T gmax, T (&jac)[10], T& pmin, T& pmax) {
-  const T p0 = L[e], p1 = L[E + e];
-  T q0[4], q1[4];
+CP_HD void vertex_jac_vals(T p0, T p1, const T (&q0)[4], const T (&q1)[4], const bool (&pres)[4], T gmin, T gmax,
+                           T (&jac)[10], T& pmin, T& pmax) {
   bool ok = MODEL == CP_UNIFORM ? valid_range(p0, p1) : valid_epa(p0, p1);
 #pragma unroll
-  for (int i = 0; i < 4; ++i) {
-    q0[i] = L[en[i]];
-    q1[i] = L[E + en[i]];
+  for (int i = 0; i < 4; ++i)
     if (pres[i]) ok = ok && (MODEL == CP_UNIFORM ? valid_range(q0[i], q1[i]) : valid_epa(q0[i], q1[i]));
-  }
   if (!ok) {
 #pragma unroll
     for (int k = 0; k < 10; ++k) jac[k] = qnan<T>();
@@ -276,49 +273,68 @@ struct BwdGeom {
   static constexpr int PX = OX + 4, PY = OY + 4, EP = PX * PY;  // parameters
 };
 
+// Stencils are dealt to threads as i = tid + k NT (k < KS).  Parameters are
+// read from global memory (L1 / L2 hits: the tile and its two-vertex halo);
+// the neighbour slots of each Jacobian (e, n, w, s: 8 planes) go to LDS, the
+// vertex's own slot stays in registers, because the thread that evaluated a
+// stencil also gathers the output at its centre.  Keeping LDS to 8 planes of
+// the stencil grid fits five workgroups per CU.
 template <typename T, int MODEL, int OX, int OY, int NT, bool WF>
 __device__ __forceinline__ void tile_bwd_ue_impl(const FieldPtrs<T>& f, int ty0, int tx0, T* lds, int tid) {
   using G = BwdGeom<OX, OY>;
-  T* par = lds;
-  T* J = lds + 2 * G::EP;
-  stage<T, G::PY, G::PX, NT>(par, f.params, 2, f.ps, f.rs, f.H, f.W, ty0 - 2, tx0 - 2, tid);
-  __syncthreads();
-  for (int i = tid; i < G::EJ; i += NT) {
-    const int ey = i / G::EX, ex = i - ey * G::EX;
-    const int gy = ty0 - 1 + ey, gx = tx0 - 1 + ex;
+  constexpr int KS = (G::EJ + NT - 1) / NT;
+  T* J = lds;  // [8][EJ]: (slot e, n, w, s) x (parameter 0, 1)
+  T own[KS][2];
+#pragma unroll
+  for (int k = 0; k < KS; ++k) {
+    const int i = tid + k * NT;
     T jac[10];
 #pragma unroll
-    for (int k = 0; k < 10; ++k) jac[k] = T(0);
-    if (gy >= 0 && gy < f.H && gx >= 0 && gx < f.W) {
-      const int e = (ey + 1) * G::PX + ex + 1;
-      const int en[4] = {e + 1, e - G::PX, e - 1, e + G::PX};
-      const bool pres[4] = {gx + 1 < f.W, gy > 0, gx > 0, gy + 1 < f.H};
-      const int64_t at = (int64_t)gy * f.rs + gx;
-      T pmin, pmax;
-      vertex_jac_ue<T, MODEL, WF>(par, G::EP, e, en, pres, f.gmin[at], f.gmax[at], jac, pmin, pmax);
-      // fused forward: the adjoint evaluates the probabilities as well
-      if (WF && ey >= 1 && ey <= OY && ex >= 1 && ex <= OX) {
-        f.pmin[at] = pmin;
-        f.pmax[at] = pmax;
-      }
-    }
+    for (int q = 0; q < 10; ++q) jac[q] = T(0);
+    if (i < G::EJ) {
+      const int ey = i / G::EX, ex = i - ey * G::EX;
+      const int gy = ty0 - 1 + ey, gx = tx0 - 1 + ex;
+      if (gy >= 0 && gy < f.H && gx >= 0 && gx < f.W) {
+        const bool pres[4] = {gx + 1 < f.W, gy > 0, gx > 0, gy + 1 < f.H};
+        const int64_t at = (int64_t)gy * f.rs + gx;
+        const int64_t an[4] = {at + 1, at - f.rs, at - 1, at + f.rs};
+        const T p0 = f.params[at], p1 = f.params[f.ps + at];
+        T q0[4], q1[4];
 #pragma unroll
-    for (int k = 0; k < 10; ++k) J[k * G::EJ + i] = jac[k];
+        for (int n = 0; n < 4; ++n) {
+          q0[n] = pres[n] ? f.params[an[n]] : T(0);
+          q1[n] = pres[n] ? f.params[f.ps + an[n]] : T(1);
+        }
+        T pmin, pmax;
+        vertex_jac_vals<T, MODEL, WF>(p0, p1, q0, q1, pres, f.gmin[at], f.gmax[at], jac, pmin, pmax);
+        // fused forward: the adjoint evaluates the probabilities as well
+        if (WF && ey >= 1 && ey <= OY && ex >= 1 && ex <= OX) {
+          f.pmin[at] = pmin;
+          f.pmax[at] = pmax;
+        }
+      }
+#pragma unroll
+      for (int q = 0; q < 8; ++q) J[q * G::EJ + i] = jac[2 + q];
+    }
+    own[k][0] = jac[0];
+    own[k][1] = jac[1];
   }
   __syncthreads();
-  for (int i = tid; i < OX * OY; i += NT) {
-    const int oy = i / OX, ox = i - oy * OX;
-    const int gy = ty0 + oy, gx = tx0 + ox;
-    if (gy < f.H && gx < f.W) {
-      const int c = (oy + 1) * G::EX + ox + 1;
 #pragma unroll
-      for (int q = 0; q < 2; ++q) {
-        // u is: slot v of its own stencil, w of its east neighbour's, e of
-        // its west neighbour's, s of its north neighbour's, n of its south's
-        const T g = J[(0 + q) * G::EJ + c] + J[(6 + q) * G::EJ + c + 1] + J[(2 + q) * G::EJ + c - 1] +
-                    J[(8 + q) * G::EJ + c - G::EX] + J[(4 + q) * G::EJ + c + G::EX];
-        f.grad[(int64_t)q * f.ps + (int64_t)gy * f.rs + gx] = g;
-      }
+  for (int k = 0; k < KS; ++k) {
+    const int i = tid + k * NT;
+    if (i >= G::EJ) continue;
+    const int ey = i / G::EX, ex = i - ey * G::EX;
+    if (ey < 1 || ey > OY || ex < 1 || ex > OX) continue;
+    const int gy = ty0 - 1 + ey, gx = tx0 - 1 + ex;
+    if (gy >= f.H || gx >= f.W) continue;
+#pragma unroll
+    for (int q = 0; q < 2; ++q) {
+      // u is: slot v of its own stencil, w of its east neighbour's, e of
+      // its west neighbour's, s of its north neighbour's, n of its south's
+      const T g = own[k][q] + J[(4 + q) * G::EJ + i + 1] + J[(0 + q) * G::EJ + i - 1] +
+                  J[(6 + q) * G::EJ + i - G::EX] + J[(2 + q) * G::EJ + i + G::EX];
+      f.grad[(int64_t)q * f.ps + (int64_t)gy * f.rs + gx] = g;
     }
   }
   __syncthreads();
@@ -334,7 +350,7 @@ __device__ __forceinline__ void tile_bwd_ue(const FieldPtrs<T>& f, int ty0, int 
 
 template <int OX, int OY>
 constexpr int bwd_ue_lds_elems() {
-  return 2 * BwdGeom<OX, OY>::EP + 10 * BwdGeom<OX, OY>::EJ;
+  return 8 * BwdGeom<OX, OY>::EJ;
 }
 
 // XCD-aware tile order: blocks are dealt to the 8 XCDs round-robin, so give
