@@ -59,6 +59,24 @@ cp_status_t check_desc(const cp_field_desc_t* d, cp::Field& f, bool sampling = t
   return CP_OK;
 }
 
+// Fit options with their defaults filled in; eps = the degenerate half-width
+// scale in effect.
+cp_status_t check_fit_opts(const cp::Field& f, int32_t n_members, const cp_fit_opts_t* opts, cp_fit_opts_t& o,
+                           double& eps) {
+  if (n_members < 1) return fail(CP_EINVAL, "n_members must be >= 1");
+  o = cp_fit_opts_t{1, 1.06, 1e-6, 0.0};
+  if (opts) o = *opts;
+  if (o.ddof < 0) return fail(CP_EDOMAIN, "ddof must be >= 0");
+  if (!(o.bw_factor > 0.0)) return fail(CP_EDOMAIN, "bw_factor must be > 0");
+  if (!(o.cov_jitter >= 0.0)) return fail(CP_EDOMAIN, "cov_jitter must be >= 0");
+  eps = o.degenerate_eps > 0.0 ? o.degenerate_eps : (f.dtype == CP_F64 ? 0x1p-30 : 0x1p-20);
+  if ((f.model == CP_EPANECHNIKOV || f.model == CP_GAUSSIAN) && n_members > 1 && n_members - o.ddof < 1)
+    return fail(CP_EDOMAIN, "n_members - ddof must be >= 1");
+  if (f.model == CP_MVGAUSS && (n_members < 2 || n_members - o.ddof < 1))
+    return fail(CP_EDOMAIN, "the Gaussian fit needs n_members >= 2 and n_members - ddof >= 1");
+  return CP_OK;
+}
+
 }  // namespace
 
 namespace cp {
@@ -133,17 +151,10 @@ cp_status_t cpu_fit_params(const cp_field_desc_t* desc, const void* members, int
   cp_status_t s = check_desc(desc, f, false);
   if (s != CP_OK) return s;
   if (!members || !params) return fail(CP_EINVAL, "members / params is NULL");
-  if (n_members < 1) return fail(CP_EINVAL, "n_members must be >= 1");
-  cp_fit_opts_t o{1, 1.06, 1e-6, 0.0};
-  if (opts) o = *opts;
-  if (o.ddof < 0) return fail(CP_EDOMAIN, "ddof must be >= 0");
-  if (!(o.bw_factor > 0.0)) return fail(CP_EDOMAIN, "bw_factor must be > 0");
-  if (!(o.cov_jitter >= 0.0)) return fail(CP_EDOMAIN, "cov_jitter must be >= 0");
-  double eps = o.degenerate_eps > 0.0 ? o.degenerate_eps : (f.dtype == CP_F64 ? 0x1p-30 : 0x1p-20);
-  if ((f.model == CP_EPANECHNIKOV || f.model == CP_GAUSSIAN) && n_members > 1 && n_members - o.ddof < 1)
-    return fail(CP_EDOMAIN, "n_members - ddof must be >= 1");
-  if (f.model == CP_MVGAUSS && (n_members < 2 || n_members - o.ddof < 1))
-    return fail(CP_EDOMAIN, "the Gaussian fit needs n_members >= 2 and n_members - ddof >= 1");
+  cp_fit_opts_t o;
+  double eps;
+  s = check_fit_opts(f, n_members, opts, o, eps);
+  if (s != CP_OK) return s;
   hipError_t e = cp::fit_params(f, members, n_members, o.ddof, o.bw_factor, o.cov_jitter, eps, params,
                                 static_cast<hipStream_t>(stream));
   if (e != hipSuccess) return device_fail(e, "fit launch");

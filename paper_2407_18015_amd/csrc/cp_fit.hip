@@ -20,6 +20,7 @@
 
 #include <cmath>
 
+#include "cp_fit.hpp"
 #include "cp_internal.hpp"
 
 namespace cp {
@@ -27,47 +28,6 @@ namespace cp {
 namespace {
 
 constexpr int kFitTX = 64, kFitTY = 4, kMaxRegMembers = 32;
-
-template <typename T>
-__device__ __forceinline__ T rn_sub(T a, T b);
-template <>
-__device__ __forceinline__ float rn_sub(float a, float b) {
-  return __fsub_rn(a, b);
-}
-template <>
-__device__ __forceinline__ double rn_sub(double a, double b) {
-  return __dsub_rn(a, b);
-}
-template <typename T>
-__device__ __forceinline__ T rn_add(T a, T b);
-template <>
-__device__ __forceinline__ float rn_add(float a, float b) {
-  return __fadd_rn(a, b);
-}
-template <>
-__device__ __forceinline__ double rn_add(double a, double b) {
-  return __dadd_rn(a, b);
-}
-template <typename T>
-__device__ __forceinline__ T rn_mul(T a, T b);
-template <>
-__device__ __forceinline__ float rn_mul(float a, float b) {
-  return __fmul_rn(a, b);
-}
-template <>
-__device__ __forceinline__ double rn_mul(double a, double b) {
-  return __dmul_rn(a, b);
-}
-template <typename T>
-__device__ __forceinline__ T rn_div(T a, T b);
-template <>
-__device__ __forceinline__ float rn_div(float a, float b) {
-  return __fdiv_rn(a, b);
-}
-template <>
-__device__ __forceinline__ double rn_div(double a, double b) {
-  return __ddiv_rn(a, b);
-}
 
 template <typename T>
 __device__ __forceinline__ int bin_of(T x, T lo, T hi, int nb) {
@@ -85,8 +45,8 @@ struct FitArgs {
   double eps;
 };
 
-// Uniform / Epanechnikov / histogram.  MM: members held in registers
-// (M <= MM); MM == 0 streams them twice from memory.
+// Uniform / Epanechnikov / histogram.  MM (histogram): members held in
+// registers (M <= MM); MM == 0 streams them twice from memory.
 template <typename T, int MODEL, int MM>
 __global__ __launch_bounds__(kFitTX* kFitTY) void k_fit(FitArgs a) {
   __shared__ int counts[MODEL == CP_HISTOGRAM ? kMaxBins * kFitTX * kFitTY : 1];
@@ -98,30 +58,20 @@ __global__ __launch_bounds__(kFitTX* kFitTY) void k_fit(FitArgs a) {
   T* par = static_cast<T*>(a.params);
   const int64_t at = (int64_t)y * a.rs + x;
   const int M = a.M;
+  if (MODEL != CP_HISTOGRAM) {
+    T p0, p1;
+    fit_ue_vertex<T, MODEL>(mem, M, a.ps, at, a.wscale, a.eps, p0, p1);
+    par[at] = p0;
+    par[a.ps + at] = p1;
+    return;
+  }
   T v[MM > 0 ? MM : 1];
   T mn, mx;
-  double s1 = 0.0, s2 = 0.0, shift;
-  if (MODEL != CP_HISTOGRAM) {
-    // one streaming pass: min, max and shifted sums
-    mn = mx = mem[at];
-    shift = (double)mn;
-#pragma unroll 4
-    for (int k = 0; k < M; ++k) {
-      const T xk = mem[(int64_t)k * a.ps + at];
-      mn = xk < mn ? xk : mn;
-      mx = xk > mx ? xk : mx;
-      if (MODEL == CP_EPANECHNIKOV) {
-        const double d = (double)xk - shift;
-        s1 += d;
-        s2 = fma(d, d, s2);
-      }
-    }
-  } else if (MM > 0) {
+  if (MM > 0) {
 #pragma unroll
     for (int k = 0; k < (MM > 0 ? MM : 1); ++k)
       if (k < M) v[k] = mem[(int64_t)k * a.ps + at];
     mn = mx = v[0];
-    shift = (double)v[0];
 #pragma unroll
     for (int k = 1; k < (MM > 0 ? MM : 1); ++k)
       if (k < M) {
@@ -130,40 +80,17 @@ __global__ __launch_bounds__(kFitTX* kFitTY) void k_fit(FitArgs a) {
       }
   } else {
     mn = mx = mem[at];
-    shift = (double)mn;
-    for (int k = 0; k < M; ++k) {
+    for (int k = 1; k < M; ++k) {
       const T xk = mem[(int64_t)k * a.ps + at];
       mn = xk < mn ? xk : mn;
       mx = xk > mx ? xk : mx;
-      const double d = (double)xk - shift;
-      s1 += d;
-      s2 = fma(d, d, s2);
     }
   }
-  const bool degenerate = !(mn < mx);
   T lo = mn, hi = mx;
-  if (degenerate) {
-    const T e = rn_mul(T(a.eps), mn < T(0) ? (-mn > T(1) ? -mn : T(1)) : (mn > T(1) ? mn : T(1)));
+  if (!(mn < mx)) {
+    const T e = degenerate_half(T(a.eps), mn);
     lo = rn_sub(mn, e);
     hi = rn_add(mn, e);
-  }
-  if (MODEL == CP_UNIFORM) {
-    par[at] = lo;
-    par[a.ps + at] = hi;
-    return;
-  }
-  if (MODEL == CP_EPANECHNIKOV) {
-    const double mean = shift + s1 / (double)M;
-    double w;
-    if (degenerate) {
-      w = a.eps * fmax(1.0, fabs(mean));
-    } else {
-      const double ss = fmax(s2 - s1 * s1 / (double)M, 0.0);
-      w = a.wscale * sqrt(ss);
-    }
-    par[at] = (T)mean;
-    par[a.ps + at] = (T)w;
-    return;
   }
   // histogram: per-thread counters in LDS (dynamic bin index)
   int* cnt = counts + tid;
@@ -340,10 +267,7 @@ hipError_t fit_params(const Field& f, const void* members, int M, int ddof, doub
   a.ddof = ddof;
   a.rs = f.rs;
   a.ps = f.plane();
-  // Epanechnikov half-width bw * sd * M^(-1/5); Gaussian sigma = sd; both as
-  // wscale * sqrt(sum of squared deviations)
-  a.wscale = M - ddof > 0 ? bw * std::pow((double)M, -0.2) / std::sqrt((double)(M - ddof)) : 0.0;
-  if (f.model == CP_GAUSSIAN) a.wscale = M - ddof > 0 ? 1.0 / std::sqrt((double)(M - ddof)) : 0.0;
+  a.wscale = fit_wscale(f.model, M, ddof, bw);
   a.eps = eps;
   if (f.model == CP_MVGAUSS) {
     dim3 grid((a.W + kFitTX - 1) / kFitTX, (a.H + kFitTY - 1) / kFitTY);

@@ -3,6 +3,7 @@
 
 #include <hip/hip_runtime.h>
 
+#include <cmath>
 #include <cstdint>
 
 #include "cpcrit.h"
@@ -39,6 +40,14 @@ hipError_t semi_forward(const Field& f, const void* params, void* pmin, void* pm
 hipError_t fit_params(const Field& f, const void* members, int M, int ddof, double bw, double jitter,
                       double eps, void* params, hipStream_t st);
 hipError_t fit_error_bound(const Field& f, const void* decompressed, double eb, void* params, hipStream_t st);
+
+// Epanechnikov half-width bw * sd * M^(-1/5), Gaussian sigma = sd; both as
+// wscale * sqrt(sum of squared deviations about the mean)
+inline double fit_wscale(int model, int M, int ddof, double bw) {
+  if (M - ddof <= 0) return 0.0;
+  if (model == CP_GAUSSIAN) return 1.0 / std::sqrt((double)(M - ddof));
+  return bw * std::pow((double)M, -0.2) / std::sqrt((double)(M - ddof));
+}
 
 // multivariate Gaussian
 hipError_t mvg_forward(const Field& f, const double* params, float* pmin, float* pmax, hipStream_t st);
