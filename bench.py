@@ -350,7 +350,19 @@ def batched_detail(cp, workloads, torch, dev):
         ms = _timed(torch, lambda: cp.batched(fields, params, pmin, pmax, **kw), 5)
         out[name + "_fwd_ms"] = ms
         out[name + "_fwd_vertices_per_s"] = nv / (ms * 1e-3)
+    # autotuned plans: the first call times every tile shape and claim chunk of
+    # each pass on these fields, later calls (and the graph) reuse the choice
+    for tag, g in (("fwd_bwd", (gmin, gmax, grad)), ("fwd", (None, None, None))):
+        t0 = time.time()
+        cp.batched(fields, params, pmin, pmax, *g, tune=True)
+        torch.cuda.synchronize()
+        out["tuning_s_" + tag] = time.time() - t0
+        ms = _timed(torch, lambda: cp.batched(fields, params, pmin, pmax, *g, graph=True), 5)
+        out["tuned_graph_" + tag + "_ms"] = ms
+        out["tuned_graph_" + tag + "_vertices_per_s"] = nv / (ms * 1e-3)
+        out["tuned_plan_" + tag] = cp.batched_describe(fields, fwd=True, bwd=g[2] is not None)
     out["speedup_fwd_bwd_graph_vs_per_field"] = out["per_field_fwd_bwd_ms"] / out["graph_fwd_bwd_ms"]
+    out["speedup_fwd_bwd_tuned_graph_vs_per_field"] = out["per_field_fwd_bwd_ms"] / out["tuned_graph_fwd_bwd_ms"]
     return out
 
 

@@ -226,6 +226,7 @@ cp_status_t cp_prob_semianalytical(const cp_field_desc_t* desc, const void* para
 #define CP_BATCH_BWD 2u       /* write grad_params (needs g_min / g_max) */
 #define CP_BATCH_GRAPH 4u     /* replay a cached HIP graph of the persistent launch */
 #define CP_BATCH_PER_FIELD 8u /* reference mode: one forward / backward launch per field */
+#define CP_BATCH_TUNE 16u     /* autotune the plan's tile shapes and claim chunks (first call) */
 
 /*
  * Many independent fields (mixed sizes, closed-form models, one dtype) in one
@@ -239,11 +240,53 @@ cp_status_t cp_prob_semianalytical(const cp_field_desc_t* desc, const void* para
  * concurrently (e.g. on two streams without ordering between them).
  * Gaussian fields (CP_MVGAUSS, CP_GAUSSIAN) are not accepted here
  * (CP_EUNSUPPORTED).
+ * CP_BATCH_TUNE: the first call with these shapes and flags times, for every
+ * pass of the plan, each tile shape the library offers (forward and
+ * histogram passes: 64 x 4 or 64 x 8 vertices; uniform / Epanechnikov
+ * adjoint: FP32 30x30, 14x14 or 62x30 outputs, FP64 14x14, 30x14 or 30x30)
+ * with each claim chunk (1, 2, 4, 8 tiles) on the caller's own buffers, and
+ * keeps the fastest for every later call; the call then blocks until the
+ * trials are done, and fails (CP_EINVAL) while the stream is being captured.
+ * The trials write the outputs, with the same values: no tile shape changes
+ * a result.  Without the flag a plan uses the first shape and a fixed chunk.
  */
 cp_status_t cp_prob_batched(int32_t n, const cp_field_desc_t* descs, const void* const* params,
                             void* const* p_min, void* const* p_max, const void* const* g_min,
                             const void* const* g_max, void* const* grad_params, uint32_t flags,
                             void* stream);
+
+/* Passes of a batched plan (index of the arrays of cp_batched_pin). */
+typedef enum {
+  CP_PASS_FORWARD = 0,        /* uniform / Epanechnikov forward */
+  CP_PASS_HIST_FORWARD = 1,   /* histogram forward */
+  CP_PASS_ADJOINT = 2,        /* uniform / Epanechnikov adjoint */
+  CP_PASS_HIST_ADJOINT = 3,   /* histogram adjoint sweep (per-stencil Jacobians) */
+  CP_PASS_HIST_GATHER = 4,    /* histogram adjoint gather */
+  CP_NUM_PASSES = 5
+} cp_batch_pass_t;
+
+/*
+ * Fix the tile shape and claim chunk of each pass of the plan that
+ * cp_prob_batched uses for these descriptors and flags (building the plan if
+ * no call has yet): shape[p] indexes the shapes listed under CP_BATCH_TUNE
+ * for pass p (0 = the default), chunk[p] >= 1 tiles per claim; entries < 0
+ * (shape) or < 1 (chunk) keep the current choice, entries of passes the plan
+ * lacks are ignored.  For callers that tuned offline and want the result
+ * without timing, or that want one shape.  A pinned plan is not re-tuned.
+ * CP_EINVAL: a shape index out of range; CP_EUNSUPPORTED: the shape does not
+ * fit a workgroup for these fields.
+ */
+cp_status_t cp_batched_pin(int32_t n, const cp_field_desc_t* descs, uint32_t flags, const int32_t* shape,
+                           const int32_t* chunk);
+
+/*
+ * The plan a cp_prob_batched call with these descriptors and flags uses, as
+ * text: "tuned", "pinned" or "default", then per pass its shape index and
+ * tile, claim chunk, tile count, resident grid and (tuned) launch time.  Returns NULL when no
+ * call has built that plan yet.  The string is thread-local, valid until
+ * the next call of this function on the thread.
+ */
+const char* cp_batched_describe(int32_t n, const cp_field_desc_t* descs, uint32_t flags);
 
 /* Number of parameter planes of a model (histogram: 2 + nbins; Gaussian: 16). */
 int32_t cp_n_params(int32_t model, int32_t nbins);

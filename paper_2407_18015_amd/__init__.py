@@ -10,8 +10,10 @@ batched persistent launch.  All computation runs in the HIP library
 ``libcpcrit.so`` behind the C ABI of ``include/cpcrit.h``.
 """
 from . import _lib
-from .ops import (CPProb, Field, backward, batched, classify, critical_point_probability, field_of, fit,
-                  fit_error_bound, forward, n_params, philox, semianalytical)
+from .ops import (CPProb, Field, backward, batched, batched_describe, batched_pin,
+                  classify, critical_point_probability, field_of, fit, fit_error_bound, forward,
+                  n_params, philox, semianalytical)
 
-__all__ = ["CPProb", "Field", "backward", "batched", "classify", "critical_point_probability", "field_of", "fit",
-           "fit_error_bound", "forward", "n_params", "philox", "semianalytical", "_lib"]
+__all__ = ["CPProb", "Field", "backward", "batched", "batched_describe", "batched_pin",
+           "classify", "critical_point_probability", "field_of", "fit", "fit_error_bound", "forward",
+           "n_params", "philox", "semianalytical", "_lib"]

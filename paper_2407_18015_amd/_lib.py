@@ -16,10 +16,10 @@ CP_OK, CP_EINVAL, CP_EDOMAIN, CP_ENOMEM, CP_EDEVICE, CP_EUNSUPPORTED = range(6)
 CP_UNIFORM, CP_EPANECHNIKOV, CP_HISTOGRAM, CP_MVGAUSS, CP_GAUSSIAN = range(5)
 CP_F32, CP_F64 = 0, 1
 CP_MC_CONDITIONAL, CP_MC_HIT = 0, 1
-CP_BATCH_FWD, CP_BATCH_BWD, CP_BATCH_GRAPH, CP_BATCH_PER_FIELD = 1, 2, 4, 8
+CP_BATCH_FWD, CP_BATCH_BWD, CP_BATCH_GRAPH, CP_BATCH_PER_FIELD, CP_BATCH_TUNE = 1, 2, 4, 8, 16
 
 EXPORTS = ["cpu_fit_params", "cp_fit_error_bound", "cp_prob_forward", "cp_prob_backward", "cp_prob_classify", "cp_prob_semianalytical",
-           "cp_prob_batched",
+           "cp_prob_batched", "cp_batched_pin", "cp_batched_describe",
            "cp_n_params", "cp_status_string", "cp_last_error", "cp_release", "cp_philox4x32_10", "cp_gauss_legendre"]
 
 
@@ -65,6 +65,8 @@ def load() -> ctypes.CDLL:
         "cp_prob_classify": (i32, [D, P, P, P, P, P, P, P]),
         "cp_prob_semianalytical": (i32, [D, P, P, P, P, P]),
         "cp_prob_batched": (i32, [i32, D, PP, PP, PP, PP, PP, PP, u32, P]),
+        "cp_batched_pin": (i32, [i32, D, u32, ctypes.POINTER(i32), ctypes.POINTER(i32)]),
+        "cp_batched_describe": (ctypes.c_char_p, [i32, D, u32]),
         "cp_n_params": (i32, [i32, i32]),
         "cp_status_string": (ctypes.c_char_p, [i32]),
         "cp_last_error": (ctypes.c_char_p, []),
@@ -123,6 +125,23 @@ def cp_prob_batched(n, descs, params, p_min, p_max, g_min, g_max, grad_params, f
     return load().cp_prob_batched(n, arr, cast(_ptr_array(params)), cast(_ptr_array(p_min)),
                                   cast(_ptr_array(p_max)), cast(_ptr_array(g_min)), cast(_ptr_array(g_max)),
                                   cast(_ptr_array(grad_params)), flags, stream)
+
+
+def cp_batched_pin(n, descs, flags, shape, chunk) -> int:
+    """shape, chunk: 5 entries each, indexed by pass (forward, histogram
+    forward, adjoint, histogram adjoint sweep, histogram gather)."""
+    arr = (cp_field_desc_t * n)(*descs)
+    sh = (ctypes.c_int32 * 5)(*shape)
+    ch = (ctypes.c_int32 * 5)(*chunk)
+    return load().cp_batched_pin(n, arr, flags, sh, ch)
+
+
+def cp_batched_describe(n, descs, flags):
+    """Text of the plan a cp_prob_batched call with these descriptors and
+    flags uses, or None before that plan exists."""
+    arr = (cp_field_desc_t * n)(*descs)
+    r = load().cp_batched_describe(n, arr, flags)
+    return None if r is None else r.decode()
 
 
 def cp_n_params(model: int, nbins: int) -> int:

@@ -247,7 +247,7 @@ cp_status_t cp_prob_batched(int32_t n, const cp_field_desc_t* descs, const void*
   if (n < 1 || !descs || !params) return fail(CP_EINVAL, "n < 1 or descs / params is NULL");
   const bool fwd = flags & CP_BATCH_FWD, bwd = flags & CP_BATCH_BWD;
   if (!fwd && !bwd) return fail(CP_EINVAL, "flags select neither forward nor backward");
-  if (flags & ~(CP_BATCH_FWD | CP_BATCH_BWD | CP_BATCH_GRAPH | CP_BATCH_PER_FIELD))
+  if (flags & ~(CP_BATCH_FWD | CP_BATCH_BWD | CP_BATCH_GRAPH | CP_BATCH_PER_FIELD | CP_BATCH_TUNE))
     return fail(CP_EINVAL, "unknown flag bits");
   if (fwd && (!p_min || !p_max)) return fail(CP_EINVAL, "p_min / p_max arrays are NULL");
   if (bwd && (!g_min || !g_max || !grad_params)) return fail(CP_EINVAL, "backward arrays are NULL");
@@ -267,6 +267,39 @@ cp_status_t cp_prob_batched(int32_t n, const cp_field_desc_t* descs, const void*
                               static_cast<hipStream_t>(stream), &why);
   if (s != CP_OK) return fail(s, why);
   return CP_OK;
+}
+
+cp_status_t cp_batched_pin(int32_t n, const cp_field_desc_t* descs, uint32_t flags, const int32_t* shape,
+                           const int32_t* chunk) {
+  if (n < 1 || !descs || !shape || !chunk) return fail(CP_EINVAL, "n < 1 or a NULL array");
+  if (!(flags & (CP_BATCH_FWD | CP_BATCH_BWD))) return fail(CP_EINVAL, "flags select neither forward nor backward");
+  std::vector<cp::Field> fs(n);
+  for (int i = 0; i < n; ++i) {
+    cp_status_t s = check_desc(&descs[i], fs[i]);
+    if (s != CP_OK) return s;
+    if (fs[i].model == CP_MVGAUSS || fs[i].model == CP_GAUSSIAN)
+      return fail(CP_EUNSUPPORTED, "batched: Gaussian fields are not accepted");
+    if (fs[i].dtype != fs[0].dtype) return fail(CP_EINVAL, "batched: all fields must share one dtype");
+  }
+  int sh[CP_NUM_PASSES], ch[CP_NUM_PASSES];
+  for (int q = 0; q < CP_NUM_PASSES; ++q) {
+    sh[q] = shape[q];
+    ch[q] = chunk[q];
+  }
+  const char* why = "batched pin failed";
+  cp_status_t s = cp::batched_pin(n, fs.data(), flags, sh, ch, &why);
+  if (s != CP_OK) return fail(s, why);
+  return CP_OK;
+}
+
+const char* cp_batched_describe(int32_t n, const cp_field_desc_t* descs, uint32_t flags) {
+  static thread_local std::string text;
+  if (n < 1 || !descs) return nullptr;
+  std::vector<cp::Field> fs(n);
+  for (int i = 0; i < n; ++i)
+    if (check_desc(&descs[i], fs[i]) != CP_OK) return nullptr;
+  if (!cp::batched_describe(n, fs.data(), flags, text)) return nullptr;
+  return text.c_str();
 }
 
 cp_status_t cp_release(void) {

@@ -23,7 +23,9 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <cstdio>
 #include <cstring>
+#include <string>
 #include <map>
 #include <memory>
 #include <mutex>
@@ -38,11 +40,20 @@ namespace cp {
 namespace {
 
 constexpr int kNT = 256;
-constexpr int kBwdF32 = 30, kBwdF64 = 14;  // uniform / Epanechnikov adjoint tile edges
 constexpr int kGatherChunk = 256;          // histogram gather: vertices per tile
 constexpr size_t kMaxLds = 160 * 1024;
 
 enum { PASS_FWD_UE = 0, PASS_FWD_HIST = 1, PASS_BWD_UE = 2, PASS_BWD_HIST = 3, PASS_GATHER = 4, NPASS = 5 };
+
+// Tile variants of each pass (the tuner picks one per pass; variant 0 is the
+// default).  Forward and histogram passes: 64 x (4 << v) vertices, one or two
+// rows per thread.  Uniform / Epanechnikov adjoint: output tiles of
+// bwd_ox x bwd_oy (FP32 30x30, 14x14, 62x30; FP64 14x14, 30x14, 30x30), i.e.
+// 1 to 8 stencils per thread.  The tile shape changes no per-vertex
+// arithmetic: every variant gives the same results bit for bit.
+constexpr int n_variants(int pass) { return pass == PASS_BWD_UE ? 3 : (pass == PASS_GATHER ? 1 : 2); }
+__host__ __device__ constexpr int bwd_ox(bool f32, int v) { return f32 ? (v == 2 ? 62 : (v == 1 ? 14 : 30)) : (v == 0 ? 14 : 30); }
+__host__ __device__ constexpr int bwd_oy(bool f32, int v) { return f32 ? (v == 1 ? 14 : 30) : (v == 2 ? 30 : 14); }
 
 struct BatchTile {
   int field, ty0, tx0, pad;  // gather tiles: ty0 = first flat vertex index
@@ -90,7 +101,7 @@ constexpr int batched_min_waves() {
 // of the next chunk is issued before the current one is processed, so its
 // latency overlaps the tile's own loads.  Every block leaves once the counter
 // has passed the last chunk (the loop ends for all).
-template <typename T, int PASS>
+template <typename T, int PASS, int V>
 __global__ __launch_bounds__(kNT, (batched_min_waves<T, PASS>())) void k_batched(
     const BatchField<T>* __restrict__ fields, const BatchTile* __restrict__ tiles, int ntiles, int chunk,
     int* queue) {
@@ -98,7 +109,8 @@ __global__ __launch_bounds__(kNT, (batched_min_waves<T, PASS>())) void k_batched
   __shared__ int claimed;
   T* lds = reinterpret_cast<T*>(smem);
   const int tid = threadIdx.x;
-  constexpr int OB = sizeof(T) == 4 ? kBwdF32 : kBwdF64;
+  constexpr int TY = 4 << V;
+  constexpr int OX = bwd_ox(sizeof(T) == 4, V), OY = bwd_oy(sizeof(T) == 4, V);
   const int nchunks = (ntiles + chunk - 1) / chunk;
   if (tid == 0) claimed = atomicAdd(&queue[0], 1);
   __syncthreads();
@@ -111,20 +123,20 @@ __global__ __launch_bounds__(kNT, (batched_min_waves<T, PASS>())) void k_batched
     for (int t = c * chunk; t < t1; ++t) {
       const BatchTile tl = tiles[t];
       const BatchField<T> F = fields[tl.field];
-      if (PASS == PASS_FWD_UE) {
+      if constexpr (PASS == PASS_FWD_UE) {
         if (F.model == CP_UNIFORM)
-          tile_fwd_ue<T, CP_UNIFORM, 4>(F.p, tl.ty0, tl.tx0, lds, tid);
+          tile_fwd_ue<T, CP_UNIFORM, TY, kNT>(F.p, tl.ty0, tl.tx0, lds, tid);
         else
-          tile_fwd_ue<T, CP_EPANECHNIKOV, 4>(F.p, tl.ty0, tl.tx0, lds, tid);
-      } else if (PASS == PASS_FWD_HIST) {
-        tile_fwd_hist<T, 4>(F.p, tl.ty0, tl.tx0, lds, tid);
-      } else if (PASS == PASS_BWD_UE) {
+          tile_fwd_ue<T, CP_EPANECHNIKOV, TY, kNT>(F.p, tl.ty0, tl.tx0, lds, tid);
+      } else if constexpr (PASS == PASS_FWD_HIST) {
+        tile_fwd_hist<T, TY, kNT>(F.p, tl.ty0, tl.tx0, lds, tid);
+      } else if constexpr (PASS == PASS_BWD_UE) {
         if (F.model == CP_UNIFORM)
-          tile_bwd_ue<T, CP_UNIFORM, OB, OB, kNT>(F.p, tl.ty0, tl.tx0, lds, tid);
+          tile_bwd_ue<T, CP_UNIFORM, OX, OY, kNT>(F.p, tl.ty0, tl.tx0, lds, tid);
         else
-          tile_bwd_ue<T, CP_EPANECHNIKOV, OB, OB, kNT>(F.p, tl.ty0, tl.tx0, lds, tid);
-      } else if (PASS == PASS_BWD_HIST) {
-        tile_hist_sweep<T, 4>(F.p, tl.ty0, tl.tx0, lds, tid, F.J);
+          tile_bwd_ue<T, CP_EPANECHNIKOV, OX, OY, kNT>(F.p, tl.ty0, tl.tx0, lds, tid);
+      } else if constexpr (PASS == PASS_BWD_HIST) {
+        tile_hist_sweep<T, TY, kNT>(F.p, tl.ty0, tl.tx0, lds, tid, F.J);
       } else {
         hist_gather_chunk<T>(F.p, F.J, tl.ty0, tid);
       }
@@ -144,6 +156,22 @@ __global__ __launch_bounds__(kNT, (batched_min_waves<T, PASS>())) void k_batched
   }
 }
 
+template <typename T>
+const void* kernel_of(int pass, int v) {
+  switch (pass * 4 + v) {
+    case PASS_FWD_UE * 4 + 0: return reinterpret_cast<const void*>(k_batched<T, PASS_FWD_UE, 0>);
+    case PASS_FWD_UE * 4 + 1: return reinterpret_cast<const void*>(k_batched<T, PASS_FWD_UE, 1>);
+    case PASS_FWD_HIST * 4 + 0: return reinterpret_cast<const void*>(k_batched<T, PASS_FWD_HIST, 0>);
+    case PASS_FWD_HIST * 4 + 1: return reinterpret_cast<const void*>(k_batched<T, PASS_FWD_HIST, 1>);
+    case PASS_BWD_UE * 4 + 0: return reinterpret_cast<const void*>(k_batched<T, PASS_BWD_UE, 0>);
+    case PASS_BWD_UE * 4 + 1: return reinterpret_cast<const void*>(k_batched<T, PASS_BWD_UE, 1>);
+    case PASS_BWD_UE * 4 + 2: return reinterpret_cast<const void*>(k_batched<T, PASS_BWD_UE, 2>);
+    case PASS_BWD_HIST * 4 + 0: return reinterpret_cast<const void*>(k_batched<T, PASS_BWD_HIST, 0>);
+    case PASS_BWD_HIST * 4 + 1: return reinterpret_cast<const void*>(k_batched<T, PASS_BWD_HIST, 1>);
+    default: return reinterpret_cast<const void*>(k_batched<T, PASS_GATHER, 0>);
+  }
+}
+
 // Relative cost per vertex (forward, adjoint), measured on MI355X with the
 // per-field kernels at 2048^2 (uniform forward = 1); histograms scale with
 // the number of bin edges.
@@ -153,26 +181,58 @@ double vertex_cost(int model, int nb, bool bwd) {
   return (bwd ? 5.6 : 2.3) * (nb + 1);
 }
 
-size_t tile_lds_bytes(int model, int nb, bool bwd, size_t el) {
-  if (model == CP_HISTOGRAM) return el * (size_t)hist_planes(nb) * (kFwdTX + 2) * 6;
-  if (!bwd) return el * 2 * (kFwdTX + 2) * 6;
-  if (el == 4) return el * bwd_ue_lds_elems<kBwdF32, kBwdF32>();
-  return el * bwd_ue_lds_elems<kBwdF64, kBwdF64>();
+const char* pass_name(int pass) {
+  static const char* names[NPASS] = {"forward", "histogram forward", "adjoint", "histogram adjoint sweep",
+                                     "histogram gather"};
+  return names[pass];
+}
+
+// output tile extents of a pass variant
+void pass_geom(int pass, int v, size_t el, int& ox, int& oy) {
+  if (pass == PASS_BWD_UE) {
+    ox = bwd_ox(el == 4, v);
+    oy = bwd_oy(el == 4, v);
+  } else if (pass == PASS_GATHER) {
+    ox = kGatherChunk;
+    oy = 1;
+  } else {
+    ox = kFwdTX;
+    oy = 4 << v;
+  }
+}
+
+size_t tile_lds_bytes(int pass, int v, int nb, size_t el) {
+  int ox, oy;
+  pass_geom(pass, v, el, ox, oy);
+  if (pass == PASS_FWD_HIST || pass == PASS_BWD_HIST) return el * (size_t)hist_planes(nb) * (ox + 2) * (oy + 2);
+  if (pass == PASS_FWD_UE) return el * 2 * (ox + 2) * (oy + 2);
+  if (pass == PASS_BWD_UE) return el * 8 * (size_t)(ox + 2) * (oy + 2);
+  return 0;
 }
 
 struct Pass {
   int kind = 0;
+  int variant = 0;
   int grid = 0;
   size_t lds = 0;
   int ntiles = 0;
   int chunk = 1;
+  double ms = -1.0;        // tuned launch time (ms), < 0 when not tuned
   int* d_queue = nullptr;  // 2 counters, zero between launches
   BatchTile* d_tiles = nullptr;
+  void release() {
+    if (d_queue) (void)hipFree(d_queue);
+    if (d_tiles) (void)hipFree(d_tiles);
+    d_queue = nullptr;
+    d_tiles = nullptr;
+  }
 };
 
 struct Plan {
   int dtype = 0;
   bool bwd = false;
+  bool tuned = false;
+  std::vector<Field> fields;
   std::vector<Pass> passes;  // launched in this order
   void* d_fields = nullptr;
   void* d_ws = nullptr;             // histogram Jacobians of all fields
@@ -180,13 +240,15 @@ struct Plan {
   std::vector<unsigned char> host_fields;  // last uploaded field table
   hipGraphExec_t exec = nullptr;
   hipGraph_t graph = nullptr;
-  ~Plan() {
+  void drop_graph() {
     if (exec) (void)hipGraphExecDestroy(exec);
     if (graph) (void)hipGraphDestroy(graph);
-    for (Pass& p : passes) {
-      if (p.d_queue) (void)hipFree(p.d_queue);
-      if (p.d_tiles) (void)hipFree(p.d_tiles);
-    }
+    exec = nullptr;
+    graph = nullptr;
+  }
+  ~Plan() {
+    drop_graph();
+    for (Pass& p : passes) p.release();
     if (d_fields) (void)hipFree(d_fields);
     if (d_ws) (void)hipFree(d_ws);
   }
@@ -196,9 +258,13 @@ std::mutex g_mu;
 std::map<std::vector<int64_t>, std::unique_ptr<Plan>> g_plans;
 int g_num_cu = 0;
 
-template <typename T, int PASS>
-hipError_t prepare_kernel(size_t lds, int* per_cu) {
-  const void* k = reinterpret_cast<const void*>(k_batched<T, PASS>);
+const void* kernel_for(int dtype, int pass, int v) {
+  return dtype == CP_F64 ? kernel_of<double>(pass, v) : kernel_of<float>(pass, v);
+}
+
+// resident blocks per CU of a pass variant (0: it cannot run)
+hipError_t blocks_per_cu(int dtype, int pass, int v, size_t lds, int* per_cu) {
+  const void* k = kernel_for(dtype, pass, v);
   if (lds > 65536) {
     hipError_t e = hipFuncSetAttribute(k, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
     if (e != hipSuccess) return e;
@@ -206,105 +272,121 @@ hipError_t prepare_kernel(size_t lds, int* per_cu) {
   return hipOccupancyMaxActiveBlocksPerMultiprocessor(per_cu, k, kNT, lds);
 }
 
-template <typename T>
-hipError_t prepare_typed(int pass, size_t lds, int* per_cu) {
-  switch (pass) {
-    case PASS_FWD_UE:
-      return prepare_kernel<T, PASS_FWD_UE>(lds, per_cu);
-    case PASS_FWD_HIST:
-      return prepare_kernel<T, PASS_FWD_HIST>(lds, per_cu);
-    case PASS_BWD_UE:
-      return prepare_kernel<T, PASS_BWD_UE>(lds, per_cu);
-    case PASS_BWD_HIST:
-      return prepare_kernel<T, PASS_BWD_HIST>(lds, per_cu);
-    default:
-      return prepare_kernel<T, PASS_GATHER>(lds, per_cu);
+// The tiles of one pass variant over every field of that pass, most
+// expensive first (field and column order among equals: a claimed chunk
+// stacks tiles vertically and shares their halo rows).
+void pass_tiles(const std::vector<Field>& fs, int pass, int v, size_t el, std::vector<BatchTile>& out,
+                int& max_nb) {
+  int ox, oy;
+  pass_geom(pass, v, el, ox, oy);
+  std::vector<BatchTile> tiles;
+  std::vector<double> cost;
+  max_nb = 0;
+  for (int i = 0; i < (int)fs.size(); ++i) {
+    const Field& f = fs[i];
+    const bool hist = f.model == CP_HISTOGRAM;
+    const bool mine = pass == PASS_FWD_UE || pass == PASS_BWD_UE ? !hist : hist;
+    if (!mine) continue;
+    max_nb = std::max(max_nb, f.nb);
+    if (pass == PASS_GATHER) {
+      const int64_t plane = (int64_t)f.H * f.W;
+      for (int64_t t = 0; t < plane; t += kGatherChunk) {
+        tiles.push_back(BatchTile{i, (int)t, 0, 0});
+        cost.push_back(1.0);
+      }
+      continue;
+    }
+    const double c = vertex_cost(f.model, f.nb, pass == PASS_BWD_UE || pass == PASS_BWD_HIST) * ox * oy;
+    for (int tx = 0; tx < f.W; tx += ox)
+      for (int ty = 0; ty < f.H; ty += oy) {
+        tiles.push_back(BatchTile{i, ty, tx, 0});
+        cost.push_back(c);
+      }
   }
-}
-
-hipError_t prepare(int dtype, int pass, size_t lds, int* per_cu) {
-  return dtype == CP_F64 ? prepare_typed<double>(pass, lds, per_cu) : prepare_typed<float>(pass, lds, per_cu);
-}
-
-// Order the tiles (most expensive first; field / row order among equals),
-// size the resident grid and upload.
-cp_status_t build_pass(const std::vector<BatchTile>& tiles, const std::vector<double>& cost, int dtype, int pass,
-                       size_t lds, Pass& P) {
-  int per_cu = 0;
-  if (prepare(dtype, pass, lds, &per_cu) != hipSuccess) return CP_EDEVICE;
-  per_cu = std::max(per_cu, 1);
-  const int grid = std::max(1, std::min<int>((int)tiles.size(), g_num_cu * per_cu));
   std::vector<int> order(tiles.size());
   for (size_t i = 0; i < order.size(); ++i) order[i] = (int)i;
   std::stable_sort(order.begin(), order.end(), [&](int a, int b) { return cost[a] > cost[b]; });
+  out.clear();
+  out.reserve(tiles.size());
+  for (int t : order) out.push_back(tiles[t]);
+}
+
+// Build (allocate, upload) the pass `pass` in variant v.  CP_EUNSUPPORTED:
+// the variant does not fit a workgroup.
+cp_status_t build_pass(const Plan& P, int pass, int v, int chunk, Pass& out) {
+  const size_t el = P.dtype == CP_F64 ? 8 : 4;
   std::vector<BatchTile> flat;
-  flat.reserve(tiles.size());
-  for (int t : order) flat.push_back(tiles[t]);
-  P.kind = pass;
-  P.grid = grid;
-  P.lds = lds;
-  P.ntiles = (int)flat.size();
-  // cheap tiles are claimed several at a time
-  P.chunk = pass == PASS_FWD_UE || pass == PASS_GATHER ? 4 : 1;
-  if (hipMalloc(&P.d_queue, 2 * sizeof(int)) != hipSuccess) return CP_ENOMEM;
-  if (hipMemset(P.d_queue, 0, 2 * sizeof(int)) != hipSuccess) return CP_EDEVICE;
-  if (hipMalloc(&P.d_tiles, sizeof(BatchTile) * std::max<size_t>(flat.size(), 1)) != hipSuccess) return CP_ENOMEM;
-  if (!flat.empty() &&
-      hipMemcpy(P.d_tiles, flat.data(), sizeof(BatchTile) * flat.size(), hipMemcpyHostToDevice) != hipSuccess)
+  int max_nb = 0;
+  pass_tiles(P.fields, pass, v, el, flat, max_nb);
+  const size_t lds = tile_lds_bytes(pass, v, max_nb, el);
+  if (lds > kMaxLds) return CP_EUNSUPPORTED;
+  int per_cu = 0;
+  if (blocks_per_cu(P.dtype, pass, v, lds, &per_cu) != hipSuccess) return CP_EDEVICE;
+  if (per_cu < 1) return CP_EUNSUPPORTED;
+  Pass Q;
+  Q.kind = pass;
+  Q.variant = v;
+  Q.lds = lds;
+  Q.ntiles = (int)flat.size();
+  Q.grid = std::max(1, std::min<int>(Q.ntiles, g_num_cu * per_cu));
+  Q.chunk = chunk;
+  if (hipMalloc(&Q.d_queue, 2 * sizeof(int)) != hipSuccess) return CP_ENOMEM;
+  if (hipMemset(Q.d_queue, 0, 2 * sizeof(int)) != hipSuccess) {
+    Q.release();
     return CP_EDEVICE;
+  }
+  if (hipMalloc(&Q.d_tiles, sizeof(BatchTile) * std::max<size_t>(flat.size(), 1)) != hipSuccess) {
+    Q.release();
+    return CP_ENOMEM;
+  }
+  if (!flat.empty() &&
+      hipMemcpy(Q.d_tiles, flat.data(), sizeof(BatchTile) * flat.size(), hipMemcpyHostToDevice) != hipSuccess) {
+    Q.release();
+    return CP_EDEVICE;
+  }
+  out = Q;
   return CP_OK;
 }
+
+// default chunk: cheap tiles are claimed several at a time
+int default_chunk(int pass) { return pass == PASS_FWD_UE || pass == PASS_GATHER ? 4 : 1; }
 
 cp_status_t build_plan(int n, const Field* fs, bool bwd, Plan& P, const char** why) {
   const size_t el = fs[0].dtype == CP_F64 ? 8 : 4;
   P.dtype = fs[0].dtype;
   P.bwd = bwd;
+  P.fields.assign(fs, fs + n);
   if (g_num_cu == 0) {
     int dev = 0;
     if (hipGetDevice(&dev) != hipSuccess) return CP_EDEVICE;
     if (hipDeviceGetAttribute(&g_num_cu, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess)
       return CP_EDEVICE;
   }
-  std::vector<BatchTile> tiles[NPASS];
-  std::vector<double> cost[NPASS];
-  size_t lds[NPASS] = {0, 0, 0, 0, 0}, ws = 0;
+  bool present[NPASS] = {false, false, false, false, false};
+  size_t ws = 0;
   P.ws_offset.assign(n, SIZE_MAX);
   for (int i = 0; i < n; ++i) {
     const Field& f = fs[i];
     const bool hist = f.model == CP_HISTOGRAM;
-    const int pass = bwd ? (hist ? PASS_BWD_HIST : PASS_BWD_UE) : (hist ? PASS_FWD_HIST : PASS_FWD_UE);
-    int ox = kFwdTX, oy = 4;
-    if (pass == PASS_BWD_UE) ox = oy = el == 4 ? kBwdF32 : kBwdF64;
-    lds[pass] = std::max(lds[pass], tile_lds_bytes(f.model, f.nb, bwd, el));
-    const double c = vertex_cost(f.model, f.nb, bwd) * ox * oy;
-    // columns of tiles (a claimed chunk stacks vertically and shares halo rows)
-    for (int tx = 0; tx < f.W; tx += ox)
-      for (int ty = 0; ty < f.H; ty += oy) {
-        tiles[pass].push_back(BatchTile{i, ty, tx, 0});
-        cost[pass].push_back(c);
-      }
-    if (pass == PASS_BWD_HIST) {
-      const int64_t plane = (int64_t)f.H * f.W;
+    present[bwd ? (hist ? PASS_BWD_HIST : PASS_BWD_UE) : (hist ? PASS_FWD_HIST : PASS_FWD_UE)] = true;
+    if (hist && bwd) {
+      present[PASS_GATHER] = true;
       P.ws_offset[i] = ws;
-      ws += el * (size_t)5 * f.nb * plane;
+      ws += el * (size_t)5 * f.nb * f.H * (size_t)f.W;
       ws = (ws + 255) / 256 * 256;
-      for (int64_t v = 0; v < plane; v += kGatherChunk) {
-        tiles[PASS_GATHER].push_back(BatchTile{i, (int)v, 0, 0});
-        cost[PASS_GATHER].push_back(1.0);
-      }
     }
   }
-  for (int q = 0; q < NPASS; ++q)
-    if (lds[q] > kMaxLds) {
-      *why = "batched: staged planes exceed the LDS of a workgroup (too many bins for this dtype)";
-      return CP_EUNSUPPORTED;
-    }
   // histogram passes first (the longest), the gather last (it reads their Jacobians)
   for (int q : {PASS_FWD_HIST, PASS_BWD_HIST, PASS_FWD_UE, PASS_BWD_UE, PASS_GATHER}) {
-    if (tiles[q].empty()) continue;
-    P.passes.emplace_back();
-    cp_status_t s = build_pass(tiles[q], cost[q], P.dtype, q, lds[q], P.passes.back());
+    if (!present[q]) continue;
+    Pass Q;
+    cp_status_t s = build_pass(P, q, 0, default_chunk(q), Q);
+    if (s == CP_EUNSUPPORTED) {
+      *why = "batched: staged planes exceed the LDS of a workgroup (too many bins for this dtype)";
+      return s;
+    }
     if (s != CP_OK) return s;
+    P.passes.push_back(Q);
   }
   if (ws > 0 && hipMalloc(&P.d_ws, ws) != hipSuccess) return CP_ENOMEM;
   P.host_fields.clear();
@@ -340,35 +422,125 @@ void fill_fields(int n, const Field* fs, const Plan& P, const void* const* param
   }
 }
 
-template <typename T>
-hipError_t launch_typed(const Plan& P, hipStream_t st) {
-  const auto* F = static_cast<const BatchField<T>*>(P.d_fields);
+hipError_t launch_pass(const Plan& P, const Pass& q, hipStream_t st) {
+  const void* fields = P.d_fields;
+  const BatchTile* tiles = q.d_tiles;
+  int ntiles = q.ntiles, chunk = q.chunk;
+  int* queue = q.d_queue;
+  void* args[] = {&fields, &tiles, &ntiles, &chunk, &queue};
+  hipError_t e = hipLaunchKernel(kernel_for(P.dtype, q.kind, q.variant), dim3(q.grid), dim3(kNT), args, q.lds, st);
+  if (e != hipSuccess) return e;
+  return hipGetLastError();
+}
+
+hipError_t launch(const Plan& P, hipStream_t st) {
   for (const Pass& q : P.passes) {
-    const dim3 g(q.grid), b(kNT);
-    switch (q.kind) {
-      case PASS_FWD_UE:
-        hipLaunchKernelGGL((k_batched<T, PASS_FWD_UE>), g, b, q.lds, st, F, q.d_tiles, q.ntiles, q.chunk, q.d_queue);
-        break;
-      case PASS_FWD_HIST:
-        hipLaunchKernelGGL((k_batched<T, PASS_FWD_HIST>), g, b, q.lds, st, F, q.d_tiles, q.ntiles, q.chunk, q.d_queue);
-        break;
-      case PASS_BWD_UE:
-        hipLaunchKernelGGL((k_batched<T, PASS_BWD_UE>), g, b, q.lds, st, F, q.d_tiles, q.ntiles, q.chunk, q.d_queue);
-        break;
-      case PASS_BWD_HIST:
-        hipLaunchKernelGGL((k_batched<T, PASS_BWD_HIST>), g, b, q.lds, st, F, q.d_tiles, q.ntiles, q.chunk, q.d_queue);
-        break;
-      default:
-        hipLaunchKernelGGL((k_batched<T, PASS_GATHER>), g, b, q.lds, st, F, q.d_tiles, q.ntiles, q.chunk, q.d_queue);
-    }
-    hipError_t e = hipGetLastError();
+    hipError_t e = launch_pass(P, q, st);
     if (e != hipSuccess) return e;
   }
   return hipSuccess;
 }
 
-hipError_t launch(const Plan& P, hipStream_t st) {
-  return P.dtype == CP_F64 ? launch_typed<double>(P, st) : launch_typed<float>(P, st);
+// mean time (ms) of `reps` back-to-back launches of one pass on st
+cp_status_t time_pass(const Plan& P, const Pass& q, hipStream_t st, int reps, double& ms) {
+  hipEvent_t a, b;
+  if (hipEventCreate(&a) != hipSuccess) return CP_EDEVICE;
+  if (hipEventCreate(&b) != hipSuccess) {
+    (void)hipEventDestroy(a);
+    return CP_EDEVICE;
+  }
+  bool ok = launch_pass(P, q, st) == hipSuccess;  // warm-up
+  ok = ok && hipEventRecord(a, st) == hipSuccess;
+  for (int r = 0; r < reps && ok; ++r) ok = launch_pass(P, q, st) == hipSuccess;
+  ok = ok && hipEventRecord(b, st) == hipSuccess && hipEventSynchronize(b) == hipSuccess;
+  float t = 0.f;
+  ok = ok && hipEventElapsedTime(&t, a, b) == hipSuccess;
+  (void)hipEventDestroy(a);
+  (void)hipEventDestroy(b);
+  ms = t / reps;
+  return ok ? CP_OK : CP_EDEVICE;
+}
+
+// Autotuner: for every pass, time each tile variant with each claim chunk on
+// the plan's own fields (the field table must be current) and keep the
+// fastest.  Every trial writes the pass's outputs, with the same values.
+cp_status_t tune(Plan& P, hipStream_t st) {
+  constexpr int kReps = 3;
+  const int chunks[] = {1, 2, 4, 8};
+  for (Pass& cur : P.passes) {
+    Pass best = cur;
+    double best_ms = 0.0;
+    cp_status_t s = time_pass(P, cur, st, kReps, best_ms);
+    if (s != CP_OK) return s;
+    // `best` shares its device tables with `cur` or with one built candidate;
+    // a built candidate's tables are freed as soon as it is not the best
+    for (int v = 0; v < n_variants(cur.kind); ++v) {
+      Pass cand;
+      const bool built = v != cur.variant;
+      if (!built) {
+        cand = cur;
+      } else {
+        s = build_pass(P, cur.kind, v, 1, cand);
+        if (s == CP_EUNSUPPORTED) continue;
+        if (s != CP_OK) return s;
+      }
+      for (int c : chunks) {
+        if (!built && c == cur.chunk) continue;
+        cand.chunk = c;
+        double ms = 0.0;
+        s = time_pass(P, cand, st, kReps, ms);
+        if (s != CP_OK) {
+          if (built && best.d_tiles != cand.d_tiles) cand.release();
+          return s;
+        }
+        if (ms < best_ms) {
+          if (best.d_tiles != cur.d_tiles && best.d_tiles != cand.d_tiles) best.release();
+          best = cand;
+          best_ms = ms;
+        }
+      }
+      if (built && best.d_tiles != cand.d_tiles) cand.release();
+    }
+    if (best.d_tiles != cur.d_tiles) cur.release();
+    best.ms = best_ms;
+    cur = best;
+  }
+  P.tuned = true;
+  return CP_OK;
+}
+
+std::string describe(const Plan& P) {
+  const size_t el = P.dtype == CP_F64 ? 8 : 4;
+  std::string out = P.tuned ? (P.passes.empty() || P.passes[0].ms >= 0.0 ? "tuned" : "pinned") : "default";
+  char buf[256];
+  for (const Pass& q : P.passes) {
+    int ox, oy;
+    pass_geom(q.kind, q.variant, el, ox, oy);
+    std::snprintf(buf, sizeof buf, "; %s: shape %d (tile %dx%d), chunk %d, %d tiles, grid %d", pass_name(q.kind),
+                  q.variant, ox, oy, q.chunk, q.ntiles, q.grid);
+    out += buf;
+    if (q.ms >= 0.0) {
+      std::snprintf(buf, sizeof buf, ", %.4f ms", q.ms);
+      out += buf;
+    }
+  }
+  return out;
+}
+
+std::vector<int64_t> plan_key(int n, const Field* fs, uint32_t flags, int dev) {
+  std::vector<int64_t> key;
+  key.reserve(4 + 4 * (size_t)n);
+  key.push_back(n);
+  key.push_back(fs[0].dtype);
+  key.push_back(flags & (CP_BATCH_FWD | CP_BATCH_BWD));
+  key.push_back(dev);
+  for (int i = 0; i < n; ++i) {
+    key.push_back(fs[i].H);
+    key.push_back(fs[i].W);
+    key.push_back(fs[i].rs);
+    key.push_back(fs[i].model * 1000 + fs[i].nb);
+  }
+  return key;
 }
 
 }  // namespace
@@ -389,20 +561,9 @@ cp_status_t batched(int n, const Field* fs, const void* const* params, void* con
     }
     return CP_OK;
   }
-  std::vector<int64_t> key;
-  key.reserve(4 + 4 * (size_t)n);
-  key.push_back(n);
-  key.push_back(fs[0].dtype);
-  key.push_back(flags & (CP_BATCH_FWD | CP_BATCH_BWD));
   int dev = 0;
   if (hipGetDevice(&dev) != hipSuccess) return CP_EDEVICE;
-  key.push_back(dev);
-  for (int i = 0; i < n; ++i) {
-    key.push_back(fs[i].H);
-    key.push_back(fs[i].W);
-    key.push_back(fs[i].rs);
-    key.push_back(fs[i].model * 1000 + fs[i].nb);
-  }
+  const std::vector<int64_t> key = plan_key(n, fs, flags, dev);
   std::lock_guard<std::mutex> lk(g_mu);
   auto it = g_plans.find(key);
   if (it == g_plans.end()) {
@@ -425,6 +586,20 @@ cp_status_t batched(int n, const Field* fs, const void* const* params, void* con
       return CP_EDEVICE;
     }
     P.host_fields.swap(table);
+  }
+  if ((flags & CP_BATCH_TUNE) && !P.tuned) {
+    hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
+    if (hipStreamIsCapturing(st, &cs) != hipSuccess) return CP_EDEVICE;
+    if (cs != hipStreamCaptureStatusNone) {
+      *why = "batched: tuning times launches and cannot run while the stream is being captured";
+      return CP_EINVAL;
+    }
+    cp_status_t s = tune(P, st);
+    if (s != CP_OK) {
+      *why = "batched: tuning launch failed";
+      return s;
+    }
+    P.drop_graph();  // captured with the default configuration
   }
   if (!(flags & CP_BATCH_GRAPH)) {
     if (launch(P, st) != hipSuccess) {
@@ -459,6 +634,56 @@ cp_status_t batched(int n, const Field* fs, const void* const* params, void* con
     return CP_EDEVICE;
   }
   return CP_OK;
+}
+
+cp_status_t batched_pin(int n, const Field* fs, uint32_t flags, const int* shape, const int* chunk,
+                        const char** why) {
+  int dev = 0;
+  if (hipGetDevice(&dev) != hipSuccess) return CP_EDEVICE;
+  const std::vector<int64_t> key = plan_key(n, fs, flags, dev);
+  std::lock_guard<std::mutex> lk(g_mu);
+  auto it = g_plans.find(key);
+  if (it == g_plans.end()) {
+    auto P = std::make_unique<Plan>();
+    cp_status_t s = build_plan(n, fs, (flags & CP_BATCH_BWD) != 0, *P, why);
+    if (s != CP_OK) return s;
+    it = g_plans.emplace(key, std::move(P)).first;
+  }
+  Plan& P = *it->second;
+  for (int q = 0; q < NPASS; ++q)
+    if (shape[q] >= n_variants(q)) {
+      *why = "batched pin: no such tile shape for this pass";
+      return CP_EINVAL;
+    }
+  for (Pass& cur : P.passes) {
+    const int v = shape[cur.kind] < 0 ? cur.variant : shape[cur.kind];
+    const int c = chunk[cur.kind] < 1 ? cur.chunk : chunk[cur.kind];
+    if (v == cur.variant) {
+      cur.chunk = c;
+    } else {
+      Pass Q;
+      cp_status_t s = build_pass(P, cur.kind, v, c, Q);
+      if (s == CP_EUNSUPPORTED) *why = "batched pin: the tile shape does not fit a workgroup";
+      if (s != CP_OK) return s;
+      cur.release();
+      cur = Q;
+    }
+    cur.ms = -1.0;
+  }
+  P.tuned = true;  // a pinned plan is not tuned over
+  P.drop_graph();
+  return CP_OK;
+}
+
+bool batched_describe(int n, const Field* fs, uint32_t flags, std::string& out) {
+  int dev = 0;
+  if (hipGetDevice(&dev) != hipSuccess) return false;
+  const std::vector<int64_t> key = plan_key(n, fs, flags, dev);
+  std::lock_guard<std::mutex> lk(g_mu);
+  auto it = g_plans.find(key);
+  if (it == g_plans.end()) return false;
+  out = describe(*it->second);
+  return true;
 }
 
 void batched_release() {

@@ -180,10 +180,12 @@ __host__ __device__ void hist_stencil_jac(const HistLds<T>& L, const HistSuf<T>&
 // Sweep tile for the per-field adjoint: 64 x TY stencils (params staged with a
 // one-vertex halo), Jacobians written to the workspace J ([5][h][H][W]); a
 // gather kernel then adds the five entries of every parameter.  If f.pmin is
-// non-null the probabilities are written too (fused forward + adjoint).
-template <typename T, int TY>
+// non-null the probabilities are written too (fused forward + adjoint).  NT
+// threads; each takes the rows ly, ly + NT/64, ... of its column.
+template <typename T, int TY, int NT = kFwdTX * TY>
 __device__ __forceinline__ void tile_hist_sweep(const FieldPtrs<T>& f, int ty0, int tx0, T* lds, int tid, T* J) {
-  constexpr int TX = kFwdTX, EX = TX + 2, EY = TY + 2, E = EX * EY, NT = TX * TY;
+  constexpr int TX = kFwdTX, EX = TX + 2, EY = TY + 2, E = EX * EY;
+  static_assert(NT % TX == 0 && TY % (NT / TX) == 0, "rows must split evenly over the threads");
   const int h = f.nb;
   stage<T, EY, EX, NT>(lds, f.params, 2 + h, f.ps, f.rs, f.H, f.W, ty0 - 1, tx0 - 1, tid);
   __syncthreads();
@@ -191,19 +193,21 @@ __device__ __forceinline__ void tile_hist_sweep(const FieldPtrs<T>& f, int ty0, 
   hist_stage_validity<T, NT>(lds, E, h, tid);
   hist_stage_suffix<T, NT>(lds, E, h, tid);
   __syncthreads();
-  const int lx = tid % TX, ly = tid / TX;
-  const int x = tx0 + lx, y = ty0 + ly;
-  if (x < f.W && y < f.H) {
-    const HistLds<T> L{lds, E, h, T(1) / T(h)};
-    const HistSuf<T> U{lds, E, h};
-    const int64_t at = (int64_t)y * f.rs + x;
-    const int64_t plane = (int64_t)f.H * f.W;
-    T pmin, pmax;
-    hist_stencil_jac(L, U, lds, E, EX, (ly + 1) * EX + lx + 1, y, x, f.H, f.W, f.gmin[at], f.gmax[at], J, plane,
-                     (int64_t)y * f.W + x, pmin, pmax);
-    if (f.pmin) {
-      f.pmin[at] = pmin;
-      f.pmax[at] = pmax;
+  const int lx = tid % TX, x = tx0 + lx;
+  for (int ly = tid / TX; ly < TY; ly += NT / TX) {
+    const int y = ty0 + ly;
+    if (x < f.W && y < f.H) {
+      const HistLds<T> L{lds, E, h, T(1) / T(h)};
+      const HistSuf<T> U{lds, E, h};
+      const int64_t at = (int64_t)y * f.rs + x;
+      const int64_t plane = (int64_t)f.H * f.W;
+      T pmin, pmax;
+      hist_stencil_jac(L, U, lds, E, EX, (ly + 1) * EX + lx + 1, y, x, f.H, f.W, f.gmin[at], f.gmax[at], J, plane,
+                       (int64_t)y * f.W + x, pmin, pmax);
+      if (f.pmin) {
+        f.pmin[at] = pmin;
+        f.pmax[at] = pmax;
+      }
     }
   }
   __syncthreads();

@@ -5,6 +5,7 @@
 
 #include <cmath>
 #include <cstdint>
+#include <string>
 
 #include "cpcrit.h"
 
@@ -64,6 +65,12 @@ void workspace_release();
 cp_status_t batched(int n, const Field* fields, const void* const* params, void* const* pmin,
                     void* const* pmax, const void* const* gmin, const void* const* gmax,
                     void* const* grad, uint32_t flags, hipStream_t st, const char** why);
+// text description of the plan a batched call with these shapes and flags
+// uses (false: no such plan yet)
+bool batched_describe(int n, const Field* fields, uint32_t flags, std::string& out);
+// fix tile shapes / chunks of a plan (index by pass kind; < 0: keep)
+cp_status_t batched_pin(int n, const Field* fields, uint32_t flags, const int* shape, const int* chunk,
+                        const char** why);
 void batched_release();
 
 // Gauss-Legendre tables (host copies)

@@ -198,32 +198,37 @@ CP_HD void vertex_jac_vals(T p0, T p1, const T (&q0)[4], const T (&q1)[4], const
 }
 
 // ---------------------------------------------------------------------------
-// forward tiles: 64 x TY outputs, halo 1
+// forward tiles: 64 x TY outputs, halo 1; NT threads, each evaluating the
+// rows ly, ly + NT/64, ... of its column (one row when NT = 64 TY)
 // ---------------------------------------------------------------------------
 constexpr int kFwdTX = 64;
 
-template <typename T, int MODEL, int TY>
+template <typename T, int MODEL, int TY, int NT = kFwdTX * TY>
 __device__ __forceinline__ void tile_fwd_ue(const FieldPtrs<T>& f, int ty0, int tx0, T* lds, int tid) {
-  constexpr int TX = kFwdTX, EX = TX + 2, EY = TY + 2, E = EX * EY, NT = TX * TY;
+  constexpr int TX = kFwdTX, EX = TX + 2, EY = TY + 2, E = EX * EY;
+  static_assert(NT % TX == 0 && TY % (NT / TX) == 0, "rows must split evenly over the threads");
   stage<T, EY, EX, NT>(lds, f.params, 2, f.ps, f.rs, f.H, f.W, ty0 - 1, tx0 - 1, tid);
   __syncthreads();
-  const int lx = tid % TX, ly = tid / TX;
-  const int x = tx0 + lx, y = ty0 + ly;
-  if (x < f.W && y < f.H) {
-    const int e = (ly + 1) * EX + lx + 1;
-    const int en[4] = {e + 1, e - EX, e - 1, e + EX};
-    const bool pres[4] = {x + 1 < f.W, y > 0, x > 0, y + 1 < f.H};
-    T pmin, pmax;
-    vertex_fwd_ue<T, MODEL>(lds, E, e, en, pres, pmin, pmax);
-    f.pmin[(int64_t)y * f.rs + x] = pmin;
-    f.pmax[(int64_t)y * f.rs + x] = pmax;
+  const int lx = tid % TX, x = tx0 + lx;
+  for (int ly = tid / TX; ly < TY; ly += NT / TX) {
+    const int y = ty0 + ly;
+    if (x < f.W && y < f.H) {
+      const int e = (ly + 1) * EX + lx + 1;
+      const int en[4] = {e + 1, e - EX, e - 1, e + EX};
+      const bool pres[4] = {x + 1 < f.W, y > 0, x > 0, y + 1 < f.H};
+      T pmin, pmax;
+      vertex_fwd_ue<T, MODEL>(lds, E, e, en, pres, pmin, pmax);
+      f.pmin[(int64_t)y * f.rs + x] = pmin;
+      f.pmax[(int64_t)y * f.rs + x] = pmax;
+    }
   }
   __syncthreads();
 }
 
-template <typename T, int TY>
+template <typename T, int TY, int NT = kFwdTX * TY>
 __device__ __forceinline__ void tile_fwd_hist(const FieldPtrs<T>& f, int ty0, int tx0, T* lds, int tid) {
-  constexpr int TX = kFwdTX, EX = TX + 2, EY = TY + 2, E = EX * EY, NT = TX * TY;
+  constexpr int TX = kFwdTX, EX = TX + 2, EY = TY + 2, E = EX * EY;
+  static_assert(NT % TX == 0 && TY % (NT / TX) == 0, "rows must split evenly over the threads");
   const int h = f.nb;
   stage<T, EY, EX, NT>(lds, f.params, 2 + h, f.ps, f.rs, f.H, f.W, ty0 - 1, tx0 - 1, tid);
   __syncthreads();
@@ -231,30 +236,32 @@ __device__ __forceinline__ void tile_fwd_hist(const FieldPtrs<T>& f, int ty0, in
   hist_stage_validity<T, NT>(lds, E, h, tid);
   hist_stage_suffix<T, NT>(lds, E, h, tid);
   __syncthreads();
-  const int lx = tid % TX, ly = tid / TX;
-  const int x = tx0 + lx, y = ty0 + ly;
-  if (x < f.W && y < f.H) {
-    const HistLds<T> L{lds, E, h, T(1) / T(h)};
-    const HistSuf<T> U{lds, E, h};
-    const int e = (ly + 1) * EX + lx + 1;
-    const int en[4] = {e + 1, e - EX, e - 1, e + EX};
-    const bool pres[4] = {x + 1 < f.W, y > 0, x > 0, y + 1 < f.H};
-    bool ok = L.valid(e);
+  const int lx = tid % TX, x = tx0 + lx;
+  for (int ly = tid / TX; ly < TY; ly += NT / TX) {
+    const int y = ty0 + ly;
+    if (x < f.W && y < f.H) {
+      const HistLds<T> L{lds, E, h, T(1) / T(h)};
+      const HistSuf<T> U{lds, E, h};
+      const int e = (ly + 1) * EX + lx + 1;
+      const int en[4] = {e + 1, e - EX, e - 1, e + EX};
+      const bool pres[4] = {x + 1 < f.W, y > 0, x > 0, y + 1 < f.H};
+      bool ok = L.valid(e);
 #pragma unroll
-    for (int i = 0; i < 4; ++i) ok = ok && (!pres[i] || L.valid(en[i]));
-    T pmin = qnan<T>(), pmax = qnan<T>();
-    if (ok) {
-      const T lov = lds[e], hiv = lds[E + e];
-      T lo[4], hi[4];
+      for (int i = 0; i < 4; ++i) ok = ok && (!pres[i] || L.valid(en[i]));
+      T pmin = qnan<T>(), pmax = qnan<T>();
+      if (ok) {
+        const T lov = lds[e], hiv = lds[E + e];
+        T lo[4], hi[4];
 #pragma unroll
-      for (int i = 0; i < 4; ++i) {
-        lo[i] = lds[en[i]] - lov;
-        hi[i] = lds[E + en[i]] - lov;
+        for (int i = 0; i < 4; ++i) {
+          lo[i] = lds[en[i]] - lov;
+          hi[i] = lds[E + en[i]] - lov;
+        }
+        hist_vertex_minmax(U, e, en, pres, hiv - lov, lo, hi, pmin, pmax);
       }
-      hist_vertex_minmax(U, e, en, pres, hiv - lov, lo, hi, pmin, pmax);
+      f.pmin[(int64_t)y * f.rs + x] = pmin;
+      f.pmax[(int64_t)y * f.rs + x] = pmax;
     }
-    f.pmin[(int64_t)y * f.rs + x] = pmin;
-    f.pmax[(int64_t)y * f.rs + x] = pmax;
   }
   __syncthreads();
 }

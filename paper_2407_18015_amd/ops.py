@@ -183,24 +183,54 @@ def semianalytical(params: torch.Tensor, f: Field, terms: bool = False) -> dict:
     return out
 
 
-def batched(fields: list[Field], params: list[torch.Tensor], pmin=None, pmax=None, gmin=None, gmax=None,
-            grad=None, graph: bool = False, per_field: bool = False) -> None:
-    """cp_prob_batched over caller-allocated outputs (lists of tensors)."""
-    n = len(fields)
+def _batch_flags(fwd: bool, bwd: bool, graph: bool = False, per_field: bool = False, tune: bool = False) -> int:
     flags = 0
-    if pmin is not None:
+    if fwd:
         flags |= L.CP_BATCH_FWD
-    if grad is not None:
+    if bwd:
         flags |= L.CP_BATCH_BWD
     if graph:
         flags |= L.CP_BATCH_GRAPH
     if per_field:
         flags |= L.CP_BATCH_PER_FIELD
+    if tune:
+        flags |= L.CP_BATCH_TUNE
+    return flags
+
+
+def batched(fields: list[Field], params: list[torch.Tensor], pmin=None, pmax=None, gmin=None, gmax=None,
+            grad=None, graph: bool = False, per_field: bool = False, tune: bool = False) -> None:
+    """cp_prob_batched over caller-allocated outputs (lists of tensors).
+    tune=True autotunes the plan's tile shapes on its first call."""
+    n = len(fields)
+    flags = _batch_flags(pmin is not None, grad is not None, graph, per_field, tune)
     for i, f in enumerate(fields):
         _planes(params[i], f.height, f.width, f.param_dtype, f"params[{i}]", f.row_stride)
     lst = lambda ts: None if ts is None else [_ptr(t) for t in ts]
     L.check(L.cp_prob_batched(n, [f.desc() for f in fields], lst(params), lst(pmin), lst(pmax), lst(gmin),
                               lst(gmax), lst(grad), flags, _stream(params[0])))
+
+
+BATCH_PASSES = ("forward", "hist_forward", "adjoint", "hist_adjoint", "hist_gather")
+
+
+def batched_pin(fields: list[Field], fwd: bool = True, bwd: bool = False, shape: dict | None = None,
+                chunk: dict | None = None) -> None:
+    """cp_batched_pin: fix the tile shape index / claim chunk of passes of the
+    plan used by batched calls over these fields (keys of BATCH_PASSES)."""
+    shape, chunk = shape or {}, chunk or {}
+    for k in list(shape) + list(chunk):
+        if k not in BATCH_PASSES:
+            raise ValueError(f"unknown pass {k!r}")
+    sh = [int(shape.get(k, -1)) for k in BATCH_PASSES]
+    ch = [int(chunk.get(k, 0)) for k in BATCH_PASSES]
+    L.check(L.cp_batched_pin(len(fields), [f.desc() for f in fields], _batch_flags(fwd, bwd), sh, ch))
+
+
+def batched_describe(fields: list[Field], fwd: bool = True, bwd: bool = False) -> str | None:
+    """cp_batched_describe: the tile shapes, chunks and grids of the plan used
+    by batched calls over these fields (None before the first call)."""
+    return L.cp_batched_describe(len(fields), [f.desc() for f in fields], _batch_flags(fwd, bwd))
 
 
 def philox(counters: torch.Tensor, seed: int) -> torch.Tensor:

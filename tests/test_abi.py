@@ -116,6 +116,25 @@ def test_batched_validation():
                              None) == L.CP_EINVAL
 
 
+def test_batched_tune_flag_and_describe_without_a_plan():
+    # the tune flag is a known bit (validation stops at the NULL table first)
+    assert L.cp_prob_batched(1, [desc()], [FAKE], None, None, None, None, None,
+                             L.CP_BATCH_FWD | L.CP_BATCH_TUNE, None) == L.CP_EINVAL
+    assert "NULL" in L.load().cp_last_error().decode()
+    assert L.cp_prob_batched(1, [desc()], [FAKE], [FAKE], [FAKE], None, None, None, 32 | L.CP_BATCH_FWD,
+                             None) == L.CP_EINVAL
+    assert "flag" in L.load().cp_last_error().decode()
+    # pin: argument checks come before any device call
+    sh, ch = [0] * 5, [1] * 5
+    assert L.cp_batched_pin(1, [desc()], 0, sh, ch) == L.CP_EINVAL
+    assert L.cp_batched_pin(1, [desc(height=0)], L.CP_BATCH_FWD, sh, ch) == L.CP_EINVAL
+    assert L.cp_batched_pin(1, [desc(model=L.CP_MVGAUSS, nsamples=4)], L.CP_BATCH_FWD, sh, ch) == L.CP_EUNSUPPORTED
+    assert L.load().cp_batched_pin(1, None, L.CP_BATCH_FWD, None, None) == L.CP_EINVAL
+    # no plan has been built for these shapes, and bad descriptors give none
+    assert L.cp_batched_describe(1, [desc(height=3, width=3)], L.CP_BATCH_FWD) is None
+    assert L.cp_batched_describe(1, [desc(height=0)], L.CP_BATCH_FWD) is None
+
+
 def test_classify_validation():
     lib = L.load()
     assert lib.cp_prob_classify(desc(), None, FAKE, FAKE, FAKE, FAKE, FAKE, None) == L.CP_EINVAL
