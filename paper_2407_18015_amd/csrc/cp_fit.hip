@@ -19,6 +19,8 @@
 #include <hip/hip_runtime.h>
 
 #include <cmath>
+#include <cstdint>
+#include <type_traits>
 
 #include "cp_fit.hpp"
 #include "cp_internal.hpp"
@@ -107,6 +109,46 @@ __global__ __launch_bounds__(kFitTX* kFitTY) void k_fit(FitArgs a) {
   par[a.ps + at] = hi;
   const T fm = T(M);
   for (int j = 0; j < a.nb; ++j) par[(int64_t)(2 + j) * a.ps + at] = rn_div(T(cnt[j * NT]), fm);
+}
+
+// Uniform / Epanechnikov with 16-byte loads: a thread fits V = 16 / sizeof(T)
+// consecutive vertices of a row, reading each member plane as one vector
+// (4 FP32 or 2 FP64 values).  On MI355X a stream of 16-byte loads reads HBM
+// at ~6.7 TB/s against ~4 TB/s for 4-byte loads.  Needs W, the row stride and
+// both base addresses multiples of V elements (the host checks).  The
+// per-vertex operations are FitAcc's, as in k_fit.
+template <typename T, int MODEL>
+__global__ __launch_bounds__(256) void k_fit_vec(FitArgs a, int64_t nvec) {
+  constexpr int V = 16 / sizeof(T);
+  using Vec = typename std::conditional<sizeof(T) == 4, float4, double2>::type;
+  const int64_t q = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (q >= nvec) return;
+  const int wv = a.W / V;
+  const int y = (int)(q / wv), x = (int)(q - (int64_t)y * wv) * V;
+  const int64_t at = (int64_t)y * a.rs + x;
+  const T* mem = static_cast<const T*>(a.members);
+  T* par = static_cast<T*>(a.params);
+  FitAcc<T, MODEL> acc[V];
+  {
+    const Vec v = *reinterpret_cast<const Vec*>(mem + at);
+    const T* e = reinterpret_cast<const T*>(&v);
+#pragma unroll
+    for (int j = 0; j < V; ++j) acc[j].first(e[j]);
+  }
+#pragma unroll 4
+  for (int k = 1; k < a.M; ++k) {
+    const Vec v = *reinterpret_cast<const Vec*>(mem + (int64_t)k * a.ps + at);
+    const T* e = reinterpret_cast<const T*>(&v);
+#pragma unroll
+    for (int j = 0; j < V; ++j) acc[j].add(e[j]);
+  }
+  Vec o0, o1;
+  T* r0 = reinterpret_cast<T*>(&o0);
+  T* r1 = reinterpret_cast<T*>(&o1);
+#pragma unroll
+  for (int j = 0; j < V; ++j) acc[j].finish(a.M, a.wscale, a.eps, r0[j], r1[j]);
+  *reinterpret_cast<Vec*>(par + at) = o0;
+  *reinterpret_cast<Vec*>(par + a.ps + at) = o1;
 }
 
 // ---------------------------------------------------------------------------
@@ -203,6 +245,15 @@ __global__ __launch_bounds__(256) void k_fit_mvg(FitArgs a, double jitter) {
 
 template <typename T, int MODEL>
 hipError_t launch_fit(const FitArgs& a, hipStream_t st) {
+  constexpr int V = 16 / sizeof(T);
+  if constexpr (MODEL != CP_HISTOGRAM) {
+    if (a.W % V == 0 && a.rs % V == 0 && reinterpret_cast<uintptr_t>(a.members) % 16 == 0 &&
+        reinterpret_cast<uintptr_t>(a.params) % 16 == 0) {
+      const int64_t nvec = (int64_t)a.H * (a.W / V);
+      hipLaunchKernelGGL((k_fit_vec<T, MODEL>), dim3((unsigned)((nvec + 255) / 256)), dim3(256), 0, st, a, nvec);
+      return hipGetLastError();
+    }
+  }
   dim3 grid((a.W + kFitTX - 1) / kFitTX, (a.H + kFitTY - 1) / kFitTY);
   if (MODEL != CP_HISTOGRAM)
     hipLaunchKernelGGL((k_fit<T, MODEL, 0>), grid, dim3(kFitTX * kFitTY), 0, st, a);

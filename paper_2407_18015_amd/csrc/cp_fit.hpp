@@ -67,9 +67,11 @@ __device__ __forceinline__ T degenerate_half(T eps, T x) {
   return rn_mul(eps, x < T(0) ? (-x > T(1) ? -x : T(1)) : (x > T(1) ? x : T(1)));
 }
 
-// Parameters (p0, p1) of one vertex from its M members, member k at
-// mem[at + k*ps].  Uniform: (lo, hi); Epanechnikov / Gaussian: (m, w) with
-// w = wscale * sqrt(sum of squared deviations).
+// Running statistics of one vertex's members, then its parameters.
+// Uniform: (lo, hi) = (min, max); Epanechnikov / Gaussian: (m, w) with
+// w = wscale * sqrt(sum of squared deviations).  Every fit kernel feeds the
+// members of a vertex in order k = 0, 1, ..., M-1 through these operations,
+// so all of them give the same parameters bit for bit.
 //
 // The Epanechnikov branch detects "all members equal" without a min / max:
 // with x0 the first member and d = x - x0 in FP64, some member differs from
@@ -78,47 +80,65 @@ __device__ __forceinline__ T degenerate_half(T eps, T x) {
 // test ignores, as the min / max comparisons ignore it; a NaN first member
 // makes every d NaN: degenerate, as !(min < max) is then.
 template <typename T, int MODEL>
-__device__ __forceinline__ void fit_ue_vertex(const T* __restrict__ mem, int M, int64_t ps, int64_t at,
-                                              double wscale, double eps, T& p0, T& p1) {
-  const T x0 = mem[at];
-  if (MODEL == CP_UNIFORM) {
-    T mn = x0, mx = x0;
-#pragma unroll 4
-    for (int k = 1; k < M; ++k) {
-      const T xk = mem[(int64_t)k * ps + at];
+struct FitAcc {
+  T mn, mx;
+  double shift, s1, s2;
+  bool spread;
+  __device__ __forceinline__ void first(T x0) {
+    if (MODEL == CP_UNIFORM) {
+      mn = mx = x0;
+    } else {
+      shift = (double)x0;
+      s1 = s2 = 0.0;
+      spread = false;
+    }
+  }
+  __device__ __forceinline__ void add(T xk) {
+    if (MODEL == CP_UNIFORM) {
       mn = xk < mn ? xk : mn;
       mx = xk > mx ? xk : mx;
-    }
-    if (!(mn < mx)) {
-      const T e = degenerate_half(T(eps), mn);
-      p0 = rn_sub(mn, e);
-      p1 = rn_add(mn, e);
     } else {
-      p0 = mn;
-      p1 = mx;
+      const double d = (double)xk - shift;
+      spread = spread || fabs(d) > 0.0;
+      s1 += d;
+      s2 = fma(d, d, s2);
     }
-    return;
   }
-  const double shift = (double)x0;
-  double s1 = 0.0, s2 = 0.0;
-  bool spread = false;
+  __device__ __forceinline__ void finish(int M, double wscale, double eps, T& p0, T& p1) const {
+    if (MODEL == CP_UNIFORM) {
+      if (!(mn < mx)) {
+        const T e = degenerate_half(T(eps), mn);
+        p0 = rn_sub(mn, e);
+        p1 = rn_add(mn, e);
+      } else {
+        p0 = mn;
+        p1 = mx;
+      }
+      return;
+    }
+    const double mean = shift + s1 / (double)M;
+    double w;
+    if (!spread) {
+      w = eps * fmax(1.0, fabs(mean));
+    } else {
+      const double ss = fmax(s2 - s1 * s1 / (double)M, 0.0);
+      w = wscale * sqrt(ss);
+    }
+    p0 = (T)mean;
+    p1 = (T)w;
+  }
+};
+
+// Parameters (p0, p1) of one vertex from its M members, member k at
+// mem[at + k*ps].
+template <typename T, int MODEL>
+__device__ __forceinline__ void fit_ue_vertex(const T* __restrict__ mem, int M, int64_t ps, int64_t at,
+                                              double wscale, double eps, T& p0, T& p1) {
+  FitAcc<T, MODEL> acc;
+  acc.first(mem[at]);
 #pragma unroll 4
-  for (int k = 1; k < M; ++k) {
-    const double d = (double)mem[(int64_t)k * ps + at] - shift;
-    spread = spread || fabs(d) > 0.0;
-    s1 += d;
-    s2 = fma(d, d, s2);
-  }
-  const double mean = shift + s1 / (double)M;
-  double w;
-  if (!spread) {
-    w = eps * fmax(1.0, fabs(mean));
-  } else {
-    const double ss = fmax(s2 - s1 * s1 / (double)M, 0.0);
-    w = wscale * sqrt(ss);
-  }
-  p0 = (T)mean;
-  p1 = (T)w;
+  for (int k = 1; k < M; ++k) acc.add(mem[(int64_t)k * ps + at]);
+  acc.finish(M, wscale, eps, p0, p1);
 }
 
 }  // namespace cp

@@ -193,6 +193,23 @@ def test_fit_parity(model):
         np.testing.assert_allclose(got[2:], ref[2:].astype(np.float32), rtol=0, atol=6e-8)
 
 
+@pytest.mark.parametrize("dtype", [torch.float32, torch.float64])
+@pytest.mark.parametrize("model", [U, E])
+def test_fit_vector_loads_equal_scalar_loads(model, dtype):
+    """Width a multiple of 4 (FP32) / 2 (FP64): the fit reads 16-byte vectors;
+    one more column: 4-byte (8-byte) loads.  The shared columns must agree bit
+    for bit, also for degenerate and NaN members."""
+    note("fit vector vs scalar", NAMES[model], dtype)
+    H, W = 37, 128
+    mem = workloads.smooth_ensemble(9, H, W + 1)
+    mem[:, 3, 5] = mem[0, 3, 5]
+    mem[4, 6, 7] = np.nan
+    mem[0, 8, 9] = np.nan
+    vec = host(cp.fit(dev(mem[:, :, :W], dtype), model))
+    sca = host(cp.fit(dev(mem, dtype), model))[:, :, :W]
+    assert np.array_equal(vec, sca, equal_nan=True)
+
+
 def test_fit_fp64_and_many_members():
     note("fit fp64 / 40 members")
     mem = np.random.default_rng(3).normal(size=(40, 33, 70))
