@@ -402,10 +402,48 @@ def cpu_baseline(mem_np, gmin_np, gmax_np, budget_s=12.0, band=32):
         done += band * W
         y += band
     cores = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
-    return {"value": done / dt, "unit": UNIT, "cores": cores, "kind": "oracle",
-            "sample": f"fit+forward+adjoint of the first {done // W} rows x {W} columns of the same "
-                      f"20-member field, in bands of {band} rows", "seconds": dt}
+    out = {"value": done / dt, "unit": UNIT, "cores": cores, "kind": "oracle",
+           "sample": f"fit+forward+adjoint of the first {done // W} rows x {W} columns of the same "
+                     f"20-member field, in bands of {band} rows", "seconds": dt}
+    out["single_core"] = single_core_baseline(mem_np[:, :band + 1], gmin_np[:band + 1], gmax_np[:band + 1])
+    return out
+
+
+def single_core_baseline(mem_np, gmin_np, gmax_np):
+    """The same oracle work on one thread (a child process started with
+    OMP_NUM_THREADS=1) for the first band of rows."""
+    import subprocess
+    import tempfile
+    with tempfile.TemporaryDirectory() as d:
+        np.save(os.path.join(d, "mem.npy"), mem_np)
+        np.save(os.path.join(d, "g.npy"), np.stack([gmin_np, gmax_np]))
+        env = dict(os.environ, OMP_NUM_THREADS="1")
+        r = subprocess.run([sys.executable, os.path.abspath(__file__), "--oracle-band", d], env=env,
+                           capture_output=True, text=True, timeout=600)
+    if r.returncode != 0:
+        return None
+    return json.loads(r.stdout.strip().splitlines()[-1])
+
+
+def oracle_band(d):
+    """Child of single_core_baseline: fit + forward + adjoint of all rows but
+    the last (its halo row) of the saved band, timed."""
+    import oracle
+    mem = np.load(os.path.join(d, "mem.npy")).astype(np.float64)
+    g = np.load(os.path.join(d, "g.npy")).astype(np.float64)
+    H, W = mem.shape[1] - 1, mem.shape[2]
+    idx = np.arange(H * W, dtype=np.int64)
+    t = time.time()
+    par = oracle.fit(1, mem, single=True)
+    oracle.forward_at(1, par, idx)
+    oracle.grad_at(1, par, g[0], g[1], idx)
+    dt = time.time() - t
+    print(json.dumps({"value": H * W / dt, "unit": UNIT, "cores": 1, "seconds": dt,
+                      "sample": f"fit+forward+adjoint of the first {H} rows x {W} columns"}))
 
 
 if __name__ == "__main__":
-    main()
+    if len(sys.argv) == 3 and sys.argv[1] == "--oracle-band":
+        oracle_band(sys.argv[2])
+    else:
+        main()
