@@ -216,6 +216,10 @@ def main():
         return a.elapsed_time(b) / reps
 
     reps = min(50, max(5, args.steps))
+    # forward and adjoint in one launch, for callers whose upstream gradients
+    # are known before the forward (sensitivity maps of a fixed functional):
+    # the adjoint tiles also write P_min / P_max (one-field batched call)
+    t_fused = timed(lambda: cp.batched([f], [params], [pmin], [pmax], [gmin], [gmax], [grad], graph=True), reps)
     t_cls = timed(lambda: cp.classify(params, f), reps)
     t_sad = timed(lambda: cp.classify(params, f, outputs=("saddle",)), reps)
     ph = params.cpu().numpy()
@@ -235,6 +239,7 @@ def main():
             "fwd_tflops": fl_fwd / (t_fwd * 1e-3) / 1e12, "bwd_tflops": fl_bwd / (t_bwd * 1e-3) / 1e12,
             "fit_hbm_gbs": (20 * 4 + 8) * S * S / (t_fit * 1e-3) / 1e9,
             "classify_ms": t_cls, "saddle_ms": t_sad,
+            "fused_fwd_bwd_ms": t_fused, "fused_fwd_bwd_vertices_per_s": S * S / (t_fused * 1e-3),
             "pieces_by_started_neighbours": counts.tolist(),
         }
     }
