@@ -380,6 +380,22 @@ def test_mvg_backward_parity():
     assert bad.sum() <= max(2, H * W // 200), bad.sum()
 
 
+def test_mvg_backward_full_size_sampled():
+    """1024^2 x 4096 samples (the benchmark's Monte Carlo workload): the
+    gathered gradient at sampled vertices, corners and edges included."""
+    note("mvg backward full size")
+    H, W, ns = 1024, 1024, 4096
+    params, _ = mvg_setup(H, W, 2)
+    gmin, gmax = workloads.upstream(6, H, W)
+    f = cp.Field(H, W, MVG, torch.float32, nsamples=ns, seed=4321, field_id=3)
+    g = host(cp.backward(params, dev(gmin, torch.float32), dev(gmax, torch.float32), f)).reshape(16, -1).T
+    idx = sample_idx(H, W, 48, 8)
+    ref = oracle.mvg_grad_at(host(params), gmin.astype(np.float64), gmax.astype(np.float64), idx, ns, 4321, 3)
+    scale = 1 + np.abs(ref).max(axis=1, keepdims=True)
+    bad = np.any(np.abs(g[idx] - ref) > 2e-5 * scale, axis=1)
+    assert bad.sum() <= 2, bad.sum()
+
+
 # ----------------------------------------------------------------------------
 # batched persistent launch
 # ----------------------------------------------------------------------------
@@ -472,6 +488,38 @@ def test_batched_many_tiles_back_to_back(graph):
     torch.cuda.synchronize()
     for i, (f, p) in enumerate(fl):
         assert torch.equal(cp.backward(p, gmin[i], gmax[i], f), grad[i]), i
+
+
+def test_batched_full_layout_tuned_graph():
+    """The benchmark's 64-field layout (sides 2^U[7,11], 47 M vertices),
+    autotuned and replayed as a graph, as the benchmark times it: forward
+    only equals the per-field forward bit for bit; forward + adjoint gives
+    the per-field gradients bit for bit and the probabilities within 1e-6."""
+    note("batched full layout")
+    fields, params = [], []
+    for side, model, seed in workloads.batched_layout(0):
+        p = dev(workloads.random_params(model, seed, side, side, nbins=10, width=0.05), torch.float32)
+        fields.append(cp.field_of(p, model, 10 if model == HST else 0))
+        params.append(p)
+    assert sum(f.height * f.width for f in fields) > 40e6
+    pmin = [torch.full((f.height, f.width), -1.0, device="cuda") for f in fields]
+    pmax = [torch.full((f.height, f.width), -1.0, device="cuda") for f in fields]
+    for _ in range(2):
+        cp.batched(fields, params, pmin=pmin, pmax=pmax, graph=True, tune=True)
+    torch.cuda.synchronize()
+    for i, (f, p) in enumerate(zip(fields, params)):
+        a, b = cp.forward(p, f)
+        assert torch.equal(a, pmin[i]) and torch.equal(b, pmax[i]), i
+    gmin = [dev(workloads.upstream(i, f.height, f.width)[0], torch.float32) for i, f in enumerate(fields)]
+    gmax = [dev(workloads.upstream(i, f.height, f.width)[1], torch.float32) for i, f in enumerate(fields)]
+    grad = [torch.full_like(p, -1.0) for p in params]
+    for _ in range(2):
+        cp.batched(fields, params, pmin, pmax, gmin, gmax, grad, graph=True, tune=True)
+    torch.cuda.synchronize()
+    for i, (f, p) in enumerate(zip(fields, params)):
+        assert torch.equal(cp.backward(p, gmin[i], gmax[i], f), grad[i]), i
+        a, b = cp.forward(p, f)
+        assert torch.allclose(a, pmin[i], rtol=0, atol=1e-6) and torch.allclose(b, pmax[i], rtol=0, atol=1e-6), i
 
 
 def test_batched_pointer_refresh():
