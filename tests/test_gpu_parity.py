@@ -121,6 +121,25 @@ def test_forward_edge_shapes(model, shape):
     assert_close(host(pmax), rmax, 1e-12, "P_max")
 
 
+def test_golden_fixtures_fp64():
+    """The fixtures under tests/golden: the Sec. 4.1.1 example (exact
+    rational) and the oracle's small fields, through the FP64 kernels."""
+    from fractions import Fraction
+    from conftest import golden_small_fields, read_golden
+    note("golden fixtures")
+    g = read_golden("paper_1d_ordering.txt")
+    grid = np.array([[[float(v) for v in g["lo"][0].split()]], [[float(v) for v in g["hi"][0].split()]]])
+    pmin, pmax = gpu_forward(dev(grid, torch.float64), U)
+    k = int(g["vertex"][0])
+    assert abs(host(pmin)[0, k] - float(Fraction(g["p_min"][0]))) <= 1e-15
+    assert abs(host(pmax)[0, k] - float(Fraction(g["p_max"][0]))) <= 1e-15
+    for name, model, H, W, nb, seed, width, rmin, rmax in golden_small_fields():
+        p = workloads.random_params(model, seed, H, W, nbins=max(nb, 1), width=width)
+        pmin, pmax = gpu_forward(dev(p, torch.float64), model, nb)
+        assert_close(host(pmin), rmin, 1e-12, f"{name} P_min")
+        assert_close(host(pmax), rmax, 1e-12, f"{name} P_max")
+
+
 def test_forward_iid_exact():
     """All vertices identical: 1/5 inside, 1/4 on edges, 1/3 at corners."""
     note("iid exact")

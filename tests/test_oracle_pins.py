@@ -19,6 +19,7 @@ from scipy import integrate, stats
 
 import oracle
 import workloads
+from conftest import golden_small_fields, read_golden
 
 U, E, HST = oracle.UNIFORM, oracle.EPANECHNIKOV, oracle.HISTOGRAM
 
@@ -90,17 +91,27 @@ def test_shifted_uniform_closed_form(c):
 
 
 def test_paper_one_dimensional_ordering():
-    """The running example of Sec. 4.1.1 orders the limits a2 < a1 < a3 <
-    b2 < b1 < b3.  With v = U[1,4] and neighbours U[0,3], U[2,5] (a 1-D
-    vertex has two neighbours, Eq. 1):
-      P_min = int_1^2 (1/3)(3-x)/3 dx + int_2^3 (1/3)(3-x)(5-x)/9 dx
-            = 1/6 + 4/81 = 35/162,
-    and the configuration is symmetric under x -> 5 - x, so P_max = 35/162."""
-    g = np.array([[[0.0, 1.0, 2.0]], [[3.0, 4.0, 5.0]]])
-    pmin, pmax = oracle.forward(U, g)
-    exact = float(Fraction(35, 162))
-    assert pmin[0, 1] == pytest.approx(exact, abs=1e-15)
-    assert pmax[0, 1] == pytest.approx(exact, abs=1e-15)
+    """The running example of Sec. 4.1.1 (ordering a2 < a1 < a3 < b2 < b1 <
+    b3), instantiated with uniform densities; the exact values and their
+    derivation are in tests/golden/paper_1d_ordering.txt."""
+    g = read_golden("paper_1d_ordering.txt")
+    assert g["model"] == ["uniform"]
+    grid = np.array([[[float(v) for v in g["lo"][0].split()]], [[float(v) for v in g["hi"][0].split()]]])
+    pmin, pmax = oracle.forward(U, grid)
+    k = int(g["vertex"][0])
+    assert pmin[0, k] == pytest.approx(float(Fraction(g["p_min"][0])), abs=1e-15)
+    assert pmax[0, k] == pytest.approx(float(Fraction(g["p_max"][0])), abs=1e-15)
+
+
+def test_oracle_reproduces_its_golden_fields():
+    """Regression fixture (tests/golden/oracle_small_fields.txt, written by
+    make_oracle_golden.py from the oracle): a change of the oracle's
+    arithmetic shows here."""
+    for name, model, H, W, nb, seed, width, rmin, rmax in golden_small_fields():
+        p = workloads.random_params(model, seed, H, W, nbins=max(nb, 1), width=width)
+        pmin, pmax = oracle.forward(model, p)
+        np.testing.assert_allclose(pmin, rmin, rtol=0, atol=1e-15, err_msg=name)
+        np.testing.assert_allclose(pmax, rmax, rtol=0, atol=1e-15, err_msg=name)
 
 
 @pytest.mark.parametrize("model", [U, E, HST])
