@@ -1075,33 +1075,43 @@ static void g_adapt(const gstencil_t* g, double lo, double hi, int depth, double
   g_adapt(g, m, hi, depth + 1, acc);
 }
 
-static void gauss_vertex(const grid_t* gr, int y, int x, double out[4]) {
-  gstencil_t g;
+static void gauss_load(const grid_t* gr, int y, int x, gstencil_t* g) {
   int64_t plane = (int64_t)gr->H * gr->W;
   for (int s = 0; s < NSLOT; ++s) {
     int yy = y + SLOT_DY[s], xx = x + SLOT_DX[s];
-    g.pres[s] = yy >= 0 && yy < gr->H && xx >= 0 && xx < gr->W;
-    g.mu[s] = g.sg[s] = 1.0;
-    if (g.pres[s]) {
+    g->pres[s] = yy >= 0 && yy < gr->H && xx >= 0 && xx < gr->W;
+    g->mu[s] = g->sg[s] = 1.0;
+    if (g->pres[s]) {
       int64_t at = (int64_t)yy * gr->W + xx;
-      g.mu[s] = gr->par[at];
-      g.sg[s] = gr->par[plane + at];
+      g->mu[s] = gr->par[at];
+      g->sg[s] = gr->par[plane + at];
     }
   }
+}
+
+/* the forward's pieces: mu_v -/+ 12 sigma_v cut at mu_i + k sigma_i */
+static int gauss_pieces(const gstencil_t* g, double* bp) {
   const double ks[9] = {-8, -4, -2, -1, 0, 1, 2, 4, 8};
-  double lo = g.mu[0] - 12.0 * g.sg[0], hi = g.mu[0] + 12.0 * g.sg[0];
-  double bp[2 + NSLOT * 9];
+  double lo = g->mu[0] - 12.0 * g->sg[0], hi = g->mu[0] + 12.0 * g->sg[0];
   int nbp = 0;
   bp[nbp++] = lo;
   bp[nbp++] = hi;
   for (int s = 0; s < NSLOT; ++s) {
-    if (!g.pres[s]) continue;
+    if (!g->pres[s]) continue;
     for (int k = 0; k < 9; ++k) {
-      double p = g.mu[s] + ks[k] * g.sg[s];
+      double p = g->mu[s] + ks[k] * g->sg[s];
       if (p > lo && p < hi) bp[nbp++] = p;
     }
   }
   qsort(bp, nbp, sizeof(double), cmp_double);
+  return nbp;
+}
+
+static void gauss_vertex(const grid_t* gr, int y, int x, double out[4]) {
+  gstencil_t g;
+  gauss_load(gr, y, x, &g);
+  double bp[2 + NSLOT * 9];
+  int nbp = gauss_pieces(&g, bp);
   double acc[4] = {0, 0, 0, 0};
   for (int i = 0; i + 1 < nbp; ++i)
     if (bp[i + 1] > bp[i]) g_adapt(&g, bp[i], bp[i + 1], 0, acc);
@@ -1110,6 +1120,146 @@ static void gauss_vertex(const grid_t* gr, int y, int x, double out[4]) {
   out[1] = acc[1];
   out[2] = interior ? acc[2] : 0.0;
   out[3] = interior ? acc[3] : 0.0;
+}
+
+/*
+ * Jacobian of P_min and P_max of one stencil with respect to (mu, sigma) of
+ * its five slots (v, e, n, w, s), by differentiating the integrand:
+ *   d pdf_v / d mu_v = pdf_v z_v / sigma_v,
+ *   d pdf_v / d sigma_v = pdf_v (z_v^2 - 1) / sigma_v,       z_v = (x - mu_v)/sigma_v
+ *   d S_k / d mu_k = pdf_k(x),  d S_k / d sigma_k = pdf_k(x) z_k,  d F_k = -d S_k,
+ * and integrating each derivative of the product over the same pieces as the
+ * forward.  A piece is accepted when the 20- and 40-point rules agree to
+ * 1e-13 of the integral of each integrand's magnitude (the vertex-slot
+ * derivatives cancel, so their own value is no scale).
+ */
+#define GJ_N (2 * NSLOT * 2) /* (min, max) x slot x (mu, sigma) */
+
+static void gj_integrands(const gstencil_t* g, double x, double out[GJ_N]) {
+  double zv = (x - g->mu[0]) / g->sg[0];
+  double pdf = exp(-0.5 * zv * zv) / (g->sg[0] * sqrt(2.0 * M_PI));
+  double S[NSLOT], F[NSLOT], dS[NSLOT][2];
+  for (int k = 1; k < NSLOT; ++k) {
+    S[k] = F[k] = 1.0;
+    dS[k][0] = dS[k][1] = 0.0;
+    if (!g->pres[k]) continue;
+    double zk = (x - g->mu[k]) / g->sg[k];
+    double pk = exp(-0.5 * zk * zk) / (g->sg[k] * sqrt(2.0 * M_PI));
+    S[k] = g_surv(x, g->mu[k], g->sg[k]);
+    F[k] = g_cdf(x, g->mu[k], g->sg[k]);
+    dS[k][0] = pk;
+    dS[k][1] = pk * zk;
+  }
+  double PS = 1.0, PF = 1.0;
+  for (int k = 1; k < NSLOT; ++k) {
+    PS *= S[k];
+    PF *= F[k];
+  }
+  /* slot 0: derivatives of the vertex density */
+  double dv[2] = {pdf * zv / g->sg[0], pdf * (zv * zv - 1.0) / g->sg[0]};
+  for (int q = 0; q < 2; ++q) {
+    out[0 * NSLOT * 2 + 0 * 2 + q] = dv[q] * PS;
+    out[1 * NSLOT * 2 + 0 * 2 + q] = dv[q] * PF;
+  }
+  for (int k = 1; k < NSLOT; ++k) {
+    double ls = pdf, lf = pdf;
+    for (int j = 1; j < NSLOT; ++j)
+      if (j != k) {
+        ls *= S[j];
+        lf *= F[j];
+      }
+    for (int q = 0; q < 2; ++q) {
+      out[0 * NSLOT * 2 + k * 2 + q] = ls * dS[k][q];
+      out[1 * NSLOT * 2 + k * 2 + q] = -lf * dS[k][q];
+    }
+  }
+}
+
+static void gj_rule(const gstencil_t* g, int r, double lo, double hi, double out[GJ_N], double mag[GJ_N]) {
+  double c = 0.5 * (lo + hi), h = 0.5 * (hi - lo), f[GJ_N];
+  for (int q = 0; q < GJ_N; ++q) out[q] = mag[q] = 0.0;
+  for (int i = 0; i < gq_n[r]; ++i) {
+    gj_integrands(g, c + h * gq_x[r][i], f);
+    for (int q = 0; q < GJ_N; ++q) {
+      out[q] += gq_w[r][i] * f[q];
+      mag[q] += gq_w[r][i] * fabs(f[q]);
+    }
+  }
+  for (int q = 0; q < GJ_N; ++q) {
+    out[q] *= h;
+    mag[q] *= h;
+  }
+}
+
+static void gj_adapt(const gstencil_t* g, double lo, double hi, int depth, double acc[GJ_N]) {
+  double a[GJ_N], b[GJ_N], ma[GJ_N], mb[GJ_N];
+  gj_rule(g, 0, lo, hi, a, ma);
+  gj_rule(g, 1, lo, hi, b, mb);
+  int ok = 1;
+  for (int q = 0; q < GJ_N; ++q)
+    if (fabs(a[q] - b[q]) > 1e-300 + 1e-13 * mb[q]) ok = 0;
+  if (ok || depth >= 30) {
+    for (int q = 0; q < GJ_N; ++q) acc[q] += b[q];
+    return;
+  }
+  double m = 0.5 * (lo + hi);
+  gj_adapt(g, lo, m, depth + 1, acc);
+  gj_adapt(g, m, hi, depth + 1, acc);
+}
+
+/* jm, jx: [NSLOT][2] derivatives of P_min, P_max; absent slots 0 */
+static void gauss_jac_vertex(const grid_t* gr, int y, int x, double jm[NSLOT * 2], double jx[NSLOT * 2]) {
+  gstencil_t g;
+  gauss_load(gr, y, x, &g);
+  double bp[2 + NSLOT * 9];
+  int nbp = gauss_pieces(&g, bp);
+  double acc[GJ_N];
+  for (int q = 0; q < GJ_N; ++q) acc[q] = 0.0;
+  for (int i = 0; i + 1 < nbp; ++i)
+    if (bp[i + 1] > bp[i]) gj_adapt(&g, bp[i], bp[i + 1], 0, acc);
+  for (int k = 0; k < NSLOT * 2; ++k) {
+    int present = g.pres[k / 2];
+    jm[k] = present ? acc[k] : 0.0;
+    jx[k] = present ? acc[NSLOT * 2 + k] : 0.0;
+  }
+}
+
+/* Jacobians of the stencils centred at idx: [nidx][NSLOT][2] each */
+int or_gauss_jacobian_at(int H, int W, const double* params, int64_t nidx, const int64_t* idx, double* jmin,
+                         double* jmax) {
+  if (H < 1 || W < 1) return 1;
+  if (!gq_ready) gq_init();
+  grid_t g = {OR_GAUSSIAN, H, W, 0, params};
+#pragma omp parallel for schedule(dynamic, 4)
+  for (int64_t i = 0; i < nidx; ++i)
+    gauss_jac_vertex(&g, (int)(idx[i] / W), (int)(idx[i] % W), jmin + i * NSLOT * 2, jmax + i * NSLOT * 2);
+  return 0;
+}
+
+/* adjoint of the independent Gaussian at idx ([nidx][2]: mu, sigma), as or_grad_at */
+int or_gauss_grad_at(int H, int W, const double* params, const double* gmin, const double* gmax, int64_t nidx,
+                     const int64_t* idx, double* out, int absval) {
+  if (H < 1 || W < 1) return 1;
+  if (!gq_ready) gq_init();
+  grid_t g = {OR_GAUSSIAN, H, W, 0, params};
+#pragma omp parallel for schedule(dynamic, 4)
+  for (int64_t i = 0; i < nidx; ++i) {
+    int y = (int)(idx[i] / W), x = (int)(idx[i] % W);
+    double* o = out + i * 2;
+    o[0] = o[1] = 0.0;
+    double jm[NSLOT * 2], jx[NSLOT * 2];
+    for (int s = 0; s < NSLOT; ++s) {
+      int vy = y - SLOT_DY[s], vx = x - SLOT_DX[s];
+      if (vy < 0 || vy >= H || vx < 0 || vx >= W) continue;
+      gauss_jac_vertex(&g, vy, vx, jm, jx);
+      int64_t at = (int64_t)vy * W + vx;
+      for (int k = 0; k < 2; ++k) {
+        double a = gmin[at] * jm[s * 2 + k], b = gmax[at] * jx[s * 2 + k];
+        o[k] += absval ? fabs(a) + fabs(b) : a + b;
+      }
+    }
+  }
+  return 0;
 }
 
 /* out [nidx][4] = (P_min, P_max, t1, t2) at flat indices idx */

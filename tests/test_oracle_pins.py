@@ -983,6 +983,67 @@ def test_gauss_equals_diagonal_multivariate_model():
         assert abs(got - p) < 4 * math.sqrt(p * (1 - p) / (1 << 15)), (got, p)
 
 
+def test_gauss_jacobian_matches_finite_differences():
+    """Derivatives of P_min / P_max of a stencil with respect to (mu, sigma)
+    of each slot, against central differences of the oracle's forward (an
+    independent route: no derivative formula)."""
+    rng = np.random.default_rng(21)
+    slots = "venws"
+    for _ in range(6):
+        d = random_gauss_stencil(rng)
+        par = gauss_grid(d)
+        jm, jx = oracle.gauss_jacobian_at(par, [4])
+        for si, k in enumerate(slots):
+            for q in range(2):
+                h = 1e-5 * d[k][1]
+                pp, pm = par.copy(), par.copy()
+                pp[q][POS[k]] += h
+                pm[q][POS[k]] -= h
+                fp, fm = oracle.gauss_at(pp, [4])[0], oracle.gauss_at(pm, [4])[0]
+                for j, r in ((0, jm), (1, jx)):
+                    fd = (fp[j] - fm[j]) / (2 * h)
+                    assert r[0, si, q] == pytest.approx(fd, rel=2e-6, abs=2e-7 / d[k][1]), (k, q, j)
+
+
+def test_gauss_jacobian_invariances():
+    """Translation (sum of the mu-derivatives is 0) and scale about the vertex
+    mean (sigma_v dP/dsigma_v + sum_n (mu_n - mu_v) dP/dmu_n + sigma_n
+    dP/dsigma_n = 0): the identities the device adjoint uses for the vertex
+    slot, checked on the oracle, which integrates that slot directly."""
+    rng = np.random.default_rng(23)
+    for _ in range(8):
+        d = random_gauss_stencil(rng)
+        jm, jx = oracle.gauss_jacobian_at(gauss_grid(d), [4])
+        for r in (jm[0], jx[0]):
+            scale = np.abs(r).sum()
+            assert abs(r[:, 0].sum()) <= 1e-11 * scale
+            sc = sum((d[k][0] - d["v"][0]) * r[i, 0] + d[k][1] * r[i, 1] for i, k in enumerate("venws"))
+            assert abs(sc) <= 1e-11 * (scale * (1 + max(abs(d[k][0] - d["v"][0]) + d[k][1] for k in "venws")))
+
+
+def test_gauss_adjoint_matches_finite_differences_of_the_loss():
+    """Gathered adjoint of L = sum g_min P_min + g_max P_max on a 5x6 grid
+    (edges, corners) against central differences of L itself."""
+    rng = np.random.default_rng(25)
+    H, W = 5, 6
+    par = np.stack([rng.normal(0, 0.2, (H, W)), 10 ** rng.uniform(-1.3, -0.5, (H, W))])
+    g1, g2 = rng.normal(size=(H, W)), rng.normal(size=(H, W))
+    idx = np.arange(H * W)
+    got = oracle.gauss_grad_at(par, g1, g2, idx)
+    def loss(p):
+        r = oracle.gauss(p)
+        return float((g1 * r[0] + g2 * r[1]).sum())
+    for i in idx[::3]:
+        y, x = divmod(int(i), W)
+        for q in range(2):
+            h = 1e-5 * par[1, y, x]
+            pp, pm = par.copy(), par.copy()
+            pp[q, y, x] += h
+            pm[q, y, x] -= h
+            fd = (loss(pp) - loss(pm)) / (2 * h)
+            assert got[i, q] == pytest.approx(fd, rel=2e-6, abs=1e-6 / par[1, y, x]), (i, q)
+
+
 def test_gauss_fit_against_numpy():
     mem = workloads.smooth_ensemble(2, 9, 13)
     par = oracle.fit(G, mem.astype(np.float64))
