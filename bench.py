@@ -301,8 +301,12 @@ def more_detail(cp, workloads, torch, dev, S, reps):
     f = cp.field_of(params, "gaussian")
     a, b = torch.empty((S, S), device=dev), torch.empty((S, S), device=dev)
     tf = _timed(torch, lambda: cp.forward(params, f, a, b), reps)
-    res["gaussian_2048"] = {"fwd_ms": tf, "fwd_vertices_per_s": S * S / (tf * 1e-3)}
-    del params
+    g1, g2 = (torch.as_tensor(g, device=dev) for g in workloads.upstream(1, S, S))
+    grad = torch.empty_like(params)
+    tb = _timed(torch, lambda: cp.backward(params, g1, g2, f, grad), max(3, reps // 4))
+    res["gaussian_2048"] = {"fwd_ms": tf, "bwd_ms": tb, "fwd_vertices_per_s": S * S / (tf * 1e-3),
+                            "fwd_bwd_vertices_per_s": S * S / ((tf + tb) * 1e-3)}
+    del params, grad
     # multivariate Gaussian 1024^2, 4096 samples
     n = 1024
     mem = torch.as_tensor(workloads.correlated_ensemble(0, n, n), device=dev)

@@ -1130,8 +1130,12 @@ static void gauss_vertex(const grid_t* gr, int y, int x, double out[4]) {
  *   d S_k / d mu_k = pdf_k(x),  d S_k / d sigma_k = pdf_k(x) z_k,  d F_k = -d S_k,
  * and integrating each derivative of the product over the same pieces as the
  * forward.  A piece is accepted when the 20- and 40-point rules agree to
- * 1e-13 of the integral of each integrand's magnitude (the vertex-slot
- * derivatives cancel, so their own value is no scale).
+ * 1e-13 of (piece length x the largest magnitude of the integrand on it)
+ * plus 1e-15 of (piece length x the largest magnitude over the whole range):
+ * the vertex-slot integrands change sign (pdf_v (z_v^2 - 1) vanishes at
+ * mu_v -/+ sigma_v, where it is known only to a rounding noise set by the
+ * integrand's overall size), so neither their own value nor their local
+ * size is a scale there; plus 1e-30 for far-tail pieces that underflow.
  */
 #define GJ_N (2 * NSLOT * 2) /* (min, max) x slot x (mu, sigma) */
 
@@ -1175,6 +1179,7 @@ static void gj_integrands(const gstencil_t* g, double x, double out[GJ_N]) {
   }
 }
 
+/* out: the rule's value; mag: 2h max |f| over its nodes */
 static void gj_rule(const gstencil_t* g, int r, double lo, double hi, double out[GJ_N], double mag[GJ_N]) {
   double c = 0.5 * (lo + hi), h = 0.5 * (hi - lo), f[GJ_N];
   for (int q = 0; q < GJ_N; ++q) out[q] = mag[q] = 0.0;
@@ -1182,29 +1187,31 @@ static void gj_rule(const gstencil_t* g, int r, double lo, double hi, double out
     gj_integrands(g, c + h * gq_x[r][i], f);
     for (int q = 0; q < GJ_N; ++q) {
       out[q] += gq_w[r][i] * f[q];
-      mag[q] += gq_w[r][i] * fabs(f[q]);
+      mag[q] = fmax(mag[q], fabs(f[q]));
     }
   }
   for (int q = 0; q < GJ_N; ++q) {
     out[q] *= h;
-    mag[q] *= h;
+    mag[q] *= 2.0 * h;
   }
 }
 
-static void gj_adapt(const gstencil_t* g, double lo, double hi, int depth, double acc[GJ_N]) {
+/* fs: the largest magnitude of each integrand over the stencil's range */
+static void gj_adapt(const gstencil_t* g, double lo, double hi, int depth, const double fs[GJ_N],
+                     double acc[GJ_N]) {
   double a[GJ_N], b[GJ_N], ma[GJ_N], mb[GJ_N];
   gj_rule(g, 0, lo, hi, a, ma);
   gj_rule(g, 1, lo, hi, b, mb);
   int ok = 1;
   for (int q = 0; q < GJ_N; ++q)
-    if (fabs(a[q] - b[q]) > 1e-300 + 1e-13 * mb[q]) ok = 0;
+    if (fabs(a[q] - b[q]) > 1e-30 + 1e-13 * fmax(ma[q], mb[q]) + 1e-15 * (hi - lo) * fs[q]) ok = 0;
   if (ok || depth >= 30) {
     for (int q = 0; q < GJ_N; ++q) acc[q] += b[q];
     return;
   }
   double m = 0.5 * (lo + hi);
-  gj_adapt(g, lo, m, depth + 1, acc);
-  gj_adapt(g, m, hi, depth + 1, acc);
+  gj_adapt(g, lo, m, depth + 1, fs, acc);
+  gj_adapt(g, m, hi, depth + 1, fs, acc);
 }
 
 /* jm, jx: [NSLOT][2] derivatives of P_min, P_max; absent slots 0 */
@@ -1213,10 +1220,15 @@ static void gauss_jac_vertex(const grid_t* gr, int y, int x, double jm[NSLOT * 2
   gauss_load(gr, y, x, &g);
   double bp[2 + NSLOT * 9];
   int nbp = gauss_pieces(&g, bp);
-  double acc[GJ_N];
-  for (int q = 0; q < GJ_N; ++q) acc[q] = 0.0;
+  double acc[GJ_N], fs[GJ_N], tmp[GJ_N], mag[GJ_N];
+  for (int q = 0; q < GJ_N; ++q) acc[q] = fs[q] = 0.0;
   for (int i = 0; i + 1 < nbp; ++i)
-    if (bp[i + 1] > bp[i]) gj_adapt(&g, bp[i], bp[i + 1], 0, acc);
+    if (bp[i + 1] > bp[i]) {
+      gj_rule(&g, 1, bp[i], bp[i + 1], tmp, mag);
+      for (int q = 0; q < GJ_N; ++q) fs[q] = fmax(fs[q], mag[q] / (bp[i + 1] - bp[i]));
+    }
+  for (int i = 0; i + 1 < nbp; ++i)
+    if (bp[i + 1] > bp[i]) gj_adapt(&g, bp[i], bp[i + 1], 0, fs, acc);
   for (int k = 0; k < NSLOT * 2; ++k) {
     int present = g.pres[k / 2];
     jm[k] = present ? acc[k] : 0.0;

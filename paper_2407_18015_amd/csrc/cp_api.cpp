@@ -199,7 +199,6 @@ cp_status_t cp_prob_backward(const cp_field_desc_t* desc, const void* params, co
   cp_status_t s = check_desc(desc, f);
   if (s != CP_OK) return s;
   if (!params || !g_min || !g_max || !grad_params) return fail(CP_EINVAL, "a backward argument is NULL");
-  if (f.model == CP_GAUSSIAN) return fail(CP_EUNSUPPORTED, "backward: no adjoint for the independent Gaussian");
   hipStream_t st = static_cast<hipStream_t>(stream);
   hipError_t e;
   if (f.model == CP_MVGAUSS)

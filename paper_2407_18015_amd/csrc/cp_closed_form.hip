@@ -147,6 +147,16 @@ static hipError_t launch_bwd_ue(const FieldPtrs<T>& p, int model, hipStream_t st
   return hipGetLastError();
 }
 
+// independent Gaussian: one stencil per thread (16x16 stencils, 14x14
+// outputs); its panel sweep is a loop, not straight-line code
+template <typename T>
+static hipError_t launch_bwd_gauss(const FieldPtrs<T>& p, hipStream_t st) {
+  constexpr int O = 14;
+  const int tx = cdiv(p.W, O), ty = cdiv(p.H, O), n = tx * ty;
+  hipLaunchKernelGGL((k_bwd_ue<T, CP_GAUSSIAN, O, O>), dim3(n), dim3(256), 0, st, p, tx, n);
+  return hipGetLastError();
+}
+
 template <typename T, int TY>
 static hipError_t launch_bwd_hist(const FieldPtrs<T>& p, hipStream_t st) {
   const int tx = cdiv(p.W, kFwdTX), ty = cdiv(p.H, TY), n = tx * ty;
@@ -170,6 +180,7 @@ template <typename T>
 static hipError_t bwd_typed(const Field& f, const void* params, const void* gmin, const void* gmax, void* grad,
                             hipStream_t st) {
   FieldPtrs<T> p = make_ptrs<T>(f, params, nullptr, nullptr, gmin, gmax, grad);
+  if (f.model == CP_GAUSSIAN) return launch_bwd_gauss<T>(p, st);
   if (f.model != CP_HISTOGRAM) {
     // 30x30 outputs (32x32 stencils, 4 per thread) keep the FP32 tile under
     // 64 KiB of static LDS; FP64 uses 14x14 (16x16 stencils)

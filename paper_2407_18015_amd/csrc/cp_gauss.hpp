@@ -130,4 +130,139 @@ CP_HD void gauss_vertex(T mv, T sv, const T (&mn)[4], const T (&sn)[4], const bo
   out[3] = interior ? acc[3] * inv_sqrt_2pi : T(0);
 }
 
+// Weighted Jacobian of one stencil: jac[2 slot + q] = g_min dP_min/dtheta_q
+// + g_max dP_max/dtheta_q, theta = (mu, sigma), slots v, e, n, w, s (absent
+// neighbours: 0); also P_min and P_max.  In vertex units, with
+// p_n(x) = phi(z_n) / sigma_n the density of neighbour n:
+//   dP_min/dmu_n    = int phi(t) p_n prod_{k!=n} S_k dt,
+//   dP_min/dsigma_n = int phi(t) p_n z_n prod_{k!=n} S_k dt,
+// and for P_max the same with F and the opposite sign (dF = -dS).  The
+// vertex slot follows from translation invariance (dP/dmu_v = -sum_n
+// dP/dmu_n) and scale invariance about mu_v (sigma_v dP/dsigma_v = -sum_n
+// ((mu_n - mu_v) dP/dmu_n + sigma_n dP/dsigma_n)).  Same panels and rule as
+// gauss_vertex; the leave-one-out products come from prefix / suffix
+// products.
+template <typename T>
+CP_HD void gauss_vertex_jac(T mv, T sv, const T (&mn)[4], const T (&sn)[4], const bool (&pres)[4], T gmin,
+                            T gmax, T (&jac)[10], T& pmin, T& pmax) {
+  using R = GaussRule<T>;
+  constexpr int K = R::K, N = R::N;
+  constexpr T C = R::c[K - 1];
+  const T big = T(4) * C;
+  const T isv = crcp(sv);
+  T d[4], s[4], r[4], nx[4];
+  int k[4];
+#pragma unroll
+  for (int n = 0; n < 4; ++n) {
+    d[n] = (mn[n] - mv) * isv;
+    s[n] = sn[n] * isv;
+    r[n] = sv * crcp(sn[n]);
+    k[n] = 0;
+    nx[n] = pres[n] ? cfma(T(R::c[0]), s[n], d[n]) : big;
+    for (int q = 0; q < K && pres[n] && !(nx[n] > -C); ++q) {
+      k[n] += 1;
+      nx[n] = k[n] < K ? cfma(T(R::c[k[n]]), s[n], d[n]) : big;
+    }
+  }
+  int kv = 1;
+  T nv = T(R::c[1]);
+  T x0 = -C;
+  T fS = T(0), fF = T(0);
+  T aS[4] = {T(0), T(0), T(0), T(0)}, bS[4] = {T(0), T(0), T(0), T(0)};
+  T aF[4] = {T(0), T(0), T(0), T(0)}, bF[4] = {T(0), T(0), T(0), T(0)};
+  constexpr T rs2 = T(0.70710678118654752440);
+  for (int it = 0; it < 5 * K; ++it) {
+    if (!(x0 < C)) break;
+    T x1 = nv;
+#pragma unroll
+    for (int n = 0; n < 4; ++n) x1 = tmin(x1, nx[n]);
+    const T mid = (x0 + x1) * T(0.5), hl = (x1 - x0) * T(0.5);
+    T pS = T(0), pF = T(0), qaS[4], qbS[4], qaF[4], qbF[4];
+#pragma unroll
+    for (int n = 0; n < 4; ++n) qaS[n] = qbS[n] = qaF[n] = qbF[n] = T(0);
+    // the node loop stays a loop (the rule's nodes and weights are read from
+    // constant memory): unrolled, its live values do not fit the registers
+#pragma unroll 1
+    for (int j = 0; j < N; ++j) {
+      const T t = cfma(hl, T(GL<N>::x[j]), mid);
+      const T phi = T(GL<N>::w[j]) * gexp(T(-0.5) * t * t);
+      T S[4], F[4], z[4], pz[4];
+#pragma unroll
+      for (int n = 0; n < 4; ++n) {
+        S[n] = F[n] = T(1);
+        z[n] = pz[n] = T(0);
+        if (!pres[n]) continue;
+        z[n] = (t - d[n]) * r[n];
+        const T e = T(0.5) * gerfc(fabs(z[n]) * rs2);
+        S[n] = z[n] > T(0) ? e : T(1) - e;
+        F[n] = z[n] > T(0) ? T(1) - e : e;
+        pz[n] = gexp(T(-0.5) * z[n] * z[n]);
+      }
+      // prefix products carry the node weight and the vertex density
+      T preS[5], preF[5], sufS[5], sufF[5];
+      preS[0] = preF[0] = phi;
+#pragma unroll
+      for (int n = 0; n < 4; ++n) {
+        preS[n + 1] = preS[n] * S[n];
+        preF[n + 1] = preF[n] * F[n];
+      }
+      sufS[4] = sufF[4] = T(1);
+#pragma unroll
+      for (int n = 3; n >= 0; --n) {
+        sufS[n] = sufS[n + 1] * S[n];
+        sufF[n] = sufF[n + 1] * F[n];
+      }
+      pS += preS[4];
+      pF += preF[4];
+#pragma unroll
+      for (int n = 0; n < 4; ++n) {
+        const T ls = pz[n] * (preS[n] * sufS[n + 1]);
+        const T lf = pz[n] * (preF[n] * sufF[n + 1]);
+        qaS[n] += ls;
+        qbS[n] = cfma(ls, z[n], qbS[n]);
+        qaF[n] += lf;
+        qbF[n] = cfma(lf, z[n], qbF[n]);
+      }
+    }
+    fS = cfma(pS, hl, fS);
+    fF = cfma(pF, hl, fF);
+#pragma unroll
+    for (int n = 0; n < 4; ++n) {
+      aS[n] = cfma(qaS[n], hl, aS[n]);
+      bS[n] = cfma(qbS[n], hl, bS[n]);
+      aF[n] = cfma(qaF[n], hl, aF[n]);
+      bF[n] = cfma(qbF[n], hl, bF[n]);
+    }
+    if (nv == x1) {
+      kv += 1;
+      nv = kv < K ? T(R::c[kv]) : big;
+    }
+#pragma unroll
+    for (int n = 0; n < 4; ++n)
+      if (nx[n] == x1) {
+        k[n] += 1;
+        nx[n] = k[n] < K ? cfma(T(R::c[k[n]]), s[n], d[n]) : big;
+      }
+    x0 = x1;
+  }
+  constexpr T inv_sqrt_2pi = T(0.39894228040143267794), inv_2pi = T(0.15915494309189533577);
+  pmin = fS * inv_sqrt_2pi;
+  pmax = fF * inv_sqrt_2pi;
+  T smu = T(0), ssg = T(0);
+#pragma unroll
+  for (int n = 0; n < 4; ++n) {
+    jac[2 + 2 * n] = jac[3 + 2 * n] = T(0);
+    if (!pres[n]) continue;
+    const T c = inv_2pi * crcp(sn[n]);
+    const T dmu = c * (gmin * aS[n] - gmax * aF[n]);  // g-weighted dP/dmu_n
+    const T dsg = c * (gmin * bS[n] - gmax * bF[n]);  // g-weighted dP/dsigma_n
+    jac[2 + 2 * n] = dmu;
+    jac[3 + 2 * n] = dsg;
+    smu += dmu;
+    ssg = cfma(d[n], dmu, cfma(s[n], dsg, ssg));
+  }
+  jac[0] = -smu;
+  jac[1] = -ssg;
+}
+
 }  // namespace cp

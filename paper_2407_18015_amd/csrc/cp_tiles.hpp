@@ -6,6 +6,7 @@
 #pragma once
 
 #include "cp_device.hpp"
+#include "cp_gauss.hpp"
 #include "cp_hist.hpp"
 #include "cpcrit.h"
 
@@ -125,7 +126,9 @@ CP_HD void vertex_jac_vals(T p0, T p1, const T (&q0)[4], const T (&q1)[4], const
     pmin = pmax = qnan<T>();
     return;
   }
-  if (MODEL == CP_UNIFORM) {
+  if constexpr (MODEL == CP_GAUSSIAN) {
+    gauss_vertex_jac<T>(p0, p1, q0, q1, pres, gmin, gmax, jac, pmin, pmax);
+  } else if constexpr (MODEL == CP_UNIFORM) {
     const T Lv = p1 - p0, iLv = crcp(Lv);
     T a[4], b[4], iL[4];
     UniSide<T> s;
