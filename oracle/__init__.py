@@ -57,7 +57,7 @@ def _load():
         "or_jacobian_at": (i32, [i32, i32, i32, i32, P, i64, P, P, P]),
         "or_saddle_at": (i32, [i32, i32, i32, i32, P, i64, P, P, P]),
         "or_gauss_at": (i32, [i32, i32, P, i64, P, P]),
-        "or_gauss_jacobian_at": (i32, [i32, i32, P, i64, P, P, P]),
+        "or_gauss_jacobian_at": (i32, [i32, i32, P, i64, P, P, P, i32]),
         "or_gauss_grad_at": (i32, [i32, i32, P, P, P, i64, P, P, i32]),
         "or_semi_at": (i32, [i32, i32, i32, P, i32, ctypes.c_uint64, ctypes.c_uint32, i64, P, P]),
         "or_semi_samples": (i32, [i32, i32, i32, P, i32, i32, i32, ctypes.c_uint64, ctypes.c_uint32, P]),
@@ -209,24 +209,27 @@ def gauss(params) -> np.ndarray:
     return gauss_at(params, np.arange(H * W)).T.reshape(4, H, W).copy()
 
 
-def gauss_jacobian_at(params, idx):
+def gauss_jacobian_at(params, idx, absolute: bool = False):
     """Independent Gaussian: derivatives of P_min and P_max of the stencils
     centred at idx with respect to (mu, sigma) of their slots (v, e, n, w,
-    s): two arrays [n][5][2] (absent slots 0)."""
+    s): two arrays [n][5][2] (absent slots 0).  absolute: the integrals of
+    the magnitudes of the same integrands (the scale of rounding in any
+    quadrature of them)."""
     params = _f64(params)
     _, H, W = params.shape
     idx = np.ascontiguousarray(idx, dtype=np.int64)
     jm = np.empty((idx.size, 5, 2))
     jx = np.empty((idx.size, 5, 2))
-    _check(_load().or_gauss_jacobian_at(H, W, _ptr(params), idx.size, _ptr(idx), _ptr(jm), _ptr(jx)),
+    _check(_load().or_gauss_jacobian_at(H, W, _ptr(params), idx.size, _ptr(idx), _ptr(jm), _ptr(jx),
+                                               int(absolute)),
            "gauss_jacobian_at")
     return jm, jx
 
 
 def gauss_grad_at(params, gmin, gmax, idx, absolute: bool = False) -> np.ndarray:
     """Independent Gaussian adjoint at flat indices: [n][2] (d/d mu, d/d sigma)
-    of sum g_min P_min + g_max P_max (absolute: the sum of the magnitudes of
-    the contributing terms, as grad_at)."""
+    of sum g_min P_min + g_max P_max (absolute: the sum over the contributing
+    terms of |g| times the integral of the magnitude of the integrand)."""
     params = _f64(params)
     _, H, W = params.shape
     gmin = _f64(gmin); gmax = _f64(gmax)

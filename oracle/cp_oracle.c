@@ -1179,76 +1179,94 @@ static void gj_integrands(const gstencil_t* g, double x, double out[GJ_N]) {
   }
 }
 
-/* out: the rule's value; mag: 2h max |f| over its nodes */
-static void gj_rule(const gstencil_t* g, int r, double lo, double hi, double out[GJ_N], double mag[GJ_N]) {
+/* out: the rule's value; mag: 2h max |f| over its nodes; absout: the rule
+ * applied to |f| */
+static void gj_rule(const gstencil_t* g, int r, double lo, double hi, double out[GJ_N], double mag[GJ_N],
+                    double absout[GJ_N]) {
   double c = 0.5 * (lo + hi), h = 0.5 * (hi - lo), f[GJ_N];
-  for (int q = 0; q < GJ_N; ++q) out[q] = mag[q] = 0.0;
+  for (int q = 0; q < GJ_N; ++q) out[q] = mag[q] = absout[q] = 0.0;
   for (int i = 0; i < gq_n[r]; ++i) {
     gj_integrands(g, c + h * gq_x[r][i], f);
     for (int q = 0; q < GJ_N; ++q) {
       out[q] += gq_w[r][i] * f[q];
+      absout[q] += gq_w[r][i] * fabs(f[q]);
       mag[q] = fmax(mag[q], fabs(f[q]));
     }
   }
   for (int q = 0; q < GJ_N; ++q) {
     out[q] *= h;
+    absout[q] *= h;
     mag[q] *= 2.0 * h;
   }
 }
 
-/* fs: the largest magnitude of each integrand over the stencil's range */
+/* fs: the largest magnitude of each integrand over the stencil's range;
+ * acc += the integrals, aacc += the integrals of the magnitudes (over the
+ * pieces the integrals accept) */
 static void gj_adapt(const gstencil_t* g, double lo, double hi, int depth, const double fs[GJ_N],
-                     double acc[GJ_N]) {
-  double a[GJ_N], b[GJ_N], ma[GJ_N], mb[GJ_N];
-  gj_rule(g, 0, lo, hi, a, ma);
-  gj_rule(g, 1, lo, hi, b, mb);
+                     double acc[GJ_N], double aacc[GJ_N]) {
+  double a[GJ_N], b[GJ_N], ma[GJ_N], mb[GJ_N], aa[GJ_N], ab[GJ_N];
+  gj_rule(g, 0, lo, hi, a, ma, aa);
+  gj_rule(g, 1, lo, hi, b, mb, ab);
   int ok = 1;
   for (int q = 0; q < GJ_N; ++q)
     if (fabs(a[q] - b[q]) > 1e-30 + 1e-13 * fmax(ma[q], mb[q]) + 1e-15 * (hi - lo) * fs[q]) ok = 0;
   if (ok || depth >= 30) {
-    for (int q = 0; q < GJ_N; ++q) acc[q] += b[q];
+    for (int q = 0; q < GJ_N; ++q) {
+      acc[q] += b[q];
+      aacc[q] += ab[q];
+    }
     return;
   }
   double m = 0.5 * (lo + hi);
-  gj_adapt(g, lo, m, depth + 1, fs, acc);
-  gj_adapt(g, m, hi, depth + 1, fs, acc);
+  gj_adapt(g, lo, m, depth + 1, fs, acc, aacc);
+  gj_adapt(g, m, hi, depth + 1, fs, acc, aacc);
 }
 
-/* jm, jx: [NSLOT][2] derivatives of P_min, P_max; absent slots 0 */
-static void gauss_jac_vertex(const grid_t* gr, int y, int x, double jm[NSLOT * 2], double jx[NSLOT * 2]) {
+/* jm, jx: [NSLOT][2] derivatives of P_min, P_max; absent slots 0.
+ * absval != 0: the integrals of the integrands' magnitudes instead, the
+ * scale against which rounding in any quadrature of them is measured (the
+ * vertex-slot integrands change sign, so their integral can be far smaller) */
+static void gauss_jac_vertex(const grid_t* gr, int y, int x, double jm[NSLOT * 2], double jx[NSLOT * 2],
+                             int absval) {
   gstencil_t g;
   gauss_load(gr, y, x, &g);
   double bp[2 + NSLOT * 9];
   int nbp = gauss_pieces(&g, bp);
-  double acc[GJ_N], fs[GJ_N], tmp[GJ_N], mag[GJ_N];
-  for (int q = 0; q < GJ_N; ++q) acc[q] = fs[q] = 0.0;
+  double acc[GJ_N], aacc[GJ_N], fs[GJ_N], tmp[GJ_N], mag[GJ_N], atmp[GJ_N];
+  for (int q = 0; q < GJ_N; ++q) acc[q] = aacc[q] = fs[q] = 0.0;
   for (int i = 0; i + 1 < nbp; ++i)
     if (bp[i + 1] > bp[i]) {
-      gj_rule(&g, 1, bp[i], bp[i + 1], tmp, mag);
+      gj_rule(&g, 1, bp[i], bp[i + 1], tmp, mag, atmp);
       for (int q = 0; q < GJ_N; ++q) fs[q] = fmax(fs[q], mag[q] / (bp[i + 1] - bp[i]));
     }
   for (int i = 0; i + 1 < nbp; ++i)
-    if (bp[i + 1] > bp[i]) gj_adapt(&g, bp[i], bp[i + 1], 0, fs, acc);
+    if (bp[i + 1] > bp[i]) gj_adapt(&g, bp[i], bp[i + 1], 0, fs, acc, aacc);
+  const double* r = absval ? aacc : acc;
   for (int k = 0; k < NSLOT * 2; ++k) {
     int present = g.pres[k / 2];
-    jm[k] = present ? acc[k] : 0.0;
-    jx[k] = present ? acc[NSLOT * 2 + k] : 0.0;
+    jm[k] = present ? r[k] : 0.0;
+    jx[k] = present ? r[NSLOT * 2 + k] : 0.0;
   }
 }
 
-/* Jacobians of the stencils centred at idx: [nidx][NSLOT][2] each */
+/* Jacobians of the stencils centred at idx: [nidx][NSLOT][2] each (absval:
+ * the integrals of the integrands' magnitudes) */
 int or_gauss_jacobian_at(int H, int W, const double* params, int64_t nidx, const int64_t* idx, double* jmin,
-                         double* jmax) {
+                         double* jmax, int absval) {
   if (H < 1 || W < 1) return 1;
   if (!gq_ready) gq_init();
   grid_t g = {OR_GAUSSIAN, H, W, 0, params};
 #pragma omp parallel for schedule(dynamic, 4)
   for (int64_t i = 0; i < nidx; ++i)
-    gauss_jac_vertex(&g, (int)(idx[i] / W), (int)(idx[i] % W), jmin + i * NSLOT * 2, jmax + i * NSLOT * 2);
+    gauss_jac_vertex(&g, (int)(idx[i] / W), (int)(idx[i] % W), jmin + i * NSLOT * 2, jmax + i * NSLOT * 2,
+                     absval);
   return 0;
 }
 
-/* adjoint of the independent Gaussian at idx ([nidx][2]: mu, sigma), as or_grad_at */
+/* adjoint of the independent Gaussian at idx ([nidx][2]: mu, sigma), as
+ * or_grad_at; absval != 0 sums |g| times the integrals of the integrands'
+ * magnitudes */
 int or_gauss_grad_at(int H, int W, const double* params, const double* gmin, const double* gmax, int64_t nidx,
                      const int64_t* idx, double* out, int absval) {
   if (H < 1 || W < 1) return 1;
@@ -1263,7 +1281,7 @@ int or_gauss_grad_at(int H, int W, const double* params, const double* gmin, con
     for (int s = 0; s < NSLOT; ++s) {
       int vy = y - SLOT_DY[s], vx = x - SLOT_DX[s];
       if (vy < 0 || vy >= H || vx < 0 || vx >= W) continue;
-      gauss_jac_vertex(&g, vy, vx, jm, jx);
+      gauss_jac_vertex(&g, vy, vx, jm, jx, absval);
       int64_t at = (int64_t)vy * W + vx;
       for (int k = 0; k < 2; ++k) {
         double a = gmin[at] * jm[s * 2 + k], b = gmax[at] * jx[s * 2 + k];

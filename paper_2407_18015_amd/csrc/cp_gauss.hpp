@@ -146,37 +146,47 @@ template <typename T>
 CP_HD void gauss_vertex_jac(T mv, T sv, const T (&mn)[4], const T (&sn)[4], const bool (&pres)[4], T gmin,
                             T gmax, T (&jac)[10], T& pmin, T& pmax) {
   using R = GaussRule<T>;
+  // Positions (panel ends, nodes, z_n) in FP64 for both dtypes: in FP32 a
+  // node's t carries half an ulp of |t| <= 6 (2.4e-7), which z_n multiplies
+  // by sigma_v / sigma_n; the derivative integrands p_n z_n would inherit a
+  // relative error of that size for narrow neighbours.  The factors
+  // themselves (erfc, exp) and the sums stay in T.
+  using P = double;
   constexpr int K = R::K, N = R::N;
-  constexpr T C = R::c[K - 1];
-  const T big = T(4) * C;
-  const T isv = crcp(sv);
-  T d[4], s[4], r[4], nx[4];
+  constexpr P C = R::c[K - 1];
+  const P big = P(4) * C;
+  const P isv = P(1) / P(sv);
+  P d[4], s[4], r[4], nx[4];
   int k[4];
 #pragma unroll
   for (int n = 0; n < 4; ++n) {
-    d[n] = (mn[n] - mv) * isv;
-    s[n] = sn[n] * isv;
-    r[n] = sv * crcp(sn[n]);
+    d[n] = (P(mn[n]) - P(mv)) * isv;
+    s[n] = P(sn[n]) * isv;
+    r[n] = P(sv) / P(sn[n]);
     k[n] = 0;
-    nx[n] = pres[n] ? cfma(T(R::c[0]), s[n], d[n]) : big;
+    nx[n] = pres[n] ? cfma(P(R::c[0]), s[n], d[n]) : big;
     for (int q = 0; q < K && pres[n] && !(nx[n] > -C); ++q) {
       k[n] += 1;
-      nx[n] = k[n] < K ? cfma(T(R::c[k[n]]), s[n], d[n]) : big;
+      nx[n] = k[n] < K ? cfma(P(R::c[k[n]]), s[n], d[n]) : big;
     }
   }
   int kv = 1;
-  T nv = T(R::c[1]);
-  T x0 = -C;
-  T fS = T(0), fF = T(0);
-  T aS[4] = {T(0), T(0), T(0), T(0)}, bS[4] = {T(0), T(0), T(0), T(0)};
-  T aF[4] = {T(0), T(0), T(0), T(0)}, bF[4] = {T(0), T(0), T(0), T(0)};
+  P nv = P(R::c[1]);
+  P x0 = -C;
+  // panel sums in T (z_n keeps its sign on a panel: its mean is a cut), the
+  // sums over panels in FP64: dP/dsigma_n cancels between the panels below
+  // and above the neighbour's mean
+  P fS = P(0), fF = P(0);
+  P aS[4] = {P(0), P(0), P(0), P(0)}, bS[4] = {P(0), P(0), P(0), P(0)};
+  P aF[4] = {P(0), P(0), P(0), P(0)}, bF[4] = {P(0), P(0), P(0), P(0)};
   constexpr T rs2 = T(0.70710678118654752440);
   for (int it = 0; it < 5 * K; ++it) {
     if (!(x0 < C)) break;
-    T x1 = nv;
+    P x1 = nv;
 #pragma unroll
     for (int n = 0; n < 4; ++n) x1 = tmin(x1, nx[n]);
-    const T mid = (x0 + x1) * T(0.5), hl = (x1 - x0) * T(0.5);
+    const P mid = (x0 + x1) * P(0.5), hlp = (x1 - x0) * P(0.5);
+    const T hl = T(hlp);
     T pS = T(0), pF = T(0), qaS[4], qbS[4], qaF[4], qbF[4];
 #pragma unroll
     for (int n = 0; n < 4; ++n) qaS[n] = qbS[n] = qaF[n] = qbF[n] = T(0);
@@ -184,7 +194,8 @@ CP_HD void gauss_vertex_jac(T mv, T sv, const T (&mn)[4], const T (&sn)[4], cons
     // constant memory): unrolled, its live values do not fit the registers
 #pragma unroll 1
     for (int j = 0; j < N; ++j) {
-      const T t = cfma(hl, T(GL<N>::x[j]), mid);
+      const P tp = cfma(hlp, P(GL<N>::x[j]), mid);
+      const T t = T(tp);
       const T phi = T(GL<N>::w[j]) * gexp(T(-0.5) * t * t);
       T S[4], F[4], z[4], pz[4];
 #pragma unroll
@@ -192,7 +203,7 @@ CP_HD void gauss_vertex_jac(T mv, T sv, const T (&mn)[4], const T (&sn)[4], cons
         S[n] = F[n] = T(1);
         z[n] = pz[n] = T(0);
         if (!pres[n]) continue;
-        z[n] = (t - d[n]) * r[n];
+        z[n] = T((tp - d[n]) * r[n]);
         const T e = T(0.5) * gerfc(fabs(z[n]) * rs2);
         S[n] = z[n] > T(0) ? e : T(1) - e;
         F[n] = z[n] > T(0) ? T(1) - e : e;
@@ -224,45 +235,46 @@ CP_HD void gauss_vertex_jac(T mv, T sv, const T (&mn)[4], const T (&sn)[4], cons
         qbF[n] = cfma(lf, z[n], qbF[n]);
       }
     }
-    fS = cfma(pS, hl, fS);
-    fF = cfma(pF, hl, fF);
+    fS = cfma(P(pS), hlp, fS);
+    fF = cfma(P(pF), hlp, fF);
 #pragma unroll
     for (int n = 0; n < 4; ++n) {
-      aS[n] = cfma(qaS[n], hl, aS[n]);
-      bS[n] = cfma(qbS[n], hl, bS[n]);
-      aF[n] = cfma(qaF[n], hl, aF[n]);
-      bF[n] = cfma(qbF[n], hl, bF[n]);
+      aS[n] = cfma(P(qaS[n]), hlp, aS[n]);
+      bS[n] = cfma(P(qbS[n]), hlp, bS[n]);
+      aF[n] = cfma(P(qaF[n]), hlp, aF[n]);
+      bF[n] = cfma(P(qbF[n]), hlp, bF[n]);
     }
     if (nv == x1) {
       kv += 1;
-      nv = kv < K ? T(R::c[kv]) : big;
+      nv = kv < K ? P(R::c[kv]) : big;
     }
 #pragma unroll
     for (int n = 0; n < 4; ++n)
       if (nx[n] == x1) {
         k[n] += 1;
-        nx[n] = k[n] < K ? cfma(T(R::c[k[n]]), s[n], d[n]) : big;
+        nx[n] = k[n] < K ? cfma(P(R::c[k[n]]), s[n], d[n]) : big;
       }
     x0 = x1;
   }
   constexpr T inv_sqrt_2pi = T(0.39894228040143267794), inv_2pi = T(0.15915494309189533577);
-  pmin = fS * inv_sqrt_2pi;
-  pmax = fF * inv_sqrt_2pi;
-  T smu = T(0), ssg = T(0);
+  pmin = T(fS * P(inv_sqrt_2pi));
+  pmax = T(fF * P(inv_sqrt_2pi));
+  // the vertex slot sums terms that cancel (the invariances): in FP64
+  P smu = P(0), ssg = P(0);
 #pragma unroll
   for (int n = 0; n < 4; ++n) {
     jac[2 + 2 * n] = jac[3 + 2 * n] = T(0);
     if (!pres[n]) continue;
-    const T c = inv_2pi * crcp(sn[n]);
-    const T dmu = c * (gmin * aS[n] - gmax * aF[n]);  // g-weighted dP/dmu_n
-    const T dsg = c * (gmin * bS[n] - gmax * bF[n]);  // g-weighted dP/dsigma_n
-    jac[2 + 2 * n] = dmu;
-    jac[3 + 2 * n] = dsg;
+    const P c = P(inv_2pi) / P(sn[n]);
+    const P dmu = c * (P(gmin) * aS[n] - P(gmax) * aF[n]);  // g-weighted dP/dmu_n
+    const P dsg = c * (P(gmin) * bS[n] - P(gmax) * bF[n]);  // g-weighted dP/dsigma_n
+    jac[2 + 2 * n] = T(dmu);
+    jac[3 + 2 * n] = T(dsg);
     smu += dmu;
     ssg = cfma(d[n], dmu, cfma(s[n], dsg, ssg));
   }
-  jac[0] = -smu;
-  jac[1] = -ssg;
+  jac[0] = T(-smu);
+  jac[1] = T(-ssg);
 }
 
 }  // namespace cp

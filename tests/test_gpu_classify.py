@@ -293,8 +293,11 @@ def test_gaussian_invalid_parameters():
 
 def gauss_grad_check(pt, g1, g2, idx, dtype, what):
     """Device adjoint at idx against the oracle; tolerances as for the other
-    models (FP32 1e-5 (1 + |g|) + 5e-7 S, FP64 1e-10 (1 + |g|) + 1e-13 S, S the
-    sum of the magnitudes of the terms the adjoint adds)."""
+    models (FP32 1e-5 (1 + |g|) + 5e-7 S, FP64 1e-10 (1 + |g|) + 1e-13 S), S
+    the sum over the terms the adjoint adds of |g| times the integral of the
+    integrand's magnitude: the vertex-slot integrands change sign, and when
+    sigma_v is far below its neighbours' their integral is a cancellation
+    far below that scale, which bounds the rounding of any quadrature."""
     f = cp.field_of(pt, G)
     grad = host(cp.backward(pt, dev(g1, dtype), dev(g2, dtype), f)).reshape(2, -1).T[idx]
     ph = host(pt)

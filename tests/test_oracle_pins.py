@@ -1021,6 +1021,29 @@ def test_gauss_jacobian_invariances():
             assert abs(sc) <= 1e-11 * (scale * (1 + max(abs(d[k][0] - d["v"][0]) + d[k][1] for k in "venws")))
 
 
+def test_gauss_jacobian_magnitude_scale():
+    """The integrals of the integrands' magnitudes (the rounding scale the
+    adjoint tolerances use): a lone vertex has closed forms (the integrals of
+    phi(u) |u| and phi(u) |u^2 - 1| are sqrt(2/pi) and 4 phi(1), over
+    sigma); in a stencil they bound the signed integrals and equal them
+    where the integrand has one sign (the mu-derivatives of the neighbours'
+    survival and distribution factors)."""
+    sg = 0.37
+    par = np.array([[[0.2]], [[sg]]])
+    for r in oracle.gauss_jacobian_at(par, [0], absolute=True):
+        assert r[0, 0, 0] == pytest.approx(math.sqrt(2 / math.pi) / sg, rel=1e-12)
+        assert r[0, 0, 1] == pytest.approx(4 * math.exp(-0.5) / math.sqrt(2 * math.pi) / sg, rel=1e-12)
+        assert np.all(r[0, 1:] == 0)
+    rng = np.random.default_rng(27)
+    for _ in range(6):
+        par = gauss_grid(random_gauss_stencil(rng))
+        jm, jx = oracle.gauss_jacobian_at(par, [4])
+        am, ax = oracle.gauss_jacobian_at(par, [4], absolute=True)
+        for j, a in ((jm, am), (jx, ax)):
+            assert np.all(a >= np.abs(j) * (1 - 1e-12))
+            assert a[0, 1:, 0] == pytest.approx(np.abs(j[0, 1:, 0]), rel=1e-11)
+
+
 def test_gauss_adjoint_matches_finite_differences_of_the_loss():
     """Gathered adjoint of L = sum g_min P_min + g_max P_max on a 5x6 grid
     (edges, corners) against central differences of L itself."""
