@@ -53,8 +53,8 @@
  *                   form exists; the 1-D integrals are evaluated by a fixed
  *                   composite Gauss-Legendre rule on panels cut at multiples of
  *                   every sigma of the stencil, accurate to ~1e-8 (FP32) and
- *                   ~1e-14 (FP64) absolute.  Forward and classification only:
- *                   cp_prob_backward and cp_prob_batched return CP_EUNSUPPORTED.
+ *                   ~1e-14 (FP64) absolute.  Forward, classification and
+ *                   adjoint; cp_prob_batched returns CP_EUNSUPPORTED.
  *  CP_MVGAUSS       16 FP64 planes: mean, then the packed lower-triangular
  *                   Cholesky factor L (row-major: L00, L10, L11, L20, ...,
  *                   L44) of the covariance of (e, n, w, s, v) at that vertex.
@@ -162,7 +162,10 @@ cp_status_t cp_prob_forward(const cp_field_desc_t* desc, const void* params, voi
  *   g_min(v) * dP_min(v)/dtheta_k(u) + g_max(v) * dP_max(v)/dtheta_k(u).
  * Parameters differentiated: uniform (lo, hi); Epanechnikov (m, w);
  * histogram masses, taken as free variables (no renormalisation; the lo/hi
- * planes of grad_params receive 0); multivariate Gaussian: mean plane
+ * planes of grad_params receive 0); independent Gaussian (mu, sigma), by
+ * the forward's quadrature applied to the differentiated integrand (the
+ * vertex's own slot through the translation and scale invariances of P);
+ * multivariate Gaussian: mean plane
  * (gathered over stencils) and the Cholesky factor of each vertex, through
  * the conditional estimator (desc->estimator is ignored).
  * Contributions are gathered, not scattered: no atomics, and the result is
