@@ -170,6 +170,11 @@ cp_status_t cp_prob_forward(const cp_field_desc_t* desc, const void* params, voi
  * the conditional estimator (desc->estimator is ignored).
  * Contributions are gathered, not scattered: no atomics, and the result is
  * bit-reproducible.
+ * The histogram and multivariate Gaussian adjoints pass per-stencil
+ * partials through a library-owned device buffer, one per (device, stream),
+ * allocated with hipMalloc on first use and grown on demand (growing frees
+ * the old buffer, which waits for the device); calls on different streams
+ * never share one.  cp_release() frees them.
  *   g_min, g_max  [H][row_stride]; grad_params [n_param][H][row_stride]
  */
 cp_status_t cp_prob_backward(const cp_field_desc_t* desc, const void* params, const void* g_min,
@@ -300,7 +305,8 @@ const char* cp_status_string(cp_status_t status);
 /* Thread-local description of the last non-OK status of this thread. */
 const char* cp_last_error(void);
 
-/* Free the library's own device tables and cached graphs (optional). */
+/* Free the library's own device tables, adjoint buffers and cached graphs
+ * (optional); no call may be running on any stream. */
 cp_status_t cp_release(void);
 
 /*

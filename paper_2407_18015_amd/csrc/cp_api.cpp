@@ -5,6 +5,7 @@
 
 #include <climits>
 #include <cstdio>
+#include <map>
 #include <mutex>
 #include <string>
 #include <vector>
@@ -87,33 +88,48 @@ int n_params(int model, int nb) {
 }
 
 namespace {
+// one buffer per (device, stream): calls ordered on one stream reuse it,
+// calls on different streams or devices never share one
+struct WsBuf {
+  void* ptr = nullptr;
+  size_t bytes = 0;
+};
 std::mutex g_ws_mu;
-void* g_ws = nullptr;
-size_t g_ws_bytes = 0;
+std::map<std::pair<int, hipStream_t>, WsBuf> g_ws;
 }  // namespace
 
-hipError_t workspace(size_t bytes, void** out) {
+hipError_t workspace(size_t bytes, hipStream_t st, void** out) {
+  int dev = 0;
+  hipError_t e = hipGetDevice(&dev);
+  if (e != hipSuccess) return e;
   std::lock_guard<std::mutex> lk(g_ws_mu);
-  if (bytes > g_ws_bytes) {
-    if (g_ws) {
-      hipError_t e = hipFree(g_ws);  // waits for work that may still use it
+  WsBuf& w = g_ws[{dev, st}];
+  if (bytes > w.bytes) {
+    if (w.ptr) {
+      e = hipFree(w.ptr);  // waits for work that may still use it
       if (e != hipSuccess) return e;
-      g_ws = nullptr;
-      g_ws_bytes = 0;
+      w.ptr = nullptr;
+      w.bytes = 0;
     }
-    hipError_t e = hipMalloc(&g_ws, bytes);
+    e = hipMalloc(&w.ptr, bytes);
     if (e != hipSuccess) return e;
-    g_ws_bytes = bytes;
+    w.bytes = bytes;
   }
-  *out = g_ws;
+  *out = w.ptr;
   return hipSuccess;
 }
 
 void workspace_release() {
   std::lock_guard<std::mutex> lk(g_ws_mu);
-  if (g_ws) (void)hipFree(g_ws);
-  g_ws = nullptr;
-  g_ws_bytes = 0;
+  int cur = 0;
+  const bool have = hipGetDevice(&cur) == hipSuccess;
+  for (auto& kv : g_ws)
+    if (kv.second.ptr) {
+      (void)hipSetDevice(kv.first.first);
+      (void)hipFree(kv.second.ptr);
+    }
+  if (have) (void)hipSetDevice(cur);
+  g_ws.clear();
 }
 }  // namespace cp
 

@@ -56,9 +56,10 @@ hipError_t mvg_backward(const Field& f, const double* params, const float* gmin,
                         double* grad, hipStream_t st);
 hipError_t philox_raw(int64_t n, const uint32_t* ctr, uint64_t seed, uint32_t* out, hipStream_t st);
 
-// Library-owned device workspace (per-stencil adjoint partials), grown on
-// demand, shared by the adjoints that gather through memory.
-hipError_t workspace(size_t bytes, void** out);
+// Library-owned device workspace (per-stencil adjoint partials) of the
+// current device for work on stream st, grown on demand; the adjoints that
+// gather through memory share it along one stream.
+hipError_t workspace(size_t bytes, hipStream_t st, void** out);
 void workspace_release();
 
 // batched persistent launch

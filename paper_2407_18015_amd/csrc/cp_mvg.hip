@@ -276,7 +276,7 @@ hipError_t mvg_backward(const Field& f, const double* params, const float* gmin,
   a.grad = grad;
   const int64_t nv = (int64_t)f.H * f.W;
   void* ws = nullptr;
-  hipError_t e = workspace(sizeof(double) * 5 * (size_t)nv, &ws);
+  hipError_t e = workspace(sizeof(double) * 5 * (size_t)nv, st, &ws);
   if (e != hipSuccess) return e;
   a.jmu = static_cast<double*>(ws);
   hipLaunchKernelGGL(k_mvg_bwd, dim3((unsigned)((nv + 3) / 4)), dim3(256), 0, st, a);

@@ -293,6 +293,35 @@ def test_autograd_function_matches_backward():
     assert torch.equal(p.grad, g)
 
 
+def test_adjoint_buffers_on_two_streams():
+    """The histogram and multivariate Gaussian adjoints pass partials through
+    a library buffer; issued on two streams at once they give the same bits
+    as one after the other on the current stream (one buffer per stream)."""
+    note("adjoint on two streams")
+    cases = []
+    for i, (H, W) in enumerate(((61, 83), (47, 59))):
+        p = dev(workloads.random_params(HST, 71 + i, H, W, nbins=6, width=0.06), torch.float32)
+        cases.append((p, cp.field_of(p, HST, 6), H, W))
+    for i, (H, W) in enumerate(((23, 31), (19, 27))):
+        p, _ = mvg_setup(H, W, 11 + i)
+        cases.append((p, cp.Field(H, W, MVG, torch.float32, nsamples=128, seed=5 + i, field_id=i), H, W))
+    ups = []
+    for i, (p, f, H, W) in enumerate(cases):
+        gmin, gmax = workloads.upstream(20 + i, H, W)
+        ups.append((dev(gmin, torch.float32), dev(gmax, torch.float32)))
+    refs = [cp.backward(p, *u, f) for (p, f, _, _), u in zip(cases, ups)]
+    torch.cuda.synchronize()
+    streams = [torch.cuda.Stream(), torch.cuda.Stream()]
+    for rep in range(3):
+        outs = []
+        for i, ((p, f, _, _), u) in enumerate(zip(cases, ups)):
+            with torch.cuda.stream(streams[i % 2]):
+                outs.append(cp.backward(p, *u, f))
+        torch.cuda.synchronize()
+        for i, (o, r) in enumerate(zip(outs, refs)):
+            assert torch.equal(o, r), (rep, i)
+
+
 # ----------------------------------------------------------------------------
 # full-size workloads, sampled vertices
 # ----------------------------------------------------------------------------
