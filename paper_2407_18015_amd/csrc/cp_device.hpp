@@ -156,6 +156,49 @@ CP_HD void sort4(T (&k)[4], T (&p)[4][P], int (&tag)[4]) {
   cswap<T, P>(k[1], k[2], p[1], p[2], tag[1], tag[2]);
 }
 
+// The same network, recording whether each comparator swapped, so that
+// values computed in sorted order can be taken back to neighbour order by
+// unsort4 (the comparators in reverse order, each its own inverse): ten
+// selects per array instead of a select per (slot, neighbour) pair.
+template <typename T, int P>
+CP_HD void cswap_rec(T& ka, T& kb, T (&pa)[P], T (&pb)[P], bool& s) {
+  s = kb < ka;
+  T t = s ? kb : ka;
+  kb = s ? ka : kb;
+  ka = t;
+#pragma unroll
+  for (int p = 0; p < P; ++p) {
+    T u = s ? pb[p] : pa[p];
+    pb[p] = s ? pa[p] : pb[p];
+    pa[p] = u;
+  }
+}
+
+template <typename T, int P>
+CP_HD void sort4_rec(T (&k)[4], T (&p)[4][P], bool (&sw)[5]) {
+  cswap_rec<T, P>(k[0], k[1], p[0], p[1], sw[0]);
+  cswap_rec<T, P>(k[2], k[3], p[2], p[3], sw[1]);
+  cswap_rec<T, P>(k[0], k[2], p[0], p[2], sw[2]);
+  cswap_rec<T, P>(k[1], k[3], p[1], p[3], sw[3]);
+  cswap_rec<T, P>(k[1], k[2], p[1], p[2], sw[4]);
+}
+
+template <typename T>
+CP_HD void uswap(T& a, T& b, bool s) {
+  const T t = s ? b : a;
+  b = s ? a : b;
+  a = t;
+}
+
+template <typename T>
+CP_HD void unsort4(T (&v)[4], const bool (&sw)[5]) {
+  uswap(v[1], v[2], sw[4]);
+  uswap(v[1], v[3], sw[3]);
+  uswap(v[0], v[2], sw[2]);
+  uswap(v[2], v[3], sw[1]);
+  uswap(v[0], v[1], sw[0]);
+}
+
 // ===========================================================================
 // Uniform model (Sec. 4.3).  Local frame with origin at the vertex lower
 // end: vertex support [0, Lv]; neighbour i support [a_i, b_i].
@@ -174,7 +217,7 @@ struct UniSide {
   T c[4];      // sorted clamped start points
   T b[4];      // matching upper ends
   T iL[4];     // matching 1/(b - a)
-  int tag[4];  // neighbour index (0..3) of each sorted slot
+  bool sw[5];  // comparator swaps of the sort (unsort4 restores neighbour order)
   T bmin;
   bool empty;
 };
@@ -199,9 +242,8 @@ CP_HD void uni_setup(UniSide<T>& s, T Lv, T iLv, const T (&a)[4], const T (&b)[4
     key[i] = pres[i] ? tclamp(a[i], T(0), bmin) : bmin;
     pay[i][0] = pres[i] ? b[i] : T(3) * Lv;
     pay[i][1] = pres[i] ? iL[i] : iLv;
-    s.tag[i] = i;
   }
-  sort4<T, 2>(key, pay, s.tag);
+  sort4_rec<T, 2>(key, pay, s.sw);
 #pragma unroll
   for (int i = 0; i < 4; ++i) {
     s.c[i] = key[i];
@@ -324,16 +366,12 @@ CP_HD void uni_side_grad(const UniSide<T>& s, UniGrad<T>& g) {
   g.dLv = (gend - f) * iLv;
 #pragma unroll
   for (int i = 0; i < 4; ++i) {
-    const T da = act[i] * iLv * s.iL[i];
-    const T db = (loo[i] - act[i]) * iLv * s.iL[i];
-    const int t = s.tag[i];
-    // scatter back to neighbour index (registers: unrolled selects)
-#pragma unroll
-    for (int n = 0; n < 4; ++n) {
-      g.da[n] = (t == n) ? da : g.da[n];
-      g.db[n] = (t == n) ? db : g.db[n];
-    }
+    g.da[i] = act[i] * iLv * s.iL[i];
+    g.db[i] = (loo[i] - act[i]) * iLv * s.iL[i];
   }
+  // sorted slots -> neighbour index
+  unsort4(g.da, s.sw);
+  unsort4(g.db, s.sw);
 }
 
 // ===========================================================================
@@ -348,7 +386,7 @@ template <typename T>
 struct EpaSide {
   T wv, iwv;
   T c[4], d[4], iw[4], w[4];
-  int tag[4];
+  bool sw[5];  // comparator swaps of the sort (unsort4 restores neighbour order)
   T bmin;
   bool empty;
 };
@@ -375,9 +413,8 @@ CP_HD void epa_setup(EpaSide<T>& s, T wv, T iwv, const T (&d)[4], const T (&w)[4
     pay[i][0] = pres[i] ? d[i] : T(3) * wv;
     pay[i][1] = pres[i] ? iw[i] : s.iwv;
     if constexpr (WW) pay[i][2] = pres[i] ? w[i] : wv;
-    s.tag[i] = i;
   }
-  sort4<T, P>(key, pay, s.tag);
+  sort4_rec<T, P>(key, pay, s.sw);
 #pragma unroll
   for (int i = 0; i < 4; ++i) {
     s.c[i] = key[i];
@@ -538,17 +575,14 @@ CP_HD void epa_side_grad(const EpaSide<T>& s, EpaGrad<T>& g) {
       aw += sc[k - 1] * gw[k][i];
     }
     const T ki = T(0.75) * s.iw[i] * kv;
-    const T dd = ki * ad;
-    const T dw = ki * aw;
-    xsum = cfma(s.d[i], dd, cfma(s.w[i], dw, xsum));
-    const int t = s.tag[i];
-#pragma unroll
-    for (int n = 0; n < 4; ++n) {
-      g.dd[n] = (t == n) ? dd : g.dd[n];
-      g.dw[n] = (t == n) ? dw : g.dw[n];
-    }
+    g.dd[i] = ki * ad;
+    g.dw[i] = ki * aw;
+    xsum = cfma(s.d[i], g.dd[i], cfma(s.w[i], g.dw[i], xsum));
   }
   g.dwv = -xsum * s.iwv;
+  // sorted slots -> neighbour index
+  unsort4(g.dd, s.sw);
+  unsort4(g.dw, s.sw);
 }
 
 }  // namespace cp
