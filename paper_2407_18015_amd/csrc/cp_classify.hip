@@ -39,43 +39,47 @@ __device__ __forceinline__ void class_store(const ClassPtrs<T>& f, int y, int x,
   if (f.preg) f.preg[at] = T(1) - pmin - pmax - ps;
 }
 
-template <typename T, int MODEL, int TY>
-__global__ __launch_bounds__(kFwdTX* TY) void k_classify_ue(ClassPtrs<T> f, int tiles_x, int ntiles) {
-  constexpr int TX = kFwdTX, EX = TX + 2, EY = TY + 2, E = EX * EY, NT = TX * TY;
+// 64 x TY vertices per block of NT threads (TY / (NT / 64) rows per thread)
+template <typename T, int MODEL, int TY, int NT>
+__global__ __launch_bounds__(NT) void k_classify_ue(ClassPtrs<T> f, int tiles_x, int ntiles) {
+  constexpr int TX = kFwdTX, EX = TX + 2, EY = TY + 2, E = EX * EY;
+  static_assert(NT % TX == 0 && TY % (NT / TX) == 0, "rows must split evenly over the threads");
   __shared__ T lds[2 * E];
   const int t = xcd_tile(blockIdx.x, ntiles);
   const int ty0 = (t / tiles_x) * TY, tx0 = (t % tiles_x) * TX, tid = threadIdx.x;
   stage<T, EY, EX, NT>(lds, f.params, 2, f.ps, f.rs, f.H, f.W, ty0 - 1, tx0 - 1, tid);
   __syncthreads();
-  const int lx = tid % TX, ly = tid / TX;
-  const int x = tx0 + lx, y = ty0 + ly;
-  if (x >= f.W || y >= f.H) return;
-  const int e = (ly + 1) * EX + lx + 1;
-  const int en[4] = {e + 1, e - EX, e - 1, e + EX};
-  const bool pres[4] = {x + 1 < f.W, y > 0, x > 0, y + 1 < f.H};
+  const int lx = tid % TX, x = tx0 + lx;
   const bool mm = f.pmin || f.pmax || f.preg;
   const bool sad = f.psad || f.terms || f.preg;
-  T pmin = T(0), pmax = T(0), t1 = T(0), t2 = T(0);
-  if (!stencil_valid_ue<T, MODEL>(lds, E, e, en, pres)) {
-    pmin = pmax = t1 = t2 = qnan<T>();
-  } else if constexpr (MODEL == CP_GAUSSIAN) {
-    T mn[4], sn[4], o[4];
+  for (int ly = tid / TX; ly < TY; ly += NT / TX) {
+    const int y = ty0 + ly;
+    if (x >= f.W || y >= f.H) continue;
+    const int e = (ly + 1) * EX + lx + 1;
+    const int en[4] = {e + 1, e - EX, e - 1, e + EX};
+    const bool pres[4] = {x + 1 < f.W, y > 0, x > 0, y + 1 < f.H};
+    T pmin = T(0), pmax = T(0), t1 = T(0), t2 = T(0);
+    if (!stencil_valid_ue<T, MODEL>(lds, E, e, en, pres)) {
+      pmin = pmax = t1 = t2 = qnan<T>();
+    } else if constexpr (MODEL == CP_GAUSSIAN) {
+      T mn[4], sn[4], o[4];
 #pragma unroll
-    for (int i = 0; i < 4; ++i) {
-      mn[i] = pres[i] ? lds[en[i]] : T(0);
-      sn[i] = pres[i] ? lds[E + en[i]] : T(1);
+      for (int i = 0; i < 4; ++i) {
+        mn[i] = pres[i] ? lds[en[i]] : T(0);
+        sn[i] = pres[i] ? lds[E + en[i]] : T(1);
+      }
+      gauss_vertex<T>(lds[e], lds[E + e], mn, sn, pres, o);
+      pmin = o[0];
+      pmax = o[1];
+      t1 = o[2];
+      t2 = o[3];
+    } else {
+      if (mm) vertex_fwd_ue<T, MODEL>(lds, E, e, en, pres, pmin, pmax);
+      // the alternating pattern needs all four neighbours: 0 on the boundary
+      if (sad && pres[0] && pres[1] && pres[2] && pres[3]) vertex_saddle_ue<T, MODEL>(lds, E, e, en, t1, t2);
     }
-    gauss_vertex<T>(lds[e], lds[E + e], mn, sn, pres, o);
-    pmin = o[0];
-    pmax = o[1];
-    t1 = o[2];
-    t2 = o[3];
-  } else {
-    if (mm) vertex_fwd_ue<T, MODEL>(lds, E, e, en, pres, pmin, pmax);
-    // the alternating pattern needs all four neighbours: 0 on the boundary
-    if (sad && pres[0] && pres[1] && pres[2] && pres[3]) vertex_saddle_ue<T, MODEL>(lds, E, e, en, t1, t2);
+    class_store(f, y, x, pmin, pmax, t1, t2);
   }
-  class_store(f, y, x, pmin, pmax, t1, t2);
 }
 
 template <typename T, int TY>
@@ -156,18 +160,28 @@ static hipError_t classify_typed(const Field& f, const void* params, void* pmin,
   p.nb = f.nb;
   p.rs = f.rs;
   p.ps = f.plane();
-  constexpr int TY = 4;
-  const int tx = cdiv_c(f.W, kFwdTX), ty = cdiv_c(f.H, TY), n = tx * ty;
+  // uniform / Epanechnikov: 64 x 16 vertices per 256-thread block on grids
+  // with at least eight such blocks per CU (as the forward), else 64 x 4;
+  // the Gaussian quadrature keeps one row per thread (64 x 4)
+  const int tx = cdiv_c(f.W, kFwdTX);
+  const bool tall = (int64_t)tx * cdiv_c(f.H, 16) >= kTallTileBlocks;
+  const int n4 = tx * cdiv_c(f.H, 4), n16 = tx * cdiv_c(f.H, 16);
   if (f.model == CP_UNIFORM) {
-    hipLaunchKernelGGL((k_classify_ue<T, CP_UNIFORM, TY>), dim3(n), dim3(kFwdTX * TY), 0, st, p, tx, n);
+    if (tall)
+      hipLaunchKernelGGL((k_classify_ue<T, CP_UNIFORM, 16, 256>), dim3(n16), dim3(256), 0, st, p, tx, n16);
+    else
+      hipLaunchKernelGGL((k_classify_ue<T, CP_UNIFORM, 4, 256>), dim3(n4), dim3(256), 0, st, p, tx, n4);
     return hipGetLastError();
   }
   if (f.model == CP_EPANECHNIKOV) {
-    hipLaunchKernelGGL((k_classify_ue<T, CP_EPANECHNIKOV, TY>), dim3(n), dim3(kFwdTX * TY), 0, st, p, tx, n);
+    if (tall)
+      hipLaunchKernelGGL((k_classify_ue<T, CP_EPANECHNIKOV, 16, 256>), dim3(n16), dim3(256), 0, st, p, tx, n16);
+    else
+      hipLaunchKernelGGL((k_classify_ue<T, CP_EPANECHNIKOV, 4, 256>), dim3(n4), dim3(256), 0, st, p, tx, n4);
     return hipGetLastError();
   }
   if (f.model == CP_GAUSSIAN) {
-    hipLaunchKernelGGL((k_classify_ue<T, CP_GAUSSIAN, TY>), dim3(n), dim3(kFwdTX * TY), 0, st, p, tx, n);
+    hipLaunchKernelGGL((k_classify_ue<T, CP_GAUSSIAN, 4, 256>), dim3(n4), dim3(256), 0, st, p, tx, n4);
     return hipGetLastError();
   }
   const size_t per_row = sizeof(T) * (size_t)hist_planes(f.nb) * (kFwdTX + 2);

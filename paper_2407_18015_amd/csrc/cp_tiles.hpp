@@ -205,6 +205,9 @@ CP_HD void vertex_jac_vals(T p0, T p1, const T (&q0)[4], const T (&q1)[4], const
 // rows ly, ly + NT/64, ... of its column (one row when NT = 64 TY)
 // ---------------------------------------------------------------------------
 constexpr int kFwdTX = 64;
+// per-field forward / classification: 64 x 16 tiles (four rows per thread)
+// once the grid gives at least this many of them (eight per CU), else 64 x 4
+constexpr int kTallTileBlocks = 2048;
 
 template <typename T, int MODEL, int TY, int NT = kFwdTX * TY>
 __device__ __forceinline__ void tile_fwd_ue(const FieldPtrs<T>& f, int ty0, int tx0, T* lds, int tid) {

@@ -333,6 +333,32 @@ def sample_idx(H, W, n, seed):
     return np.array(sorted(idx), dtype=np.int64)
 
 
+@pytest.mark.parametrize("model", [U, E])
+@pytest.mark.parametrize("dtype", [torch.float32, torch.float64])
+def test_tall_tiles_ragged(model, dtype):
+    """A grid large enough for the 64 x 16 forward and classification tiles
+    (1030 x 2113: neither side a multiple of the tile): sampled vertices plus
+    every vertex of the last row and column against the oracle, and the
+    classification's P_min / P_max equal to the forward's bit for bit."""
+    H, W = 1030, 2113
+    note("tall tiles ragged", NAMES[model], dtype, (H, W))
+    pt = dev(workloads.random_params(model, 90 + model, H, W, width=0.05), dtype)
+    f = cp.field_of(pt, model)
+    pmin, pmax = cp.forward(pt, f)
+    out = cp.classify(pt, f, terms=True)
+    assert torch.equal(out["min"], pmin) and torch.equal(out["max"], pmax)
+    idx = np.union1d(sample_idx(H, W, 1500, 7),
+                     np.concatenate([(H - 1) * W + np.arange(W), np.arange(H) * W + W - 1]))
+    ph = host(pt)
+    tol = 1e-6 if dtype == torch.float32 else 1e-12
+    rmin, rmax = oracle.forward_at(model, ph, idx)
+    assert_close(host(pmin).ravel()[idx], rmin, tol, "P_min")
+    assert_close(host(pmax).ravel()[idx], rmax, tol, "P_max")
+    t1, t2 = oracle.saddle_at(model, ph, idx)
+    assert_close(host(out["terms"][0]).ravel()[idx], t1, tol, "t1")
+    assert_close(host(out["terms"][1]).ravel()[idx], t2, tol, "t2")
+
+
 @pytest.mark.parametrize("model,n", [(E, 2048), (HST, 2048), (U, 2048)])
 def test_full_size_2048_sampled(model, n):
     """2048^2, 20 members: the benchmark's launch configuration; every output
