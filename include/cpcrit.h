@@ -249,9 +249,10 @@ cp_status_t cp_prob_semianalytical(const cp_field_desc_t* desc, const void* para
  * Gaussian fields (CP_MVGAUSS, CP_GAUSSIAN) are not accepted here
  * (CP_EUNSUPPORTED).
  * CP_BATCH_TUNE: the first call with these shapes and flags times, for every
- * pass of the plan, each tile shape the library offers (forward and
- * histogram passes: 64 x 4 or 64 x 8 vertices; uniform / Epanechnikov
- * adjoint: FP32 30x30, 14x14 or 62x30 outputs, FP64 14x14, 30x14 or 30x30)
+ * pass of the plan, each tile shape the library offers (uniform /
+ * Epanechnikov forward: 64 x 4, 64 x 8 or 64 x 16 vertices; histogram
+ * passes: 64 x 4 or 64 x 8; uniform / Epanechnikov adjoint: FP32 30x30,
+ * 14x14 or 62x30 outputs, FP64 14x14, 30x14 or 30x30)
  * with each claim chunk (1, 2, 4, 8 tiles) on the caller's own buffers, and
  * keeps the fastest for every later call; the call then blocks until the
  * trials are done, and fails (CP_EINVAL) while the stream is being captured.

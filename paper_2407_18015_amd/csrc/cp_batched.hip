@@ -46,12 +46,15 @@ constexpr size_t kMaxLds = 160 * 1024;
 enum { PASS_FWD_UE = 0, PASS_FWD_HIST = 1, PASS_BWD_UE = 2, PASS_BWD_HIST = 3, PASS_GATHER = 4, NPASS = 5 };
 
 // Tile variants of each pass (the tuner picks one per pass; variant 0 is the
-// default).  Forward and histogram passes: 64 x (4 << v) vertices, one or two
-// rows per thread.  Uniform / Epanechnikov adjoint: output tiles of
+// default).  Forward and histogram passes: 64 x (4 << v) vertices, one, two
+// or (uniform / Epanechnikov forward) four rows per thread.  Uniform /
+// Epanechnikov adjoint: output tiles of
 // bwd_ox x bwd_oy (FP32 30x30, 14x14, 62x30; FP64 14x14, 30x14, 30x30), i.e.
 // 1 to 8 stencils per thread.  The tile shape changes no per-vertex
 // arithmetic: every variant gives the same results bit for bit.
-constexpr int n_variants(int pass) { return pass == PASS_BWD_UE ? 3 : (pass == PASS_GATHER ? 1 : 2); }
+constexpr int n_variants(int pass) {
+  return pass == PASS_BWD_UE || pass == PASS_FWD_UE ? 3 : (pass == PASS_GATHER ? 1 : 2);
+}
 __host__ __device__ constexpr int bwd_ox(bool f32, int v) { return f32 ? (v == 2 ? 62 : (v == 1 ? 14 : 30)) : (v == 0 ? 14 : 30); }
 __host__ __device__ constexpr int bwd_oy(bool f32, int v) { return f32 ? (v == 1 ? 14 : 30) : (v == 2 ? 30 : 14); }
 
@@ -161,6 +164,7 @@ const void* kernel_of(int pass, int v) {
   switch (pass * 4 + v) {
     case PASS_FWD_UE * 4 + 0: return reinterpret_cast<const void*>(k_batched<T, PASS_FWD_UE, 0>);
     case PASS_FWD_UE * 4 + 1: return reinterpret_cast<const void*>(k_batched<T, PASS_FWD_UE, 1>);
+    case PASS_FWD_UE * 4 + 2: return reinterpret_cast<const void*>(k_batched<T, PASS_FWD_UE, 2>);
     case PASS_FWD_HIST * 4 + 0: return reinterpret_cast<const void*>(k_batched<T, PASS_FWD_HIST, 0>);
     case PASS_FWD_HIST * 4 + 1: return reinterpret_cast<const void*>(k_batched<T, PASS_FWD_HIST, 1>);
     case PASS_BWD_UE * 4 + 0: return reinterpret_cast<const void*>(k_batched<T, PASS_BWD_UE, 0>);
