@@ -158,11 +158,13 @@ static hipError_t launch_bwd_ue(const FieldPtrs<T>& p, int model, hipStream_t st
   return hipGetLastError();
 }
 
-// independent Gaussian: one stencil per thread (16x16 stencils, 14x14
-// outputs); its panel sweep is a loop, not straight-line code
+// independent Gaussian: FP32 30x30 outputs (32x32 stencils, four per
+// thread), so the ring of halo stencils is 12% of the work against 24% for
+// 14x14; FP64 keeps 14x14 (one stencil per thread: its 250 registers leave
+// no room for a second)
 template <typename T>
 static hipError_t launch_bwd_gauss(const FieldPtrs<T>& p, hipStream_t st) {
-  constexpr int O = 14;
+  constexpr int O = sizeof(T) == 4 ? 30 : 14;
   const int tx = cdiv(p.W, O), ty = cdiv(p.H, O), n = tx * ty;
   hipLaunchKernelGGL((k_bwd_ue<T, CP_GAUSSIAN, O, O>), dim3(n), dim3(256), 0, st, p, tx, n);
   return hipGetLastError();

@@ -323,13 +323,17 @@ def test_gaussian_backward_parity(dtype, mixed):
     gauss_grad_check(pt, g1, g2, np.arange(H * W), dtype, "grad")
 
 
-@pytest.mark.parametrize("shape", [(1, 1), (1, 9), (9, 1), (2, 2), (15, 15), (16, 29)])
-def test_gaussian_backward_edge_shapes(shape):
-    note("gaussian backward edge shape", shape)
+@pytest.mark.parametrize("shape", [(1, 1), (1, 9), (9, 1), (2, 2), (15, 15), (16, 29), (31, 33)])
+@pytest.mark.parametrize("dtype", [torch.float32, torch.float64])
+def test_gaussian_backward_edge_shapes(shape, dtype):
+    """Edge shapes around the adjoint tiles (FP32 30x30, FP64 14x14)."""
+    note("gaussian backward edge shape", shape, dtype)
     H, W = shape
-    pt = dev(gauss_params(11, H, W), torch.float64)
+    pt = dev(gauss_params(11, H, W), dtype)
     g1, g2 = workloads.upstream(4, H, W, np.float64)
-    gauss_grad_check(pt, g1, g2, np.arange(H * W), torch.float64, f"grad {shape}")
+    if dtype == torch.float32:
+        g1, g2 = g1.astype(np.float32), g2.astype(np.float32)
+    gauss_grad_check(pt, g1, g2, np.arange(H * W), dtype, f"grad {shape}")
 
 
 def test_gaussian_backward_full_size_sampled():
