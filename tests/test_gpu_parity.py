@@ -282,15 +282,30 @@ def test_backward_fitted_fields(model):
     assert_grad(g, oracle.grad(*args), oracle.grad(*args, absolute=True), torch.float32)
 
 
-def test_autograd_function_matches_backward():
-    note("autograd")
-    p = dev(workloads.random_params(E, 8, 40, 50, width=0.05), torch.float32).requires_grad_(True)
-    pmin, pmax = cp.critical_point_probability(p, "epanechnikov")
-    gmin, gmax = workloads.upstream(3, 40, 50)
+@pytest.mark.parametrize("model", ["uniform", "epanechnikov", "gaussian"])
+def test_autograd_function_matches_backward(model):
+    """torch.autograd through CPProb gives the adjoint entry point's bits;
+    a loss on P_min alone passes zeros for the P_max gradient."""
+    note("autograd", model)
+    H, W = 40, 50
+    if model == "gaussian":
+        rng = np.random.default_rng(8)
+        base = rng.normal(0, 0.05, (H, W))
+        raw = np.stack([base, rng.uniform(0.02, 0.06, (H, W))])
+    else:
+        raw = workloads.random_params(U if model == "uniform" else E, 8, H, W, width=0.05)
+    p = dev(raw, torch.float32).requires_grad_(True)
+    pmin, pmax = cp.critical_point_probability(p, model)
+    gmin, gmax = workloads.upstream(3, H, W)
     (pmin * dev(gmin, torch.float32) + pmax * dev(gmax, torch.float32)).sum().backward()
-    f = cp.field_of(p.detach(), E)
+    f = cp.field_of(p.detach(), model)
     g = cp.backward(p.detach(), dev(gmin, torch.float32), dev(gmax, torch.float32), f)
     assert torch.equal(p.grad, g)
+    q = dev(raw, torch.float32).requires_grad_(True)
+    qmin, _ = cp.critical_point_probability(q, model)
+    (qmin * dev(gmin, torch.float32)).sum().backward()
+    g0 = cp.backward(q.detach(), dev(gmin, torch.float32), torch.zeros_like(qmin), f)
+    assert torch.equal(q.grad, g0)
 
 
 def test_adjoint_buffers_on_two_streams():
