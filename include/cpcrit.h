@@ -174,7 +174,9 @@ cp_status_t cp_prob_forward(const cp_field_desc_t* desc, const void* params, voi
  * partials through a library-owned device buffer, one per (device, stream),
  * allocated with hipMalloc on first use and grown on demand (growing frees
  * the old buffer, which waits for the device); calls on different streams
- * never share one.  cp_release() frees them.
+ * never share one, and a stream being captured into a graph must have made
+ * an uncaptured call of at least the same size first.  cp_release() frees
+ * them.
  *   g_min, g_max  [H][row_stride]; grad_params [n_param][H][row_stride]
  */
 cp_status_t cp_prob_backward(const cp_field_desc_t* desc, const void* params, const void* g_min,
