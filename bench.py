@@ -453,6 +453,55 @@ def cpu_baseline(mem_np, gmin_np, gmax_np, budget_s=12.0, band=32):
            "sample": f"fit+forward+adjoint of the first {done // W} rows x {W} columns of the same "
                      f"20-member field, in bands of {band} rows", "seconds": dt}
     out["single_core"] = single_core_baseline(mem_np[:, :band + 1], gmin_np[:band + 1], gmax_np[:band + 1])
+    out["per_model"] = oracle_per_model(cores)
+    return out
+
+
+def _timed_loop(fn, budget_s):
+    n, t = 0, time.time()
+    while n == 0 or time.time() - t < budget_s:
+        fn()
+        n += 1
+    return n, time.time() - t
+
+
+def oracle_per_model(cores, S=2048, budget_s=2.0):
+    """The oracle (as above: FP64, untuned, `cores` host threads) on bounded
+    samples of the other workloads, each as forward + adjoint in
+    vertex-probabilities/s: the uniform 64x64 field whole, a band of rows of
+    the histogram and independent-Gaussian 2048^2 fields, sampled vertices of
+    the 1024^2 Monte Carlo field."""
+    import oracle
+    import workloads
+    out = {}
+    p = workloads.uniform_params_field(0, 64, 64)
+    g1, g2 = workloads.upstream(1, 64, 64, np.float64)
+    n, dt = _timed_loop(lambda: (oracle.forward(0, p), oracle.grad(0, p, g1, g2)), budget_s)
+    out["uniform_fp64_64"] = {"value": n * 64 * 64 / dt, "cores": cores, "seconds": dt,
+                              "sample": f"forward+adjoint of the whole 64x64 field, {n} times"}
+    band = 4
+    g1, g2 = (g[: band + 2].astype(np.float64) for g in workloads.upstream(1, S, S))
+    idx = np.arange(S, S * (band + 1), dtype=np.int64)  # rows 1..band of the strip
+    mem = workloads.mixture_ensemble(0, S, S)[:, : band + 2].astype(np.float64)
+    ph = oracle.fit(2, mem, nbins=10, single=True)
+    n, dt = _timed_loop(lambda: (oracle.forward_at(2, ph, idx), oracle.grad_at(2, ph, g1, g2, idx)), budget_s)
+    out["histogram_2048"] = {"value": n * idx.size / dt, "cores": cores, "seconds": dt,
+                             "sample": f"forward+adjoint of {band} rows x {S} of the 10-bin field, {n} times"}
+    mem = workloads.smooth_ensemble(1, S, S)[:, :6].astype(np.float64)
+    pg = oracle.fit(4, mem, single=True)
+    gi = np.arange(S, S + 256, dtype=np.int64)
+    n, dt = _timed_loop(lambda: (oracle.gauss_at(pg, gi), oracle.gauss_grad_at(pg, g1[:6], g2[:6], gi)), budget_s)
+    out["gaussian_2048"] = {"value": n * gi.size / dt, "cores": cores, "seconds": dt,
+                            "sample": f"forward+adjoint of 256 vertices of row 1 of the fitted field, {n} times"}
+    M = 1024
+    cm = workloads.correlated_ensemble(2, M, M)[:, :8].astype(np.float64)
+    pm = oracle.mvg_fit(cm)
+    mi = np.arange(3 * M, 3 * M + 32, dtype=np.int64)
+    h1, h2 = (g[:8].astype(np.float64) for g in workloads.upstream(5, M, M))
+    n, dt = _timed_loop(lambda: (oracle.mvg_forward_at(pm, mi, 4096, 1234, 7),
+                                 oracle.mvg_grad_at(pm, h1, h2, mi, 4096, 1234, 7)), budget_s)
+    out["mvg_1024_4096"] = {"value": n * mi.size / dt, "cores": cores, "seconds": dt,
+                            "sample": f"forward (both estimators)+adjoint of 32 vertices, 4096 samples each, {n} times"}
     return out
 
 
