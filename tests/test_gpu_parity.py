@@ -282,6 +282,39 @@ def test_backward_fitted_fields(model):
     assert_grad(g, oracle.grad(*args), oracle.grad(*args, absolute=True), torch.float32)
 
 
+def test_histogram_adjoint_finite_differences_on_crop():
+    """The histogram workload's gradient check: on a 32x32 crop (seeded
+    offset) of the fitted 2048^2, 10-bin mixture field, the FP64 adjoint with
+    respect to the bin masses equals central differences of the FP64 forward
+    of L = sum g_min P_min + g_max P_max.  P is linear in each single mass
+    (masses are free variables), so the differences are exact up to
+    rounding; no oracle involved."""
+    note("histogram adjoint vs finite differences, 32x32 crop")
+    S, C, nb = 2048, 32, 10
+    mem = dev(workloads.mixture_ensemble(0, S, S), torch.float32)
+    full = cp.fit(mem, HST, nbins=nb)
+    del mem
+    rng = np.random.default_rng(17)
+    y0, x0 = (int(v) for v in rng.integers(0, S - C, 2))
+    par = full[:, y0:y0 + C, x0:x0 + C].to(torch.float64).contiguous()
+    del full
+    f = cp.field_of(par, HST, nb)
+    g1, g2 = (dev(g, torch.float64) for g in workloads.upstream(6, C, C, np.float64))
+    grad = host(cp.backward(par, g1, g2, f))
+
+    a0, b0 = cp.forward(par, f)
+    h = 1e-3  # one-sided: L is linear in the mass, and a zero mass stays valid
+    for _ in range(150):
+        y, x, j = int(rng.integers(C)), int(rng.integers(C)), int(rng.integers(nb))
+        pp = par.clone()
+        pp[2 + j, y, x] += h
+        a, b = cp.forward(pp, f)
+        # only the five stencils holding (y, x) change: sum the changes alone
+        fd = float(((a - a0) * g1 + (b - b0) * g2).sum()) / h
+        assert abs(grad[2 + j, y, x] - fd) <= 1e-9 * (1 + abs(fd)), (y, x, j, grad[2 + j, y, x], fd)
+    assert np.all(grad[:2] == 0)
+
+
 @pytest.mark.parametrize("model", ["uniform", "epanechnikov", "gaussian"])
 def test_autograd_function_matches_backward(model):
     """torch.autograd through CPProb gives the adjoint entry point's bits;
