@@ -315,6 +315,35 @@ def test_histogram_adjoint_finite_differences_on_crop():
     assert np.all(grad[:2] == 0)
 
 
+def test_epanechnikov_adjoint_finite_differences_on_crop():
+    """The quoted workload's gradient, checked without the oracle: on a 32x32
+    crop (seeded offset) of the fitted 2048^2 field, the FP64 adjoint with
+    respect to centre and half-width against central differences of the FP64
+    forward of L = sum g_min P_min + g_max P_max (step 1e-4 of the width;
+    the differences of the five stencils that change are summed alone)."""
+    note("Epanechnikov adjoint vs finite differences, 32x32 crop")
+    S, C = 2048, 32
+    mem = dev(workloads.smooth_ensemble(0, S, S), torch.float32)
+    full = cp.fit(mem, E)
+    del mem
+    rng = np.random.default_rng(19)
+    y0, x0 = (int(v) for v in rng.integers(0, S - C, 2))
+    par = full[:, y0:y0 + C, x0:x0 + C].to(torch.float64).contiguous()
+    del full
+    f = cp.field_of(par, E)
+    g1, g2 = (dev(g, torch.float64) for g in workloads.upstream(7, C, C, np.float64))
+    grad = host(cp.backward(par, g1, g2, f))
+    for _ in range(120):
+        y, x, q = int(rng.integers(C)), int(rng.integers(C)), int(rng.integers(2))
+        h = 1e-4 * float(par[1, y, x])
+        pp, pm = par.clone(), par.clone()
+        pp[q, y, x] += h
+        pm[q, y, x] -= h
+        (ap, bp), (am, bm) = cp.forward(pp, f), cp.forward(pm, f)
+        fd = float(((ap - am) * g1 + (bp - bm) * g2).sum()) / (2 * h)
+        assert abs(grad[q, y, x] - fd) <= 1e-6 * (1 + abs(fd)), (y, x, q, grad[q, y, x], fd)
+
+
 @pytest.mark.parametrize("model", ["uniform", "epanechnikov", "gaussian"])
 def test_autograd_function_matches_backward(model):
     """torch.autograd through CPProb gives the adjoint entry point's bits;
