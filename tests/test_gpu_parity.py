@@ -531,6 +531,35 @@ def test_mvg_backward_parity():
     assert bad.sum() <= max(2, H * W // 200), bad.sum()
 
 
+def test_mvg_diagonal_agrees_with_independent_gaussian():
+    """Two device paths that share no code: with a diagonal stencil covariance
+    the Monte Carlo model is the independent Gaussian, so its conditional
+    estimate (4096 Philox samples) must agree with the deterministic
+    quadrature of the independent model within 5 binomial standard errors at
+    every vertex (the conditional estimator's spread is below that)."""
+    note("mvg diagonal vs independent gaussian")
+    H, W, ns = 48, 56, 4096
+    rng = np.random.default_rng(23)
+    mu = rng.normal(0, 0.03, (H, W))
+    sg = rng.uniform(0.01, 0.04, (H, W))
+    gp = dev(np.stack([mu, sg]), torch.float32)
+    ref = host(cp.forward(gp, cp.field_of(gp, "gaussian"))[0]).astype(np.float64)
+    mp = np.zeros((16, H, W))
+    mp[0] = gp[0].double().cpu().numpy()
+    sgf = gp[1].double().cpu().numpy()
+    diag = [1, 3, 6, 10, 15]  # packed positions of L00, L11, L22, L33, L44
+    for i, (dy, dx) in enumerate(((0, 1), (-1, 0), (0, -1), (1, 0), (0, 0))):
+        sh = np.ones((H, W))
+        ys, xs = slice(max(0, -dy), H - max(0, dy)), slice(max(0, -dx), W - max(0, dx))
+        yd, xd = slice(max(0, dy), H - max(0, -dy)), slice(max(0, dx), W - max(0, -dx))
+        sh[ys, xs] = sgf[yd, xd]
+        mp[diag[i]] = sh
+    f = cp.Field(H, W, MVG, torch.float32, nsamples=ns, seed=41, field_id=3, estimator=L.CP_MC_CONDITIONAL)
+    est = host(cp.forward(dev(mp, torch.float64), f)[0]).astype(np.float64)
+    se = np.sqrt(np.clip(ref * (1 - ref), 0, None) / ns)
+    assert np.all(np.abs(est - ref) <= 5 * se + 1e-6), float(np.max(np.abs(est - ref) - 5 * se))
+
+
 def test_mvg_backward_full_size_sampled():
     """1024^2 x 4096 samples (the benchmark's Monte Carlo workload): the
     gathered gradient at sampled vertices, corners and edges included."""
