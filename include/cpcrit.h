@@ -21,8 +21,9 @@
  *
  * Conventions shared by every entry point
  * ---------------------------------------
- *  - All array arguments are DEVICE pointers owned by the caller; the
- *    library never frees or retains them.  Calls are asynchronous on
+ *  - All array arguments are DEVICE pointers owned by the caller, on the
+ *    current HIP device (the one `stream` belongs to); the library never
+ *    frees or retains them.  Calls are asynchronous on
  *    `stream` (a hipStream_t; NULL = the null stream): results are ready
  *    once the caller synchronises that stream.
  *  - A field is H x W vertices.  Every plane (parameters, probabilities,

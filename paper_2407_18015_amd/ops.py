@@ -61,6 +61,13 @@ class Field:
 
 
 def _stream(t: torch.Tensor) -> int:
+    """The current stream of t's device; the library works on the current
+    HIP device, so t must live there."""
+    if t.device.type != "cuda":
+        raise ValueError(f"expected a GPU tensor, got one on {t.device}")
+    if t.device.index != torch.cuda.current_device():
+        raise ValueError(f"tensors on {t.device} but the current device is cuda:{torch.cuda.current_device()}: "
+                         "call under torch.cuda.device(...)")
     return torch.cuda.current_stream(t.device).cuda_stream
 
 
