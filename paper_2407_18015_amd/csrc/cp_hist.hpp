@@ -178,16 +178,17 @@ __host__ __device__ void hist_vertex_minmax(const HistSuf<T>& L, int ev, const i
   SufCursor<T> c[4];
 #pragma unroll
   for (int i = 0; i < 4; ++i) suf_cursor_init(c[i], L, en[i], lo[i], hi[i], pres[i], big);
-  T s0[4], f0[4], s1[4], f1[4];
+  // survival / distribution values at the current left end (sa, fa) and at
+  // the next edge (sb, fb); the loop body takes two intervals with the roles
+  // swapped, so no values are copied between intervals
+  T sa[4], fa[4], sb[4], fb[4];
 #pragma unroll
   for (int i = 0; i < 4; ++i) {
-    s0[i] = cfma(c[i].slope, c[i].nxt, c[i].snx);
-    f0[i] = c[i].tot - s0[i];
+    sa[i] = cfma(c[i].slope, c[i].nxt, c[i].snx);
+    fa[i] = c[i].tot - sa[i];
   }
   T x0 = T(0), amin = T(0), amax = T(0);
-  const int maxit = 5 * (h + 1) + 2;  // every step crosses at least one edge
-  for (int it = 0; it < maxit; ++it) {
-    if (!(x0 < hv)) break;
+  const auto interval = [&](const T(&s0)[4], const T(&f0)[4], T(&s1)[4], T(&f1)[4]) {
     T x1 = nv;
 #pragma unroll
     for (int i = 0; i < 4; ++i) x1 = tmin(x1, c[i].nxt);
@@ -208,12 +209,14 @@ __host__ __device__ void hist_vertex_minmax(const HistSuf<T>& L, int ev, const i
     }
 #pragma unroll
     for (int i = 0; i < 4; ++i) suf_cursor_step(c[i], L, en[i], hi[i], x1, big);
-#pragma unroll
-    for (int i = 0; i < 4; ++i) {
-      s0[i] = s1[i];
-      f0[i] = f1[i];
-    }
     x0 = x1;
+  };
+  const int maxit = 5 * (h + 1) + 2;  // every step crosses at least one edge
+  for (int it = 0; it < maxit; it += 2) {
+    if (!(x0 < hv)) break;
+    interval(sa, fa, sb, fb);
+    if (!(x0 < hv) || it + 1 >= maxit) break;
+    interval(sb, fb, sa, fa);
   }
   pmin = amin;
   pmax = amax;
