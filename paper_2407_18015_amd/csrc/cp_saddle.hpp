@@ -147,13 +147,13 @@ __host__ __device__ T hist_saddle_term(int term, const HistSuf<T>& L, int ev, co
     const T sv = cfma(q.slope, q.nxt - x, q.snx);
     return saddle_is_cdf(term, i) ? q.tot - sv : sv;
   };
-  T f0[4], f1[4];
+  // factor values at the current left end (fa) and the next edge (fb); two
+  // intervals per pass with the roles swapped, so nothing is copied
+  T fa[4], fb[4];
 #pragma unroll
-  for (int i = 0; i < 4; ++i) f0[i] = val(c[i], i, T(0));
+  for (int i = 0; i < 4; ++i) fa[i] = val(c[i], i, T(0));
   T x0 = T(0), acc = T(0);
-  const int maxit = 5 * (h + 1) + 2;
-  for (int it = 0; it < maxit; ++it) {
-    if (!(x0 < end)) break;
+  const auto interval = [&](const T(&f0)[4], T(&f1)[4]) {
     T x1 = tmin(cv.nxt, end);
 #pragma unroll
     for (int i = 0; i < 4; ++i) x1 = tmin(x1, c[i].nxt);
@@ -163,9 +163,14 @@ __host__ __device__ T hist_saddle_term(int term, const HistSuf<T>& L, int ev, co
     suf_cursor_step(cv, L, ev, hv - a, x1, big);
 #pragma unroll
     for (int i = 0; i < 4; ++i) suf_cursor_step(c[i], L, en[i], hs[i], x1, big);
-#pragma unroll
-    for (int i = 0; i < 4; ++i) f0[i] = f1[i];
     x0 = x1;
+  };
+  const int maxit = 5 * (h + 1) + 2;
+  for (int it = 0; it < maxit; it += 2) {
+    if (!(x0 < end)) break;
+    interval(fa, fb);
+    if (!(x0 < end) || it + 1 >= maxit) break;
+    interval(fb, fa);
   }
   return acc;
 }
