@@ -67,7 +67,7 @@ def _load():
         "or_philox4x32_10": (None, [P, P, P]),
         "or_mvg_fit": (i32, [P, i32, i32, i32, i32, f64, P]),
         "or_mvg_forward_at": (i32, [P, i32, i32, i32, u64, u32, i64, P, P, P]),
-        "or_mvg_grad_at": (i32, [P, i32, i32, i32, u64, u32, P, P, i64, P, P]),
+        "or_mvg_grad_at": (i32, [P, i32, i32, i32, u64, u32, P, P, i64, P, P, P]),
     }
     for name, (res, args) in sigs.items():
         fn = getattr(lib, name)
@@ -306,13 +306,19 @@ def mvg_forward_at(params, idx, nsamples: int, seed: int, field_id: int = 0):
     return out, amb
 
 
-def mvg_grad_at(params, gmin, gmax, idx, nsamples: int, seed: int, field_id: int = 0) -> np.ndarray:
-    """Gradient of the conditional estimator at idx: [n][16] (mu gathered, L local)."""
+def mvg_grad_at(params, gmin, gmax, idx, nsamples: int, seed: int, field_id: int = 0, slack: bool = False):
+    """Gradient of the conditional estimator at idx: [n][16] (mu gathered, L
+    local).  With slack=True also returns the near-tie slack [n][16]: per
+    component, the summed magnitude of the sample terms whose extreme
+    neighbour is within rounding of another present neighbour (0 where no
+    such sample occurs), i.e. how far a computation that breaks those ties
+    the other way may differ."""
     params = _f64(params)
     _, H, W = params.shape
     gmin = _f64(gmin); gmax = _f64(gmax)
     idx = np.ascontiguousarray(idx, dtype=np.int64)
     out = np.empty((idx.size, 16))
+    sl = np.empty((idx.size, 16)) if slack else None
     _check(_load().or_mvg_grad_at(_ptr(params), H, W, nsamples, seed, field_id, _ptr(gmin), _ptr(gmax),
-                                  idx.size, _ptr(idx), _ptr(out)), "mvg_grad_at")
-    return out
+                                  idx.size, _ptr(idx), _ptr(out), _ptr(sl) if slack else None), "mvg_grad_at")
+    return (out, sl) if slack else out

@@ -809,6 +809,8 @@ typedef struct {
   int amb_min, amb_max;
   double dmu_min[NSLOT], dmu_max[NSLOT]; /* by stencil slot */
   double dl_min[15], dl_max[15];
+  /* near-tie slack per unit upstream gradient (see mvg_vertex) */
+  double tmu_min[NSLOT], tmu_max[NSLOT], tl_min[15], tl_max[15];
 } mvg_out_t;
 
 /*
@@ -824,6 +826,17 @@ typedef struct {
  * Pr(min) = Phi((min_n x_n - c) / L44), Pr(max) = Phi((c - max_n x_n) / L44).
  * Gradient: pathwise derivative of the conditional estimator.
  * amb_*: samples whose hit decision has a margin below 1e-5 * max row norm of L.
+ *
+ * Near-tie slack (t*_min, t*_max): the gradient routes each sample's term to
+ * the neighbour that attains the minimum (maximum).  A computation in lower
+ * precision may pick another neighbour when two neighbour values lie within
+ * its rounding of each other; then that sample's term moves between the two
+ * neighbours' slots.  For every sample where more than one present neighbour
+ * lies within tt = 2^-18 * max_r (|mu_r - mu_v| + sum_c |L_rc z_c|) of the
+ * extreme (the operands of the neighbour values, about 64 FP32 units in the
+ * last place of their magnitude), the magnitude of the term is added to the
+ * slack of every such neighbour's components.  The slack is 0 wherever no
+ * such near-tie occurs.
  */
 static void mvg_vertex(const double* par, int H, int W, int y, int x, int ns, uint64_t seed,
                        uint32_t field_id, int want_grad, mvg_out_t* o) {
@@ -882,6 +895,20 @@ static void mvg_vertex(const double* par, int H, int W, int y, int x, int ns, ui
       if (amax < 0 || xv[r] > xv[amax]) amax = r;
     }
     double lo = xv[amin], hi = xv[amax];
+    double tmag = 0.0;
+    for (int r = 0; r < 4; ++r) {
+      if (!present[r]) continue;
+      double m = fabs(mu[r] - mu[4]);
+      for (int c = 0; c <= r; ++c) m += fabs(L[r][c] * z[c]);
+      if (m > tmag) tmag = m;
+    }
+    double tt = 0x1p-18 * tmag;
+    int tie_lo = 0, tie_hi = 0;
+    for (int r = 0; r < 4; ++r) {
+      if (!present[r]) continue;
+      tie_lo += xv[r] - lo < tt;
+      tie_hi += hi - xv[r] < tt;
+    }
     o->hit_min += xv[4] < lo ? 1.0 : 0.0;
     o->hit_max += xv[4] > hi ? 1.0 : 0.0;
     if (fabs(xv[4] - lo) < tau) o->amb_min++;
@@ -905,6 +932,17 @@ static void mvg_vertex(const double* par, int H, int W, int y, int x, int ns, ui
     for (int c = 0; c < 4; ++c) o->dl_max[tri(4, c)] += gmax * z[c];
     for (int c = 0; c <= amax; ++c) o->dl_max[tri(amax, c)] -= gmax * z[c];
     o->dl_max[tri(4, 4)] -= gmax * rmax;
+    for (int r = 0; r < 4; ++r) {
+      if (!present[r]) continue;
+      if (tie_lo > 1 && xv[r] - lo < tt) {
+        o->tmu_min[MVG_SLOT[r]] += gmin;
+        for (int c = 0; c <= r; ++c) o->tl_min[tri(r, c)] += gmin * fabs(z[c]);
+      }
+      if (tie_hi > 1 && hi - xv[r] < tt) {
+        o->tmu_max[MVG_SLOT[r]] += gmax;
+        for (int c = 0; c <= r; ++c) o->tl_max[tri(r, c)] += gmax * fabs(z[c]);
+      }
+    }
   }
   double inv = 1.0 / (double)ns;
   o->hit_min *= inv;
@@ -914,10 +952,14 @@ static void mvg_vertex(const double* par, int H, int W, int y, int x, int ns, ui
   for (int k = 0; k < NSLOT; ++k) {
     o->dmu_min[k] *= inv;
     o->dmu_max[k] *= inv;
+    o->tmu_min[k] *= inv;
+    o->tmu_max[k] *= inv;
   }
   for (int k = 0; k < 15; ++k) {
     o->dl_min[k] *= inv;
     o->dl_max[k] *= inv;
+    o->tl_min[k] *= inv;
+    o->tl_max[k] *= inv;
   }
 }
 
@@ -943,16 +985,21 @@ int or_mvg_forward_at(const double* params, int H, int W, int ns, uint64_t seed,
  * Gradient of the conditional estimator: for listed vertices u,
  * out[i][0] = d/dmu(u) gathered over the stencils containing u,
  * out[i][1..15] = d/dL(u) (the factor is local to its stencil).
+ * slack (may be NULL): [nidx][16], the near-tie slack of mvg_vertex gathered
+ * the same way and weighted by |gmin|, |gmax|.
  */
 int or_mvg_grad_at(const double* params, int H, int W, int ns, uint64_t seed, uint32_t field_id,
                    const double* gmin, const double* gmax, int64_t nidx, const int64_t* idx,
-                   double* out) {
+                   double* out, double* slack) {
   if (H < 1 || W < 1 || ns < 1) return 1;
 #pragma omp parallel for schedule(dynamic, 2)
   for (int64_t i = 0; i < nidx; ++i) {
     int y = (int)(idx[i] / W), x = (int)(idx[i] % W);
     double* o = out + 16 * i;
+    double* t = slack ? slack + 16 * i : NULL;
     for (int k = 0; k < 16; ++k) o[k] = 0.0;
+    if (t)
+      for (int k = 0; k < 16; ++k) t[k] = 0.0;
     for (int s = 0; s < NSLOT; ++s) {
       int vy = y - SLOT_DY[s], vx = x - SLOT_DX[s];
       if (vy < 0 || vy >= H || vx < 0 || vx >= W) continue;
@@ -962,6 +1009,10 @@ int or_mvg_grad_at(const double* params, int H, int W, int ns, uint64_t seed, ui
       o[0] += gmin[at] * r.dmu_min[s] + gmax[at] * r.dmu_max[s];
       if (s == 0)
         for (int k = 0; k < 15; ++k) o[1 + k] += gmin[at] * r.dl_min[k] + gmax[at] * r.dl_max[k];
+      if (!t) continue;
+      t[0] += fabs(gmin[at]) * r.tmu_min[s] + fabs(gmax[at]) * r.tmu_max[s];
+      if (s == 0)
+        for (int k = 0; k < 15; ++k) t[1 + k] += fabs(gmin[at]) * r.tl_min[k] + fabs(gmax[at]) * r.tl_max[k];
     }
   }
   return 0;

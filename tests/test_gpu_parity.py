@@ -10,12 +10,14 @@ Philox words bit-identical, conditional estimator within 1e-6, hit counts
 equal up to samples whose decision margin is below the oracle's ambiguity
 threshold; histogram bins (an integer decision) identical.
 """
+import os
 import sys
 
 import numpy as np
 import pytest
 import torch
 
+import exact_stencil
 import oracle
 import workloads
 import paper_2407_18015_amd as cp
@@ -73,6 +75,23 @@ def assert_close(got, ref, atol, what):
 # ----------------------------------------------------------------------------
 # forward
 # ----------------------------------------------------------------------------
+EXACT_2D = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden", "exact_2d_stencils.txt")
+
+
+@pytest.mark.parametrize("case", exact_stencil.load_cases(EXACT_2D), ids=lambda c: c["name"])
+@pytest.mark.parametrize("dtype", [torch.float64, torch.float32])
+def test_exact_2d_stencils(case, dtype):
+    """The exact rationals of the 2-D uniform, Epanechnikov and histogram
+    stencils (Eq. 3, Sec. 4.3, Sec. 4.4.1 / Eq. 5; fixture re-derived with
+    fractions on the CPU): FP64 within 1e-12, FP32 within 1e-6."""
+    note("exact 2-D stencil", case["name"], dtype)
+    model, nb, grid = exact_stencil.case_grid(case)
+    pmin, pmax = gpu_forward(dev(grid, dtype), model, nb)
+    tol = 1e-12 if dtype == torch.float64 else 1e-6
+    assert abs(host(pmin)[1, 1] - float(case["p_min"])) <= tol
+    assert abs(host(pmax)[1, 1] - float(case["p_max"])) <= tol
+
+
 @pytest.mark.parametrize("seed", [0, 1, 2])
 def test_forward_fp64_uniform_64x64(seed):
     """Independent uniform noise on a 64x64 grid in FP64 (1e-12)."""
@@ -480,6 +499,21 @@ def test_philox_bit_identical():
         assert np.array_equal(got[i], oracle.philox4x32_10(ctr[i], key)), i
 
 
+def assert_mvg_grad(g, ref, slack, what):
+    """FP32 samples against FP64 samples: every component within 2e-5 of the
+    vertex's largest gradient component (plus 2e-5 absolute), plus the
+    oracle's near-tie slack -- the summed magnitude of the sample terms whose
+    extreme neighbour lies within rounding of another neighbour, which a
+    lower-precision evaluation may route to the other one (0 where no such
+    sample occurs).  No vertex is exempt."""
+    scale = 1 + np.abs(ref).max(axis=1, keepdims=True)
+    d = np.abs(g - ref)
+    over = d - (2e-5 * scale + slack)
+    i, k = np.unravel_index(int(np.argmax(over)), over.shape)
+    assert np.all(over <= 0), (f"{what}: vertex {i} component {k}: got {g[i, k]}, ref {ref[i, k]}, "
+                               f"slack {slack[i, k]}, vertices with slack {int(np.count_nonzero(slack.any(axis=1)))}")
+
+
 def mvg_setup(H, W, seed):
     mem = workloads.correlated_ensemble(seed, H, W)
     params = cp.fit(dev(mem, torch.float32), "mvg")
@@ -522,13 +556,9 @@ def test_mvg_backward_parity():
     f = cp.Field(H, W, MVG, torch.float32, nsamples=ns, seed=99, field_id=2)
     g = host(cp.backward(params, dev(gmin, torch.float32), dev(gmax, torch.float32), f))
     idx = np.arange(H * W)
-    ref = oracle.mvg_grad_at(host(params), gmin.astype(np.float64), gmax.astype(np.float64), idx, ns, 99, 2)
-    g = g.reshape(16, -1).T
-    scale = 1 + np.abs(ref).max(axis=1, keepdims=True)
-    # FP32 samples against FP64 samples: argmin flips on near-ties are allowed
-    # for at most a few vertices; everything else within 2e-5 relative
-    bad = np.any(np.abs(g - ref) > 2e-5 * scale, axis=1)
-    assert bad.sum() <= max(2, H * W // 200), bad.sum()
+    ref, slack = oracle.mvg_grad_at(host(params), gmin.astype(np.float64), gmax.astype(np.float64), idx, ns, 99,
+                                    2, slack=True)
+    assert_mvg_grad(g.reshape(16, -1).T, ref, slack, "mvg gradient 29x41")
 
 
 def test_mvg_diagonal_agrees_with_independent_gaussian():
@@ -570,10 +600,9 @@ def test_mvg_backward_full_size_sampled():
     f = cp.Field(H, W, MVG, torch.float32, nsamples=ns, seed=4321, field_id=3)
     g = host(cp.backward(params, dev(gmin, torch.float32), dev(gmax, torch.float32), f)).reshape(16, -1).T
     idx = sample_idx(H, W, 48, 8)
-    ref = oracle.mvg_grad_at(host(params), gmin.astype(np.float64), gmax.astype(np.float64), idx, ns, 4321, 3)
-    scale = 1 + np.abs(ref).max(axis=1, keepdims=True)
-    bad = np.any(np.abs(g[idx] - ref) > 2e-5 * scale, axis=1)
-    assert bad.sum() <= 2, bad.sum()
+    ref, slack = oracle.mvg_grad_at(host(params), gmin.astype(np.float64), gmax.astype(np.float64), idx, ns, 4321,
+                                    3, slack=True)
+    assert_mvg_grad(g[idx], ref, slack, "mvg gradient 1024^2 sampled")
 
 
 # ----------------------------------------------------------------------------
@@ -632,11 +661,16 @@ def test_batched_forward_backward(graph):
             assert_close(host(pmin[i]), host(a), 1e-6, f"P_min field {i}")
             assert_close(host(pmax[i]), host(b), 1e-6, f"P_max field {i}")
             assert torch.equal(g, grad[i]), (rep, i)
-    # and the oracle on one field of each model
+    # and the oracle on one field of each model: probabilities and gradients
     for i in range(3):
         f, p = fl[i]
-        r = oracle.forward(f.model, host(p))
-        assert_close(host(pmin[i]), r[0], 1e-6, "oracle P_min")
+        ph = host(p)
+        r = oracle.forward(f.model, ph)
+        assert_close(host(pmin[i]), r[0], 1e-6, f"oracle P_min field {i}")
+        assert_close(host(pmax[i]), r[1], 1e-6, f"oracle P_max field {i}")
+        args = (f.model, ph, host(gmin[i]), host(gmax[i]))
+        assert_grad(host(grad[i]), oracle.grad(*args), oracle.grad(*args, absolute=True), torch.float32,
+                    f"oracle gradient field {i} ({NAMES[f.model]})")
 
 
 @pytest.mark.parametrize("graph", [False, True])

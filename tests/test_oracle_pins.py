@@ -17,6 +17,7 @@ import numpy as np
 import pytest
 from scipy import integrate, stats
 
+import exact_stencil
 import oracle
 import workloads
 from conftest import golden_small_fields, read_golden
@@ -112,6 +113,28 @@ def test_oracle_reproduces_its_golden_fields():
         pmin, pmax = oracle.forward(model, p)
         np.testing.assert_allclose(pmin, rmin, rtol=0, atol=1e-15, err_msg=name)
         np.testing.assert_allclose(pmax, rmax, rtol=0, atol=1e-15, err_msg=name)
+
+
+EXACT_2D = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden", "exact_2d_stencils.txt")
+
+
+@pytest.mark.parametrize("case", exact_stencil.load_cases(EXACT_2D), ids=lambda c: c["name"])
+def test_exact_2d_stencil_values_rederived(case):
+    """The fixture's rationals equal an exact Fraction integration of the
+    definitions (Eq. 3 and its mirror, densities of Sec. 4.3 / 4.4.1)."""
+    pmin, pmax = exact_stencil.case_exact(case)
+    assert pmin == case["p_min"] and pmax == case["p_max"], (pmin, pmax)
+
+
+@pytest.mark.parametrize("case", exact_stencil.load_cases(EXACT_2D), ids=lambda c: c["name"])
+def test_oracle_matches_exact_2d_stencils(case):
+    """The oracle at 1e-15 on the exact 2-D stencils: tighter than the 1e-12
+    the FP64 device path is held to against it (inputs such as 1/10 are
+    rounded once to FP64, which moves P by ~1e-16)."""
+    model, nb, grid = exact_stencil.case_grid(case)
+    pmin, pmax = oracle.forward(model, grid)
+    assert abs(pmin[1, 1] - float(case["p_min"])) <= 1e-15, pmin[1, 1]
+    assert abs(pmax[1, 1] - float(case["p_max"])) <= 1e-15, pmax[1, 1]
 
 
 @pytest.mark.parametrize("model", [U, E, HST])
@@ -654,6 +677,49 @@ def test_mvg_conditional_gradient_matches_finite_differences():
             pp[q, y, x] += h; pm[q, y, x] -= h
             fd = (loss(pp) - loss(pm)) / (2 * h)
             assert gr[y * W + x, q] == pytest.approx(fd, abs=2e-6 * (1 + abs(fd)))
+
+
+def test_mvg_gradient_tie_slack_bounds_a_flipped_tie():
+    """The near-tie slack of the gradient: a neighbour (w) that duplicates
+    another (e) exactly ties with it in every sample.  Moving mu_w by +-1e-13
+    (far below any rounding bound) breaks every tie one way or the other, which
+    moves whole sample terms between the two neighbours' gradient slots; the
+    slack reported on either side bounds that change component by component,
+    and it is exactly 0 for a stencil without ties."""
+    rng = np.random.default_rng(12)
+    A = rng.normal(size=(5, 5))
+    L = np.linalg.cholesky(A @ A.T / 5 + 0.2 * np.eye(5))
+    L[2, :] = 0.0
+    L[2, 0] = L[0, 0]  # x_w = mu_w + L00 z0 = x_e when mu_w = mu_e
+    mu = [0.05, -0.02, 0.05, 0.01, 0.0]  # e, n, w, s, v
+    H, W = 3, 3
+    gmin, gmax = workloads.upstream(3, H, W, np.float64)
+    idx = np.arange(H * W)
+    ns, seed = 512, 17
+    res = []
+    for d in (1e-13, -1e-13):
+        m = list(mu)
+        m[2] += d
+        res.append(oracle.mvg_grad_at(mvg_grid(mu_plane(m), L), gmin, gmax, idx, ns, seed, slack=True))
+    (gp, sp), (gm, sm) = res
+    diff = np.abs(gp - gm)
+    assert diff.max() > 1e-3  # the ties moved terms between e and w
+    assert np.all(diff <= sp + 1e-9) and np.all(diff <= sm + 1e-9)
+    # the slack sits on the tied neighbours only: mean gradients of e and w
+    # (through the centre's stencil) and the centre's L rows of e and w
+    rows_e, rows_w = [1], [4, 5, 6]  # packed positions of L_00 and L_20..L_22 (offset 1)
+    for flat in range(H * W):
+        y, x = divmod(flat, W)
+        if (y, x) not in (POS["e"], POS["w"]):
+            assert sp[flat, 0] == 0.0 and sm[flat, 0] == 0.0, (y, x)
+    centre_slack = sp[4, 1:]
+    nz = set(np.nonzero(centre_slack)[0] + 1)
+    assert nz <= set(rows_e + rows_w) and nz, nz
+    # without the duplicate there is no tie and no slack
+    L2 = np.linalg.cholesky(A @ A.T / 5 + 0.2 * np.eye(5))
+    _, s0 = oracle.mvg_grad_at(mvg_grid(mu_plane([0.1, -0.2, 0.3, 0.05, 0.0]), L2), gmin, gmax, idx, ns, seed,
+                               slack=True)
+    assert np.all(s0 == 0.0)
 
 
 def test_mvg_fit_against_numpy():
