@@ -173,11 +173,12 @@ cp_status_t cp_prob_forward(const cp_field_desc_t* desc, const void* params, voi
  * bit-reproducible.
  * The histogram and multivariate Gaussian adjoints pass per-stencil
  * partials through a library-owned device buffer, one per (device, stream),
- * allocated with hipMalloc on first use and grown on demand (growing frees
- * the old buffer, which waits for the device); calls on different streams
- * never share one, and a stream being captured into a graph must have made
- * an uncaptured call of at least the same size first.  cp_release() frees
- * them.
+ * allocated with hipMalloc on first use and replaced by a larger one when a
+ * call needs more (the replaced buffer is kept, not freed, since a graph
+ * captured from an earlier call may still write it); calls on different
+ * streams never share one, and a stream being captured into a graph must
+ * have made an uncaptured call of at least the same size first.
+ * cp_release() frees all of them.
  *   g_min, g_max  [H][row_stride]; grad_params [n_param][H][row_stride]
  */
 cp_status_t cp_prob_backward(const cp_field_desc_t* desc, const void* params, const void* g_min,

@@ -18,7 +18,8 @@ CP_F32, CP_F64 = 0, 1
 CP_MC_CONDITIONAL, CP_MC_HIT = 0, 1
 CP_BATCH_FWD, CP_BATCH_BWD, CP_BATCH_GRAPH, CP_BATCH_PER_FIELD, CP_BATCH_TUNE = 1, 2, 4, 8, 16
 
-EXPORTS = ["cpu_fit_params", "cp_fit_error_bound", "cp_prob_forward", "cp_prob_backward", "cp_prob_classify", "cp_prob_semianalytical",
+EXPORTS = ["cpu_fit_params", "cp_fit_error_bound", "cp_prob_forward", "cp_prob_backward", "cp_prob_classify",
+           "cp_prob_semianalytical",
            "cp_prob_batched", "cp_batched_pin", "cp_batched_describe",
            "cp_n_params", "cp_status_string", "cp_last_error", "cp_release", "cp_philox4x32_10", "cp_gauss_legendre"]
 

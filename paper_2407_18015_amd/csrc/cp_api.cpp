@@ -11,6 +11,7 @@
 #include <vector>
 
 #include "cp_internal.hpp"
+#include "cp_workspace.hpp"
 #include "cpcrit.h"
 
 namespace {
@@ -88,48 +89,41 @@ int n_params(int model, int nb) {
 }
 
 namespace {
-// one buffer per (device, stream): calls ordered on one stream reuse it,
-// calls on different streams or devices never share one
-struct WsBuf {
-  void* ptr = nullptr;
-  size_t bytes = 0;
-};
-std::mutex g_ws_mu;
-std::map<std::pair<int, hipStream_t>, WsBuf> g_ws;
+int ws_alloc(void** out, size_t bytes) { return (int)hipMalloc(out, bytes); }
+void ws_free(int dev, void* p) {
+  (void)hipSetDevice(dev);
+  (void)hipFree(p);
+}
+const PoolOps kWsOps{ws_alloc, ws_free};
+WorkspacePool g_ws;
 }  // namespace
 
 hipError_t workspace(size_t bytes, hipStream_t st, void** out) {
   int dev = 0;
   hipError_t e = hipGetDevice(&dev);
   if (e != hipSuccess) return e;
-  std::lock_guard<std::mutex> lk(g_ws_mu);
-  WsBuf& w = g_ws[{dev, st}];
-  if (bytes > w.bytes) {
-    if (w.ptr) {
-      e = hipFree(w.ptr);  // waits for work that may still use it
-      if (e != hipSuccess) return e;
-      w.ptr = nullptr;
-      w.bytes = 0;
-    }
-    e = hipMalloc(&w.ptr, bytes);
-    if (e != hipSuccess) return e;
-    w.bytes = bytes;
-  }
-  *out = w.ptr;
-  return hipSuccess;
+  return (hipError_t)g_ws.get(dev, st, bytes, kWsOps, out);
 }
 
 void workspace_release() {
-  std::lock_guard<std::mutex> lk(g_ws_mu);
   int cur = 0;
   const bool have = hipGetDevice(&cur) == hipSuccess;
-  for (auto& kv : g_ws)
-    if (kv.second.ptr) {
-      (void)hipSetDevice(kv.first.first);
-      (void)hipFree(kv.second.ptr);
-    }
+  g_ws.release(kWsOps);
   if (have) (void)hipSetDevice(cur);
-  g_ws.clear();
+}
+
+size_t backward_scratch_bytes(const Field& f) {
+  const size_t nv = (size_t)f.H * (size_t)f.W;
+  if (f.model == CP_HISTOGRAM) return (f.dtype == CP_F64 ? 8 : 4) * (size_t)5 * (size_t)f.nb * nv;
+  if (f.model == CP_MVGAUSS) return sizeof(double) * 5 * nv;
+  return 0;
+}
+
+hipError_t adjoint_scratch(size_t bytes, hipStream_t st, const Scratch& scr, void** out) {
+  if (!scr.ptr) return workspace(bytes, st, out);
+  if (bytes > scr.bytes) return hipErrorInvalidValue;
+  *out = scr.ptr;
+  return hipSuccess;
 }
 }  // namespace cp
 

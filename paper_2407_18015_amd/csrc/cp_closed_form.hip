@@ -171,11 +171,11 @@ static hipError_t launch_bwd_gauss(const FieldPtrs<T>& p, hipStream_t st) {
 }
 
 template <typename T, int TY>
-static hipError_t launch_bwd_hist(const FieldPtrs<T>& p, hipStream_t st) {
+static hipError_t launch_bwd_hist(const FieldPtrs<T>& p, hipStream_t st, const Scratch& scr) {
   const int tx = cdiv(p.W, kFwdTX), ty = cdiv(p.H, TY), n = tx * ty;
   const int64_t plane = (int64_t)p.H * p.W;
   void* ws = nullptr;
-  hipError_t e = workspace(sizeof(T) * (size_t)5 * p.nb * plane, st, &ws);
+  hipError_t e = adjoint_scratch(sizeof(T) * (size_t)5 * p.nb * plane, st, scr, &ws);
   if (e != hipSuccess) return e;
   T* J = static_cast<T*>(ws);
   const size_t lds = sizeof(T) * (size_t)hist_planes(p.nb) * (kFwdTX + 2) * (TY + 2);
@@ -191,7 +191,7 @@ static hipError_t launch_bwd_hist(const FieldPtrs<T>& p, hipStream_t st) {
 
 template <typename T>
 static hipError_t bwd_typed(const Field& f, const void* params, const void* gmin, const void* gmax, void* grad,
-                            hipStream_t st) {
+                            hipStream_t st, const Scratch& scr) {
   FieldPtrs<T> p = make_ptrs<T>(f, params, nullptr, nullptr, gmin, gmax, grad);
   if (f.model == CP_GAUSSIAN) return launch_bwd_gauss<T>(p, st);
   if (f.model != CP_HISTOGRAM) {
@@ -204,15 +204,15 @@ static hipError_t bwd_typed(const Field& f, const void* params, const void* gmin
   }
   // sweep tiles as in the forward; the Jacobians go through the workspace
   const size_t per_row = sizeof(T) * (size_t)hist_planes(f.nb) * (kFwdTX + 2);
-  if (per_row * 6 <= 64 * 1024) return launch_bwd_hist<T, 4>(p, st);
-  if (per_row * 4 <= kMaxLds) return launch_bwd_hist<T, 2>(p, st);
-  return launch_bwd_hist<T, 1>(p, st);
+  if (per_row * 6 <= 64 * 1024) return launch_bwd_hist<T, 4>(p, st, scr);
+  if (per_row * 4 <= kMaxLds) return launch_bwd_hist<T, 2>(p, st, scr);
+  return launch_bwd_hist<T, 1>(p, st, scr);
 }
 
 hipError_t cf_backward(const Field& f, const void* params, const void* gmin, const void* gmax, void* grad,
-                       hipStream_t st) {
-  if (f.dtype == CP_F64) return bwd_typed<double>(f, params, gmin, gmax, grad, st);
-  return bwd_typed<float>(f, params, gmin, gmax, grad, st);
+                       hipStream_t st, const Scratch& scr) {
+  if (f.dtype == CP_F64) return bwd_typed<double>(f, params, gmin, gmax, grad, st, scr);
+  return bwd_typed<float>(f, params, gmin, gmax, grad, st, scr);
 }
 
 bool gl_table(int n, double* x, double* w) {

@@ -27,8 +27,21 @@ int n_params(int model, int nb);
 
 // closed-form models (uniform, Epanechnikov, histogram)
 hipError_t cf_forward(const Field& f, const void* params, void* pmin, void* pmax, hipStream_t st);
+// Device memory for the per-stencil partials of an adjoint: a caller-given
+// region (ptr, bytes), or the library-owned workspace when ptr is null.
+struct Scratch {
+  void* ptr = nullptr;
+  size_t bytes = 0;
+};
+// bytes of per-stencil partials the adjoint of field f passes through memory
+// (0: the model's adjoint needs none)
+size_t backward_scratch_bytes(const Field& f);
+// the region an adjoint uses: the caller's (hipErrorInvalidValue if too
+// small), else the library workspace of (device, st)
+hipError_t adjoint_scratch(size_t bytes, hipStream_t st, const Scratch& scr, void** out);
+
 hipError_t cf_backward(const Field& f, const void* params, const void* gmin, const void* gmax, void* grad,
-                       hipStream_t st);
+                       hipStream_t st, const Scratch& scr = Scratch());
 
 // classification (min, max, saddle, regular); any output may be null
 hipError_t cf_classify(const Field& f, const void* params, void* pmin, void* pmax, void* psad, void* preg,
@@ -53,12 +66,14 @@ inline double fit_wscale(int model, int M, int ddof, double bw) {
 // multivariate Gaussian
 hipError_t mvg_forward(const Field& f, const double* params, float* pmin, float* pmax, hipStream_t st);
 hipError_t mvg_backward(const Field& f, const double* params, const float* gmin, const float* gmax,
-                        double* grad, hipStream_t st);
+                        double* grad, hipStream_t st, const Scratch& scr = Scratch());
 hipError_t philox_raw(int64_t n, const uint32_t* ctr, uint64_t seed, uint32_t* out, hipStream_t st);
 
 // Library-owned device workspace (per-stencil adjoint partials) of the
-// current device for work on stream st, grown on demand; the adjoints that
-// gather through memory share it along one stream.
+// current device for work on stream st, grown on demand (a replaced buffer
+// stays allocated until workspace_release, since a captured graph may still
+// write it); the adjoints that gather through memory share it along one
+// stream.
 hipError_t workspace(size_t bytes, hipStream_t st, void** out);
 void workspace_release();
 

@@ -269,14 +269,14 @@ hipError_t mvg_forward(const Field& f, const double* params, float* pmin, float*
 }
 
 hipError_t mvg_backward(const Field& f, const double* params, const float* gmin, const float* gmax, double* grad,
-                        hipStream_t st) {
+                        hipStream_t st, const Scratch& scr) {
   MvgArgs a = make_args(f, params);
   a.gmin = gmin;
   a.gmax = gmax;
   a.grad = grad;
   const int64_t nv = (int64_t)f.H * f.W;
   void* ws = nullptr;
-  hipError_t e = workspace(sizeof(double) * 5 * (size_t)nv, st, &ws);
+  hipError_t e = adjoint_scratch(sizeof(double) * 5 * (size_t)nv, st, scr, &ws);
   if (e != hipSuccess) return e;
   a.jmu = static_cast<double*>(ws);
   hipLaunchKernelGGL(k_mvg_bwd, dim3((unsigned)((nv + 3) / 4)), dim3(256), 0, st, a);
