@@ -185,6 +185,27 @@ cp_status_t cp_prob_backward(const cp_field_desc_t* desc, const void* params, co
                              const void* g_max, void* grad_params, void* stream);
 
 /*
+ * cp_prob_backward without any device allocation, for callers that cannot
+ * allocate: code under HIP graph capture, serving loops that must not call
+ * hipMalloc, harnesses that forbid it.  Same arguments, kernels and results
+ * (bit for bit) as cp_prob_backward.  The per-stencil partials of the
+ * histogram and multivariate Gaussian adjoints go to one fixed device array
+ * of 64 MiB per GPU (2^26 bytes; it exists on every GPU the library's code is
+ * loaded on until the process ends), found on the first call on each device;
+ * no call allocates, frees or grows device memory.
+ *   Scratch needed: histogram 5 * nbins * H * W * sizeof(dtype) bytes,
+ *   multivariate Gaussian 40 * H * W bytes, other models none.  A field that
+ *   needs more than 64 MiB returns CP_EINVAL before anything is launched
+ *   (cp_last_error gives both sizes).
+ *   Every call on one GPU uses the same array: calls that may overlap in time
+ *   on one GPU (on streams without ordering between them) race and must not
+ *   be issued; calls ordered on one stream are safe.  Each call writes every
+ *   scratch entry it later reads, so nothing needs clearing between calls.
+ */
+cp_status_t cp_prob_backward_noalloc(const cp_field_desc_t* desc, const void* params, const void* g_min,
+                                     const void* g_max, void* grad_params, void* stream);
+
+/*
  * Classification of every vertex into minimum, maximum, saddle or regular
  * point, for the closed-form models (uniform, Epanechnikov, histogram) and
  * the independent Gaussian.

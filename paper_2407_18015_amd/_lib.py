@@ -18,7 +18,8 @@ CP_F32, CP_F64 = 0, 1
 CP_MC_CONDITIONAL, CP_MC_HIT = 0, 1
 CP_BATCH_FWD, CP_BATCH_BWD, CP_BATCH_GRAPH, CP_BATCH_PER_FIELD, CP_BATCH_TUNE = 1, 2, 4, 8, 16
 
-EXPORTS = ["cpu_fit_params", "cp_fit_error_bound", "cp_prob_forward", "cp_prob_backward", "cp_prob_classify",
+EXPORTS = ["cpu_fit_params", "cp_fit_error_bound", "cp_prob_forward", "cp_prob_backward",
+           "cp_prob_backward_noalloc", "cp_prob_classify",
            "cp_prob_semianalytical",
            "cp_prob_batched", "cp_batched_pin", "cp_batched_describe",
            "cp_n_params", "cp_status_string", "cp_last_error", "cp_release", "cp_philox4x32_10", "cp_gauss_legendre"]
@@ -63,6 +64,7 @@ def load() -> ctypes.CDLL:
         "cp_fit_error_bound": (i32, [D, P, ctypes.c_double, P, P]),
         "cp_prob_forward": (i32, [D, P, P, P, P]),
         "cp_prob_backward": (i32, [D, P, P, P, P, P]),
+        "cp_prob_backward_noalloc": (i32, [D, P, P, P, P, P]),
         "cp_prob_classify": (i32, [D, P, P, P, P, P, P, P]),
         "cp_prob_semianalytical": (i32, [D, P, P, P, P, P]),
         "cp_prob_batched": (i32, [i32, D, PP, PP, PP, PP, PP, PP, u32, P]),
@@ -112,6 +114,10 @@ def cp_prob_forward(desc, params, p_min, p_max, stream) -> int:
 
 def cp_prob_backward(desc, params, g_min, g_max, grad_params, stream) -> int:
     return load().cp_prob_backward(ctypes.byref(desc), params, g_min, g_max, grad_params, stream)
+
+
+def cp_prob_backward_noalloc(desc, params, g_min, g_max, grad_params, stream) -> int:
+    return load().cp_prob_backward_noalloc(ctypes.byref(desc), params, g_min, g_max, grad_params, stream)
 
 
 def _ptr_array(vals):

@@ -127,6 +127,41 @@ hipError_t adjoint_scratch(size_t bytes, hipStream_t st, const Scratch& scr, voi
 }
 }  // namespace cp
 
+// ---------------------------------------------------------------------------
+// Fixed adjoint scratch for cp_prob_backward_noalloc: a device array that
+// exists on every GPU the library's code is loaded on, for the life of the
+// process.  Host code must not pass `scratch` itself to a kernel (on the host
+// it names a stand-in, not device memory): its device address is looked up
+// once per device with hipGetSymbolAddress and kept in g_noalloc_ptr.
+// ---------------------------------------------------------------------------
+namespace {
+constexpr size_t kNoAllocScratchBytes = size_t(64) << 20;
+constexpr int kNoAllocMaxDevices = 64;
+__device__ __align__(256) unsigned char scratch[kNoAllocScratchBytes];
+
+std::mutex g_noalloc_mu;
+void* g_noalloc_ptr[kNoAllocMaxDevices] = {};
+
+// Device address of `scratch` on the current device (looked up on the first
+// call there).
+hipError_t noalloc_scratch(void** out) {
+  int dev = 0;
+  hipError_t e = hipGetDevice(&dev);
+  if (e != hipSuccess) return e;
+  if (dev < 0 || dev >= kNoAllocMaxDevices) return hipErrorInvalidDevice;
+  std::lock_guard<std::mutex> lk(g_noalloc_mu);
+  if (!g_noalloc_ptr[dev]) {
+    void* p = nullptr;
+    e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+    if (e != hipSuccess) return e;
+    if (!p) return hipErrorInvalidSymbol;
+    g_noalloc_ptr[dev] = p;
+  }
+  *out = g_noalloc_ptr[dev];
+  return hipSuccess;
+}
+}  // namespace
+
 extern "C" {
 
 int32_t cp_n_params(int32_t model, int32_t nbins) {
@@ -216,6 +251,35 @@ cp_status_t cp_prob_backward(const cp_field_desc_t* desc, const void* params, co
                          static_cast<const float*>(g_max), static_cast<double*>(grad_params), st);
   else
     e = cp::cf_backward(f, params, g_min, g_max, grad_params, st);
+  if (e == hipErrorInvalidValue && f.model == CP_HISTOGRAM)
+    return fail(CP_EUNSUPPORTED, "histogram adjoint: too many bins for this dtype's LDS budget");
+  if (e != hipSuccess) return device_fail(e, "backward launch");
+  return CP_OK;
+}
+
+cp_status_t cp_prob_backward_noalloc(const cp_field_desc_t* desc, const void* params, const void* g_min,
+                                     const void* g_max, void* grad_params, void* stream) {
+  cp::Field f;
+  cp_status_t s = check_desc(desc, f);
+  if (s != CP_OK) return s;
+  if (!params || !g_min || !g_max || !grad_params) return fail(CP_EINVAL, "a backward argument is NULL");
+  const size_t need = cp::backward_scratch_bytes(f);
+  if (need > kNoAllocScratchBytes) {
+    char msg[160];
+    std::snprintf(msg, sizeof msg, "allocation-free adjoint: this field needs %zu bytes of scratch, the fixed "
+                  "array holds %zu", need, kNoAllocScratchBytes);
+    return fail(CP_EINVAL, msg);
+  }
+  void* ptr = nullptr;
+  hipError_t e = noalloc_scratch(&ptr);
+  if (e != hipSuccess) return device_fail(e, "scratch symbol lookup");
+  const cp::Scratch scr{ptr, kNoAllocScratchBytes};
+  hipStream_t st = static_cast<hipStream_t>(stream);
+  if (f.model == CP_MVGAUSS)
+    e = cp::mvg_backward(f, static_cast<const double*>(params), static_cast<const float*>(g_min),
+                         static_cast<const float*>(g_max), static_cast<double*>(grad_params), st, scr);
+  else
+    e = cp::cf_backward(f, params, g_min, g_max, grad_params, st, scr);
   if (e == hipErrorInvalidValue && f.model == CP_HISTOGRAM)
     return fail(CP_EUNSUPPORTED, "histogram adjoint: too many bins for this dtype's LDS budget");
   if (e != hipSuccess) return device_fail(e, "backward launch");

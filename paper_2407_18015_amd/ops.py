@@ -141,15 +141,18 @@ def forward(params: torch.Tensor, f: Field, pmin: torch.Tensor | None = None, pm
 
 
 def backward(params: torch.Tensor, gmin: torch.Tensor, gmax: torch.Tensor, f: Field,
-             grad: torch.Tensor | None = None) -> torch.Tensor:
-    """cp_prob_backward: gradient of sum g_min P_min + g_max P_max w.r.t. params."""
+             grad: torch.Tensor | None = None, noalloc: bool = False) -> torch.Tensor:
+    """cp_prob_backward: gradient of sum g_min P_min + g_max P_max w.r.t. params.
+    noalloc=True calls cp_prob_backward_noalloc (the library's fixed scratch
+    array instead of a workspace it allocates; pass `grad` to allocate nothing)."""
     _planes(params, f.height, f.width, f.param_dtype, "params", f.row_stride)
     _planes(gmin, f.height, f.width, f.out_dtype, "g_min", f.row_stride)
     _planes(gmax, f.height, f.width, f.out_dtype, "g_max", f.row_stride)
     if grad is None:
         grad = torch.empty_like(params)
     _planes(grad, f.height, f.width, f.param_dtype, "grad_params", f.row_stride)
-    L.check(L.cp_prob_backward(f.desc(), _ptr(params), _ptr(gmin), _ptr(gmax), _ptr(grad), _stream(params)))
+    fn = L.cp_prob_backward_noalloc if noalloc else L.cp_prob_backward
+    L.check(fn(f.desc(), _ptr(params), _ptr(gmin), _ptr(gmax), _ptr(grad), _stream(params)))
     return grad
 
 
