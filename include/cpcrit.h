@@ -269,8 +269,11 @@ cp_status_t cp_prob_semianalytical(const cp_field_desc_t* desc, const void* para
  * those of cp_prob_forward / cp_prob_backward on each field.  The graph cache
  * is keyed by the field shapes; each call refreshes the descriptor table
  * (pointers may change between calls).  Calls with the same shapes share one
- * plan, including its device-side tile queue: they must not execute
- * concurrently (e.g. on two streams without ordering between them).
+ * plan, including its device-side tile queue and histogram workspace: a call
+ * on another stream than the plan's last uncaptured call is ordered after
+ * that call on the device (a stream wait), and such a call while its stream
+ * is being captured into a graph returns CP_EINVAL; replays of graphs that
+ * the caller captured must not overlap other calls with the same shapes.
  * Gaussian fields (CP_MVGAUSS, CP_GAUSSIAN) are not accepted here
  * (CP_EUNSUPPORTED).
  * CP_BATCH_TUNE: the first call with these shapes and flags times, for every

@@ -19,7 +19,9 @@
 // bound histogram sweep keeps the occupancy of its per-field kernel).
 // Histogram adjoint tiles write their per-stencil Jacobians to a workspace
 // owned by the plan, and a last pass gathers them; forward values are written
-// by the adjoint tiles when both are requested.
+// by the adjoint tiles when both are requested.  A plan used from a second
+// stream waits (on the device) for the first stream's last use of it, so
+// calls on different streams never share a tile queue while it is in flight.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -68,28 +70,6 @@ struct BatchField {
   T* J;  // histogram adjoint workspace ([5][h][H][W]) or null
   int model;
 };
-
-// histogram gather over vertices [i0, i0 + n) of one field (flat y*W + x)
-template <typename T>
-__device__ __forceinline__ void hist_gather_chunk(const FieldPtrs<T>& f, const T* __restrict__ J, int64_t i0,
-                                                  int tid) {
-  const int64_t plane = (int64_t)f.H * f.W;
-  const int64_t id = i0 + tid;
-  if (id >= plane) return;
-  const int y = (int)(id / f.W), x = (int)(id - (int64_t)y * f.W);
-  const int h = f.nb;
-  const int64_t at = (int64_t)y * f.rs + x;
-  f.grad[at] = T(0);
-  f.grad[f.ps + at] = T(0);
-  for (int k = 0; k < h; ++k) {
-    T g = J[(int64_t)(0 * h + k) * plane + id];
-    if (x + 1 < f.W) g += J[(int64_t)(3 * h + k) * plane + id + 1];
-    if (x > 0) g += J[(int64_t)(1 * h + k) * plane + id - 1];
-    if (y > 0) g += J[(int64_t)(4 * h + k) * plane + id - f.W];
-    if (y + 1 < f.H) g += J[(int64_t)(2 * h + k) * plane + id + f.W];
-    f.grad[(int64_t)(2 + k) * f.ps + at] = g;
-  }
-}
 
 // The FP32 histogram forward pass keeps the 5 waves per SIMD of its per-field
 // kernel (the tile loop would otherwise push it one register over).
@@ -141,7 +121,7 @@ __global__ __launch_bounds__(kNT, (batched_min_waves<T, PASS>())) void k_batched
       } else if constexpr (PASS == PASS_BWD_HIST) {
         tile_hist_sweep<T, TY, kNT>(F.p, tl.ty0, tl.tx0, lds, tid, F.J);
       } else {
-        hist_gather_chunk<T>(F.p, F.J, tl.ty0, tid);
+        hist_gather_vertex<T>(F.p, F.J, (int64_t)tl.ty0 + tid);
       }
     }
     if (tid == 0) claimed = ahead;
@@ -242,6 +222,9 @@ struct Plan {
   void* d_ws = nullptr;             // histogram Jacobians of all fields
   std::vector<size_t> ws_offset;    // bytes, per field (SIZE_MAX: none)
   std::vector<unsigned char> host_fields;  // last uploaded field table
+  hipStream_t last = nullptr;       // stream of the last call that used the plan
+  hipEvent_t done = nullptr;        // recorded on `last` after that call's launches
+  bool used = false;
   hipGraphExec_t exec = nullptr;
   hipGraph_t graph = nullptr;
   void drop_graph() {
@@ -255,6 +238,7 @@ struct Plan {
     for (Pass& p : passes) p.release();
     if (d_fields) (void)hipFree(d_fields);
     if (d_ws) (void)hipFree(d_ws);
+    if (done) (void)hipEventDestroy(done);
   }
 };
 
@@ -393,6 +377,7 @@ cp_status_t build_plan(int n, const Field* fs, bool bwd, Plan& P, const char** w
     P.passes.push_back(Q);
   }
   if (ws > 0 && hipMalloc(&P.d_ws, ws) != hipSuccess) return CP_ENOMEM;
+  if (hipEventCreateWithFlags(&P.done, hipEventDisableTiming) != hipSuccess) return CP_EDEVICE;
   P.host_fields.clear();
   const size_t fb = (el == 4 ? sizeof(BatchField<float>) : sizeof(BatchField<double>)) * (size_t)n;
   if (hipMalloc(&P.d_fields, fb) != hipSuccess) return CP_ENOMEM;
@@ -577,6 +562,18 @@ cp_status_t batched(int n, const Field* fs, const void* const* params, void* con
     it = g_plans.emplace(key, std::move(P)).first;
   }
   Plan& P = *it->second;
+  hipStreamCaptureStatus capst = hipStreamCaptureStatusNone;
+  if (hipStreamIsCapturing(st, &capst) != hipSuccess) return CP_EDEVICE;
+  const bool capturing = capst != hipStreamCaptureStatusNone;
+  // the plan's tile queues, field table and workspace may still be in use by
+  // the last call on another stream: order this stream after it
+  if (P.used && P.last != st) {
+    if (capturing) {
+      *why = "batched: the plan was last used on another stream; make an uncaptured call on this stream first";
+      return CP_EINVAL;
+    }
+    if (hipStreamWaitEvent(st, P.done, 0) != hipSuccess) return CP_EDEVICE;
+  }
   std::vector<unsigned char> table;
   if (P.dtype == CP_F64)
     fill_fields<double>(n, fs, P, params, pmin, pmax, gmin, gmax, grad, fwd, bwd, table);
@@ -592,9 +589,7 @@ cp_status_t batched(int n, const Field* fs, const void* const* params, void* con
     P.host_fields.swap(table);
   }
   if ((flags & CP_BATCH_TUNE) && !P.tuned) {
-    hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
-    if (hipStreamIsCapturing(st, &cs) != hipSuccess) return CP_EDEVICE;
-    if (cs != hipStreamCaptureStatusNone) {
+    if (capturing) {
       *why = "batched: tuning times launches and cannot run while the stream is being captured";
       return CP_EINVAL;
     }
@@ -605,12 +600,20 @@ cp_status_t batched(int n, const Field* fs, const void* const* params, void* con
     }
     P.drop_graph();  // captured with the default configuration
   }
+  // every path below ends by marking the plan as used on st
+  const auto used_on = [&]() -> cp_status_t {
+    if (capturing) return CP_OK;
+    if (hipEventRecord(P.done, st) != hipSuccess) return CP_EDEVICE;
+    P.last = st;
+    P.used = true;
+    return CP_OK;
+  };
   if (!(flags & CP_BATCH_GRAPH)) {
     if (launch(P, st) != hipSuccess) {
       *why = "batched: launch failed";
       return CP_EDEVICE;
     }
-    return CP_OK;
+    return used_on();
   }
   if (!P.exec) {
     hipStream_t cs;
@@ -637,7 +640,7 @@ cp_status_t batched(int n, const Field* fs, const void* const* params, void* con
     *why = "batched: graph launch failed";
     return CP_EDEVICE;
   }
-  return CP_OK;
+  return used_on();
 }
 
 cp_status_t batched_pin(int n, const Field* fs, uint32_t flags, const int* shape, const int* chunk,

@@ -153,3 +153,33 @@ def test_tuned_forward_only():
     assert cp.batched_describe(fields, fwd=True) == d
     check_forward(fields, params, pmin, pmax, "tuned, graph")
     note("tuned plan:", d)
+
+
+def test_plan_shared_by_two_streams():
+    """Calls with the same shapes on two streams, issued back to back with
+    no ordering between the streams: the library orders each call after the
+    plan's last use on the other stream, so no tile queue is shared in flight
+    and every call matches the per-field launches (forward and adjoint)."""
+    note("plan on two streams")
+    dtype = torch.float32
+    fields, params = mixed_fields(18, dtype, n=9)
+    gmin, gmax = upstream(fields, dtype)
+    main = torch.cuda.current_stream()
+    streams = [torch.cuda.Stream(), torch.cuda.Stream()]
+    for s in streams:
+        s.wait_stream(main)  # inputs were written on the main stream
+    results = []
+    for k in range(6):
+        st = streams[k % 2]
+        with torch.cuda.stream(st):
+            pmin, pmax = outputs(fields, dtype)
+            grad = [torch.full_like(p, -1.0) for p in params]
+            cp.batched(fields, params, pmin, pmax, gmin, gmax, grad, graph=(k >= 2))
+        results.append((pmin, pmax, grad))
+    torch.cuda.synchronize()
+    for k, (pmin, pmax, grad) in enumerate(results):
+        check_backward(fields, params, gmin, gmax, grad, f"call {k}")
+        for i, (f, p) in enumerate(zip(fields, params)):
+            a, b = cp.forward(p, f)
+            assert torch.allclose(a, pmin[i], rtol=0, atol=1e-6, equal_nan=True), (k, i)
+            assert torch.allclose(b, pmax[i], rtol=0, atol=1e-6, equal_nan=True), (k, i)
