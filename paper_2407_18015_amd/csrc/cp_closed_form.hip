@@ -37,7 +37,7 @@ __global__ __launch_bounds__(256) void k_bwd_ue(FieldPtrs<T> f, int tiles_x, int
   tile_bwd_ue<T, MODEL, OX, OY, 256>(f, (t / tiles_x) * OY, (t % tiles_x) * OX, lds, threadIdx.x);
 }
 
-// histogram adjoint, pass 1: per-stencil Jacobians into the workspace
+// histogram adjoint, pass 1: per-stencil entries into the workspace
 template <typename T, int TY>
 __global__ __launch_bounds__(kFwdTX* TY) void k_hist_sweep(FieldPtrs<T> f, int tiles_x, int ntiles, T* J) {
   extern __shared__ __align__(16) unsigned char smem[];
@@ -50,22 +50,7 @@ __global__ __launch_bounds__(kFwdTX* TY) void k_hist_sweep(FieldPtrs<T> f, int t
 // and the entries of its four neighbours' stencils that refer to u
 template <typename T>
 __global__ __launch_bounds__(256) void k_hist_gather(FieldPtrs<T> f, const T* __restrict__ J) {
-  const int64_t id = (int64_t)blockIdx.x * 256 + threadIdx.x;
-  const int64_t plane = (int64_t)f.H * f.W;
-  if (id >= plane) return;
-  const int y = (int)(id / f.W), x = (int)(id - (int64_t)y * f.W);
-  const int h = f.nb;
-  const int64_t at = (int64_t)y * f.rs + x;
-  f.grad[at] = T(0);
-  f.grad[f.ps + at] = T(0);
-  for (int k = 0; k < h; ++k) {
-    T g = J[(int64_t)(0 * h + k) * plane + id];
-    if (x + 1 < f.W) g += J[(int64_t)(3 * h + k) * plane + id + 1];
-    if (x > 0) g += J[(int64_t)(1 * h + k) * plane + id - 1];
-    if (y > 0) g += J[(int64_t)(4 * h + k) * plane + id - f.W];
-    if (y + 1 < f.H) g += J[(int64_t)(2 * h + k) * plane + id + f.W];
-    f.grad[(int64_t)(2 + k) * f.ps + at] = g;
-  }
+  hist_gather_vertex<T>(f, J, (int64_t)blockIdx.x * 256 + threadIdx.x);
 }
 
 // ---------------------------------------------------------------------------
@@ -202,7 +187,7 @@ static hipError_t bwd_typed(const Field& f, const void* params, const void* gmin
     else
       return launch_bwd_ue<T, 14, 14>(p, f.model, st);
   }
-  // sweep tiles as in the forward; the Jacobians go through the workspace
+  // sweep tiles as in the forward; the entries go through the workspace
   const size_t per_row = sizeof(T) * (size_t)hist_planes(f.nb) * (kFwdTX + 2);
   if (per_row * 6 <= 64 * 1024) return launch_bwd_hist<T, 4>(p, st, scr);
   if (per_row * 4 <= kMaxLds) return launch_bwd_hist<T, 2>(p, st, scr);

@@ -13,17 +13,19 @@
 // cancellation occurs.
 //
 // Staged per vertex in LDS (planes of the extended tile, E vertices each):
-//   0 lo, 1 hi, 2..h+1 masses.  An invalid histogram (lo >= hi, non-finite,
-// negative mass) is marked by lo = NaN while staging.  The sweeps then
-// replace the masses by their suffix sums U_j = m_j + ... + m_{h-1} (FP64
-// sums rounded once), so the survival at an edge is one read.
+//   0 lo, 1 hi, 2..h+1 masses, h+2 zero.  An invalid histogram (lo >= hi,
+// non-finite, negative mass) is marked by lo = NaN while staging.  The
+// sweeps then replace the masses by their suffix sums U_j = m_j + ... +
+// m_{h-1} (FP64 sums rounded once; U_h = 0 is the zero plane), so the
+// survival at an edge is one read.
 #pragma once
 
 #include "cp_device.hpp"
 
 namespace cp {
 
-__host__ __device__ constexpr int hist_planes(int h) { return h + 2; }
+// staged planes per vertex: lo, hi, h masses (then suffix sums), one zero plane
+__host__ __device__ constexpr int hist_planes(int h) { return h + 3; }
 
 template <typename T>
 struct HistLds {
@@ -77,7 +79,8 @@ CP_HD T bern4(const T (&f0)[4], const T (&f1)[4]) {
 // ---------------------------------------------------------------------------
 namespace cp {
 
-// masses (planes 2..h+1) -> suffix sums U_0 .. U_{h-1}; U_0 = total mass
+// masses (planes 2..h+1) -> suffix sums U_0 .. U_{h-1}; U_0 = total mass;
+// plane h+2 := 0 (U_h)
 template <typename T, int NT>
 CP_HD void hist_stage_suffix(T* lds, int E, int h, int tid) {
   for (int e = tid; e < E; e += NT) {
@@ -86,6 +89,7 @@ CP_HD void hist_stage_suffix(T* lds, int E, int h, int tid) {
       acc += (double)lds[(2 + j) * E + e];
       lds[(2 + j) * E + e] = (T)acc;
     }
+    lds[(2 + h) * E + e] = T(0);
   }
 }
 
@@ -161,6 +165,122 @@ CP_HD void suf_cursor_step(SufCursor<T>& c, const HistSuf<T>& L, int e, T hi, T 
     c.snx = T(0);
     c.slope = T(0);
   }
+}
+
+// ---------------------------------------------------------------------------
+// Branch-free cursor (the adjoint sweep): the same survival function as
+// SufCursor, S(x) = snx + slope (nxt - x) on the current bin, F = tot - S, in
+// a frame where the sweep runs from x = 0.  It holds the index m of its next
+// edge (0 below the range, h + 1 past it) and the LDS index of U_m, clamped
+// to the zero plane; the edges are lo + m Delta for m < h and hi itself for
+// m = h.  Every step is written with selects, so a wave whose lanes cross
+// different edges runs one straight sequence of instructions.  The forward
+// and saddle sweeps keep SufCursor: its branchy steps need fewer registers,
+// and those sweeps gain more from occupancy than from fewer instructions.
+// ---------------------------------------------------------------------------
+template <typename T>
+struct HistCursor {
+  T m;        // index of the next edge (0 below the range, h + 1 past it)
+  int a, az;  // LDS index of U_m, of this vertex's zero plane
+  T nxt;      // next edge (big past the range)
+  T snx;      // U_m: survival at the next edge
+  T slope;    // mass density of the current bin (0 outside the range)
+  T kin;      // 1 / Delta inside the range, 0 outside
+  T tot, lo, hi, d, id;
+};
+
+// `present` false: the constant factor 1 in both products (S = 1, F = 2 - 1)
+template <typename T>
+CP_HD void hist_cursor_init(HistCursor<T>& c, const T* base, int E, int h, int e, T lo, T hi, bool present, T big) {
+  const T hf = T(h);
+  c.lo = lo;
+  c.hi = hi;
+  c.d = (hi - lo) * (T(1) / hf);
+  c.id = hf * crcp(hi - lo);
+  c.az = (2 + h) * E + e;
+  c.slope = c.kin = T(0);
+  if (!present) {
+    c.m = hf + T(1);
+    c.a = c.az;
+    c.nxt = big;
+    c.snx = T(1);
+    c.tot = T(2);
+    return;
+  }
+  c.tot = base[2 * E + e];
+  if (!(hi > T(0))) {  // the whole range lies at or below x = 0
+    c.m = hf + T(1);
+    c.a = c.az;
+    c.nxt = big;
+    c.snx = T(0);
+    return;
+  }
+  if (!(lo < T(0))) {  // range starts at or after x = 0
+    c.m = T(0);
+    c.a = 2 * E + e;
+    c.nxt = lo;
+    c.snx = c.tot;
+    return;
+  }
+  int j = (int)(-lo * c.id);
+  j = j < 0 ? 0 : (j > h - 1 ? h - 1 : j);
+  const auto edge = [&](int k) { return k >= h ? hi : cfma(T(k), c.d, lo); };
+  if (j + 1 < h && !(edge(j + 1) > T(0))) ++j;
+  if (j > 0 && edge(j) > T(0)) --j;
+  c.m = T(j + 1);
+  c.a = (3 + j) * E + e;
+  c.nxt = edge(j + 1);
+  c.snx = base[c.a];
+  c.slope = (base[(2 + j) * E + e] - c.snx) * c.id;
+  c.kin = c.id;
+}
+
+// advance to the next edge where adv
+template <typename T>
+CP_HD void hist_cursor_step(HistCursor<T>& c, const T* base, int E, T hf, T big, bool adv) {
+  const T m1 = c.m + T(1);
+  const int a1 = c.a + E < c.az ? c.a + E : c.az;
+  const T u1 = base[a1];
+  const bool inr = !(m1 > hf);
+  const T nx1 = m1 < hf ? cfma(m1, c.d, c.lo) : (inr ? c.hi : big);
+  const T sl1 = (c.snx - u1) * c.id;
+  const T k1 = inr ? c.id : T(0);
+  c.m = adv ? m1 : c.m;
+  c.a = adv ? a1 : c.a;
+  c.snx = adv ? u1 : c.snx;
+  c.slope = adv ? sl1 : c.slope;
+  c.kin = adv ? k1 : c.kin;
+  c.nxt = adv ? nx1 : c.nxt;
+}
+
+// The vertex's own bins over [0, hv]: bin jv, next edge nv (hv for the last
+// bin, big past it), density pv, U above the bin uv; stepped with selects.
+template <typename T>
+struct VertexBins {
+  int jv;
+  T nv, pv, uv, dv, idv;
+};
+
+template <typename T>
+CP_HD void vertex_bins_init(VertexBins<T>& b, const T* base, int E, int h, int ev, T hv) {
+  b.dv = hv * (T(1) / T(h));
+  b.idv = T(h) * crcp(hv);
+  b.jv = 0;
+  b.nv = h > 1 ? b.dv : hv;
+  b.uv = base[3 * E + ev];
+  b.pv = (base[2 * E + ev] - b.uv) * b.idv;
+}
+
+template <typename T>
+CP_HD void vertex_bins_step(VertexBins<T>& b, const T* base, int E, int h, int ev, T hv, T big, bool adv) {
+  const int jn = b.jv + 1;
+  const T un = base[(jn + 3 < h + 2 ? jn + 3 : h + 2) * E + ev];  // U_{jn+1}
+  const T pn = (b.uv - un) * b.idv;
+  const T nn = jn + 1 < h ? T(jn + 1) * b.dv : (jn + 1 == h ? hv : big);
+  b.jv = adv ? jn : b.jv;
+  b.uv = adv ? un : b.uv;
+  b.pv = adv ? pn : b.pv;
+  b.nv = adv ? nn : b.nv;
 }
 
 // P_min and P_max of vertex ev; neighbour ranges [lo_i, hi_i] in the vertex

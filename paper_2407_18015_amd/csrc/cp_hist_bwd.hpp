@@ -3,10 +3,13 @@
 //
 // One sweep over the vertex range integrates, for both P_min (prod S) and
 // P_max (prod F = T - S), the leave-one-out products of every neighbour and
-// their products with the survival / CDF of the current bin's kernel, and
-// writes each bin's weighted entry when the sweep leaves the bin.  Every
-// sub-interval is integrated with 3-point Gauss-Legendre (integrands of
-// degree <= 4).  Entries of absent neighbours are not written.
+// their products with the survival function of the neighbour's current bin
+// kernel, and emits each bin's weighted entry when the sweep leaves the bin.
+// Every sub-interval is integrated with 3-point Gauss-Legendre (integrands of
+// degree <= 4).  Entries of absent neighbours are not emitted.
+//
+// The sweep tile writes each stencil's entries to a workspace; a second
+// kernel gathers every mass's five entries (no atomics).
 #pragma once
 
 #include "cp_hist.hpp"
@@ -19,126 +22,119 @@ namespace cp {
 //   dP_min/dm_j(v) = (1/Delta_v) int_{bin j of v} prod_n S_n
 //   dP_max/dm_j(v) = (1/Delta_v) int_{bin j of v} prod_n F_n
 //   dP_min/dm_j(n) = QS_n(e_j) + int_{bin j of n} pdf_v Kbar_j prod_{k!=n} S_k
-//   dP_max/dm_j(n) = QF_n(hv) - QF_n(e_{j+1}) + int_{bin j of n} pdf_v K_j prod_{k!=n} F_k
+//   dP_max/dm_j(n) = QF_n(hv) - QF_n(e_j) - int_{bin j of n} pdf_v Kbar_j prod_{k!=n} F_k
 // with QS_n(y) = int_0^y pdf_v prod_{k!=n} S_k, QF_n likewise with F, and
-// Kbar_j = (e_{j+1} - x)/Delta_n, K_j = 1 - Kbar_j the survival / CDF of bin
-// j's kernel.  The sweep writes g_min dP_min + g_max dP_max for a bin when it
-// leaves it, without the g_max QF_n(hv) term, which is known only at the end:
-// then the bins already written receive it (read-modify-write), the open bin
-// and the bins above and below the sweep are written once.
+// Kbar_j = (e_{j+1} - x)/Delta_n the survival function of bin j's kernel
+// (dS_n/dm_j = Kbar_j, dF_n/dm_j = 1 - Kbar_j).  The upstream weights are
+// folded into the accumulators (QS' = g_min QS, QF' = -g_max QF), so the
+// entry of a neighbour bin is B + (1/Delta_n) int_{bin} (e_{j+1} - x)(lS + lF)
+// with B = QS' + QF' at the bin's lower edge; it is emitted when the sweep
+// leaves the bin, without the g_max QF_n(hv) term, which is known only at the
+// end: then the bins already emitted receive it (J.add), the open bin and the
+// bins above and below the sweep are emitted once.  The node weights carry
+// the vertex pdf and the half-length of the sub-interval, so the
+// accumulators run over the whole sweep.
+//
+// Cursors as in the forward (HistCursor, VertexBins, staged layout of
+// cp_hist.hpp); every sub-interval advances the cursors that end it with
+// selects rather than branches.
+//
+// J must provide set(slot, k, value) and add(slot, k, value); slot 0 is the
+// vertex's own histogram, slot 1 + i neighbour i (e, n, w, s).
 // ---------------------------------------------------------------------------
-template <typename T>
+template <typename T, typename JOut>
 __host__ __device__ void hist_jac_both(const HistSuf<T>& L, int ev, const int (&en)[4], const bool (&pres)[4],
-                                       T hv, const T (&lo)[4], const T (&hi)[4], T gmin, T gmax, T* J, int64_t EJ,
-                                       int64_t sj, T& pmin, T& pmax) {
-  const int h = L.h;
-  auto at = [&](int slot, int k) { return (int64_t)(slot * h + k) * EJ + sj; };
+                                       T hv, const T (&lo)[4], const T (&hi)[4], T gmin, T gmax, JOut& J, T& pmin,
+                                       T& pmax) {
+  const int h = L.h, E = L.E;
+  const T* base = L.base;
+  const T hf = T(h);
   const T big = hv + hv + T(1);
-  const T dv = hv * (T(1) / T(h)), idv = T(h) * crcp(hv);
-  int jv = 0;
-  T nv = h > 1 ? dv : hv;
-  T uv = L.U(ev, 1);
-  T pv = (L.U(ev, 0) - uv) * idv;
-  SufCursor<T> c[4];
+  VertexBins<T> vb;
+  vertex_bins_init(vb, base, E, h, ev, hv);
+  HistCursor<T> c[4];
   int first[4];
 #pragma unroll
   for (int i = 0; i < 4; ++i) {
-    suf_cursor_init(c[i], L, en[i], lo[i], hi[i], pres[i], big);
-    first[i] = c[i].j < 0 ? 0 : c[i].j;  // first bin the sweep enters
+    hist_cursor_init(c[i], base, E, h, en[i], lo[i], hi[i], pres[i], big);
+    const int j = (int)c[i].m - 1;
+    first[i] = j < 0 ? 0 : j;  // first bin the sweep enters
   }
-  T QS[4] = {T(0), T(0), T(0), T(0)}, QF[4] = {T(0), T(0), T(0), T(0)};
-  T QSin[4] = {T(0), T(0), T(0), T(0)};  // QS at the lower edge of the current bin
-  T cS[4] = {T(0), T(0), T(0), T(0)}, cF[4] = {T(0), T(0), T(0), T(0)};
+  T QS[4], QF[4], B[4], Eh[4];
+#pragma unroll
+  for (int i = 0; i < 4; ++i) QS[i] = QF[i] = B[i] = Eh[i] = T(0);
   T vS = T(0), vF = T(0), amin = T(0), amax = T(0);
   T x0 = T(0);
   const int maxit = 5 * (h + 1) + 2;
   for (int it = 0; it < maxit; ++it) {
     if (!(x0 < hv)) break;
-    T x1 = nv;
+    T x1 = vb.nv;
 #pragma unroll
     for (int i = 0; i < 4; ++i) x1 = tmin(x1, c[i].nxt);
     const T mid = (x0 + x1) * T(0.5), hl = (x1 - x0) * T(0.5);
-    T fs = T(0), ff = T(0), ls[4], lf[4], ks[4], kf[4];
-    T kin[4];
-#pragma unroll
-    for (int i = 0; i < 4; ++i) {
-      ls[i] = lf[i] = ks[i] = kf[i] = T(0);
-      kin[i] = (c[i].j >= 0 && c[i].j < h) ? c[i].id : T(0);
-    }
+    const T php = vb.pv * hl, wS = php * gmin, wF = -php * gmax;
 #pragma unroll
     for (int q = 0; q < 3; ++q) {
       const T x = cfma(hl, T(GL<3>::x[q]), mid);
-      const T w = T(GL<3>::w[q]);
-      T S[4], F[4], K[4];
+      const T wv = T(GL<3>::w[q]) * hl, wnS = T(GL<3>::w[q]) * wS, wnF = T(GL<3>::w[q]) * wF;
+      T S[4], F[4], r[4];
 #pragma unroll
       for (int i = 0; i < 4; ++i) {
-        const T r = c[i].nxt - x;
-        S[i] = cfma(c[i].slope, r, c[i].snx);
+        r[i] = c[i].nxt - x;
+        S[i] = cfma(c[i].slope, r[i], c[i].snx);
         F[i] = c[i].tot - S[i];
-        K[i] = r * kin[i];  // Kbar inside the current bin, 0 outside
       }
       const T s01 = S[0] * S[1], s23 = S[2] * S[3], f01 = F[0] * F[1], f23 = F[2] * F[3];
-      fs = cfma(w, s01 * s23, fs);
-      ff = cfma(w, f01 * f23, ff);
-      const T wls[4] = {w * (S[1] * s23), w * (S[0] * s23), w * (s01 * S[3]), w * (s01 * S[2])};
-      const T wlf[4] = {w * (F[1] * f23), w * (F[0] * f23), w * (f01 * F[3]), w * (f01 * F[2])};
+      vS = cfma(wv * s01, s23, vS);
+      vF = cfma(wv * f01, f23, vF);
+      const T ps01 = wnS * s01, ps23 = wnS * s23, pf01 = wnF * f01, pf23 = wnF * f23;
+      const T ls[4] = {S[1] * ps23, S[0] * ps23, S[3] * ps01, S[2] * ps01};
+      const T lf[4] = {F[1] * pf23, F[0] * pf23, F[3] * pf01, F[2] * pf01};
 #pragma unroll
       for (int i = 0; i < 4; ++i) {
-        ls[i] += wls[i];
-        lf[i] += wlf[i];
-        ks[i] = cfma(wls[i], K[i], ks[i]);
-        // K = 1 - Kbar inside the bin: kf accumulates wlf (K) as (inbin ? wlf - wlf Kbar : 0)
-        kf[i] = kin[i] != T(0) ? cfma(-wlf[i], K[i], kf[i] + wlf[i]) : kf[i];
+        QS[i] += ls[i];
+        QF[i] += lf[i];
+        Eh[i] = cfma(ls[i] + lf[i], r[i], Eh[i]);
       }
     }
-    const T php = pv * hl;
-    amin = cfma(php, fs, amin);
-    amax = cfma(php, ff, amax);
-    vS = cfma(hl, fs, vS);
-    vF = cfma(hl, ff, vF);
+    // vertex bin boundary: its entry is complete
+    const bool advv = vb.nv == x1;
+    if (advv && vb.jv < h) J.set(0, vb.jv, (gmin * vS + gmax * vF) * vb.idv);
+    amin = advv ? cfma(vb.pv, vS, amin) : amin;
+    amax = advv ? cfma(vb.pv, vF, amax) : amax;
+    vS = advv ? T(0) : vS;
+    vF = advv ? T(0) : vF;
+    vertex_bins_step(vb, base, E, h, ev, hv, big, advv);
+    // neighbour bin boundaries
 #pragma unroll
     for (int i = 0; i < 4; ++i) {
-      QS[i] = cfma(php, ls[i], QS[i]);
-      QF[i] = cfma(php, lf[i], QF[i]);
-      cS[i] = cfma(php, ks[i], cS[i]);
-      cF[i] = cfma(php, kf[i], cF[i]);
-    }
-    if (nv == x1) {  // vertex bin boundary: its entry is complete
-      if (jv < h) J[at(0, jv)] = (gmin * vS + gmax * vF) * idv;
-      vS = vF = T(0);
-      ++jv;
-      const T un = L.U(ev, jv + 1);
-      pv = (uv - un) * idv;
-      uv = un;
-      nv = jv + 1 < h ? T(jv + 1) * dv : (jv + 1 == h ? hv : big);
-    }
-#pragma unroll
-    for (int i = 0; i < 4; ++i) {  // neighbour bin boundaries
-      if (!(c[i].nxt == x1)) continue;
-      const int jo = c[i].j;
-      if (jo >= 0 && jo < h) J[at(1 + i, jo)] = gmin * (QSin[i] + cS[i]) + gmax * (cF[i] - QF[i]);
-      QSin[i] = QS[i];
-      cS[i] = cF[i] = T(0);
-      suf_cursor_step(c[i], L, en[i], hi[i], x1, big);
+      const bool adv = c[i].nxt == x1;
+      // bin m - 1 is left; it is a bin of the range for 1 <= m <= h
+      if (adv && c[i].kin != T(0)) J.set(1 + i, (int)c[i].m - 1, cfma(c[i].kin, Eh[i], B[i]));
+      B[i] = adv ? QS[i] + QF[i] : B[i];
+      Eh[i] = adv ? T(0) : Eh[i];
+      hist_cursor_step(c[i], base, E, hf, big, adv);
     }
     x0 = x1;
   }
   // remaining vertex bins (the sweep ended inside or past them): no range
-  for (int k = jv; k < h; ++k) J[at(0, k)] = (k == jv) ? (gmin * vS + gmax * vF) * idv : T(0);
+  for (int k = vb.jv; k < h; ++k) J.set(0, k, (k == vb.jv) ? (gmin * vS + gmax * vF) * vb.idv : T(0));
+  amin = cfma(vb.pv, vS, amin);
+  amax = cfma(vb.pv, vF, amax);
 #pragma unroll
   for (int i = 0; i < 4; ++i) {
     if (!pres[i]) continue;
-    const int j = c[i].j;  // open bin (h: past the range)
-    const T tf = gmax * QF[i];
+    const int j = (int)c[i].m - 1;  // open bin (-1: below the range, h: past it)
+    const T tf = -QF[i];            // g_max QF_n(hv)
     for (int k = 0; k < h; ++k) {
       if (k < first[i]) {
-        J[at(1 + i, k)] = tf;  // entirely below the sweep: F = 1 there
+        J.set(1 + i, k, tf);  // entirely below the sweep: dF/dm = 1 there
       } else if (k < j) {
-        J[at(1 + i, k)] += tf;  // written when the sweep left it
+        J.add(1 + i, k, tf);  // emitted when the sweep left it
       } else if (k == j) {
-        J[at(1 + i, k)] = gmin * (QSin[i] + cS[i]) + gmax * cF[i];
+        J.set(1 + i, k, cfma(c[i].kin, Eh[i], B[i]) + tf);
       } else {
-        J[at(1 + i, k)] = gmin * QS[i];  // entirely above the sweep: S = 1 there
+        J.set(1 + i, k, QS[i]);  // entirely above the sweep: dS/dm = 1 there
       }
     }
   }
@@ -146,12 +142,24 @@ __host__ __device__ void hist_jac_both(const HistSuf<T>& L, int ev, const int (&
   pmax = amax;
 }
 
-// Both sides of one stencil (centre e in the staged tile, grid position
-// (gy, gx)) into J; returns the probabilities; an invalid stencil writes NaN.
+// Entries of one stencil stored at J[(slot * h + k) * EJ + sj] (the layout
+// of a per-stencil Jacobian array, used by the host-side checks).
 template <typename T>
+struct JPlanes {
+  T* J;
+  int64_t EJ, sj;
+  int h;
+  CP_HD void set(int slot, int k, T v) const { J[(int64_t)(slot * h + k) * EJ + sj] = v; }
+  CP_HD void add(int slot, int k, T v) const { J[(int64_t)(slot * h + k) * EJ + sj] += v; }
+};
+
+// Both sides of one stencil (centre e in the staged tile, grid position
+// (gy, gx)) into J; returns the probabilities; an invalid stencil emits NaN
+// for its own bins and those of its present neighbours.
+template <typename T, typename JOut>
 __host__ __device__ void hist_stencil_jac(const HistLds<T>& L, const HistSuf<T>& U, const T* par, int EP, int PX,
-                                          int e, int gy, int gx, int H, int W, T gmin, T gmax, T* J, int64_t EJ,
-                                          int64_t sj, T& pmin, T& pmax) {
+                                          int e, int gy, int gx, int H, int W, T gmin, T gmax, JOut& J, T& pmin,
+                                          T& pmax) {
   const int h = L.h;
   const int en[4] = {e + 1, e - PX, e - 1, e + PX};
   const bool pres[4] = {gx + 1 < W, gy > 0, gx > 0, gy + 1 < H};
@@ -159,11 +167,11 @@ __host__ __device__ void hist_stencil_jac(const HistLds<T>& L, const HistSuf<T>&
 #pragma unroll
   for (int k = 0; k < 4; ++k) ok = ok && (!pres[k] || L.valid(en[k]));
   if (!ok) {
-    for (int k = 0; k < h; ++k) J[(int64_t)k * EJ + sj] = qnan<T>();
+    for (int k = 0; k < h; ++k) J.set(0, k, qnan<T>());
 #pragma unroll
     for (int i = 0; i < 4; ++i)
       if (pres[i])
-        for (int k = 0; k < h; ++k) J[(int64_t)((1 + i) * h + k) * EJ + sj] = qnan<T>();
+        for (int k = 0; k < h; ++k) J.set(1 + i, k, qnan<T>());
     pmin = pmax = qnan<T>();
     return;
   }
@@ -174,14 +182,16 @@ __host__ __device__ void hist_stencil_jac(const HistLds<T>& L, const HistSuf<T>&
     lo[k] = par[en[k]] - lov;
     hi[k] = par[EP + en[k]] - lov;
   }
-  hist_jac_both(U, e, en, pres, hiv - lov, lo, hi, gmin, gmax, J, EJ, sj, pmin, pmax);
+  hist_jac_both(U, e, en, pres, hiv - lov, lo, hi, gmin, gmax, J, pmin, pmax);
 }
 
-// Sweep tile for the per-field adjoint: 64 x TY stencils (params staged with a
-// one-vertex halo), Jacobians written to the workspace J ([5][h][H][W]); a
-// gather kernel then adds the five entries of every parameter.  If f.pmin is
-// non-null the probabilities are written too (fused forward + adjoint).  NT
-// threads; each takes the rows ly, ly + NT/64, ... of its column.
+// Sweep tile of the adjoint: 64 x TY stencils (params staged with a
+// one-vertex halo), entries written to the workspace J
+// ([5][h][H][W]: one plane per slot and bin, so the lanes of a wave that
+// emit the same entry write consecutive words); a gather kernel then adds the
+// five entries of every parameter.  If f.pmin is non-null the probabilities
+// are written too (fused forward + adjoint).  NT threads; each takes the rows
+// ly, ly + NT/64, ... of its column.
 template <typename T, int TY, int NT = kFwdTX * TY>
 __device__ __forceinline__ void tile_hist_sweep(const FieldPtrs<T>& f, int ty0, int tx0, T* lds, int tid, T* J) {
   constexpr int TX = kFwdTX, EX = TX + 2, EY = TY + 2, E = EX * EY;
@@ -189,7 +199,6 @@ __device__ __forceinline__ void tile_hist_sweep(const FieldPtrs<T>& f, int ty0, 
   const int h = f.nb;
   stage<T, EY, EX, NT>(lds, f.params, 2 + h, f.ps, f.rs, f.H, f.W, ty0 - 1, tx0 - 1, tid);
   __syncthreads();
-  // validity, then masses -> suffix sums (the same thread owns each staged vertex)
   hist_stage_validity<T, NT>(lds, E, h, tid);
   hist_stage_suffix<T, NT>(lds, E, h, tid);
   __syncthreads();
@@ -200,10 +209,11 @@ __device__ __forceinline__ void tile_hist_sweep(const FieldPtrs<T>& f, int ty0, 
       const HistLds<T> L{lds, E, h, T(1) / T(h)};
       const HistSuf<T> U{lds, E, h};
       const int64_t at = (int64_t)y * f.rs + x;
-      const int64_t plane = (int64_t)f.H * f.W;
+      const int64_t sj = (int64_t)y * f.W + x;
       T pmin, pmax;
-      hist_stencil_jac(L, U, lds, E, EX, (ly + 1) * EX + lx + 1, y, x, f.H, f.W, f.gmin[at], f.gmax[at], J, plane,
-                       (int64_t)y * f.W + x, pmin, pmax);
+      JPlanes<T> Jo{J, (int64_t)f.H * f.W, sj, h};
+      hist_stencil_jac(L, U, lds, E, EX, (ly + 1) * EX + lx + 1, y, x, f.H, f.W, f.gmin[at], f.gmax[at], Jo, pmin,
+                       pmax);
       if (f.pmin) {
         f.pmin[at] = pmin;
         f.pmax[at] = pmax;
@@ -211,6 +221,29 @@ __device__ __forceinline__ void tile_hist_sweep(const FieldPtrs<T>& f, int ty0, 
     }
   }
   __syncthreads();
+}
+
+// gather of the two-kernel adjoint: every mass of u adds its own stencil's
+// entry and the entries of its four neighbours' stencils that refer to u
+// (own, east's w slot, west's e slot, north's s slot, south's n slot)
+template <typename T>
+__device__ __forceinline__ void hist_gather_vertex(const FieldPtrs<T>& f, const T* __restrict__ J, int64_t id) {
+  const int64_t plane = (int64_t)f.H * f.W;
+  if (id >= plane) return;
+  const int y = (int)(id / f.W), x = (int)(id - (int64_t)y * f.W);
+  const int h = f.nb;
+  const int64_t at = (int64_t)y * f.rs + x;
+  f.grad[at] = T(0);
+  f.grad[f.ps + at] = T(0);
+  const auto e = [&](int64_t v, int slot, int k) { return J[(int64_t)(slot * h + k) * plane + v]; };
+  for (int k = 0; k < h; ++k) {
+    T g = e(id, 0, k);
+    if (x + 1 < f.W) g += e(id + 1, 3, k);
+    if (x > 0) g += e(id - 1, 1, k);
+    if (y > 0) g += e(id - f.W, 4, k);
+    if (y + 1 < f.H) g += e(id + f.W, 2, k);
+    f.grad[(int64_t)(2 + k) * f.ps + at] = g;
+  }
 }
 
 }  // namespace cp

@@ -86,6 +86,7 @@ template <typename T>
 void run_hist(const std::vector<double>& p, const std::vector<double>& gmin, const std::vector<double>& gmax, int H,
               int W, int h, std::vector<double>& out) {
   Grid<T> g = padded<T>(p, 2 + h, H, W, h);
+  g.par.resize((size_t)(3 + h) * g.E, T(0));  // zero plane after the suffix sums (U_h)
   cp::hist_stage_validity<T, 1>(g.par.data(), g.E, h, 0);
   std::vector<T> raw = g.par;  // validity-marked masses (for the Jacobian routine)
   cp::hist_stage_suffix<T, 1>(g.par.data(), g.E, h, 0);
@@ -114,8 +115,8 @@ void run_hist(const std::vector<double>& p, const std::vector<double>& gmin, con
       out[v] = (double)pmin;
       out[nv + v] = (double)pmax;
       T a, b;
-      cp::hist_stencil_jac(L, U, g.par.data(), g.E, g.PX, e, y, x, H, W, (T)gmin[v], (T)gmax[v], J.data(),
-                           (int64_t)nv, (int64_t)v, a, b);
+      cp::JPlanes<T> jp{J.data(), (int64_t)nv, (int64_t)v, h};
+      cp::hist_stencil_jac(L, U, g.par.data(), g.E, g.PX, e, y, x, H, W, (T)gmin[v], (T)gmax[v], jp, a, b);
     }
   for (int y = 0; y < H; ++y)
     for (int x = 0; x < W; ++x) {
