@@ -25,11 +25,15 @@ import numpy as np
 
 METRIC = "vertex-probabilities/s (fwd, fwd+bwd) per model; batched vs plain at 1e-6 abs err"
 UNIT = "vertex-probabilities/s"
-# FP32 vector peak reachable without packed FP32 (v_pk_* is not generated on
-# this platform): 256 CUs x 64 lanes x 2 FLOP (FMA) x 2.4 GHz.  The published
-# 157.3 TFLOP/s counts the packed two-wide FMA.
-PEAK_FP32_VALU = 256 * 64 * 2 * 2.4e9
-PEAK_FP32_PACKED = 157.3e12
+# MI355X published FP32 vector peak.  No packed FP32 instruction is
+# generated here, and yet plain FMAs reach it within ~15% when a wave has
+# eight or more independent FMAs in flight (the FMA probe of libcpprobes.so,
+# measured in every run: `detail.ceilings.fp32_fma_tflops_by_chains`); with
+# four or fewer the rate stays near 256 CUs x 64 lanes x 2 x 2.4 GHz =
+# 78.6 TFLOP/s, the single-issue rate, reported beside it.
+PEAK_FP32 = 157.3e12
+RATE_FP32_SINGLE_ISSUE = 256 * 64 * 2 * 2.4e9
+PEAK_HBM = 8e12
 
 # HBM bytes of one launch of the Epanechnikov FP32 adjoint at 2048^2, from
 # two rocprofv3 --pmc passes (FETCH_SIZE, WRITE_SIZE, KiB per dispatch) over
@@ -102,41 +106,174 @@ def flops_bwd_piece(k):
     return 6 + 7 * k + GL_NODES[k] * (4 + 15 * k)
 
 
-def epa_piece_counts(params: np.ndarray) -> np.ndarray:
+def _torch(a):
+    import torch
+    return a if isinstance(a, torch.Tensor) else torch.as_tensor(np.asarray(a))
+
+
+def _nbrs(a, fill=float("nan")):
+    """e, n, w, s neighbour planes of a [H, W] tensor (`fill` outside the grid)."""
+    import torch
+    p = torch.nn.functional.pad(a[None, None], (1, 1, 1, 1), value=fill)[0, 0]
+    return [p[1:-1, 2:], p[:-2, 1:-1], p[1:-1, :-2], p[2:, 1:-1]]
+
+
+def _side_pieces(lower, bmin, starts):
+    """Non-empty pieces by started-neighbour count of one side: support from
+    `lower`, end bmin, clamped neighbour starts (absent: bmin)."""
+    import torch
+    c = torch.sort(torch.stack(starts), dim=0).values
+    ok = bmin > lower
+    edges = torch.cat([lower[None], c, bmin[None]])
+    return np.array([int(((edges[k + 1] > edges[k]) & ok).sum()) for k in range(5)], dtype=np.int64)
+
+
+def epa_piece_counts(params) -> np.ndarray:
     """counts[k] = number of non-empty pieces with k started neighbours over
     all vertices and both sides (minimum, and maximum by reflection)."""
-    m = params[0].astype(np.float64)
-    w = params[1].astype(np.float64)
-    H, W = m.shape
+    import torch
+    p = _torch(params).to(torch.float64)
+    m, w = p[0], p[1]
+    mn, wn = _nbrs(m), _nbrs(w)
     counts = np.zeros(5, dtype=np.int64)
-    pad = lambda a, v: np.pad(a, 1, constant_values=v)
-    mp, wp = pad(m, np.nan), pad(w, np.nan)
-    nbr = [(mp[1:-1, 2:], wp[1:-1, 2:]), (mp[:-2, 1:-1], wp[:-2, 1:-1]), (mp[1:-1, :-2], wp[1:-1, :-2]),
-           (mp[2:, 1:-1], wp[2:, 1:-1])]
     for sign in (1.0, -1.0):
-        bmin = w.copy()
-        starts = []
-        for mn, wn in nbr:
-            d = sign * (mn - m)
-            pres = np.isfinite(d)
-            bmin = np.where(pres, np.minimum(bmin, d + wn), bmin)
-        for mn, wn in nbr:
-            d = sign * (mn - m)
-            pres = np.isfinite(d)
-            starts.append(np.where(pres, np.clip(d - wn, -w, bmin), bmin))
-        c = np.sort(np.stack(starts), axis=0)
-        ok = bmin > -w
-        edges = np.concatenate([-w[None], c, bmin[None]])
-        for k in range(5):
-            counts[k] += int(np.count_nonzero(ok & (edges[k + 1] > edges[k])))
+        d = [sign * (x - m) for x in mn]
+        bmin = w.clone()
+        for di, wi in zip(d, wn):
+            bmin = torch.where(torch.isfinite(di), torch.minimum(bmin, di + wi), bmin)
+        starts = [torch.where(torch.isfinite(di), torch.minimum(torch.maximum(di - wi, -w), bmin), bmin)
+                  for di, wi in zip(d, wn)]
+        counts += _side_pieces(-w, bmin, starts)
     return counts
 
 
-def epa_flops(params: np.ndarray):
+def uni_piece_counts(params) -> np.ndarray:
+    """As epa_piece_counts for the uniform model: vertex support [0, Lv]
+    from its lower end (minimum) or reflected from its upper end (maximum)."""
+    import torch
+    p = _torch(params).to(torch.float64)
+    lo, hi = p[0], p[1]
+    lon, hin = _nbrs(lo), _nbrs(hi)
+    zero = torch.zeros_like(lo)
+    counts = np.zeros(5, dtype=np.int64)
+    for side in (0, 1):
+        a = [(ln - lo) if side == 0 else (hi - hn) for ln, hn in zip(lon, hin)]
+        b = [(hn - lo) if side == 0 else (hi - ln) for ln, hn in zip(lon, hin)]
+        bmin = hi - lo
+        for bi in b:
+            bmin = torch.where(torch.isfinite(bi), torch.minimum(bmin, bi), bmin)
+        starts = [torch.where(torch.isfinite(ai), torch.minimum(torch.maximum(ai, zero), bmin), bmin) for ai in a]
+        counts += _side_pieces(zero, bmin, starts)
+    return counts
+
+
+def hist_interval_count(params, nbins: int, rows: int = 128) -> int:
+    """Sub-intervals the histogram sweep integrates, over all vertices: per
+    vertex 1 + the number of distinct bin edges of the five histograms
+    strictly inside the vertex range (vertex frame, FP32 as in the kernel)."""
+    import torch
+    p = _torch(params).to(torch.float32)
+    lo, hi = p[0], p[1]
+    lon, hin = _nbrs(lo), _nbrs(hi)
+    H = lo.shape[0]
+    k = torch.arange(nbins + 1, dtype=torch.float32, device=lo.device)
+    kv = torch.arange(1, nbins, dtype=torch.float32, device=lo.device)
+    total = 0
+    for r0 in range(0, H, rows):
+        r1 = min(H, r0 + rows)
+        lv, hv = lo[r0:r1].reshape(-1), (hi[r0:r1] - lo[r0:r1]).reshape(-1)
+        cols = [kv[None, :] * (hv * (1.0 / nbins))[:, None]]
+        for ln, hn in zip(lon, hin):
+            a = ln[r0:r1].reshape(-1) - lv
+            b = hn[r0:r1].reshape(-1) - lv
+            cols.append(a[:, None] + k[None, :] * ((b - a) * (1.0 / nbins))[:, None])
+        e = torch.cat(cols, dim=1)
+        e = torch.where((e > 0) & (e < hv[:, None]), e, torch.full_like(e, float("inf")))
+        e = torch.sort(e, dim=1).values
+        fin = torch.isfinite(e)
+        new = fin.clone()
+        new[:, 1:] &= e[:, 1:] != e[:, :-1]
+        valid = hv > 0
+        total += int(((new.sum(dim=1) + 1) * valid).sum())
+    return total
+
+
+def epa_flops(params):
     c = epa_piece_counts(params)
     fwd = sum(int(c[k]) * flops_fwd_piece(k) for k in range(5))
     bwd = sum(int(c[k]) * flops_bwd_piece(k) for k in range(5)) + 8 * params.shape[1] * params.shape[2]
     return fwd, bwd, c
+
+
+# ----------------------------------------------------------------------------
+# uniform model, same convention (uni_piece / uni_piece_grad): a piece with k
+# started neighbours is integrated exactly with 1, 2, 2, 3 nodes (k = 1..4).
+#   forward piece k:  setup 4 + 3k (midpoint, half-length, per factor slope
+#                     and offset); per node 3k + 1 (k factors, product,
+#                     weighted sum); 2 to scale and accumulate.  Piece 0: 0.
+#   adjoint piece k:  setup 4 + 3k; per node 7k (factors, prefix and suffix
+#                     products, full product, k leave-one-out products
+#                     accumulated); 1 + 2k to scale and accumulate.
+#   adjoint per vertex: 2 x 27 (each side's sums of the active integrals and
+#                     the lo / hi / width partials), 30 to weight the ten
+#                     Jacobian entries by g_min / g_max, 8 for the gather.
+# ----------------------------------------------------------------------------
+UNI_NODES = {1: 1, 2: 2, 3: 2, 4: 3}
+UNI_BWD_VERTEX = 2 * 27 + 30 + 8
+
+
+def flops_uni_fwd_piece(k):
+    return 0 if k == 0 else 6 + 3 * k + UNI_NODES[k] * (3 * k + 1)
+
+
+def flops_uni_bwd_piece(k):
+    return 0 if k == 0 else 5 + 5 * k + UNI_NODES[k] * 7 * k
+
+
+def uni_flops(params):
+    c = uni_piece_counts(params)
+    nv = params.shape[1] * params.shape[2]
+    fwd = sum(int(c[k]) * flops_uni_fwd_piece(k) for k in range(5)) + 2 * nv
+    bwd = sum(int(c[k]) * flops_uni_bwd_piece(k) for k in range(5)) + UNI_BWD_VERTEX * nv
+    return fwd, bwd, c
+
+
+# ----------------------------------------------------------------------------
+# histogram model (cp_hist.hpp, cp_hist_bwd.hpp), per sub-interval of the
+# merged sweep (both sides at once):
+#   forward 88:  end values of the four survival functions (12) and CDFs
+#                (4), interval weight (2), two exact integrals of a product
+#                of four linear factors from their end values (2 x 31), two
+#                accumulations (4), advancing the edge that ends it (4).
+#   adjoint 206: midpoint, half-length and node-weight scales (7); per
+#                Gauss-Legendre node (3) 63 (node, weights, four S and F
+#                values, pair products, vertex-slot sums, upstream-weighted
+#                leave-one-out products for both sides and their plain and
+#                bin-kernel-weighted sums); 10 to emit the entry of the edge
+#                that ends it and advance that edge.  Per vertex 9h: the
+#                closing pass over each neighbour's bins and the gather of
+#                five stencils' entries.
+# ----------------------------------------------------------------------------
+HIST_FWD_INTERVAL = 88
+HIST_BWD_INTERVAL = 206
+
+
+def hist_flops(params, nbins: int):
+    n = hist_interval_count(params, nbins)
+    nv = params.shape[1] * params.shape[2]
+    return HIST_FWD_INTERVAL * n, HIST_BWD_INTERVAL * n + 9 * nbins * nv, n
+
+
+def roofline(bound: str, work: float, seconds: float, peak: float, unit: str, **extra) -> dict:
+    """One roofline object: `work` algorithmic FLOPs (or bytes, or samples)
+    per launch over the launch time, against `peak` (same unit per second,
+    scaled by 1e12 for TFLOP/s and TB/s)."""
+    scale = {"TFLOP/s": 1e12, "TB/s": 1e12, "GB/s": 1e9, "G samples/s": 1e9}[unit]
+    achieved = work / seconds / scale
+    out = {"bound": bound, "achieved": achieved, "peak": peak / scale, "unit": unit, "frac": achieved * scale / peak,
+           "work_per_launch": work, "launch_us": seconds * 1e6}
+    out.update(extra)
+    return out
 
 
 # ----------------------------------------------------------------------------
@@ -223,17 +360,22 @@ def main():
     t_pipe = pipelined_step(cp, torch, mem, E, f, params, pmin, pmax, gmin, gmax, grad, reps)
     t_cls = timed(lambda: cp.classify(params, f), reps)
     t_sad = timed(lambda: cp.classify(params, f, outputs=("saddle",)), reps)
-    ph = params.cpu().numpy()
-    fl_fwd, fl_bwd, counts = epa_flops(ph)
+    fl_fwd, fl_bwd, counts = epa_flops(params)
     achieved = fl_bwd / (t_bwd * 1e-3)
     roof = {"bound": "alu", "kernel": "adjoint, Epanechnikov FP32 (k_bwd_ue<float,1,30,30>)",
-            "achieved": achieved / 1e12, "peak": PEAK_FP32_VALU / 1e12, "unit": "TFLOP/s",
-            "frac": achieved / PEAK_FP32_VALU, "traffic": adjoint_traffic(S),
+            "achieved": achieved / 1e12, "peak": PEAK_FP32 / 1e12, "unit": "TFLOP/s",
+            "frac": achieved / PEAK_FP32, "traffic": adjoint_traffic(S),
             "algorithmic_flops_per_launch": fl_bwd, "launch_us": t_bwd * 1e3,
-            "peak_packed": PEAK_FP32_PACKED / 1e12, "frac_packed": achieved / PEAK_FP32_PACKED,
+            "single_issue_rate": RATE_FP32_SINGLE_ISSUE / 1e12,
+            "frac_of_single_issue_rate": achieved / RATE_FP32_SINGLE_ISSUE,
             "algorithmic_bytes_per_launch": 24 * S * S}
+    ceil = probe_ceilings(torch, dev)
     detail = {
+        "ceilings": ceil,
         "epanechnikov_2048": {
+            "roofline_fwd": roofline("alu", fl_fwd, t_fwd * 1e-3, PEAK_FP32, "TFLOP/s"),
+            "roofline_bwd": roofline("alu", fl_bwd, t_bwd * 1e-3, PEAK_FP32, "TFLOP/s"),
+            "roofline_fit": roofline("hbm", (20 * 4 + 8) * S * S, t_fit * 1e-3, PEAK_HBM, "TB/s"),
             "fit_ms": t_fit, "fwd_ms": t_fwd, "bwd_ms": t_bwd,
             "fwd_vertices_per_s": S * S / (t_fwd * 1e-3),
             "fwd_bwd_vertices_per_s": S * S / ((t_fwd + t_bwd) * 1e-3),
@@ -246,7 +388,7 @@ def main():
         }
     }
     if not args.no_detail:
-        detail.update(more_detail(cp, workloads, torch, dev, S, reps))
+        detail.update(more_detail(cp, workloads, torch, dev, S, reps, ceil))
 
     cpu = None
     if not args.no_cpu_baseline:
@@ -299,7 +441,40 @@ def pipelined_step(cp, torch, mem, model, f, params, pmin, pmax, gmin, gmax, gra
     return a.elapsed_time(z) / reps
 
 
-def more_detail(cp, workloads, torch, dev, S, reps):
+def probe_ceilings(torch, dev):
+    """Ceilings measured in this run by the probes of libcpprobes.so: the
+    random-number and transcendental work of the conditional Monte Carlo
+    estimator at its benchmark shape (1024^2 vertices x 4096 samples, one
+    wave per vertex), FP32 FMA issue, and a 1 GiB + 1 GiB streaming copy."""
+    import ctypes
+    path = os.path.join(os.path.dirname(os.path.abspath(__file__)), "paper_2407_18015_amd", "libcpprobes.so")
+    lib = ctypes.CDLL(path)
+    P = ctypes.c_void_p
+    lib.cpb_mc_ceiling.argtypes = [ctypes.c_int, ctypes.c_int, ctypes.c_uint64, ctypes.c_uint32, ctypes.c_int, P, P]
+    lib.cpb_fma_peak.argtypes = [ctypes.c_int, ctypes.c_int, ctypes.c_int, P, P]
+    lib.cpb_copy.argtypes = [ctypes.c_int64, P, P, P]
+    st = torch.cuda.current_stream().cuda_stream
+    n, ns = 1024 * 1024, 4096
+    out = torch.empty((n, 2), dtype=torch.float64, device=dev)
+    t_mc = _timed(torch, lambda: lib.cpb_mc_ceiling(n, ns, 1, 3, 0, out.data_ptr(), st), 3)
+    t_mcp = _timed(torch, lambda: lib.cpb_mc_ceiling(n, ns, 1, 3, 1, out.data_ptr(), st), 3)
+    blocks, iters = 256 * 32, 2048
+    fo = torch.empty(blocks * 256, device=dev)
+    fma = {}
+    for c in (1, 2, 4, 8, 16):
+        t = _timed(torch, lambda: lib.cpb_fma_peak(blocks, iters * 8 // c, c, fo.data_ptr(), st), 5)
+        fma[c] = blocks * 256 * 8 * iters * 2 / (t * 1e-3) / 1e12
+    src = torch.ones(1 << 28, device=dev)
+    dst = torch.empty_like(src)
+    t_cp = _timed(torch, lambda: lib.cpb_copy(src.numel() // 4, src.data_ptr(), dst.data_ptr(), st), 10)
+    del src, dst
+    return {"mc_samples_per_s": n * ns / (t_mc * 1e-3), "mc_ms": t_mc,
+            "mc_pdf_samples_per_s": n * ns / (t_mcp * 1e-3), "mc_pdf_ms": t_mcp,
+            "fp32_fma_tflops_by_chains": fma, "fp32_fma_tflops": max(fma.values()),
+            "copy_tbs": 2 * 4 * (1 << 28) / (t_cp * 1e-3) / 1e12}
+
+
+def more_detail(cp, workloads, torch, dev, S, reps, ceil):
     res = {}
     # uniform FP64 64x64
     p = torch.as_tensor(workloads.uniform_params_field(0, 64, 64), device=dev)
@@ -322,9 +497,17 @@ def more_detail(cp, workloads, torch, dev, S, reps):
         tb = _timed(torch, lambda: cp.backward(params, g1, g2, f, grad), max(3, reps // 2))
         tc = _timed(torch, lambda: cp.classify(params, f), reps)
         ts = _timed(torch, lambda: cp.classify(params, f, outputs=("saddle",)), reps)
+        if model == 2:
+            ff, fb, nint = hist_flops(params, nb)
+            work = {"intervals": nint}
+        else:
+            ff, fb, cnt = uni_flops(params)
+            work = {"pieces_by_started_neighbours": cnt.tolist()}
         res[name] = {"fwd_ms": tf, "bwd_ms": tb, "classify_ms": tc, "saddle_ms": ts,
                      "fwd_vertices_per_s": S * S / (tf * 1e-3),
-                     "fwd_bwd_vertices_per_s": S * S / ((tf + tb) * 1e-3)}
+                     "fwd_bwd_vertices_per_s": S * S / ((tf + tb) * 1e-3),
+                     "roofline_fwd": roofline("alu", ff, tf * 1e-3, PEAK_FP32, "TFLOP/s"),
+                     "roofline_bwd": roofline("alu", fb, tb * 1e-3, PEAK_FP32, "TFLOP/s"), **work}
         if model == 2:
             # semianalytical estimator (Sec. 4.4.2), 1000 samples per vertex
             fs = cp.field_of(params, model, nb, nsamples=1000, seed=1)
@@ -358,10 +541,16 @@ def more_detail(cp, workloads, torch, dev, S, reps):
     t_rb = _timed(torch, lambda: cp.forward(params, fr, a, b), 3)
     t_hit = _timed(torch, lambda: cp.forward(params, fh, a, b), 3)
     t_bwd = _timed(torch, lambda: cp.backward(params, g1, g2, fr, grad), 3)
+    mc_peak = ceil["mc_samples_per_s"]
     res["mvg_1024_4096"] = {"fwd_conditional_ms": t_rb, "fwd_hit_ms": t_hit, "bwd_ms": t_bwd,
                             "fwd_vertices_per_s": n * n / (t_rb * 1e-3),
                             "fwd_bwd_vertices_per_s": n * n / ((t_rb + t_bwd) * 1e-3),
-                            "samples_per_s_conditional": n * n * 4096 / (t_rb * 1e-3)}
+                            "samples_per_s_conditional": n * n * 4096 / (t_rb * 1e-3),
+                            "roofline_fwd": roofline("alu", n * n * 4096, t_rb * 1e-3, mc_peak, "G samples/s",
+                                                     ceiling="Philox + Box-Muller + normal CDF probe"),
+                            "roofline_bwd": roofline("alu", n * n * 4096, t_bwd * 1e-3, ceil["mc_pdf_samples_per_s"],
+                                                     "G samples/s",
+                                                     ceiling="Philox + Box-Muller + normal density probe")}
     del params, grad
     res["batched_64_fields"] = batched_detail(cp, workloads, torch, dev)
     return res
@@ -390,7 +579,13 @@ def batched_detail(cp, workloads, torch, dev):
     nv = sum(f.height * f.width for f in fields)
     print(f"[bench] batched inputs ({nv / 1e6:.1f} M vertices) in {time.time() - t0:.1f}s", file=sys.stderr,
           flush=True)
-    out = {"fields": len(fields), "vertices": nv}
+    # algorithmic work of every field, as for the single-field workloads
+    fl_f = fl_b = 0
+    for f, p in zip(fields, params):
+        a, b, _ = (hist_flops(p, f.nbins) if f.model == 2 else uni_flops(p) if f.model == 0 else epa_flops(p))
+        fl_f += a
+        fl_b += b
+    out = {"fields": len(fields), "vertices": nv, "algorithmic_flops_fwd": fl_f, "algorithmic_flops_fwd_bwd": fl_f + fl_b}
     for name, kw in (("per_field", dict(per_field=True)), ("persistent", dict()), ("graph", dict(graph=True))):
         ms = _timed(torch, lambda: cp.batched(fields, params, pmin, pmax, gmin, gmax, grad, **kw), 5)
         out[name + "_fwd_bwd_ms"] = ms
@@ -410,6 +605,12 @@ def batched_detail(cp, workloads, torch, dev):
         out["tuned_graph_" + tag + "_ms"] = ms
         out["tuned_graph_" + tag + "_vertices_per_s"] = nv / (ms * 1e-3)
         out["tuned_plan_" + tag] = cp.batched_describe(fields, fwd=True, bwd=g[2] is not None)
+    out["roofline_tuned_graph_fwd_bwd"] = roofline("alu", fl_f + fl_b, out["tuned_graph_fwd_bwd_ms"] * 1e-3,
+                                                   PEAK_FP32, "TFLOP/s")
+    out["roofline_tuned_graph_fwd"] = roofline("alu", fl_f, out["tuned_graph_fwd_ms"] * 1e-3, PEAK_FP32,
+                                               "TFLOP/s")
+    out["roofline_per_field_fwd_bwd"] = roofline("alu", fl_f + fl_b, out["per_field_fwd_bwd_ms"] * 1e-3,
+                                                 PEAK_FP32, "TFLOP/s")
     out["speedup_fwd_bwd_graph_vs_per_field"] = out["per_field_fwd_bwd_ms"] / out["graph_fwd_bwd_ms"]
     out["speedup_fwd_bwd_tuned_graph_vs_per_field"] = out["per_field_fwd_bwd_ms"] / out["tuned_graph_fwd_bwd_ms"]
     return out

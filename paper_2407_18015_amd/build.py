@@ -1,7 +1,9 @@
 """Build libcpcrit.so (HIP, gfx950) in-tree with hipcc.
 
-Every source under csrc/ is compiled to an object in _build/ (in parallel),
-then linked into paper_2407_18015_amd/libcpcrit.so.  Packed FP32 instructions
+Every library source under csrc/ is compiled to an object in _build/ (in
+parallel), then linked into paper_2407_18015_amd/libcpcrit.so; the
+benchmark's measurement probes (csrc/cp_probes.hip: the Monte Carlo, FP32
+and HBM ceilings) go to libcpprobes.so beside it.  Packed FP32 instructions
 are disabled for all device code.  The device assembly of the closed-form
 kernels is also emitted, and a SHA-256 of each kernel's instructions is
 written to libcpcrit.isa.json: measurements taken on a kernel (hardware
@@ -22,6 +24,8 @@ ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 BUILD = os.path.join(HERE, "_build")
 LIB = os.path.join(HERE, "libcpcrit.so")
+PROBES_LIB = os.path.join(HERE, "libcpprobes.so")
+PROBE_SOURCES = ["cp_probes.hip"]
 ISA_JSON = os.path.join(HERE, "libcpcrit.isa.json")
 ISA_SOURCES = ["cp_closed_form.hip"]
 ARCH = os.environ.get("CPCRIT_ARCH", "gfx950")
@@ -74,22 +78,29 @@ def _isa(src: str) -> dict:
 
 def build(jobs: int | None = None) -> str:
     os.makedirs(BUILD, exist_ok=True)
-    jobs = jobs or min(len(SOURCES) + len(ISA_SOURCES), max(1, (os.cpu_count() or 4)))
+    jobs = jobs or min(len(SOURCES) + len(ISA_SOURCES) + len(PROBE_SOURCES), max(1, (os.cpu_count() or 4)))
     with cf.ThreadPoolExecutor(jobs) as ex:
         isa = [ex.submit(_isa, s) for s in ISA_SOURCES]
+        probes = [ex.submit(_compile, s) for s in PROBE_SOURCES]
         objs = list(ex.map(_compile, SOURCES))
         hashes = {}
         for fut in isa:
             hashes.update(fut.result())
+        probe_objs = [fut.result() for fut in probes]
     with open(ISA_JSON, "w") as fh:
         json.dump(hashes, fh, indent=1, sort_keys=True)
-    tmp = LIB + ".tmp"
+    _link(objs, LIB)
+    _link(probe_objs, PROBES_LIB)
+    return LIB
+
+
+def _link(objs, out):
+    tmp = out + ".tmp"
     cmd = [_hipcc(), "-shared", "-fPIC", f"--offload-arch={ARCH}", "-o", tmp, *objs]
     r = subprocess.run(cmd, capture_output=True, text=True)
     if r.returncode != 0:
-        raise RuntimeError(f"link failed:\n{r.stderr[-4000:]}")
-    os.replace(tmp, LIB)
-    return LIB
+        raise RuntimeError(f"link of {os.path.basename(out)} failed:\n{r.stderr[-4000:]}")
+    os.replace(tmp, out)
 
 
 if __name__ == "__main__":

@@ -58,3 +58,59 @@ def test_piece_counts_match_a_per_vertex_count():
                 for k in range(5):
                     ref[k] += edges[k + 1] > edges[k]
     assert bench.epa_piece_counts(p).tolist() == ref.tolist()
+
+
+def test_uniform_piece_counts_match_a_per_vertex_count():
+    """Uniform pieces: vertex support [0, Lv] from its lower end (minimum) or
+    reflected from its upper end (maximum), against a plain loop."""
+    rng = np.random.default_rng(4)
+    H, W = 6, 8
+    c = rng.normal(0, 0.05, (H, W))
+    hw = rng.uniform(0.02, 0.08, (H, W))
+    p = np.stack([c - hw, c + hw])
+    ref = np.zeros(5, dtype=np.int64)
+    for y in range(H):
+        for x in range(W):
+            lo, hi = p[0, y, x], p[1, y, x]
+            nb = [(y + dy, x + dx) for dy, dx in ((0, 1), (-1, 0), (0, -1), (1, 0))
+                  if 0 <= y + dy < H and 0 <= x + dx < W]
+            for side in (0, 1):
+                if side == 0:
+                    ab = [(p[0, yy, xx] - lo, p[1, yy, xx] - lo) for yy, xx in nb]
+                else:
+                    ab = [(hi - p[1, yy, xx], hi - p[0, yy, xx]) for yy, xx in nb]
+                bmin = min([hi - lo] + [b for _, b in ab])
+                if not bmin > 0:
+                    continue
+                starts = sorted([min(max(a, 0.0), bmin) for a, _ in ab] + [bmin] * (4 - len(nb)))
+                edges = [0.0] + starts + [bmin]
+                for k in range(5):
+                    ref[k] += edges[k + 1] > edges[k]
+    assert bench.uni_piece_counts(p).tolist() == ref.tolist()
+
+
+def test_histogram_interval_count_matches_a_per_vertex_count():
+    """Sub-intervals of the merged sweep: 1 + distinct bin edges of the five
+    histograms strictly inside the vertex range, against a plain loop in
+    the same FP32 vertex frame."""
+    import workloads
+    nb = 4
+    p = workloads.random_params(2, 5, 5, 7, nbins=nb).astype(np.float32)
+    H, W = p.shape[1:]
+    total = 0
+    for y in range(H):
+        for x in range(W):
+            lo = p[0, y, x]
+            hv = np.float32(p[1, y, x] - lo)
+            edges = {float(np.float32(k) * np.float32(hv * np.float32(1.0 / nb))) for k in range(1, nb)}
+            for dy, dx in ((0, 1), (-1, 0), (0, -1), (1, 0)):
+                yy, xx = y + dy, x + dx
+                if 0 <= yy < H and 0 <= xx < W:
+                    a = np.float32(p[0, yy, xx] - lo)
+                    b = np.float32(p[1, yy, xx] - lo)
+                    d = np.float32((b - a) * np.float32(1.0 / nb))
+                    edges |= {float(np.float32(a + np.float32(k) * d)) for k in range(nb + 1)}
+            total += 1 + sum(1 for e in edges if 0 < e < hv)
+    assert bench.hist_interval_count(p, nb) == total
+    # a lone vertex: its own h - 1 interior edges, h intervals
+    assert bench.hist_interval_count(np.array([[[0.0]], [[1.0]]] + [[[0.25]]] * 4, dtype=np.float32), 4) == 4
