@@ -74,6 +74,9 @@ def parse():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--profile-only", action="store_true",
                     help="run the quoted step only (for rocprofv3), no JSON detail")
+    ap.add_argument("--profile-histogram", action="store_true",
+                    help="for rocprofv3: the 2048^2 x 10-bin histogram forward and adjoint, --steps times after "
+                         "--warmup, then a plain copy of known size (no JSON)")
     return ap.parse_args()
 
 
@@ -292,6 +295,9 @@ def main():
     dev = torch.device("cuda:0")
     torch.cuda.set_device(dev)
     S = args.size
+    if args.profile_histogram:
+        profile_histogram(cp, workloads, torch, dev, S, args.steps, args.warmup)
+        return
     t0 = time.time()
     mem_np = workloads.smooth_ensemble(0, S, S)
     gmin_np, gmax_np = workloads.upstream(0, S, S)
@@ -403,6 +409,27 @@ def main():
         "roofline": roof, "cpu_baseline": cpu, "detail": detail,
     }
     print(json.dumps(out), flush=True)
+
+
+def profile_histogram(cp, workloads, torch, dev, S, steps, warmup):
+    """The histogram workload alone (fit once, then forward + adjoint), for
+    hardware-counter runs, followed by a plain 256 MiB copy (the reference
+    that scales the HBM byte counters)."""
+    mem = torch.as_tensor(workloads.mixture_ensemble(1, S, S), device=dev)
+    params = cp.fit(mem, 2, nbins=10)
+    del mem
+    f = cp.field_of(params, 2, 10)
+    g1, g2 = (torch.as_tensor(x, device=dev) for x in workloads.upstream(1, S, S))
+    a, b = torch.empty((S, S), device=dev), torch.empty((S, S), device=dev)
+    grad = torch.empty_like(params)
+    for _ in range(warmup + steps):
+        cp.forward(params, f, a, b)
+        cp.backward(params, g1, g2, f, grad)
+    src = torch.ones(64 << 20, dtype=torch.float32, device=dev)
+    dst = torch.empty_like(src)
+    dst.copy_(src)
+    torch.cuda.synchronize()
+    print(f"[bench] histogram profile: {warmup + steps} forward + adjoint launches", file=sys.stderr, flush=True)
 
 
 def pipelined_step(cp, torch, mem, model, f, params, pmin, pmax, gmin, gmax, grad, reps):
