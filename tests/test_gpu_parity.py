@@ -65,9 +65,17 @@ def gpu_forward(params, model, nbins=0):
     return cp.forward(params, f)
 
 
+def report(what, text):
+    """One line per checked output (visible with pytest -s): the measured
+    error beside its tolerance."""
+    print(f"[parity] {what}: {text}", flush=True)
+
+
 def assert_close(got, ref, atol, what):
     d = np.abs(got - ref)
     i = int(np.nanargmax(d)) if d.size else 0
+    if d.size:
+        report(what, f"max |diff| {np.nanmax(d):.3e} (tolerance {atol:.0e}, {d.size} values)")
     assert np.all(np.isfinite(got) == np.isfinite(ref)), f"{what}: NaN pattern differs"
     assert np.nanmax(d) <= atol, f"{what}: max |diff| {np.nanmax(d):.3e} at flat {i} (got {got.flat[i]}, ref {ref.flat[i]})"
 
@@ -271,6 +279,7 @@ def assert_grad(g, ref, S, dtype, what="grad"):
     d = np.abs(g - ref)
     tol = grad_tol(ref, S, dtype)
     i = int(np.argmax(d / tol))
+    report(what, f"max |diff| {d.max():.3e}, worst |diff|/tolerance {d.flat[i] / tol.flat[i]:.3g} ({d.size} values)")
     assert np.all(d <= tol), f"{what}: worst |d|/tol {d.flat[i] / tol.flat[i]:.3g} (|d| {d.flat[i]:.3e}, g {ref.flat[i]:.4g}, S {S.flat[i]:.3g})"
 
 
@@ -510,6 +519,8 @@ def assert_mvg_grad(g, ref, slack, what):
     d = np.abs(g - ref)
     over = d - (2e-5 * scale + slack)
     i, k = np.unravel_index(int(np.argmax(over)), over.shape)
+    r = d / (2e-5 * scale + slack)
+    report(what, f"max |diff| {d.max():.3e}, worst |diff|/tolerance {r.max():.3g} ({d.size} values)")
     assert np.all(over <= 0), (f"{what}: vertex {i} component {k}: got {g[i, k]}, ref {ref[i, k]}, "
                                f"slack {slack[i, k]}, vertices with slack {int(np.count_nonzero(slack.any(axis=1)))}")
 
