@@ -180,13 +180,14 @@ CP_HD void suf_cursor_step(SufCursor<T>& c, const HistSuf<T>& L, int e, T hi, T 
 // ---------------------------------------------------------------------------
 template <typename T>
 struct HistCursor {
-  T m;        // index of the next edge (0 below the range, h + 1 past it)
-  int a, az;  // LDS index of U_m, of this vertex's zero plane
-  T nxt;      // next edge (big past the range)
-  T snx;      // U_m: survival at the next edge
-  T slope;    // mass density of the current bin (0 outside the range)
-  T kin;      // 1 / Delta inside the range, 0 outside
+  T m;     // index of the next edge (0 below the range, h + 1 past it)
+  int a;   // LDS index of U_m (the vertex's zero plane once m >= h)
+  T nxt;   // next edge (big past the range)
+  T snx;   // U_m: survival at the next edge
+  T slope; // mass density of the current bin (0 outside the range)
   T tot, lo, hi, d, id;
+  // inside the range (the current bin is a bin of this histogram)
+  CP_HD bool in_range(T hf) const { return !(m < T(1)) && !(m > hf); }
 };
 
 // `present` false: the constant factor 1 in both products (S = 1, F = 2 - 1)
@@ -197,11 +198,10 @@ CP_HD void hist_cursor_init(HistCursor<T>& c, const T* base, int E, int h, int e
   c.hi = hi;
   c.d = (hi - lo) * (T(1) / hf);
   c.id = hf * crcp(hi - lo);
-  c.az = (2 + h) * E + e;
-  c.slope = c.kin = T(0);
+  c.slope = T(0);
   if (!present) {
     c.m = hf + T(1);
-    c.a = c.az;
+    c.a = (2 + h) * E + e;
     c.nxt = big;
     c.snx = T(1);
     c.tot = T(2);
@@ -210,7 +210,7 @@ CP_HD void hist_cursor_init(HistCursor<T>& c, const T* base, int E, int h, int e
   c.tot = base[2 * E + e];
   if (!(hi > T(0))) {  // the whole range lies at or below x = 0
     c.m = hf + T(1);
-    c.a = c.az;
+    c.a = (2 + h) * E + e;
     c.nxt = big;
     c.snx = T(0);
     return;
@@ -232,24 +232,22 @@ CP_HD void hist_cursor_init(HistCursor<T>& c, const T* base, int E, int h, int e
   c.nxt = edge(j + 1);
   c.snx = base[c.a];
   c.slope = (base[(2 + j) * E + e] - c.snx) * c.id;
-  c.kin = c.id;
 }
 
-// advance to the next edge where adv
+// advance to the next edge where adv; az = LDS index of this histogram's
+// zero plane
 template <typename T>
-CP_HD void hist_cursor_step(HistCursor<T>& c, const T* base, int E, T hf, T big, bool adv) {
+CP_HD void hist_cursor_step(HistCursor<T>& c, const T* base, int E, int az, T hf, T big, bool adv) {
   const T m1 = c.m + T(1);
-  const int a1 = c.a + E < c.az ? c.a + E : c.az;
+  const int a1 = c.a + E < az ? c.a + E : az;
   const T u1 = base[a1];
   const bool inr = !(m1 > hf);
   const T nx1 = m1 < hf ? cfma(m1, c.d, c.lo) : (inr ? c.hi : big);
   const T sl1 = (c.snx - u1) * c.id;
-  const T k1 = inr ? c.id : T(0);
   c.m = adv ? m1 : c.m;
   c.a = adv ? a1 : c.a;
   c.snx = adv ? u1 : c.snx;
   c.slope = adv ? sl1 : c.slope;
-  c.kin = adv ? k1 : c.kin;
   c.nxt = adv ? nx1 : c.nxt;
 }
 

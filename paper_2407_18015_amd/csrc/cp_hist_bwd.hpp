@@ -53,13 +53,8 @@ __host__ __device__ void hist_jac_both(const HistSuf<T>& L, int ev, const int (&
   VertexBins<T> vb;
   vertex_bins_init(vb, base, E, h, ev, hv);
   HistCursor<T> c[4];
-  int first[4];
 #pragma unroll
-  for (int i = 0; i < 4; ++i) {
-    hist_cursor_init(c[i], base, E, h, en[i], lo[i], hi[i], pres[i], big);
-    const int j = (int)c[i].m - 1;
-    first[i] = j < 0 ? 0 : j;  // first bin the sweep enters
-  }
+  for (int i = 0; i < 4; ++i) hist_cursor_init(c[i], base, E, h, en[i], lo[i], hi[i], pres[i], big);
   T QS[4], QF[4], B[4], Eh[4];
 #pragma unroll
   for (int i = 0; i < 4; ++i) QS[i] = QF[i] = B[i] = Eh[i] = T(0);
@@ -73,7 +68,8 @@ __host__ __device__ void hist_jac_both(const HistSuf<T>& L, int ev, const int (&
     for (int i = 0; i < 4; ++i) x1 = tmin(x1, c[i].nxt);
     const T mid = (x0 + x1) * T(0.5), hl = (x1 - x0) * T(0.5);
     const T php = vb.pv * hl, wS = php * gmin, wF = -php * gmax;
-#pragma unroll
+    // one node at a time (fewer registers live: the sweep needs occupancy)
+#pragma unroll 1
     for (int q = 0; q < 3; ++q) {
       const T x = cfma(hl, T(GL<3>::x[q]), mid);
       const T wv = T(GL<3>::w[q]) * hl, wnS = T(GL<3>::w[q]) * wS, wnF = T(GL<3>::w[q]) * wF;
@@ -110,10 +106,10 @@ __host__ __device__ void hist_jac_both(const HistSuf<T>& L, int ev, const int (&
     for (int i = 0; i < 4; ++i) {
       const bool adv = c[i].nxt == x1;
       // bin m - 1 is left; it is a bin of the range for 1 <= m <= h
-      if (adv && c[i].kin != T(0)) J.set(1 + i, (int)c[i].m - 1, cfma(c[i].kin, Eh[i], B[i]));
+      if (adv && c[i].in_range(hf)) J.set(1 + i, (int)c[i].m - 1, cfma(c[i].id, Eh[i], B[i]));
       B[i] = adv ? QS[i] + QF[i] : B[i];
       Eh[i] = adv ? T(0) : Eh[i];
-      hist_cursor_step(c[i], base, E, hf, big, adv);
+      hist_cursor_step(c[i], base, E, (2 + h) * E + en[i], hf, big, adv);
     }
     x0 = x1;
   }
@@ -126,13 +122,18 @@ __host__ __device__ void hist_jac_both(const HistSuf<T>& L, int ev, const int (&
     if (!pres[i]) continue;
     const int j = (int)c[i].m - 1;  // open bin (-1: below the range, h: past it)
     const T tf = -QF[i];            // g_max QF_n(hv)
+    // first bin the sweep entered (the cursor's start, found again)
+    HistCursor<T> c0;
+    hist_cursor_init(c0, base, E, h, en[i], lo[i], hi[i], true, big);
+    const int first = c0.m < T(1) ? 0 : (int)c0.m - 1;
+    const T kin = c[i].in_range(hf) ? c[i].id : T(0);
     for (int k = 0; k < h; ++k) {
-      if (k < first[i]) {
+      if (k < first) {
         J.set(1 + i, k, tf);  // entirely below the sweep: dF/dm = 1 there
       } else if (k < j) {
         J.add(1 + i, k, tf);  // emitted when the sweep left it
       } else if (k == j) {
-        J.set(1 + i, k, cfma(c[i].kin, Eh[i], B[i]) + tf);
+        J.set(1 + i, k, cfma(kin, Eh[i], B[i]) + tf);
       } else {
         J.set(1 + i, k, QS[i]);  // entirely above the sweep: dS/dm = 1 there
       }
