@@ -723,7 +723,7 @@ void or_philox4x32_10(const uint32_t ctr_in[4], const uint32_t key_in[2], uint32
   out[3] = c3;
 }
 
-/* 24 high bits of a 32-bit word, centred in (0, 1): exact in FP32 and FP64 */
+/* 24 high bits of a 32-bit word, centred in (0, 1): exact in FP64 */
 static double u24(uint32_t r) { return ((double)(r >> 8) + 0.5) * (1.0 / 16777216.0); }
 
 static double phi_cdf(double r) { return 0.5 * erfc(-r / sqrt(2.0)); }

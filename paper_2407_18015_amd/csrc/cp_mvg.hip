@@ -20,6 +20,7 @@
 #include <hip/hip_runtime.h>
 
 #include "cp_internal.hpp"
+#include "cp_mc_math.hpp"
 #include "cp_philox.hpp"
 
 namespace cp {
@@ -28,16 +29,6 @@ namespace {
 
 __device__ __forceinline__ float u24(uint32_t r) { return u24_of<float>(r); }
 
-__device__ __forceinline__ void box_muller(float u0, float u1, float& z0, float& z1) {
-  const float rad = sqrtf(-2.0f * logf(u0));
-  float s, c;
-  sincospif(2.0f * u1, &s, &c);
-  z0 = rad * c;
-  z1 = rad * s;
-}
-
-__device__ __forceinline__ float phi_cdf(float r) { return 0.5f * erfcf(-r * 0.70710678118654752f); }
-__device__ __forceinline__ float phi_pdf(float r) { return 0.39894228040143268f * expf(-0.5f * r * r); }
 
 template <typename V>
 __device__ __forceinline__ V wave_sum(V v) {

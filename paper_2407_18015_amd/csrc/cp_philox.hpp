@@ -30,8 +30,9 @@ __device__ __forceinline__ void philox(uint32_t c[4], uint32_t k0, uint32_t k1) 
   }
 }
 
-// Uniform in (0, 1) from the top 24 bits of a word: ((r >> 8) + 1/2) 2^-24,
-// exact in FP32 and FP64.
+// Uniform in (0, 1] from the top 24 bits of a word: ((r >> 8) + 1/2) 2^-24,
+// exact in FP64; in FP32 the values above 1/2 need a 25th bit and round to
+// the nearest even multiple of 2^-24 (by at most 2^-25; the top one to 1).
 template <typename T>
 __device__ __forceinline__ T u24_of(uint32_t r) {
   return (T(r >> 8) + T(0.5)) * T(5.9604644775390625e-8);

@@ -4,7 +4,8 @@
 //   cpb_mc_ceiling  the random-number and transcendental work of one sample of
 //                   the conditional Monte Carlo estimator, with nothing else:
 //                   one Philox4x32-10 block, two Box-Muller pairs, two normal
-//                   CDFs (erfc; the adjoint: two normal densities, exp), the
+//                   CDFs (the adjoint: two normal densities), the same
+//                   functions as the estimator (cp_mc_math.hpp), the
 //                   FP64 accumulation, one wave64 per vertex and the wave
 //                   reduction -- the estimator's launch shape without the
 //                   stencil (mean, Cholesky product, min / max, gradients).
@@ -15,17 +16,10 @@
 
 #include <cstdint>
 
+#include "cp_mc_math.hpp"
 #include "cp_philox.hpp"
 
 namespace {
-
-__device__ __forceinline__ void bm(float u0, float u1, float& z0, float& z1) {
-  const float rad = sqrtf(-2.0f * logf(u0));
-  float s, c;
-  sincospif(2.0f * u1, &s, &c);
-  z0 = rad * c;
-  z1 = rad * s;
-}
 
 __device__ __forceinline__ double wave_sum(double v) {
 #pragma unroll
@@ -44,15 +38,15 @@ __global__ __launch_bounds__(256) void k_mc_ceiling(int nv, int ns, uint32_t k0,
     uint32_t c[4] = {(uint32_t)i, (uint32_t)v, fid, 0u};
     cp::philox(c, k0, k1);
     float z[4];
-    bm(cp::u24_of<float>(c[0]), cp::u24_of<float>(c[1]), z[0], z[1]);
-    bm(cp::u24_of<float>(c[2]), cp::u24_of<float>(c[3]), z[2], z[3]);
+    cp::box_muller(cp::u24_of<float>(c[0]), cp::u24_of<float>(c[1]), z[0], z[1]);
+    cp::box_muller(cp::u24_of<float>(c[2]), cp::u24_of<float>(c[3]), z[2], z[3]);
     const float r0 = z[1] - z[0], r1 = z[3] - z[2];
     if (PDF) {
-      a += (double)(0.39894228040143268f * expf(-0.5f * r0 * r0));
-      b += (double)(0.39894228040143268f * expf(-0.5f * r1 * r1));
+      a += (double)cp::phi_pdf(r0);
+      b += (double)cp::phi_pdf(r1);
     } else {
-      a += (double)(0.5f * erfcf(r0 * 0.70710678118654752f));
-      b += (double)(0.5f * erfcf(r1 * 0.70710678118654752f));
+      a += (double)cp::phi_cdf(r0);
+      b += (double)cp::phi_cdf(r1);
     }
   }
   a = wave_sum(a);
