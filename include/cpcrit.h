@@ -286,6 +286,11 @@ cp_status_t cp_prob_semianalytical(const cp_field_desc_t* desc, const void* para
  * trials are done, and fails (CP_EINVAL) while the stream is being captured.
  * The trials write the outputs, with the same values: no tile shape changes
  * a result.  Without the flag a plan uses the first shape and a fixed chunk.
+ * Tuning table: if the environment variable CPCRIT_TUNE_CACHE names a file,
+ * every plan the tuner times appends its choices there (one text line keyed
+ * by the GPU architecture, its CU count and the field shapes), and a later
+ * CP_BATCH_TUNE call with the same key (in any process) takes them instead
+ * of timing; cp_batched_describe then reports "tuned (table)".
  */
 cp_status_t cp_prob_batched(int32_t n, const cp_field_desc_t* descs, const void* const* params,
                             void* const* p_min, void* const* p_max, const void* const* g_min,

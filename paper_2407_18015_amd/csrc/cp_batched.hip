@@ -26,7 +26,9 @@
 
 #include <algorithm>
 #include <cstdio>
+#include <cstdlib>
 #include <cstring>
+#include <sstream>
 #include <string>
 #include <map>
 #include <memory>
@@ -222,6 +224,7 @@ struct Plan {
   void* d_ws = nullptr;             // histogram Jacobians of all fields
   std::vector<size_t> ws_offset;    // bytes, per field (SIZE_MAX: none)
   std::vector<unsigned char> host_fields;  // last uploaded field table
+  bool from_table = false;          // tuning choices read from the tuning table
   hipStream_t last = nullptr;       // stream of the last call that used the plan
   hipEvent_t done = nullptr;        // recorded on `last` after that call's launches
   bool used = false;
@@ -498,9 +501,103 @@ cp_status_t tune(Plan& P, hipStream_t st) {
   return CP_OK;
 }
 
+// ---------------------------------------------------------------------------
+// Tuning table: with CPCRIT_TUNE_CACHE naming a text file, every plan the
+// autotuner times appends one line, and a later CP_BATCH_TUNE call (another
+// process, or after cp_release) with the same shapes on the same kind of GPU
+// takes the recorded choices instead of timing again.  Line format:
+//   cpcrit-tune-1 <arch> <CUs> <n> <dtype> <flags> {<H> <W> <rs> <model*1000+nbins>}*n
+//   | {<pass kind> <tile variant> <chunk> <ms>}*
+// The last line with a matching key wins; unreadable lines are skipped.
+// ---------------------------------------------------------------------------
+std::string tune_key(int n, const Field* fs, uint32_t flags) {
+  int dev = 0;
+  hipDeviceProp_t prop;
+  if (hipGetDevice(&dev) != hipSuccess || hipGetDeviceProperties(&prop, dev) != hipSuccess) return "";
+  std::ostringstream k;
+  k << "cpcrit-tune-1 " << prop.gcnArchName << ' ' << prop.multiProcessorCount << ' ' << n << ' ' << fs[0].dtype
+    << ' ' << (flags & (CP_BATCH_FWD | CP_BATCH_BWD));
+  for (int i = 0; i < n; ++i) k << ' ' << fs[i].H << ' ' << fs[i].W << ' ' << fs[i].rs << ' ' << fs[i].model * 1000 + fs[i].nb;
+  return k.str();
+}
+
+struct TunedPass {
+  int kind, variant, chunk;
+  double ms;
+};
+
+bool tune_table_lookup(const char* path, const std::string& key, std::vector<TunedPass>& out) {
+  FILE* fh = std::fopen(path, "r");
+  if (!fh) return false;
+  std::string line;
+  bool found = false;
+  int c;
+  while (true) {
+    line.clear();
+    while ((c = std::fgetc(fh)) != EOF && c != '\n') line.push_back((char)c);
+    const size_t bar = line.find(" | ");
+    if (bar != std::string::npos && line.compare(0, bar, key) == 0 && bar == key.size()) {
+      std::istringstream rest(line.substr(bar + 3));
+      std::vector<TunedPass> v;
+      TunedPass t;
+      while (rest >> t.kind >> t.variant >> t.chunk >> t.ms) v.push_back(t);
+      if (!v.empty()) {
+        out = v;
+        found = true;
+      }
+    }
+    if (c == EOF) break;
+  }
+  std::fclose(fh);
+  return found;
+}
+
+void tune_table_store(const char* path, const std::string& key, const Plan& P) {
+  FILE* fh = std::fopen(path, "a");
+  if (!fh) return;
+  std::string line = key + " |";
+  char buf[96];
+  for (const Pass& q : P.passes) {
+    std::snprintf(buf, sizeof buf, " %d %d %d %.6f", q.kind, q.variant, q.chunk, q.ms);
+    line += buf;
+  }
+  line += '\n';
+  std::fputs(line.c_str(), fh);
+  std::fclose(fh);
+}
+
+// Apply recorded choices to the plan; false (plan unchanged in its
+// choices) when a recorded variant does not fit these fields any more.
+cp_status_t tune_table_apply(Plan& P, const std::vector<TunedPass>& rec, bool& applied) {
+  applied = false;
+  for (const TunedPass& t : rec)
+    if (t.kind < 0 || t.kind >= NPASS || t.variant < 0 || t.variant >= n_variants(t.kind) || t.chunk < 1) return CP_OK;
+  for (Pass& cur : P.passes) {
+    for (const TunedPass& t : rec) {
+      if (t.kind != cur.kind) continue;
+      if (t.variant != cur.variant) {
+        Pass Q;
+        cp_status_t s = build_pass(P, cur.kind, t.variant, t.chunk, Q);
+        if (s == CP_EUNSUPPORTED) return CP_OK;
+        if (s != CP_OK) return s;
+        cur.release();
+        cur = Q;
+      }
+      cur.chunk = t.chunk;
+      cur.ms = t.ms;
+    }
+  }
+  P.tuned = true;
+  P.from_table = true;
+  applied = true;
+  return CP_OK;
+}
+
 std::string describe(const Plan& P) {
   const size_t el = P.dtype == CP_F64 ? 8 : 4;
-  std::string out = P.tuned ? (P.passes.empty() || P.passes[0].ms >= 0.0 ? "tuned" : "pinned") : "default";
+  std::string out = P.tuned ? (P.passes.empty() || P.passes[0].ms >= 0.0 ? (P.from_table ? "tuned (table)" : "tuned")
+                                                                           : "pinned")
+                            : "default";
   char buf[256];
   for (const Pass& q : P.passes) {
     int ox, oy;
@@ -593,10 +690,24 @@ cp_status_t batched(int n, const Field* fs, const void* const* params, void* con
       *why = "batched: tuning times launches and cannot run while the stream is being captured";
       return CP_EINVAL;
     }
-    cp_status_t s = tune(P, st);
-    if (s != CP_OK) {
-      *why = "batched: tuning launch failed";
-      return s;
+    const char* table = std::getenv("CPCRIT_TUNE_CACHE");
+    const std::string tkey = table && *table ? tune_key(n, fs, flags) : std::string();
+    std::vector<TunedPass> rec;
+    bool applied = false;
+    if (!tkey.empty() && tune_table_lookup(table, tkey, rec)) {
+      cp_status_t s = tune_table_apply(P, rec, applied);
+      if (s != CP_OK) {
+        *why = "batched: rebuilding a recorded plan failed";
+        return s;
+      }
+    }
+    if (!applied) {
+      cp_status_t s = tune(P, st);
+      if (s != CP_OK) {
+        *why = "batched: tuning launch failed";
+        return s;
+      }
+      if (!tkey.empty()) tune_table_store(table, tkey, P);
     }
     P.drop_graph();  // captured with the default configuration
   }

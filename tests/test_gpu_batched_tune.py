@@ -183,3 +183,35 @@ def test_plan_shared_by_two_streams():
             a, b = cp.forward(p, f)
             assert torch.allclose(a, pmin[i], rtol=0, atol=1e-6, equal_nan=True), (k, i)
             assert torch.allclose(b, pmax[i], rtol=0, atol=1e-6, equal_nan=True), (k, i)
+
+
+def test_tuning_table_persists(tmp_path, monkeypatch):
+    """With CPCRIT_TUNE_CACHE set, the first tuned call records its choices;
+    after cp_release (as in a new process) the same shapes take them from the
+    table instead of timing again, and give the per-field results."""
+    note("tuning table")
+    table = tmp_path / "tune.txt"
+    monkeypatch.setenv("CPCRIT_TUNE_CACHE", str(table))
+    dtype = torch.float32
+    fields, params = mixed_fields(19, dtype, n=7)
+    gmin, gmax = upstream(fields, dtype)
+
+    def call():
+        pmin, pmax = outputs(fields, dtype)
+        grad = [torch.full_like(p, -1.0) for p in params]
+        cp.batched(fields, params, pmin, pmax, gmin, gmax, grad, tune=True)
+        check_backward(fields, params, gmin, gmax, grad, "table")
+        return cp.batched_describe(fields, fwd=True, bwd=True)
+
+    first = call()
+    assert first.startswith("tuned;"), first
+    lines = table.read_text().splitlines()
+    assert len(lines) == 1 and lines[0].startswith("cpcrit-tune-1 ")
+    L.check(L.cp_release())
+    second = call()
+    assert second.startswith("tuned (table);"), second
+    # the same shapes and chunks (launch times aside)
+    import re
+    strip = lambda d: re.sub(r", [0-9.]+ ms", "", d.split(";", 1)[1])
+    assert strip(second) == strip(first)
+    assert len(table.read_text().splitlines()) == 1  # nothing re-timed, nothing appended
