@@ -26,6 +26,7 @@
 #include <cmath>
 
 #include "cp_device.hpp"
+#include "cp_mc_math.hpp"
 
 namespace cp {
 
@@ -42,9 +43,25 @@ struct GaussRule<double> {
   static constexpr double c[11] = {-8.5, -6.0, -4.5, -3.0, -1.5, 0.0, 1.5, 3.0, 4.5, 6.0, 8.5};
 };
 
-CP_HD float gerfc(float x) { return erfcf(x); }
+// erfc(x) for x >= 0 and e^x for x <= 0 (the only arguments here).  FP32 on
+// the device: the hardware-instruction forms of cp_mc_math.hpp (fractional
+// error below ~2e-7, against ~1e-7 for the library functions); FP64 and
+// host code: the C library.
+CP_HD float gerfc(float x) {
+#if defined(__HIP_DEVICE_COMPILE__)
+  return erfc_pos(x);
+#else
+  return erfcf(x);
+#endif
+}
 CP_HD double gerfc(double x) { return erfc(x); }
-CP_HD float gexp(float x) { return expf(x); }
+CP_HD float gexp(float x) {
+#if defined(__HIP_DEVICE_COMPILE__)
+  return exp_neg(x);
+#else
+  return expf(x);
+#endif
+}
 CP_HD double gexp(double x) { return exp(x); }
 
 // out = (P_min, P_max, t1, t2) of a vertex with valid parameters; neighbour

@@ -1,6 +1,7 @@
 // cp_mc_math.hpp -- per-sample math of the Gaussian Monte Carlo estimators
 // (normal deviates from uniforms, the normal CDF and density), on the
-// hardware transcendental instructions of gfx950.
+// hardware transcendental instructions of gfx950; erfc_pos and exp_neg also
+// serve the FP32 independent-Gaussian quadrature.
 //
 // Measured against FP64 on the generator's uniforms: v_sin_f32 / v_cos_f32
 // (argument in revolutions) 1.3e-7 absolute, v_sqrt_f32 9e-8, v_exp_f32

@@ -51,6 +51,7 @@ def close(got, ref, atol, what):
     d = np.abs(got - ref)
     if d.size:
         i = int(np.nanargmax(d))
+        print(f"[parity] {what}: max |diff| {np.nanmax(d):.3e} (tolerance {atol:.0e})", flush=True)
         assert np.nanmax(d) <= atol, f"{what}: max |diff| {np.nanmax(d):.3e} at flat {i} (got {got.flat[i]}, ref {ref.flat[i]})"
 
 
@@ -307,6 +308,7 @@ def gauss_grad_check(pt, g1, g2, idx, dtype, what):
     bound = a * (1 + np.abs(ref)) + b * S
     d = np.abs(grad - ref)
     worst = np.unravel_index(np.argmax(d / bound), d.shape)
+    print(f"[parity] {what}: worst |diff| / bound {d[worst] / bound[worst]:.3f}", flush=True)
     assert np.all(d <= bound), f"{what}: worst {d[worst]:.3e} vs bound {bound[worst]:.3e} at {worst}"
 
 
