@@ -132,6 +132,23 @@ cp_status_t cpu_fit_params(const cp_field_desc_t* desc, const void* members, int
                            const cp_fit_opts_t* opts, void* params, void* stream);
 
 /*
+ * Fit followed by forward, as cpu_fit_params then cp_prob_forward with the
+ * same arguments (results equal bit for bit): params, p_min and p_max are
+ * all written.  For CP_UNIFORM and CP_EPANECHNIKOV fields whose width and
+ * row stride are multiples of 16 bytes and whose members / params base
+ * addresses are 16-byte aligned, one launch does both: each tile fits its
+ * vertices and their one-vertex halo from the members into on-chip memory
+ * and integrates from there, so the HBM-bound fit and the arithmetic-bound
+ * forward overlap and the parameters are not read back.  Other fields run
+ * the two calls' launches in order.
+ *   members  [n_members][H][row_stride]; params [n_param][H][row_stride];
+ *   p_min, p_max [H][row_stride]; opts as cpu_fit_params
+ * Argument errors are those of the two calls.
+ */
+cp_status_t cp_fit_forward(const cp_field_desc_t* desc, const void* members, int32_t n_members,
+                           const cp_fit_opts_t* opts, void* params, void* p_min, void* p_max, void* stream);
+
+/*
  * Uniform model of a field reconstructed by an error-bounded lossy compressor
  * (Sec. 5.3, climate data): each vertex value lies in
  *     [d' - eb/2, d' + eb/2],

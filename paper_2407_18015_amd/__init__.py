@@ -11,9 +11,9 @@ batched persistent launch.  All computation runs in the HIP library
 """
 from . import _lib
 from .ops import (CPProb, Field, backward, batched, batched_describe, batched_pin,
-                  classify, critical_point_probability, field_of, fit, fit_error_bound, forward,
-                  n_params, philox, semianalytical)
+                  classify, critical_point_probability, field_of, fit, fit_error_bound, fit_forward,
+                  forward, n_params, philox, semianalytical)
 
 __all__ = ["CPProb", "Field", "backward", "batched", "batched_describe", "batched_pin",
-           "classify", "critical_point_probability", "field_of", "fit", "fit_error_bound", "forward",
+           "classify", "critical_point_probability", "field_of", "fit", "fit_error_bound", "fit_forward", "forward",
            "n_params", "philox", "semianalytical", "_lib"]

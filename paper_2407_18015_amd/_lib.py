@@ -18,7 +18,7 @@ CP_F32, CP_F64 = 0, 1
 CP_MC_CONDITIONAL, CP_MC_HIT = 0, 1
 CP_BATCH_FWD, CP_BATCH_BWD, CP_BATCH_GRAPH, CP_BATCH_PER_FIELD, CP_BATCH_TUNE = 1, 2, 4, 8, 16
 
-EXPORTS = ["cpu_fit_params", "cp_fit_error_bound", "cp_prob_forward", "cp_prob_backward",
+EXPORTS = ["cpu_fit_params", "cp_fit_forward", "cp_fit_error_bound", "cp_prob_forward", "cp_prob_backward",
            "cp_prob_backward_noalloc", "cp_prob_classify",
            "cp_prob_semianalytical",
            "cp_prob_batched", "cp_batched_pin", "cp_batched_describe",
@@ -61,6 +61,7 @@ def load() -> ctypes.CDLL:
     PP = ctypes.POINTER(ctypes.c_void_p)
     sigs = {
         "cpu_fit_params": (i32, [D, P, i32, O, P, P]),
+        "cp_fit_forward": (i32, [D, P, i32, O, P, P, P, P]),
         "cp_fit_error_bound": (i32, [D, P, ctypes.c_double, P, P]),
         "cp_prob_forward": (i32, [D, P, P, P, P]),
         "cp_prob_backward": (i32, [D, P, P, P, P, P]),
@@ -94,6 +95,11 @@ def check(status: int) -> None:
 def cpu_fit_params(desc, members, n_members, opts, params, stream) -> int:
     return load().cpu_fit_params(ctypes.byref(desc), members, n_members, ctypes.byref(opts) if opts else None,
                                  params, stream)
+
+
+def cp_fit_forward(desc, members, n_members, opts, params, p_min, p_max, stream) -> int:
+    return load().cp_fit_forward(ctypes.byref(desc), members, n_members, ctypes.byref(opts) if opts else None,
+                                 params, p_min, p_max, stream)
 
 
 def cp_fit_error_bound(desc, decompressed, eb, params, stream) -> int:

@@ -30,7 +30,7 @@ ISA_JSON = os.path.join(HERE, "libcpcrit.isa.json")
 ISA_SOURCES = ["cp_closed_form.hip"]
 ARCH = os.environ.get("CPCRIT_ARCH", "gfx950")
 
-SOURCES = ["cp_api.cpp", "cp_closed_form.hip", "cp_fit.hip", "cp_mvg.hip", "cp_batched.hip", "cp_classify.hip", "cp_semi.hip"]
+SOURCES = ["cp_api.cpp", "cp_closed_form.hip", "cp_fit.hip", "cp_fit_forward.hip", "cp_mvg.hip", "cp_batched.hip", "cp_classify.hip", "cp_semi.hip"]
 
 COMMON = ["-O3", "-std=c++17", "-fPIC", f"--offload-arch={ARCH}",
           "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",

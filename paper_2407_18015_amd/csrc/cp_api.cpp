@@ -206,6 +206,35 @@ cp_status_t cpu_fit_params(const cp_field_desc_t* desc, const void* members, int
   return CP_OK;
 }
 
+cp_status_t cp_fit_forward(const cp_field_desc_t* desc, const void* members, int32_t n_members,
+                           const cp_fit_opts_t* opts, void* params, void* p_min, void* p_max, void* stream) {
+  cp::Field f;
+  cp_status_t s = check_desc(desc, f);
+  if (s != CP_OK) return s;
+  if (!members || !params || !p_min || !p_max) return fail(CP_EINVAL, "members / params / p_min / p_max is NULL");
+  cp_fit_opts_t o;
+  double eps;
+  s = check_fit_opts(f, n_members, opts, o, eps);
+  if (s != CP_OK) return s;
+  hipStream_t st = static_cast<hipStream_t>(stream);
+  hipError_t e;
+  if (cp::fit_forward_fusable(f, members, params)) {
+    e = cp::fit_forward_ue(f, members, n_members, cp::fit_wscale(f.model, n_members, o.ddof, o.bw_factor), eps,
+                           params, p_min, p_max, st);
+    if (e != hipSuccess) return device_fail(e, "fit + forward launch");
+    return CP_OK;
+  }
+  e = cp::fit_params(f, members, n_members, o.ddof, o.bw_factor, o.cov_jitter, eps, params, st);
+  if (e != hipSuccess) return device_fail(e, "fit launch");
+  if (f.model == CP_MVGAUSS)
+    e = cp::mvg_forward(f, static_cast<const double*>(params), static_cast<float*>(p_min),
+                        static_cast<float*>(p_max), st);
+  else
+    e = cp::cf_forward(f, params, p_min, p_max, st);
+  if (e != hipSuccess) return device_fail(e, "forward launch");
+  return CP_OK;
+}
+
 cp_status_t cp_fit_error_bound(const cp_field_desc_t* desc, const void* decompressed, double eb, void* params,
                                void* stream) {
   cp::Field f;

@@ -54,6 +54,11 @@ hipError_t semi_forward(const Field& f, const void* params, void* pmin, void* pm
 hipError_t fit_params(const Field& f, const void* members, int M, int ddof, double bw, double jitter,
                       double eps, void* params, hipStream_t st);
 hipError_t fit_error_bound(const Field& f, const void* decompressed, double eb, void* params, hipStream_t st);
+// fit + forward of a uniform / Epanechnikov field in one launch; applicable
+// when width, row stride and both base addresses are multiples of 16 bytes
+bool fit_forward_fusable(const Field& f, const void* members, const void* params);
+hipError_t fit_forward_ue(const Field& f, const void* members, int M, double wscale, double eps, void* params,
+                          void* pmin, void* pmax, hipStream_t st);
 
 // Epanechnikov half-width bw * sd * M^(-1/5), Gaussian sigma = sd; both as
 // wscale * sqrt(sum of squared deviations about the mean)

@@ -209,12 +209,12 @@ constexpr int kFwdTX = 64;
 // once the grid gives at least this many of them (eight per CU), else 64 x 4
 constexpr int kTallTileBlocks = 2048;
 
+// evaluation of a tile whose parameters (two planes, halo included) are in
+// LDS; also the second half of the fused fit + forward
 template <typename T, int MODEL, int TY, int NT = kFwdTX * TY>
-__device__ __forceinline__ void tile_fwd_ue(const FieldPtrs<T>& f, int ty0, int tx0, T* lds, int tid) {
+__device__ __forceinline__ void tile_fwd_ue_eval(const FieldPtrs<T>& f, int ty0, int tx0, const T* lds, int tid) {
   constexpr int TX = kFwdTX, EX = TX + 2, EY = TY + 2, E = EX * EY;
   static_assert(NT % TX == 0 && TY % (NT / TX) == 0, "rows must split evenly over the threads");
-  stage<T, EY, EX, NT>(lds, f.params, 2, f.ps, f.rs, f.H, f.W, ty0 - 1, tx0 - 1, tid);
-  __syncthreads();
   const int lx = tid % TX, x = tx0 + lx;
   for (int ly = tid / TX; ly < TY; ly += NT / TX) {
     const int y = ty0 + ly;
@@ -228,6 +228,14 @@ __device__ __forceinline__ void tile_fwd_ue(const FieldPtrs<T>& f, int ty0, int 
       f.pmax[(int64_t)y * f.rs + x] = pmax;
     }
   }
+}
+
+template <typename T, int MODEL, int TY, int NT = kFwdTX * TY>
+__device__ __forceinline__ void tile_fwd_ue(const FieldPtrs<T>& f, int ty0, int tx0, T* lds, int tid) {
+  constexpr int EX = kFwdTX + 2, EY = TY + 2;
+  stage<T, EY, EX, NT>(lds, f.params, 2, f.ps, f.rs, f.H, f.W, ty0 - 1, tx0 - 1, tid);
+  __syncthreads();
+  tile_fwd_ue_eval<T, MODEL, TY, NT>(f, ty0, tx0, lds, tid);
   __syncthreads();
 }
 

@@ -112,6 +112,30 @@ def fit(members: torch.Tensor, model, nbins: int = 0, ddof: int = 1, bw_factor: 
     return out
 
 
+def fit_forward(members: torch.Tensor, model, nbins: int = 0, ddof: int = 1, bw_factor: float = 1.06,
+                cov_jitter: float = 1e-6, degenerate_eps: float = 0.0, out: torch.Tensor | None = None,
+                pmin: torch.Tensor | None = None, pmax: torch.Tensor | None = None, **kw):
+    """cp_fit_forward: fit (as `fit`) and forward (as `forward`) in one call;
+    returns (params, P_min, P_max).  kw: Field options of the forward
+    (nsamples, seed, field_id, estimator for the multivariate Gaussian)."""
+    M, H, W = members.shape
+    f = Field(H, W, model_id(model), members.dtype, nbins, **kw)
+    _planes(members, H, W, members.dtype, "members")
+    if out is None:
+        out = torch.empty((f.n_param, H, W), dtype=f.param_dtype, device=members.device)
+    _planes(out, H, W, f.param_dtype, "params")
+    if pmin is None:
+        pmin = torch.empty((H, W), dtype=f.out_dtype, device=members.device)
+    if pmax is None:
+        pmax = torch.empty((H, W), dtype=f.out_dtype, device=members.device)
+    _planes(pmin, H, W, f.out_dtype, "p_min")
+    _planes(pmax, H, W, f.out_dtype, "p_max")
+    opts = L.cp_fit_opts_t(ddof, bw_factor, cov_jitter, degenerate_eps)
+    L.check(L.cp_fit_forward(f.desc(), _ptr(members), M, opts, _ptr(out), _ptr(pmin), _ptr(pmax),
+                             _stream(members)))
+    return out, pmin, pmax
+
+
 def fit_error_bound(decompressed: torch.Tensor, eb: float, out: torch.Tensor | None = None) -> torch.Tensor:
     """cp_fit_error_bound: uniform parameters [2, H, W] = d' -/+ eb/2 of an
     error-bounded reconstruction d' [H, W]."""

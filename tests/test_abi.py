@@ -94,6 +94,21 @@ def test_null_pointers_rejected():
     assert L.load().cp_prob_forward(None, FAKE, FAKE, FAKE, None) == L.CP_EINVAL
 
 
+def test_fit_forward_argument_errors():
+    """cp_fit_forward rejects what either of cpu_fit_params and cp_prob_forward
+    rejects, before anything is launched."""
+    assert L.cp_fit_forward(desc(), None, 3, None, FAKE, FAKE, FAKE, None) == L.CP_EINVAL
+    assert L.cp_fit_forward(desc(), FAKE, 3, None, None, FAKE, FAKE, None) == L.CP_EINVAL
+    assert L.cp_fit_forward(desc(), FAKE, 3, None, FAKE, None, FAKE, None) == L.CP_EINVAL
+    assert L.cp_fit_forward(desc(), FAKE, 3, None, FAKE, FAKE, None, None) == L.CP_EINVAL
+    assert L.cp_fit_forward(desc(), FAKE, 0, None, FAKE, FAKE, FAKE, None) == L.CP_EINVAL
+    assert L.cp_fit_forward(desc(height=0), FAKE, 3, None, FAKE, FAKE, FAKE, None) == L.CP_EINVAL
+    bad = L.cp_fit_opts_t(-1, 1.06, 1e-6, 0.0)
+    assert L.cp_fit_forward(desc(), FAKE, 3, bad, FAKE, FAKE, FAKE, None) == L.CP_EDOMAIN
+    # the Gaussian forward needs samples
+    assert L.cp_fit_forward(desc(model=L.CP_MVGAUSS), FAKE, 3, None, FAKE, FAKE, FAKE, None) == L.CP_EINVAL
+
+
 def test_fit_option_validation():
     bad = L.cp_fit_opts_t(-1, 1.06, 1e-6, 0.0)
     assert L.cpu_fit_params(desc(), FAKE, 3, bad, FAKE, None) == L.CP_EDOMAIN
