@@ -491,8 +491,12 @@ struct EpaGrad {
   T dd[4], dw[4];  // by neighbour index
 };
 
+// One piece with K started neighbours (sorted slots 0..K-1), N nodes.  The
+// slot sums, times the piece's factor sc = 4^-(K-1) and its half-length, are
+// added straight into the side's accumulators ad / aw (by sorted slot); WF:
+// the piece's value, times fsc = 4^-K and the half-length, into `full`.
 template <typename T, int K, int N, bool WF>
-CP_HD void epa_piece_grad(const EpaSide<T>& s, T l, T r, T& full, T (&gd)[4], T (&gw)[4]) {
+CP_HD void epa_piece_grad(const EpaSide<T>& s, T l, T r, T sc, T fsc, T& full, T (&ad)[4], T (&aw)[4]) {
   const T mid = (l + r) * T(0.5), hl = (r - l) * T(0.5);
   const T av = mid * s.iwv, bv = hl * s.iwv;
   T au[K], bu[K];
@@ -531,11 +535,12 @@ CP_HD void epa_piece_grad(const EpaSide<T>& s, T l, T r, T& full, T (&gd)[4], T 
       sww[i] = cfma(lw, u[i], sww[i]);
     }
   }
-  if (WF) full += sf * hl;
+  const T ps = sc * hl;
+  if (WF) full = cfma(sf, fsc * hl, full);
 #pragma unroll
   for (int i = 0; i < K; ++i) {
-    gd[i] += sd[i] * hl;
-    gw[i] += sww[i] * hl;
+    ad[i] = cfma(sd[i], ps, ad[i]);
+    aw[i] = cfma(sww[i], ps, aw[i]);
   }
 }
 
@@ -545,38 +550,23 @@ CP_HD void epa_side_grad(const EpaSide<T>& s, EpaGrad<T>& g) {
 #pragma unroll
   for (int i = 0; i < 4; ++i) g.dd[i] = g.dw[i] = T(0);
   if (s.empty) return;
-  T F[5] = {T(0), T(0), T(0), T(0), T(0)};
-  T gd[5][4], gw[5][4];
-#pragma unroll
-  for (int k = 0; k < 5; ++k)
-#pragma unroll
-    for (int i = 0; i < 4; ++i) gd[k][i] = gw[k][i] = T(0);
-  epa_piece_grad<T, 1, 3, WF>(s, s.c[0], s.c[1], F[1], gd[1], gw[1]);
-  epa_piece_grad<T, 2, 5, WF>(s, s.c[1], s.c[2], F[2], gd[2], gw[2]);
-  epa_piece_grad<T, 3, 6, WF>(s, s.c[2], s.c[3], F[3], gd[3], gw[3]);
-  epa_piece_grad<T, 4, 8, WF>(s, s.c[3], s.bmin, F[4], gd[4], gw[4]);
+  // neighbour slot i collects the pieces k > i, its factor p_i carrying
+  // 3/(4 w_i) and the other started factors 4^-(k-1); the value of piece k
+  // carries 4^-k
+  T ad[4] = {T(0), T(0), T(0), T(0)}, aw[4] = {T(0), T(0), T(0), T(0)};
+  T full = T(0);
+  epa_piece_grad<T, 1, 3, WF>(s, s.c[0], s.c[1], T(1), T(0.25), full, ad, aw);
+  epa_piece_grad<T, 2, 5, WF>(s, s.c[1], s.c[2], T(0.25), T(0.0625), full, ad, aw);
+  epa_piece_grad<T, 3, 6, WF>(s, s.c[2], s.c[3], T(0.0625), T(0.015625), full, ad, aw);
+  epa_piece_grad<T, 4, 8, WF>(s, s.c[3], s.bmin, T(0.015625), T(0.00390625), full, ad, aw);
   const T kv = T(0.75) * s.iwv;
-  const T sc[5] = {T(1), T(0.25), T(0.0625), T(0.015625), T(0.00390625)};
-  if (WF) {
-    T f = epa_cdf4(s, s.c[0]) * T(0.25);
-#pragma unroll
-    for (int k = 1; k < 5; ++k) f += kv * sc[k] * F[k];
-    g.f = f;
-  }
-  // neighbour terms: slot i collects pieces k > i; p_i carries 3/(4 w_i) and
-  // the other factors 4^-(k-1)
+  if (WF) g.f = cfma(kv, full, epa_cdf4(s, s.c[0]) * T(0.25));
   T xsum = T(0);
 #pragma unroll
   for (int i = 0; i < 4; ++i) {
-    T ad = T(0), aw = T(0);
-#pragma unroll
-    for (int k = i + 1; k < 5; ++k) {
-      ad += sc[k - 1] * gd[k][i];
-      aw += sc[k - 1] * gw[k][i];
-    }
     const T ki = T(0.75) * s.iw[i] * kv;
-    g.dd[i] = ki * ad;
-    g.dw[i] = ki * aw;
+    g.dd[i] = ki * ad[i];
+    g.dw[i] = ki * aw[i];
     xsum = cfma(s.d[i], g.dd[i], cfma(s.w[i], g.dw[i], xsum));
   }
   g.dwv = -xsum * s.iwv;
