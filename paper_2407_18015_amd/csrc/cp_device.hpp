@@ -385,15 +385,13 @@ CP_HD void uni_side_grad(const UniSide<T>& s, UniGrad<T>& g) {
 template <typename T>
 struct EpaSide {
   T wv, iwv;
-  T c[4], d[4], iw[4], w[4];
+  T c[4], d[4], iw[4];
   bool sw[5];  // comparator swaps of the sort (unsort4 restores neighbour order)
   T bmin;
   bool empty;
 };
 
-// WW: also carry the neighbour half-widths through the sort (the adjoint
-// needs them; the forward does not).
-template <typename T, bool WW = false>
+template <typename T>
 CP_HD void epa_setup(EpaSide<T>& s, T wv, T iwv, const T (&d)[4], const T (&w)[4], const T (&iw)[4],
                      const bool (&pres)[4]) {
   s.wv = wv;
@@ -404,7 +402,7 @@ CP_HD void epa_setup(EpaSide<T>& s, T wv, T iwv, const T (&d)[4], const T (&w)[4
     if (pres[i]) bmin = tmin(bmin, d[i] + w[i]);
   s.bmin = bmin;
   s.empty = !(bmin > -wv);
-  constexpr int P = WW ? 3 : 2;
+  constexpr int P = 2;
   T key[4];
   T pay[4][P];
 #pragma unroll
@@ -412,7 +410,6 @@ CP_HD void epa_setup(EpaSide<T>& s, T wv, T iwv, const T (&d)[4], const T (&w)[4
     key[i] = pres[i] ? tclamp(d[i] - w[i], -wv, bmin) : bmin;
     pay[i][0] = pres[i] ? d[i] : T(3) * wv;
     pay[i][1] = pres[i] ? iw[i] : s.iwv;
-    if constexpr (WW) pay[i][2] = pres[i] ? w[i] : wv;
   }
   sort4_rec<T, P>(key, pay, s.sw);
 #pragma unroll
@@ -420,7 +417,6 @@ CP_HD void epa_setup(EpaSide<T>& s, T wv, T iwv, const T (&d)[4], const T (&w)[4
     s.c[i] = key[i];
     s.d[i] = pay[i][0];
     s.iw[i] = pay[i][1];
-    if constexpr (WW) s.w[i] = pay[i][2];
   }
 }
 
@@ -479,15 +475,16 @@ CP_HD T epa_side_value(const EpaSide<T>& s) {
 // Local derivatives of one side, f(wv, d_i, w_i):
 //   df/dd_i = int p_v p_i prod_{k!=i} S_k          (dS/dm = pdf)
 //   df/dw_i = int p_v u_i p_i prod_{k!=i} S_k      (dS/dw = u pdf)
-//   df/dwv  = -(1/wv) sum_i (d_i df/dd_i + w_i df/dw_i)
-// The last line is the scale invariance of P about the vertex centre
-// (wv df/dwv + sum_i (d_i df/dd_i + w_i df/dw_i) = 0): it equals
-// -(1/wv) sum_i int x p_v p_i prod_{k!=i} S_k, since x = d_i + w_i u_i, and
-// avoids integrating dpdf_v/dwv, whose integral over the support is 0 and
-// cancels.  WF: also return f itself (the fused forward).
+// and df/dwv = -(1/wv) sum_i (d_i df/dd_i + w_i df/dw_i), the scale
+// invariance of P about the vertex centre (wv df/dwv + sum_i (d_i df/dd_i +
+// w_i df/dw_i) = 0), which the caller forms in neighbour order (absent
+// neighbours have zero derivatives): it equals -(1/wv) sum_i int x p_v p_i
+// prod_{k!=i} S_k, since x = d_i + w_i u_i, and avoids integrating
+// dpdf_v/dwv, whose integral over the support is 0 and cancels.  WF: also
+// return f itself (the fused forward).
 template <typename T>
 struct EpaGrad {
-  T f, dwv;
+  T f;
   T dd[4], dw[4];  // by neighbour index
 };
 
@@ -546,7 +543,7 @@ CP_HD void epa_piece_grad(const EpaSide<T>& s, T l, T r, T sc, T fsc, T& full, T
 
 template <typename T, bool WF = true>
 CP_HD void epa_side_grad(const EpaSide<T>& s, EpaGrad<T>& g) {
-  g.f = g.dwv = T(0);
+  g.f = T(0);
 #pragma unroll
   for (int i = 0; i < 4; ++i) g.dd[i] = g.dw[i] = T(0);
   if (s.empty) return;
@@ -561,15 +558,12 @@ CP_HD void epa_side_grad(const EpaSide<T>& s, EpaGrad<T>& g) {
   epa_piece_grad<T, 4, 8, WF>(s, s.c[3], s.bmin, T(0.015625), T(0.00390625), full, ad, aw);
   const T kv = T(0.75) * s.iwv;
   if (WF) g.f = cfma(kv, full, epa_cdf4(s, s.c[0]) * T(0.25));
-  T xsum = T(0);
 #pragma unroll
   for (int i = 0; i < 4; ++i) {
     const T ki = T(0.75) * s.iw[i] * kv;
     g.dd[i] = ki * ad[i];
     g.dw[i] = ki * aw[i];
-    xsum = cfma(s.d[i], g.dd[i], cfma(s.w[i], g.dw[i], xsum));
   }
-  g.dwv = -xsum * s.iwv;
   // sorted slots -> neighbour index
   unsort4(g.dd, s.sw);
   unsort4(g.dw, s.sw);

@@ -166,32 +166,35 @@ CP_HD void vertex_jac_vals(T p0, T p1, const T (&q0)[4], const T (&q1)[4], const
       jac[3 + 2 * i] = gmin * g.db[i] - gmax * r.da[i];
     }
   } else {
-    T d[4], iw[4];
+    T d[4], nd[4], iw[4];
     const T iwv = crcp(p1);
     EpaSide<T> s;
     EpaGrad<T> g, r;
 #pragma unroll
     for (int i = 0; i < 4; ++i) {
       d[i] = q0[i] - p0;
+      nd[i] = p0 - q0[i];
       iw[i] = crcp(q1[i]);
     }
-    epa_setup<T, true>(s, p1, iwv, d, q1, iw, pres);
+    epa_setup<T>(s, p1, iwv, d, q1, iw, pres);
     epa_side_grad<T, WF>(s, g);
-#pragma unroll
-    for (int i = 0; i < 4; ++i) d[i] = p0 - q0[i];
-    epa_setup<T, true>(s, p1, iwv, d, q1, iw, pres);
+    epa_setup<T>(s, p1, iwv, nd, q1, iw, pres);
     epa_side_grad<T, WF>(s, r);
-    T sg = T(0), sr = T(0);
+    // min side: d = m_n - m_v; max side: d = m_v - m_n; the vertex width
+    // by scale invariance, summed in neighbour order (an absent neighbour's
+    // derivatives are 0)
+    T sg = T(0), sr = T(0), xg = T(0), xr = T(0);
 #pragma unroll
     for (int i = 0; i < 4; ++i) {
       sg += g.dd[i];
       sr += r.dd[i];
+      xg = cfma(d[i], g.dd[i], cfma(q1[i], g.dw[i], xg));
+      xr = cfma(nd[i], r.dd[i], cfma(q1[i], r.dw[i], xr));
     }
-    // min side: d = m_n - m_v; max side: d = m_v - m_n
     pmin = g.f;
     pmax = r.f;
     jac[0] = -gmin * sg + gmax * sr;
-    jac[1] = gmin * g.dwv + gmax * r.dwv;
+    jac[1] = -(gmin * xg + gmax * xr) * iwv;
 #pragma unroll
     for (int i = 0; i < 4; ++i) {
       jac[2 + 2 * i] = gmin * g.dd[i] - gmax * r.dd[i];
