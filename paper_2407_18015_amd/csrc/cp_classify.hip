@@ -112,17 +112,21 @@ __global__ __launch_bounds__(kFwdTX* TY) void k_classify_hist(ClassPtrs<T> f, in
   if (!ok) {
     pmin = pmax = t1 = t2 = qnan<T>();
   } else {
-    if (mm) {
-      const T lov = lds[e], hiv = lds[E + e];
-      T lo[4], hi[4];
+    const T lov = lds[e], hiv = lds[E + e];
+    T lo[4], hi[4];
 #pragma unroll
-      for (int i = 0; i < 4; ++i) {
-        lo[i] = lds[en[i]] - lov;
-        hi[i] = lds[E + en[i]] - lov;
-      }
+    for (int i = 0; i < 4; ++i) {
+      lo[i] = lds[en[i]] - lov;
+      hi[i] = lds[E + en[i]] - lov;
+    }
+    // the saddle terms ride in the sweep of P_min / P_max (a vertex without
+    // all four neighbours has none)
+    if (sad) {
+      hist_vertex_sweep<T, true>(U, e, en, pres, hiv - lov, lo, hi, pmin, pmax, t1, t2);
+      if (!(pres[0] && pres[1] && pres[2] && pres[3])) t1 = t2 = T(0);
+    } else if (mm) {
       hist_vertex_minmax(U, e, en, pres, hiv - lov, lo, hi, pmin, pmax);
     }
-    if (sad && pres[0] && pres[1] && pres[2] && pres[3]) vertex_saddle_hist(U, e, en, t1, t2);
   }
   class_store(f, y, x, pmin, pmax, t1, t2);
 }

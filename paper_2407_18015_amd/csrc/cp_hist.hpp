@@ -64,7 +64,7 @@ CP_HD T bern4(const T (&f0)[4], const T (&f1)[4]) {
   T d0 = c0 * f0[2], d1 = cfma(c0, f1[2], c1 * f0[2]), d2 = cfma(c1, f1[2], c2 * f0[2]), d3 = c2 * f1[2];
   T e0 = d0 * f0[3], e1 = cfma(d0, f1[3], d1 * f0[3]), e2 = cfma(d1, f1[3], d2 * f0[3]),
     e3 = cfma(d2, f1[3], d3 * f0[3]), e4 = d3 * f1[3];
-  return (e0 + e4) * T(0.2) + (e1 + e3) * T(0.05) + e2 * T(1.0 / 30.0);
+  return cfma(e2, T(1.0 / 30.0), cfma(e1 + e3, T(0.05), (e0 + e4) * T(0.2)));
 }
 
 }  // namespace cp
@@ -282,10 +282,16 @@ CP_HD void vertex_bins_step(VertexBins<T>& b, const T* base, int E, int h, int e
 }
 
 // P_min and P_max of vertex ev; neighbour ranges [lo_i, hi_i] in the vertex
-// frame (origin at the vertex lower end), vertex range [0, hv].
-template <typename T>
-__host__ __device__ void hist_vertex_minmax(const HistSuf<T>& L, int ev, const int (&en)[4], const bool (&pres)[4],
-                                            T hv, const T (&lo)[4], const T (&hi)[4], T& pmin, T& pmax) {
+// frame (origin at the vertex lower end), vertex range [0, hv].  SAD: also
+// the saddle terms t1 = int pdf_v S_e F_n S_w F_s and t2 = int pdf_v F_e S_n
+// F_w S_s (Eq. 4) in the same sweep: on every merged sub-interval the four
+// survival and distribution functions are the ones P_min and P_max use, so
+// the two mixed products are two more exact Bernstein integrals (the caller
+// keeps them only for vertices with all four neighbours).
+template <typename T, bool SAD = false>
+__host__ __device__ void hist_vertex_sweep(const HistSuf<T>& L, int ev, const int (&en)[4], const bool (&pres)[4],
+                                           T hv, const T (&lo)[4], const T (&hi)[4], T& pmin, T& pmax, T& t1,
+                                           T& t2) {
   const int h = L.h;
   const T big = hv + hv + T(1);
   const T dv = hv * (T(1) / T(h)), idv = T(h) * crcp(hv);
@@ -305,7 +311,7 @@ __host__ __device__ void hist_vertex_minmax(const HistSuf<T>& L, int ev, const i
     sa[i] = cfma(c[i].slope, c[i].nxt, c[i].snx);
     fa[i] = c[i].tot - sa[i];
   }
-  T x0 = T(0), amin = T(0), amax = T(0);
+  T x0 = T(0), amin = T(0), amax = T(0), a1 = T(0), a2 = T(0);
   const auto interval = [&](const T(&s0)[4], const T(&f0)[4], T(&s1)[4], T(&f1)[4]) {
     T x1 = nv;
 #pragma unroll
@@ -318,6 +324,12 @@ __host__ __device__ void hist_vertex_minmax(const HistSuf<T>& L, int ev, const i
     const T wgt = pv * (x1 - x0);
     amin = cfma(wgt, bern4(s0, s1), amin);
     amax = cfma(wgt, bern4(f0, f1), amax);
+    if constexpr (SAD) {
+      const T m0[4] = {s0[0], f0[1], s0[2], f0[3]}, m1[4] = {s1[0], f1[1], s1[2], f1[3]};
+      const T n0[4] = {f0[0], s0[1], f0[2], s0[3]}, n1[4] = {f1[0], s1[1], f1[2], s1[3]};
+      a1 = cfma(wgt, bern4(m0, m1), a1);
+      a2 = cfma(wgt, bern4(n0, n1), a2);
+    }
     if (nv == x1) {
       ++jv;
       const T un = L.U(ev, jv + 1);
@@ -338,6 +350,15 @@ __host__ __device__ void hist_vertex_minmax(const HistSuf<T>& L, int ev, const i
   }
   pmin = amin;
   pmax = amax;
+  t1 = a1;
+  t2 = a2;
+}
+
+template <typename T>
+__host__ __device__ void hist_vertex_minmax(const HistSuf<T>& L, int ev, const int (&en)[4], const bool (&pres)[4],
+                                            T hv, const T (&lo)[4], const T (&hi)[4], T& pmin, T& pmax) {
+  T t1, t2;
+  hist_vertex_sweep<T, false>(L, ev, en, pres, hv, lo, hi, pmin, pmax, t1, t2);
 }
 
 }  // namespace cp

@@ -116,66 +116,6 @@ CP_HD T epa_saddle_term(int term, T wv, T iwv, const T (&d)[4], const T (&w)[4],
 }
 
 // ---------------------------------------------------------------------------
-// histogram: sweep from a_max^alt to b_min^alt with five cursors over the
-// staged suffix sums (the vertex cursor's slope is its density); F = T - S.
-// Local frame: origin at the vertex lower end, vertex [0, hv].
-// ---------------------------------------------------------------------------
-template <typename T>
-__host__ __device__ T hist_saddle_term(int term, const HistSuf<T>& L, int ev, const int (&en)[4], T hv,
-                                       const T (&lo)[4], const T (&hi)[4]) {
-  const int h = L.h;
-  T a = T(0), b = hv;
-#pragma unroll
-  for (int i = 0; i < 4; ++i) {
-    if (saddle_is_cdf(term, i))
-      a = tmax(a, lo[i]);
-    else
-      b = tmin(b, hi[i]);
-  }
-  if (!(b > a)) return T(0);
-  const T end = b - a;
-  const T big = (hv - a) + (hv - a) + T(1);
-  SufCursor<T> cv, c[4];
-  T hs[4];
-  suf_cursor_init(cv, L, ev, -a, hv - a, true, big);
-#pragma unroll
-  for (int i = 0; i < 4; ++i) {
-    hs[i] = hi[i] - a;
-    suf_cursor_init(c[i], L, en[i], lo[i] - a, hs[i], true, big);
-  }
-  auto val = [&](const SufCursor<T>& q, int i, T x) {
-    const T sv = cfma(q.slope, q.nxt - x, q.snx);
-    return saddle_is_cdf(term, i) ? q.tot - sv : sv;
-  };
-  // factor values at the current left end (fa) and the next edge (fb); two
-  // intervals per pass with the roles swapped, so nothing is copied
-  T fa[4], fb[4];
-#pragma unroll
-  for (int i = 0; i < 4; ++i) fa[i] = val(c[i], i, T(0));
-  T x0 = T(0), acc = T(0);
-  const auto interval = [&](const T(&f0)[4], T(&f1)[4]) {
-    T x1 = tmin(cv.nxt, end);
-#pragma unroll
-    for (int i = 0; i < 4; ++i) x1 = tmin(x1, c[i].nxt);
-#pragma unroll
-    for (int i = 0; i < 4; ++i) f1[i] = val(c[i], i, x1);
-    acc = cfma(cv.slope * (x1 - x0), bern4(f0, f1), acc);
-    suf_cursor_step(cv, L, ev, hv - a, x1, big);
-#pragma unroll
-    for (int i = 0; i < 4; ++i) suf_cursor_step(c[i], L, en[i], hs[i], x1, big);
-    x0 = x1;
-  };
-  const int maxit = 5 * (h + 1) + 2;
-  for (int it = 0; it < maxit; it += 2) {
-    if (!(x0 < end)) break;
-    interval(fa, fb);
-    if (!(x0 < end) || it + 1 >= maxit) break;
-    interval(fb, fa);
-  }
-  return acc;
-}
-
-// ---------------------------------------------------------------------------
 // per-vertex evaluation from LDS (e = centre, en = e/n/w/s LDS indices)
 // ---------------------------------------------------------------------------
 template <typename T, int MODEL>
@@ -215,22 +155,6 @@ CP_HD void vertex_saddle_ue(const T* L, int E, int e, const int (&en)[4], T& t1,
     t1 = epa_saddle_term(0, p1, iwv, d, w, iw);
     t2 = epa_saddle_term(1, p1, iwv, d, w, iw);
   }
-}
-
-// Histogram saddle terms of an interior vertex (validity checked by the
-// caller; the staged masses already replaced by their suffix sums).
-template <typename T>
-__host__ __device__ void vertex_saddle_hist(const HistSuf<T>& L, int e, const int (&en)[4], T& t1, T& t2) {
-  const int E = L.E;
-  const T lov = L.base[e], hv = L.base[E + e] - lov;
-  T lo[4], hi[4];
-#pragma unroll
-  for (int i = 0; i < 4; ++i) {
-    lo[i] = L.base[en[i]] - lov;
-    hi[i] = L.base[E + en[i]] - lov;
-  }
-  t1 = hist_saddle_term(0, L, e, en, hv, lo, hi);
-  t2 = hist_saddle_term(1, L, e, en, hv, lo, hi);
 }
 
 }  // namespace cp
