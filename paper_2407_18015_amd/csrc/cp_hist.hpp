@@ -97,8 +97,8 @@ template <typename T>
 struct HistSuf {
   const T* base;
   int E, h;
-  // U_j of vertex e (U_h = 0)
-  CP_HD T U(int e, int j) const { return j >= h ? T(0) : base[(2 + j) * E + e]; }
+  // U_j of vertex e, 0 <= j <= h (plane 2 + h is the staged zero plane, U_h)
+  CP_HD T U(int e, int j) const { return base[(2 + j) * E + e]; }
 };
 
 // One neighbour in the vertex frame: survival S(x) = snx + slope (nxt - x)
@@ -149,22 +149,19 @@ CP_HD void suf_cursor_init(SufCursor<T>& c, const HistSuf<T>& L, int e, T lo, T 
   }
 }
 
+// Cross the edge x1 if it is this cursor's next edge: one branch, and inside
+// it no other (the next suffix sum is read from the zero plane once the
+// cursor leaves the range, so survival and slope become 0 by themselves).
 template <typename T>
 CP_HD void suf_cursor_step(SufCursor<T>& c, const HistSuf<T>& L, int e, T hi, T x1, T big) {
   const int h = L.h;
   if (!(c.nxt == x1)) return;
-  if (c.j < h - 1) {
-    c.j += 1;
-    const T prev = c.snx;
-    c.snx = L.U(e, c.j + 1);
-    c.slope = (prev - c.snx) * c.id;
-    c.nxt = c.j + 1 >= h ? hi : cfma(T(c.j + 1), c.d, c.lo);
-  } else {
-    c.j = h;
-    c.nxt = big;
-    c.snx = T(0);
-    c.slope = T(0);
-  }
+  const int j1 = c.j + 1;  // the bin entered (h: past the range)
+  const T prev = c.snx;
+  c.snx = L.U(e, j1 + 1 < h ? j1 + 1 : h);
+  c.slope = (prev - c.snx) * c.id;
+  c.nxt = j1 >= h ? big : (j1 + 1 >= h ? hi : cfma(T(j1 + 1), c.d, c.lo));
+  c.j = j1;
 }
 
 // ---------------------------------------------------------------------------
@@ -332,7 +329,7 @@ __host__ __device__ void hist_vertex_sweep(const HistSuf<T>& L, int ev, const in
     }
     if (nv == x1) {
       ++jv;
-      const T un = L.U(ev, jv + 1);
+      const T un = L.U(ev, jv + 1 < h ? jv + 1 : h);
       pv = (uv - un) * idv;
       uv = un;
       nv = jv + 1 < h ? T(jv + 1) * dv : hv;
