@@ -119,6 +119,10 @@ template <typename T>
 CP_HD T tmax(T a, T b) {
   return a < b ? b : a;
 }
+// minimum of two values known not to be NaN (one v_min instruction instead
+// of a compare and a select)
+CP_HD inline float fmin_nn(float a, float b) { return __builtin_fminf(a, b); }
+CP_HD inline double fmin_nn(double a, double b) { return __builtin_fmin(a, b); }
 template <typename T>
 CP_HD T tclamp(T v, T lo, T hi) {
   return tmin(tmax(v, lo), hi);

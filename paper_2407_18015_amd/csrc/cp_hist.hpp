@@ -312,7 +312,7 @@ __host__ __device__ void hist_vertex_sweep(const HistSuf<T>& L, int ev, const in
   const auto interval = [&](const T(&s0)[4], const T(&f0)[4], T(&s1)[4], T(&f1)[4]) {
     T x1 = nv;
 #pragma unroll
-    for (int i = 0; i < 4; ++i) x1 = tmin(x1, c[i].nxt);
+    for (int i = 0; i < 4; ++i) x1 = fmin_nn(x1, c[i].nxt);  // sweep edges: finite
 #pragma unroll
     for (int i = 0; i < 4; ++i) {
       s1[i] = cfma(c[i].slope, c[i].nxt - x1, c[i].snx);

@@ -65,7 +65,7 @@ __host__ __device__ void hist_jac_both(const HistSuf<T>& L, int ev, const int (&
     if (!(x0 < hv)) break;
     T x1 = vb.nv;
 #pragma unroll
-    for (int i = 0; i < 4; ++i) x1 = tmin(x1, c[i].nxt);
+    for (int i = 0; i < 4; ++i) x1 = fmin_nn(x1, c[i].nxt);  // sweep edges: finite
     const T mid = (x0 + x1) * T(0.5), hl = (x1 - x0) * T(0.5);
     const T php = vb.pv * hl, wS = php * gmin, wF = -php * gmax;
     // one node at a time (fewer registers live: the sweep needs occupancy)
