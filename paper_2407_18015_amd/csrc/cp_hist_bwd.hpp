@@ -71,8 +71,12 @@ __host__ __device__ void hist_jac_both(const HistSuf<T>& L, int ev, const int (&
     // one node at a time (fewer registers live: the sweep needs occupancy)
 #pragma unroll 1
     for (int q = 0; q < 3; ++q) {
-      const T x = cfma(hl, T(GL<3>::x[q]), mid);
-      const T wv = T(GL<3>::w[q]) * hl, wnS = T(GL<3>::w[q]) * wS, wnF = T(GL<3>::w[q]) * wF;
+      // the node and weight by selects on the (uniform) loop counter: no
+      // table loads in the loop
+      const T gx = q == 0 ? T(GL<3>::x[0]) : (q == 1 ? T(GL<3>::x[1]) : T(GL<3>::x[2]));
+      const T gw = q == 1 ? T(GL<3>::w[1]) : T(GL<3>::w[0]);
+      const T x = cfma(hl, gx, mid);
+      const T wv = gw * hl, wnS = gw * wS, wnF = gw * wF;
       T S[4], F[4], r[4];
 #pragma unroll
       for (int i = 0; i < 4; ++i) {
@@ -145,13 +149,17 @@ __host__ __device__ void hist_jac_both(const HistSuf<T>& L, int ev, const int (&
 
 // Entries of one stencil stored at J[(slot * h + k) * EJ + sj] (the layout
 // of a per-stencil Jacobian array, used by the host-side checks).
+// The plane size EJ (= H W) is below 2^30 (the descriptor check bounds the
+// grid), so the plane offset is one 32 x 32 -> 64-bit product.
 template <typename T>
 struct JPlanes {
   T* J;
-  int64_t EJ, sj;
+  uint32_t EJ;
+  int64_t sj;
   int h;
-  CP_HD void set(int slot, int k, T v) const { J[(int64_t)(slot * h + k) * EJ + sj] = v; }
-  CP_HD void add(int slot, int k, T v) const { J[(int64_t)(slot * h + k) * EJ + sj] += v; }
+  CP_HD int64_t at(int slot, int k) const { return (int64_t)((uint64_t)(uint32_t)(slot * h + k) * EJ) + sj; }
+  CP_HD void set(int slot, int k, T v) const { J[at(slot, k)] = v; }
+  CP_HD void add(int slot, int k, T v) const { J[at(slot, k)] += v; }
 };
 
 // Both sides of one stencil (centre e in the staged tile, grid position
@@ -212,7 +220,7 @@ __device__ __forceinline__ void tile_hist_sweep(const FieldPtrs<T>& f, int ty0, 
       const int64_t at = (int64_t)y * f.rs + x;
       const int64_t sj = (int64_t)y * f.W + x;
       T pmin, pmax;
-      JPlanes<T> Jo{J, (int64_t)f.H * f.W, sj, h};
+      JPlanes<T> Jo{J, (uint32_t)((int64_t)f.H * f.W), sj, h};
       hist_stencil_jac(L, U, lds, E, EX, (ly + 1) * EX + lx + 1, y, x, f.H, f.W, f.gmin[at], f.gmax[at], Jo, pmin,
                        pmax);
       if (f.pmin) {

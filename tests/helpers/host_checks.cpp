@@ -115,7 +115,7 @@ void run_hist(const std::vector<double>& p, const std::vector<double>& gmin, con
       out[v] = (double)pmin;
       out[nv + v] = (double)pmax;
       T a, b;
-      cp::JPlanes<T> jp{J.data(), (int64_t)nv, (int64_t)v, h};
+      cp::JPlanes<T> jp{J.data(), (uint32_t)nv, (int64_t)v, h};
       cp::hist_stencil_jac(L, U, g.par.data(), g.E, g.PX, e, y, x, H, W, (T)gmin[v], (T)gmax[v], jp, a, b);
     }
   for (int y = 0; y < H; ++y)
