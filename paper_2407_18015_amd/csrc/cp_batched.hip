@@ -74,10 +74,12 @@ struct BatchField {
 };
 
 // The FP32 histogram forward pass keeps the 5 waves per SIMD of its per-field
-// kernel (the tile loop would otherwise push it one register over).
+// kernel (the tile loop would otherwise push it one register over), and the
+// FP32 histogram adjoint sweep 4 (at 132 registers it would drop to 3: the
+// tuned 64 x 8 variant then ran 7% longer).
 template <typename T, int PASS>
 constexpr int batched_min_waves() {
-  return sizeof(T) == 4 && PASS == PASS_FWD_HIST ? 5 : 1;
+  return sizeof(T) == 4 && PASS == PASS_FWD_HIST ? 5 : (sizeof(T) == 4 && PASS == PASS_BWD_HIST ? 4 : 1);
 }
 
 // Tiles are claimed in chunks of `chunk` consecutive entries (neighbouring
