@@ -73,7 +73,7 @@ __host__ __device__ void hist_jac_both(const HistSuf<T>& L, int ev, const int (&
     for (int q = 0; q < 3; ++q) {
       // the node and weight by selects on the (uniform) loop counter: no
       // table loads in the loop
-      const T gx = q == 0 ? T(GL<3>::x[0]) : (q == 1 ? T(GL<3>::x[1]) : T(GL<3>::x[2]));
+      const T gx = T(q - 1) * T(GL<3>::x[2]);  // -x2, 0, x2 (the rule is symmetric)
       const T gw = q == 1 ? T(GL<3>::w[1]) : T(GL<3>::w[0]);
       const T x = cfma(hl, gx, mid);
       const T wv = gw * hl, wnS = gw * wS, wnF = gw * wF;
