@@ -108,8 +108,8 @@ __global__ __launch_bounds__(256) void k_fit_fwd_ue(FitFwdArgs<T> a, int tiles_x
 template <typename T, int MODEL>
 hipError_t launch(const FitFwdArgs<T>& a, hipStream_t st) {
   // 64 x 12 tiles: the 14 staged rows of 16-byte groups (252 in FP32) take
-  // the 256 threads once; grids with fewer than eight such tiles per CU use
-  // 64 x 4.  Measured at 2048^2 (Epanechnikov, 20 members): 64 x 12 128 us,
+  // the 256 threads once (FP64's 476 twice); grids with fewer than eight
+  // such tiles per CU use 64 x 4.  Measured at 2048^2 (Epanechnikov, 20 members): 64 x 12 128 us,
   // 64 x 16 (two passes of groups) 135 us, fit then forward 162 us.
   const int tx = (a.f.W + kFwdTX - 1) / kFwdTX;
   const bool tall = (int64_t)tx * ((a.f.H + 11) / 12) >= kTallTileBlocks;
