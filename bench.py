@@ -248,17 +248,18 @@ def uni_flops(params):
 #                (4), interval weight (2), two exact integrals of a product
 #                of four linear factors from their end values (2 x 31), two
 #                accumulations (4), advancing the edge that ends it (4).
-#   adjoint 206: midpoint, half-length and node-weight scales (7); per
-#                Gauss-Legendre node (3) 63 (node, weights, four S and F
-#                values, pair products, vertex-slot sums, upstream-weighted
+#   adjoint 163: midpoint, half-length, node offset and weight scales (8);
+#                per Gauss-Legendre node (2) 60 (node, four S and F values,
+#                pair products, vertex-slot sums, upstream-weighted
 #                leave-one-out products for both sides and their plain and
-#                bin-kernel-weighted sums); 10 to emit the entry of the edge
+#                bin-kernel-weighted sums); the rule's degree-4 remainder
+#                from the four slopes (25); 10 to emit the entry of the edge
 #                that ends it and advance that edge.  Per vertex 9h: the
 #                closing pass over each neighbour's bins and the gather of
 #                five stencils' entries.
 # ----------------------------------------------------------------------------
 HIST_FWD_INTERVAL = 88
-HIST_BWD_INTERVAL = 206
+HIST_BWD_INTERVAL = 163
 
 
 def hist_flops(params, nbins: int):

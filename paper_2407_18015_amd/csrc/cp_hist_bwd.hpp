@@ -5,8 +5,10 @@
 // P_max (prod F = T - S), the leave-one-out products of every neighbour and
 // their products with the survival function of the neighbour's current bin
 // kernel, and emits each bin's weighted entry when the sweep leaves the bin.
-// Every sub-interval is integrated with 3-point Gauss-Legendre (integrands of
-// degree <= 4).  Entries of absent neighbours are not emitted.
+// On every sub-interval all factors are linear, so the integrands are
+// polynomials of degree <= 4: 2-point Gauss-Legendre plus the rule's
+// remainder for the quartic terms, in closed form from the factors' slopes,
+// integrates them exactly.  Entries of absent neighbours are not emitted.
 //
 // The sweep tile writes each stencil's entries to a workspace; a second
 // kernel gathers every mass's five entries (no atomics).
@@ -68,15 +70,14 @@ __host__ __device__ void hist_jac_both(const HistSuf<T>& L, int ev, const int (&
     for (int i = 0; i < 4; ++i) x1 = fmin_nn(x1, c[i].nxt);  // sweep edges: finite
     const T mid = (x0 + x1) * T(0.5), hl = (x1 - x0) * T(0.5);
     const T php = vb.pv * hl, wS = php * gmin, wF = -php * gmax;
-    // one node at a time (fewer registers live: the sweep needs occupancy)
+    // two-point Gauss-Legendre: exact for the leave-one-out products (degree
+    // 3); the degree-4 integrands (full products, leave-one-out products times
+    // the bin kernel) get the rule's remainder in closed form below.  One node
+    // at a time (fewer registers live: the sweep needs occupancy).
+    const T dx = hl * T(GL<2>::x[1]);
 #pragma unroll 1
-    for (int q = 0; q < 3; ++q) {
-      // the node and weight by selects on the (uniform) loop counter: no
-      // table loads in the loop
-      const T gx = T(q - 1) * T(GL<3>::x[2]);  // -x2, 0, x2 (the rule is symmetric)
-      const T gw = q == 1 ? T(GL<3>::w[1]) : T(GL<3>::w[0]);
-      const T x = cfma(hl, gx, mid);
-      const T wv = gw * hl, wnS = gw * wS, wnF = gw * wF;
+    for (int q = 0; q < 2; ++q) {
+      const T x = q ? mid + dx : mid - dx;  // both weights 1
       T S[4], F[4], r[4];
 #pragma unroll
       for (int i = 0; i < 4; ++i) {
@@ -85,9 +86,9 @@ __host__ __device__ void hist_jac_both(const HistSuf<T>& L, int ev, const int (&
         F[i] = c[i].tot - S[i];
       }
       const T s01 = S[0] * S[1], s23 = S[2] * S[3], f01 = F[0] * F[1], f23 = F[2] * F[3];
-      vS = cfma(wv * s01, s23, vS);
-      vF = cfma(wv * f01, f23, vF);
-      const T ps01 = wnS * s01, ps23 = wnS * s23, pf01 = wnF * f01, pf23 = wnF * f23;
+      vS = cfma(hl * s01, s23, vS);
+      vF = cfma(hl * f01, f23, vF);
+      const T ps01 = wS * s01, ps23 = wS * s23, pf01 = wF * f01, pf23 = wF * f23;
       const T ls[4] = {S[1] * ps23, S[0] * ps23, S[3] * ps01, S[2] * ps01};
       const T lf[4] = {F[1] * pf23, F[0] * pf23, F[3] * pf01, F[2] * pf01};
 #pragma unroll
@@ -96,6 +97,25 @@ __host__ __device__ void hist_jac_both(const HistSuf<T>& L, int ev, const int (&
         QF[i] += lf[i];
         Eh[i] = cfma(ls[i] + lf[i], r[i], Eh[i]);
       }
+    }
+    // The rule misses (8/45) hl^5 c4 of a quartic with leading coefficient
+    // c4.  S_k has slope -s_k and F_k slope +s_k (s_k the cursor's density),
+    // so c4 is s0 s1 s2 s3 for both full products, and pdf_v (g_min + g_max)
+    // times the other three densities for an entry's kernel-weighted
+    // integrand; in t_k = hl s_k (a change of S_k, bounded) no power of hl
+    // or of a density is formed.
+    {
+      T t[4];
+#pragma unroll
+      for (int i = 0; i < 4; ++i) t[i] = hl * c[i].slope;
+      const T t01 = t[0] * t[1], t23 = t[2] * t[3];
+      const T k45 = T(8.0 / 45.0) * hl;
+      const T kv = k45 * (t01 * t23), ke = k45 * (wS - wF);
+      vS += kv;
+      vF += kv;
+      const T lt[4] = {t[1] * t23, t[0] * t23, t[3] * t01, t[2] * t01};
+#pragma unroll
+      for (int i = 0; i < 4; ++i) Eh[i] = cfma(ke, lt[i], Eh[i]);
     }
     // vertex bin boundary: its entry is complete
     const bool advv = vb.nv == x1;
