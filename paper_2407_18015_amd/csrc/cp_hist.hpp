@@ -168,23 +168,23 @@ CP_HD void suf_cursor_step(SufCursor<T>& c, const HistSuf<T>& L, int e, T hi, T 
 // Branch-free cursor (the adjoint sweep): the same survival function as
 // SufCursor, S(x) = snx + slope (nxt - x) on the current bin, F = tot - S, in
 // a frame where the sweep runs from x = 0.  It holds the index m of its next
-// edge (0 below the range, h + 1 past it) and the LDS index of U_m, clamped
-// to the zero plane; the edges are lo + m Delta for m < h and hi itself for
-// m = h.  Every step is written with selects, so a wave whose lanes cross
-// different edges runs one straight sequence of instructions.  The forward
-// and saddle sweeps keep SufCursor: its branchy steps need fewer registers,
-// and those sweeps gain more from occupancy than from fewer instructions.
+// edge (0 below the range, h + 1 past it); U_m is read from plane
+// 2 + min(m, h) (the zero plane past the range), so no LDS index is kept; the
+// edges are lo + m Delta for m < h and hi itself for m = h.  Every step is
+// written with selects, so a wave whose lanes cross different edges runs one
+// straight sequence of instructions.  The forward and saddle sweeps keep
+// SufCursor: its branchy steps need fewer registers, and those sweeps gain
+// more from occupancy than from fewer instructions.
 // ---------------------------------------------------------------------------
 template <typename T>
 struct HistCursor {
-  T m;     // index of the next edge (0 below the range, h + 1 past it)
-  int a;   // LDS index of U_m (the vertex's zero plane once m >= h)
+  int m;   // index of the next edge (0 below the range, h + 1 past it)
   T nxt;   // next edge (big past the range)
   T snx;   // U_m: survival at the next edge
   T slope; // mass density of the current bin (0 outside the range)
   T tot, lo, hi, d, id;
   // inside the range (the current bin is a bin of this histogram)
-  CP_HD bool in_range(T hf) const { return !(m < T(1)) && !(m > hf); }
+  CP_HD bool in_range(int h) const { return (unsigned)(m - 1) < (unsigned)h; }
 };
 
 // `present` false: the constant factor 1 in both products (S = 1, F = 2 - 1)
@@ -197,8 +197,7 @@ CP_HD void hist_cursor_init(HistCursor<T>& c, const T* base, int E, int h, int e
   c.id = hf * crcp(hi - lo);
   c.slope = T(0);
   if (!present) {
-    c.m = hf + T(1);
-    c.a = (2 + h) * E + e;
+    c.m = h + 1;
     c.nxt = big;
     c.snx = T(1);
     c.tot = T(2);
@@ -206,15 +205,13 @@ CP_HD void hist_cursor_init(HistCursor<T>& c, const T* base, int E, int h, int e
   }
   c.tot = base[2 * E + e];
   if (!(hi > T(0))) {  // the whole range lies at or below x = 0
-    c.m = hf + T(1);
-    c.a = (2 + h) * E + e;
+    c.m = h + 1;
     c.nxt = big;
     c.snx = T(0);
     return;
   }
   if (!(lo < T(0))) {  // range starts at or after x = 0
-    c.m = T(0);
-    c.a = 2 * E + e;
+    c.m = 0;
     c.nxt = lo;
     c.snx = c.tot;
     return;
@@ -224,25 +221,21 @@ CP_HD void hist_cursor_init(HistCursor<T>& c, const T* base, int E, int h, int e
   const auto edge = [&](int k) { return k >= h ? hi : cfma(T(k), c.d, lo); };
   if (j + 1 < h && !(edge(j + 1) > T(0))) ++j;
   if (j > 0 && edge(j) > T(0)) --j;
-  c.m = T(j + 1);
-  c.a = (3 + j) * E + e;
+  c.m = j + 1;
   c.nxt = edge(j + 1);
-  c.snx = base[c.a];
+  c.snx = base[(3 + j) * E + e];
   c.slope = (base[(2 + j) * E + e] - c.snx) * c.id;
 }
 
-// advance to the next edge where adv; az = LDS index of this histogram's
-// zero plane
+// Advance to the next edge if `adv` (selects, no branch); e is the
+// histogram's LDS index in a plane.
 template <typename T>
-CP_HD void hist_cursor_step(HistCursor<T>& c, const T* base, int E, int az, T hf, T big, bool adv) {
-  const T m1 = c.m + T(1);
-  const int a1 = c.a + E < az ? c.a + E : az;
-  const T u1 = base[a1];
-  const bool inr = !(m1 > hf);
-  const T nx1 = m1 < hf ? cfma(m1, c.d, c.lo) : (inr ? c.hi : big);
+CP_HD void hist_cursor_step(HistCursor<T>& c, const T* base, int E, int e, int h, T big, bool adv) {
+  const int m1 = c.m + 1;
+  const T u1 = base[(2 + (m1 < h ? m1 : h)) * E + e];
+  const T nx1 = m1 < h ? cfma(T(m1), c.d, c.lo) : (m1 == h ? c.hi : big);
   const T sl1 = (c.snx - u1) * c.id;
   c.m = adv ? m1 : c.m;
-  c.a = adv ? a1 : c.a;
   c.snx = adv ? u1 : c.snx;
   c.slope = adv ? sl1 : c.slope;
   c.nxt = adv ? nx1 : c.nxt;

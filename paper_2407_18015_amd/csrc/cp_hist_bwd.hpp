@@ -57,9 +57,11 @@ __host__ __device__ void hist_jac_both(const HistSuf<T>& L, int ev, const int (&
   HistCursor<T> c[4];
 #pragma unroll
   for (int i = 0; i < 4; ++i) hist_cursor_init(c[i], base, E, h, en[i], lo[i], hi[i], pres[i], big);
-  T QS[4], QF[4], B[4], Eh[4];
+  // Y_n = B_n Delta_n + (kernel-weighted integral over the open bin so far):
+  // the entry of a bin left is Y_n / Delta_n
+  T QS[4], QF[4], Y[4];
 #pragma unroll
-  for (int i = 0; i < 4; ++i) QS[i] = QF[i] = B[i] = Eh[i] = T(0);
+  for (int i = 0; i < 4; ++i) QS[i] = QF[i] = Y[i] = T(0);
   T vS = T(0), vF = T(0), amin = T(0), amax = T(0);
   T x0 = T(0);
   const int maxit = 5 * (h + 1) + 2;
@@ -95,7 +97,7 @@ __host__ __device__ void hist_jac_both(const HistSuf<T>& L, int ev, const int (&
       for (int i = 0; i < 4; ++i) {
         QS[i] += ls[i];
         QF[i] += lf[i];
-        Eh[i] = cfma(ls[i] + lf[i], r[i], Eh[i]);
+        Y[i] = cfma(ls[i] + lf[i], r[i], Y[i]);
       }
     }
     // The rule misses (8/45) hl^5 c4 of a quartic with leading coefficient
@@ -115,7 +117,7 @@ __host__ __device__ void hist_jac_both(const HistSuf<T>& L, int ev, const int (&
       vF += kv;
       const T lt[4] = {t[1] * t23, t[0] * t23, t[3] * t01, t[2] * t01};
 #pragma unroll
-      for (int i = 0; i < 4; ++i) Eh[i] = cfma(ke, lt[i], Eh[i]);
+      for (int i = 0; i < 4; ++i) Y[i] = cfma(ke, lt[i], Y[i]);
     }
     // vertex bin boundary: its entry is complete
     const bool advv = vb.nv == x1;
@@ -130,10 +132,9 @@ __host__ __device__ void hist_jac_both(const HistSuf<T>& L, int ev, const int (&
     for (int i = 0; i < 4; ++i) {
       const bool adv = c[i].nxt == x1;
       // bin m - 1 is left; it is a bin of the range for 1 <= m <= h
-      if (adv && c[i].in_range(hf)) J.set(1 + i, (int)c[i].m - 1, cfma(c[i].id, Eh[i], B[i]));
-      B[i] = adv ? QS[i] + QF[i] : B[i];
-      Eh[i] = adv ? T(0) : Eh[i];
-      hist_cursor_step(c[i], base, E, (2 + h) * E + en[i], hf, big, adv);
+      if (adv && c[i].in_range(h)) J.set(1 + i, c[i].m - 1, c[i].id * Y[i]);
+      Y[i] = adv ? (QS[i] + QF[i]) * c[i].d : Y[i];
+      hist_cursor_step(c[i], base, E, en[i], h, big, adv);
     }
     x0 = x1;
   }
@@ -144,20 +145,19 @@ __host__ __device__ void hist_jac_both(const HistSuf<T>& L, int ev, const int (&
 #pragma unroll
   for (int i = 0; i < 4; ++i) {
     if (!pres[i]) continue;
-    const int j = (int)c[i].m - 1;  // open bin (-1: below the range, h: past it)
+    const int j = c[i].m - 1;  // open bin (-1: below the range, h: past it)
     const T tf = -QF[i];            // g_max QF_n(hv)
     // first bin the sweep entered (the cursor's start, found again)
     HistCursor<T> c0;
     hist_cursor_init(c0, base, E, h, en[i], lo[i], hi[i], true, big);
-    const int first = c0.m < T(1) ? 0 : (int)c0.m - 1;
-    const T kin = c[i].in_range(hf) ? c[i].id : T(0);
+    const int first = c0.m < 1 ? 0 : c0.m - 1;
     for (int k = 0; k < h; ++k) {
       if (k < first) {
         J.set(1 + i, k, tf);  // entirely below the sweep: dF/dm = 1 there
       } else if (k < j) {
         J.add(1 + i, k, tf);  // emitted when the sweep left it
       } else if (k == j) {
-        J.set(1 + i, k, cfma(kin, Eh[i], B[i]) + tf);
+        J.set(1 + i, k, cfma(c[i].id, Y[i], tf));  // k == j: inside the range
       } else {
         J.set(1 + i, k, QS[i]);  // entirely above the sweep: dS/dm = 1 there
       }
