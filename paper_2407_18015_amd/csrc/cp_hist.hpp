@@ -102,17 +102,19 @@ struct HistSuf {
 };
 
 // One neighbour in the vertex frame: survival S(x) = snx + slope (nxt - x)
-// on the current bin; F = tot - S.
+// on the current bin; F = tot - S.  Its edges above the first are counted
+// down from the last, hi - (h - k) Delta (k = h: hi itself), so the cursor
+// keeps hi and not lo.
 template <typename T>
 struct SufCursor {
   int j;  // -1 below the range, h above it
-  T lo, d, id, nxt, snx, slope, tot;
+  T hi, d, id, nxt, snx, slope, tot;
 };
 
 template <typename T>
 CP_HD void suf_cursor_init(SufCursor<T>& c, const HistSuf<T>& L, int e, T lo, T hi, bool present, T big) {
   const int h = L.h;
-  c.lo = lo;
+  c.hi = hi;
   c.d = (hi - lo) * (T(1) / T(h));
   c.id = T(h) * crcp(hi - lo);
   if (!present) {  // constant factor 1 in both products
@@ -133,7 +135,7 @@ CP_HD void suf_cursor_init(SufCursor<T>& c, const HistSuf<T>& L, int e, T lo, T 
   }
   int j = (int)(-lo * c.id);
   j = j < 0 ? 0 : (j > h - 1 ? h - 1 : j);
-  const auto edge = [&](int k) { return k >= h ? hi : cfma(T(k), c.d, lo); };
+  const auto edge = [&](int k) { return cfma(T(k - h), c.d, hi); };  // 1 <= k <= h
   if (j + 1 < h && !(edge(j + 1) > T(0))) ++j;
   if (j > 0 && edge(j) > T(0)) --j;
   c.j = j;
@@ -153,14 +155,14 @@ CP_HD void suf_cursor_init(SufCursor<T>& c, const HistSuf<T>& L, int e, T lo, T 
 // it no other (the next suffix sum is read from the zero plane once the
 // cursor leaves the range, so survival and slope become 0 by themselves).
 template <typename T>
-CP_HD void suf_cursor_step(SufCursor<T>& c, const HistSuf<T>& L, int e, T hi, T x1, T big) {
+CP_HD void suf_cursor_step(SufCursor<T>& c, const HistSuf<T>& L, int e, T x1, T big) {
   const int h = L.h;
   if (!(c.nxt == x1)) return;
   const int j1 = c.j + 1;  // the bin entered (h: past the range)
   const T prev = c.snx;
   c.snx = L.U(e, j1 + 1 < h ? j1 + 1 : h);
   c.slope = (prev - c.snx) * c.id;
-  c.nxt = j1 >= h ? big : (j1 + 1 >= h ? hi : cfma(T(j1 + 1), c.d, c.lo));
+  c.nxt = j1 >= h ? big : cfma(T(j1 + 1 - h), c.d, c.hi);
   c.j = j1;
 }
 
@@ -287,8 +289,8 @@ __host__ __device__ void hist_vertex_sweep(const HistSuf<T>& L, int ev, const in
   const T dv = hv * (T(1) / T(h)), idv = T(h) * crcp(hv);
   int jv = 0;
   T nv = h > 1 ? dv : hv;
-  T uv = L.U(ev, 1);
-  T pv = (L.U(ev, 0) - uv) * idv;
+  T uv = L.U(ev, 1);                // U_{jv+1} (carried by the saddle sweep only)
+  T pv = (L.U(ev, 0) - uv) * idv;   // density of the vertex's bin jv
   SufCursor<T> c[4];
 #pragma unroll
   for (int i = 0; i < 4; ++i) suf_cursor_init(c[i], L, en[i], lo[i], hi[i], pres[i], big);
@@ -323,12 +325,16 @@ __host__ __device__ void hist_vertex_sweep(const HistSuf<T>& L, int ev, const in
     if (nv == x1) {
       ++jv;
       const T un = L.U(ev, jv + 1 < h ? jv + 1 : h);
-      pv = (uv - un) * idv;
-      uv = un;
+      if constexpr (SAD) {
+        pv = (uv - un) * idv;
+        uv = un;
+      } else {  // read again: one register less, which gives P_min / P_max a sixth wave per SIMD
+        pv = (L.U(ev, jv) - un) * idv;
+      }
       nv = jv + 1 < h ? T(jv + 1) * dv : hv;
     }
 #pragma unroll
-    for (int i = 0; i < 4; ++i) suf_cursor_step(c[i], L, en[i], hi[i], x1, big);
+    for (int i = 0; i < 4; ++i) suf_cursor_step(c[i], L, en[i], x1, big);
     x0 = x1;
   };
   const int maxit = 5 * (h + 1) + 2;  // every step crosses at least one edge
