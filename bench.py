@@ -82,31 +82,35 @@ def parse():
 
 # ----------------------------------------------------------------------------
 # algorithmic work of the Epanechnikov kernels: FLOPs of the kernels'
-# formulation per non-empty piece with k started neighbours at the exact
-# quadrature order n_k (FMA = 2); redundant work (empty pieces, halo ring,
-# masked lanes, sorting) is not counted.
+# formulation per non-empty piece with k started neighbours at the quadrature
+# order n_k (FMA = 2); redundant work (empty pieces, halo ring, masked lanes,
+# sorting) is not counted.  Pieces with k = 2 and 4 take n_k = (3k + 2) / 2
+# nodes plus the rule's closed-form remainder on the top-degree terms.
 #   forward piece k:  setup 6 + 3k; per node 6 + 7k (node, vertex pdf, per
-#                     factor u, 4 S(u) and the product); 3 to accumulate.
-#                     Piece 0 (vertex CDF in closed form): 6.
+#                     factor u, 4 S(u) and the product); 3 to accumulate;
+#                     remainder 3 + 3k.  Piece 0 (vertex CDF in closed
+#                     form): 6.
 #   adjoint piece k:  setup 6 + 3k; per node 4 + 15k (node, weight x pdf,
 #                     per factor u, 4 S(u), prefix / suffix products, the
 #                     leave-one-out product times (1 - u^2), two moments);
-#                     4k to accumulate.  Piece 0 needs no adjoint work.
-#                     Per vertex 8 for the gather of the five stencils.
+#                     4k to accumulate; remainder 2 + 4k.  Piece 0 needs no
+#                     adjoint work.  Per vertex 8 for the gather of the five
+#                     stencils.
 # ----------------------------------------------------------------------------
-GL_NODES = {1: 3, 2: 5, 3: 6, 4: 8}  # exact rule for a piece with k started neighbours
+GL_NODES = {1: 3, 2: 4, 3: 6, 4: 7}  # rule for a piece with k started neighbours
+GL_REM = {1: False, 2: True, 3: False, 4: True}  # plus the remainder term
 
 
 def flops_fwd_piece(k):
     if k == 0:
         return 6
-    return 9 + 3 * k + GL_NODES[k] * (6 + 7 * k)
+    return 9 + 3 * k + GL_NODES[k] * (6 + 7 * k) + (3 + 3 * k if GL_REM[k] else 0)
 
 
 def flops_bwd_piece(k):
     if k == 0:
         return 0
-    return 6 + 7 * k + GL_NODES[k] * (4 + 15 * k)
+    return 6 + 7 * k + GL_NODES[k] * (4 + 15 * k) + (2 + 4 * k if GL_REM[k] else 0)
 
 
 def _torch(a):

@@ -369,7 +369,7 @@ cp_status_t cp_philox4x32_10(int64_t n, const uint32_t* counters, uint64_t seed,
 
 /*
  * Gauss-Legendre rule the closed-form kernels use for an n-point piece
- * (n in {1, 2, 3, 5, 6, 8, 10}): host copies of the device tables, for checking.
+ * (n in {1, 2, 3, 4, 5, 6, 7, 8, 10}): host copies of the device tables, for checking.
  * Returns CP_EINVAL for other n.
  */
 cp_status_t cp_gauss_legendre(int32_t n, double* nodes, double* weights);

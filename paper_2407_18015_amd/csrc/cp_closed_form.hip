@@ -212,8 +212,10 @@ bool gl_table(int n, double* x, double* w) {
     CP_GL_CASE(1)
     CP_GL_CASE(2)
     CP_GL_CASE(3)
+    CP_GL_CASE(4)
     CP_GL_CASE(5)
     CP_GL_CASE(6)
+    CP_GL_CASE(7)
     CP_GL_CASE(8)
     CP_GL_CASE(10)
 #undef CP_GL_CASE

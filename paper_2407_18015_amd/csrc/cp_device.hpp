@@ -69,6 +69,13 @@ struct GL<3> {
                                   0.55555555555555555556};
 };
 template <>
+struct GL<4> {
+  static constexpr double x[4] = {-0.86113631159405257522, -0.33998104358485626480, 0.33998104358485626480,
+                                  0.86113631159405257522};
+  static constexpr double w[4] = {0.34785484513745385737, 0.65214515486254614263, 0.65214515486254614263,
+                                  0.34785484513745385737};
+};
+template <>
 struct GL<5> {
   static constexpr double x[5] = {-0.90617984593866399280, -0.53846931010568309104, 0.0,
                                   0.53846931010568309104, 0.90617984593866399280};
@@ -84,6 +91,14 @@ struct GL<6> {
   static constexpr double w[6] = {0.17132449237917034504, 0.36076157304813860757,
                                   0.46791393457269104739, 0.46791393457269104739,
                                   0.36076157304813860757, 0.17132449237917034504};
+};
+template <>
+struct GL<7> {
+  static constexpr double x[7] = {-0.94910791234275852453, -0.74153118559939443986, -0.40584515137739716691, 0.0,
+                                  0.40584515137739716691,  0.74153118559939443986,  0.94910791234275852453};
+  static constexpr double w[7] = {0.12948496616886969327, 0.27970539148927666790, 0.38183005050511894495,
+                                  0.41795918367346938776, 0.38183005050511894495, 0.27970539148927666790,
+                                  0.12948496616886969327};
 };
 template <>
 struct GL<8> {
@@ -106,6 +121,25 @@ struct GL<10> {
                                    0.26926671930999635509,  0.29552422471475287017, 0.29552422471475287017,
                                    0.26926671930999635509,  0.21908636251598204400, 0.14945134915058059315,
                                    0.066671344308688137594};
+};
+
+// What the N-point rule misses on y^(2N) over [-1, 1],
+// 2^(2N+1) (N!)^4 / ((2N+1) ((2N)!)^2): for a polynomial of degree <= 2N+1
+// whose y^(2N) coefficient is c, the integral is the rule's sum plus e c (an
+// odd top term integrates to zero under both).
+template <int N>
+struct GLRem;
+template <>
+struct GLRem<2> {
+  static constexpr double e = 8.0 / 45.0;
+};
+template <>
+struct GLRem<4> {
+  static constexpr double e = 128.0 / 11025.0;
+};
+template <>
+struct GLRem<7> {
+  static constexpr double e = 512.0 / 2760615.0;
 };
 
 // ---------------------------------------------------------------------------
@@ -382,9 +416,12 @@ CP_HD void uni_side_grad(const UniSide<T>& s, UniGrad<T>& g) {
 // Epanechnikov model (Sec. 4.3).  Local frame with origin at the vertex
 // centre: vertex support [-wv, wv], neighbour i centre d_i, half-width w_i.
 // pdf_v = 3/(4 wv) (1 - t^2), S_i = (1 - u)^2 (2 + u) / 4 with t = x/wv,
-// u = (x - d_i)/w_i.  Piece k (k neighbours started) has degree 2 + 3k:
-// Gauss-Legendre with 3, 5, 6, 8 nodes is exact for k = 1..4 (the paper's
-// order-15 remark, Sec. 4.3); piece 0 is the vertex CDF in closed form.
+// u = (x - d_i)/w_i.  Piece k (k neighbours started) has degree 2 + 3k
+// (the paper's order-15 remark, Sec. 4.3): Gauss-Legendre with 3 and 6
+// nodes is exact for k = 1 and 3; k = 2 and 4 (degree 8 and 14) take 4 and 7
+// nodes plus the rule's remainder on the top-degree term, whose coefficient
+// is a product of the factors' leading coefficients; piece 0 is the vertex
+// CDF in closed form.
 // ===========================================================================
 template <typename T>
 struct EpaSide {
@@ -440,9 +477,12 @@ CP_HD T epa_s4(T u) {
   return cfma(cfma(u, u, T(-3)), u, T(2));
 }
 
-// integral over [l, r] of (1 - t^2) prod_{i<K} 4 S_i   (unscaled)
-template <typename T, int K, int N>
+// integral over [l, r] of (1 - t^2) prod_{i<K} 4 S_i   (unscaled): the
+// N-point rule, plus (REM) its remainder when the integrand's degree 2 + 3K
+// is 2N: the y^(2N) coefficient is -bv^2 prod bu_i^3
+template <typename T, int K, int N, bool REM = false>
 CP_HD T epa_piece(const EpaSide<T>& s, T l, T r) {
+  static_assert(REM ? 2 + 3 * K == 2 * N : 2 + 3 * K <= 2 * N - 1, "rule too small for the piece");
   const T mid = (l + r) * T(0.5), hl = (r - l) * T(0.5);
   const T av = mid * s.iwv, bv = hl * s.iwv;
   T au[K], bu[K];
@@ -461,6 +501,12 @@ CP_HD T epa_piece(const EpaSide<T>& s, T l, T r) {
     for (int i = 0; i < K; ++i) prod *= epa_s4(cfma(bu[i], x, au[i]));
     sum = cfma(T(GL<N>::w[j]), prod, sum);
   }
+  if constexpr (REM) {
+    T c = bv * bv;
+#pragma unroll
+    for (int i = 0; i < K; ++i) c *= bu[i] * bu[i] * bu[i];
+    sum = cfma(T(-GLRem<N>::e), c, sum);
+  }
   return sum * hl;
 }
 
@@ -470,9 +516,9 @@ CP_HD T epa_side_value(const EpaSide<T>& s) {
   const T kv = T(0.75) * s.iwv;  // pdf scale 3/(4 wv)
   T acc = epa_cdf4(s, s.c[0]) * T(0.25);
   T p = epa_piece<T, 1, 3>(s, s.c[0], s.c[1]) * T(0.25);
-  p += epa_piece<T, 2, 5>(s, s.c[1], s.c[2]) * T(0.0625);
+  p += epa_piece<T, 2, 4, true>(s, s.c[1], s.c[2]) * T(0.0625);
   p += epa_piece<T, 3, 6>(s, s.c[2], s.c[3]) * T(0.015625);
-  p += epa_piece<T, 4, 8>(s, s.c[3], s.bmin) * T(0.00390625);
+  p += epa_piece<T, 4, 7, true>(s, s.c[3], s.bmin) * T(0.00390625);
   return acc + kv * p;
 }
 
@@ -496,8 +542,14 @@ struct EpaGrad {
 // slot sums, times the piece's factor sc = 4^-(K-1) and its half-length, are
 // added straight into the side's accumulators ad / aw (by sorted slot); WF:
 // the piece's value, times fsc = 4^-K and the half-length, into `full`.
-template <typename T, int K, int N, bool WF>
+// The position sums have degree 3K + 1, the width sums and the value 3K + 2;
+// REM: N = (3K + 2) / 2 nodes and the rule's remainder, from the y^(2N)
+// coefficient, which is bv^2 prod_k bu_k^3 for every width sum (the leading
+// coefficients -bv^2, -bu_i^2 and bu_i of its own factors, bu_k^3 of the
+// others) and its negative for the value.
+template <typename T, int K, int N, bool REM, bool WF>
 CP_HD void epa_piece_grad(const EpaSide<T>& s, T l, T r, T sc, T fsc, T& full, T (&ad)[4], T (&aw)[4]) {
+  static_assert(REM ? 3 * K + 2 == 2 * N : 3 * K + 2 <= 2 * N - 1, "rule too small for the piece");
   const T mid = (l + r) * T(0.5), hl = (r - l) * T(0.5);
   const T av = mid * s.iwv, bv = hl * s.iwv;
   T au[K], bu[K];
@@ -536,6 +588,15 @@ CP_HD void epa_piece_grad(const EpaSide<T>& s, T l, T r, T sc, T fsc, T& full, T
       sww[i] = cfma(lw, u[i], sww[i]);
     }
   }
+  if constexpr (REM) {
+    T c = bv * bv;
+#pragma unroll
+    for (int i = 0; i < K; ++i) c *= bu[i] * bu[i] * bu[i];
+    const T ec = T(GLRem<N>::e) * c;
+    if (WF) sf -= ec;
+#pragma unroll
+    for (int i = 0; i < K; ++i) sww[i] += ec;
+  }
   const T ps = sc * hl;
   if (WF) full = cfma(sf, fsc * hl, full);
 #pragma unroll
@@ -556,10 +617,10 @@ CP_HD void epa_side_grad(const EpaSide<T>& s, EpaGrad<T>& g) {
   // carries 4^-k
   T ad[4] = {T(0), T(0), T(0), T(0)}, aw[4] = {T(0), T(0), T(0), T(0)};
   T full = T(0);
-  epa_piece_grad<T, 1, 3, WF>(s, s.c[0], s.c[1], T(1), T(0.25), full, ad, aw);
-  epa_piece_grad<T, 2, 5, WF>(s, s.c[1], s.c[2], T(0.25), T(0.0625), full, ad, aw);
-  epa_piece_grad<T, 3, 6, WF>(s, s.c[2], s.c[3], T(0.0625), T(0.015625), full, ad, aw);
-  epa_piece_grad<T, 4, 8, WF>(s, s.c[3], s.bmin, T(0.015625), T(0.00390625), full, ad, aw);
+  epa_piece_grad<T, 1, 3, false, WF>(s, s.c[0], s.c[1], T(1), T(0.25), full, ad, aw);
+  epa_piece_grad<T, 2, 4, true, WF>(s, s.c[1], s.c[2], T(0.25), T(0.0625), full, ad, aw);
+  epa_piece_grad<T, 3, 6, false, WF>(s, s.c[2], s.c[3], T(0.0625), T(0.015625), full, ad, aw);
+  epa_piece_grad<T, 4, 7, true, WF>(s, s.c[3], s.bmin, T(0.015625), T(0.00390625), full, ad, aw);
   const T kv = T(0.75) * s.iwv;
   if (WF) g.f = cfma(kv, full, epa_cdf4(s, s.c[0]) * T(0.25));
 #pragma unroll

@@ -111,7 +111,7 @@ __host__ __device__ void hist_jac_both(const HistSuf<T>& L, int ev, const int (&
 #pragma unroll
       for (int i = 0; i < 4; ++i) t[i] = hl * c[i].slope;
       const T t01 = t[0] * t[1], t23 = t[2] * t[3];
-      const T k45 = T(8.0 / 45.0) * hl;
+      const T k45 = T(GLRem<2>::e) * hl;
       const T kv = k45 * (t01 * t23), ke = k45 * (wS - wF);
       vS += kv;
       vF += kv;

@@ -3,6 +3,7 @@ include/cpcrit.h declares, its Gauss-Legendre tables are the textbook rules,
 and argument validation answers before anything reaches the device.  No
 compute call is made here (no GPU needed)."""
 import ctypes
+import math
 import os
 import re
 
@@ -36,7 +37,7 @@ def test_struct_layouts_match_header():
     assert ctypes.sizeof(L.cp_fit_opts_t) == 32
 
 
-@pytest.mark.parametrize("n", [1, 2, 3, 5, 6, 8, 10])
+@pytest.mark.parametrize("n", [1, 2, 3, 4, 5, 6, 7, 8, 10])
 def test_gauss_legendre_tables(n):
     """The device rules against numpy's Gauss-Legendre (Golub-Welsch)."""
     x, w = L.cp_gauss_legendre(n)
@@ -45,9 +46,24 @@ def test_gauss_legendre_tables(n):
     np.testing.assert_allclose(w, wr, atol=1e-15)
 
 
+@pytest.mark.parametrize("n,rem", [(2, 8 / 45), (4, 128 / 11025), (7, 512 / 2760615)])
+def test_gauss_legendre_remainders(n, rem):
+    """The remainders the kernels add for a top term y^(2n), 2^(2n+1) (n!)^4 /
+    ((2n+1) ((2n)!)^2, against the device rule applied to y^(2n) and to a
+    polynomial of degree 2n + 1 with random coefficients."""
+    x, w = (np.asarray(v) for v in L.cp_gauss_legendre(n))
+    f = math.factorial
+    assert rem == pytest.approx(2 ** (2 * n + 1) * f(n) ** 4 / ((2 * n + 1) * f(2 * n) ** 2), rel=1e-15)
+    assert 2 / (2 * n + 1) - np.dot(w, x ** (2 * n)) == pytest.approx(rem, rel=1e-12)
+    c = np.random.default_rng(n).normal(size=2 * n + 2)
+    exact = sum(c[k] * 2 / (k + 1) for k in range(0, 2 * n + 2, 2))
+    rule = np.dot(w, np.polynomial.polynomial.polyval(x, c))
+    assert rule + rem * c[2 * n] == pytest.approx(exact, rel=1e-13, abs=1e-14)
+
+
 def test_gauss_legendre_rejects_other_sizes():
     with pytest.raises(L.CPError):
-        L.cp_gauss_legendre(4)
+        L.cp_gauss_legendre(9)
 
 
 def test_n_params():
