@@ -53,6 +53,12 @@ __global__ __launch_bounds__(256) void k_hist_gather(FieldPtrs<T> f, const T* __
   hist_gather_vertex<T>(f, J, (int64_t)blockIdx.x * 256 + threadIdx.x);
 }
 
+// the same, 16 bytes of vertices per thread (rows and planes in 16-byte units)
+template <typename T>
+__global__ __launch_bounds__(256) void k_hist_gather_vec(FieldPtrs<T> f, const T* __restrict__ J) {
+  hist_gather_vec<T>(f, J, (int64_t)blockIdx.x * 256 + threadIdx.x);
+}
+
 // ---------------------------------------------------------------------------
 // launchers
 // ---------------------------------------------------------------------------
@@ -169,8 +175,15 @@ static hipError_t launch_bwd_hist(const FieldPtrs<T>& p, hipStream_t st, const S
   hipLaunchKernelGGL((k_hist_sweep<T, TY>), dim3(n), dim3(kFwdTX * TY), lds, st, p, tx, n, J);
   e = hipGetLastError();
   if (e != hipSuccess) return e;
-  hipLaunchKernelGGL(k_hist_gather<T>, dim3((unsigned)((plane + 255) / 256)), dim3(256), 0, st, p,
-                     static_cast<const T*>(J));
+  constexpr int V = 16 / sizeof(T);
+  if (p.W % V == 0 && p.rs % V == 0 && p.ps % V == 0 && reinterpret_cast<uintptr_t>(p.grad) % 16 == 0) {
+    const int64_t groups = plane / V;
+    hipLaunchKernelGGL(k_hist_gather_vec<T>, dim3((unsigned)((groups + 255) / 256)), dim3(256), 0, st, p,
+                       static_cast<const T*>(J));
+  } else {
+    hipLaunchKernelGGL(k_hist_gather<T>, dim3((unsigned)((plane + 255) / 256)), dim3(256), 0, st, p,
+                       static_cast<const T*>(J));
+  }
   return hipGetLastError();
 }
 

@@ -275,4 +275,49 @@ __device__ __forceinline__ void hist_gather_vertex(const FieldPtrs<T>& f, const 
   }
 }
 
+// The same gather for V = 16 / sizeof(T) vertices of one row per thread
+// (W, the row stride and the plane stride multiples of V, grad 16-byte
+// aligned): the own and north / south entries are aligned vector loads, the
+// east / west ones the same vectors shifted by one vertex (4-byte aligned
+// loads; at a row end the lane takes no entry, and every address stays
+// inside the workspace: the shifted rows of slots 1 and 3 and the rows above
+// / below of slots 4 and 2 lie between plane 1 and plane 5h - 1).  Terms
+// are added in the scalar gather's order and absent ones skipped, so the
+// sums are bit-identical to it.
+template <typename T>
+__device__ __forceinline__ void hist_gather_vec(const FieldPtrs<T>& f, const T* __restrict__ J, int64_t q) {
+  constexpr int V = 16 / sizeof(T);
+  typedef T Vec __attribute__((ext_vector_type(V)));
+  const int64_t plane = (int64_t)f.H * f.W;
+  const int64_t id = q * V;
+  if (id >= plane) return;
+  const int y = (int)(id / f.W), x = (int)(id - (int64_t)y * f.W);
+  const int h = f.nb;
+  const int64_t at = (int64_t)y * f.rs + x;
+  const Vec z = Vec(T(0));
+  *reinterpret_cast<Vec*>(f.grad + at) = z;
+  *reinterpret_cast<Vec*>(f.grad + f.ps + at) = z;
+  const bool hasn = y > 0, hass = y + 1 < f.H;
+  const auto ld = [&](int slot, int k, int64_t v) {  // V entries from vertex v on (v 4-byte aligned)
+    Vec r;
+    __builtin_memcpy(&r, J + (int64_t)(slot * h + k) * plane + v, sizeof(Vec));
+    return r;
+  };
+  for (int k = 0; k < h; ++k) {
+    Vec g = *reinterpret_cast<const Vec*>(J + (int64_t)k * plane + id);
+    const Vec e = ld(3, k, id + 1), w = ld(1, k, id - 1);
+    const Vec n = ld(4, k, hasn ? id - f.W : id), s = ld(2, k, hass ? id + f.W : id);
+#pragma unroll
+    for (int j = 0; j < V; ++j) {
+      T t = g[j];
+      if (x + j + 1 < f.W) t += e[j];
+      if (x + j > 0) t += w[j];
+      if (hasn) t += n[j];
+      if (hass) t += s[j];
+      g[j] = t;
+    }
+    *reinterpret_cast<Vec*>(f.grad + (int64_t)(2 + k) * f.ps + at) = g;
+  }
+}
+
 }  // namespace cp
