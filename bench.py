@@ -214,7 +214,8 @@ def epa_flops(params):
 
 # ----------------------------------------------------------------------------
 # uniform model, same convention (uni_piece / uni_piece_grad): a piece with k
-# started neighbours is integrated exactly with 1, 2, 2, 3 nodes (k = 1..4).
+# started neighbours is integrated exactly with 1, 1, 2, 2 nodes (k = 1..4),
+# k = 2 and 4 with the rule's remainder on the top-degree term (k + 1).
 #   forward piece k:  setup 4 + 3k (midpoint, half-length, per factor slope
 #                     and offset); per node 3k + 1 (k factors, product,
 #                     weighted sum); 2 to scale and accumulate.  Piece 0: 0.
@@ -225,16 +226,17 @@ def epa_flops(params):
 #                     the lo / hi / width partials), 30 to weight the ten
 #                     Jacobian entries by g_min / g_max, 8 for the gather.
 # ----------------------------------------------------------------------------
-UNI_NODES = {1: 1, 2: 2, 3: 2, 4: 3}
+UNI_NODES = {1: 1, 2: 1, 3: 2, 4: 2}
+UNI_REM = {1: 0, 2: 3, 3: 0, 4: 5}  # remainder FLOPs (k = 2, 4)
 UNI_BWD_VERTEX = 2 * 27 + 30 + 8
 
 
 def flops_uni_fwd_piece(k):
-    return 0 if k == 0 else 6 + 3 * k + UNI_NODES[k] * (3 * k + 1)
+    return 0 if k == 0 else 6 + 3 * k + UNI_NODES[k] * (3 * k + 1) + UNI_REM[k]
 
 
 def flops_uni_bwd_piece(k):
-    return 0 if k == 0 else 5 + 5 * k + UNI_NODES[k] * 7 * k
+    return 0 if k == 0 else 5 + 5 * k + UNI_NODES[k] * 7 * k + UNI_REM[k]
 
 
 def uni_flops(params):

@@ -130,6 +130,10 @@ struct GL<10> {
 template <int N>
 struct GLRem;
 template <>
+struct GLRem<1> {
+  static constexpr double e = 2.0 / 3.0;
+};
+template <>
 struct GLRem<2> {
   static constexpr double e = 8.0 / 45.0;
 };
@@ -247,7 +251,9 @@ CP_HD void unsort4(T (&v)[4], const bool (&sw)[5]) {
 // neighbours sorted first have started (Tasks 2-3, Template k+1), so every
 // lane runs the same five pieces (empty ones contribute zero).
 // On piece k the integrand (1/Lv) prod_{i<k} (b_i - x)/L_i has degree k:
-// Gauss-Legendre with 1, 2, 2, 3 nodes is exact for k = 1..4.
+// Gauss-Legendre with 1 and 2 nodes is exact for k = 1 and 3; k = 2 and 4
+// take 1 and 2 nodes plus the rule's remainder on the top-degree term (its
+// coefficient the product of the factors' slopes).
 // ===========================================================================
 template <typename T>
 struct UniSide {
@@ -290,9 +296,11 @@ CP_HD void uni_setup(UniSide<T>& s, T Lv, T iLv, const T (&a)[4], const T (&b)[4
   }
 }
 
-// integral over [l, r] of prod_{i<K} (b_i - x) iL_i  (times nothing else)
-template <typename T, int K, int N>
+// integral over [l, r] of prod_{i<K} (b_i - x) iL_i  (times nothing else);
+// REM: K = 2N, and the y^K coefficient prod be_i gets the rule's remainder
+template <typename T, int K, int N, bool REM = false>
 CP_HD T uni_piece(const UniSide<T>& s, T l, T r) {
+  static_assert(REM ? K == 2 * N : K <= 2 * N - 1, "rule too small for the piece");
   const T mid = (l + r) * T(0.5), hl = (r - l) * T(0.5);
   T al[K], be[K];
 #pragma unroll
@@ -309,6 +317,12 @@ CP_HD T uni_piece(const UniSide<T>& s, T l, T r) {
     for (int i = 0; i < K; ++i) prod *= cfma(-be[i], x, al[i]);
     sum = cfma(T(GL<N>::w[j]), prod, sum);
   }
+  if constexpr (REM) {
+    T c = be[0];
+#pragma unroll
+    for (int i = 1; i < K; ++i) c *= be[i];
+    sum = cfma(T(GLRem<N>::e), c, sum);  // (-be_i) for each of an even number of factors
+  }
   return sum * hl;
 }
 
@@ -317,9 +331,9 @@ CP_HD T uni_side_value(const UniSide<T>& s) {
   if (s.empty) return T(0);
   T acc = s.c[0];  // piece 0: no factor
   acc += uni_piece<T, 1, 1>(s, s.c[0], s.c[1]);
-  acc += uni_piece<T, 2, 2>(s, s.c[1], s.c[2]);
+  acc += uni_piece<T, 2, 1, true>(s, s.c[1], s.c[2]);
   acc += uni_piece<T, 3, 2>(s, s.c[2], s.c[3]);
-  acc += uni_piece<T, 4, 3>(s, s.c[3], s.bmin);
+  acc += uni_piece<T, 4, 2, true>(s, s.c[3], s.bmin);
   return acc * s.iLv;
 }
 
@@ -333,8 +347,11 @@ struct UniGrad {
   T da[4], db[4];  // by neighbour index 0..3
 };
 
-template <typename T, int K, int N>
+// REM: K = 2N; the leave-one-out sums (degree K - 1) are exact, the full
+// product (degree K) gets the rule's remainder on prod be_i
+template <typename T, int K, int N, bool REM = false>
 CP_HD void uni_piece_grad(const UniSide<T>& s, T l, T r, T& full, T (&loo)[4]) {
+  static_assert(REM ? K == 2 * N : K <= 2 * N - 1, "rule too small for the piece");
   const T mid = (l + r) * T(0.5), hl = (r - l) * T(0.5);
   T al[K], be[K];
 #pragma unroll
@@ -362,6 +379,12 @@ CP_HD void uni_piece_grad(const UniSide<T>& s, T l, T r, T& full, T (&loo)[4]) {
 #pragma unroll
     for (int i = 0; i < K; ++i) sl[i] = cfma(wj, pre[i] * suf[i + 1], sl[i]);
   }
+  if constexpr (REM) {
+    T c = be[0];
+#pragma unroll
+    for (int i = 1; i < K; ++i) c *= be[i];
+    sf = cfma(T(GLRem<N>::e), c, sf);
+  }
   full = sf * hl;
 #pragma unroll
   for (int i = 0; i < K; ++i) loo[i] += sl[i] * hl;
@@ -379,9 +402,9 @@ CP_HD void uni_side_grad(const UniSide<T>& s, UniGrad<T>& g) {
   T act[4] = {T(0), T(0), T(0), T(0)};  // full integral over pieces where slot is active
   I[0] = s.c[0];
   uni_piece_grad<T, 1, 1>(s, s.c[0], s.c[1], I[1], loo);
-  uni_piece_grad<T, 2, 2>(s, s.c[1], s.c[2], I[2], loo);
+  uni_piece_grad<T, 2, 1, true>(s, s.c[1], s.c[2], I[2], loo);
   uni_piece_grad<T, 3, 2>(s, s.c[2], s.c[3], I[3], loo);
-  uni_piece_grad<T, 4, 3>(s, s.c[3], s.bmin, I[4], loo);
+  uni_piece_grad<T, 4, 2, true>(s, s.c[3], s.bmin, I[4], loo);
   // slot i is active on pieces i+1..4
   act[3] = I[4];
   act[2] = act[3] + I[3];
