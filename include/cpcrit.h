@@ -210,7 +210,7 @@ cp_status_t cp_prob_backward(const cp_field_desc_t* desc, const void* params, co
  * of 64 MiB per GPU (2^26 bytes; it exists on every GPU the library's code is
  * loaded on until the process ends), found on the first call on each device;
  * no call allocates, frees or grows device memory.
- *   Scratch needed: histogram 5 * nbins * H * W * sizeof(dtype) bytes,
+ *   Scratch needed: histogram (5 * nbins + 4) * H * W * sizeof(dtype) bytes,
  *   multivariate Gaussian 40 * H * W bytes, other models none.  A field that
  *   needs more than 64 MiB returns CP_EINVAL before anything is launched
  *   (cp_last_error gives both sizes).

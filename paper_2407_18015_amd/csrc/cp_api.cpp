@@ -114,7 +114,7 @@ void workspace_release() {
 
 size_t backward_scratch_bytes(const Field& f) {
   const size_t nv = (size_t)f.H * (size_t)f.W;
-  if (f.model == CP_HISTOGRAM) return (f.dtype == CP_F64 ? 8 : 4) * (size_t)5 * (size_t)f.nb * nv;
+  if (f.model == CP_HISTOGRAM) return (f.dtype == CP_F64 ? 8 : 4) * (size_t)hist_ws_planes(f.nb) * nv;
   if (f.model == CP_MVGAUSS) return sizeof(double) * 5 * nv;
   return 0;
 }

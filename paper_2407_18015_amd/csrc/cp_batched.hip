@@ -69,7 +69,7 @@ struct BatchTile {
 template <typename T>
 struct BatchField {
   FieldPtrs<T> p;
-  T* J;  // histogram adjoint workspace ([5][h][H][W]) or null
+  T* J;  // histogram adjoint workspace ([5 h + 4][H][W]) or null
   int model;
 };
 
@@ -368,7 +368,7 @@ cp_status_t build_plan(int n, const Field* fs, bool bwd, Plan& P, const char** w
     if (hist && bwd) {
       present[PASS_GATHER] = true;
       P.ws_offset[i] = ws;
-      ws += el * (size_t)5 * f.nb * f.H * (size_t)f.W;
+      ws += el * (size_t)hist_ws_planes(f.nb) * f.H * (size_t)f.W;
       ws = (ws + 255) / 256 * 256;
     }
   }

@@ -166,7 +166,7 @@ static hipError_t launch_bwd_hist(const FieldPtrs<T>& p, hipStream_t st, const S
   const int tx = cdiv(p.W, kFwdTX), ty = cdiv(p.H, TY), n = tx * ty;
   const int64_t plane = (int64_t)p.H * p.W;
   void* ws = nullptr;
-  hipError_t e = adjoint_scratch(sizeof(T) * (size_t)5 * p.nb * plane, st, scr, &ws);
+  hipError_t e = adjoint_scratch(sizeof(T) * (size_t)hist_ws_planes(p.nb) * plane, st, scr, &ws);
   if (e != hipSuccess) return e;
   T* J = static_cast<T*>(ws);
   const size_t lds = sizeof(T) * (size_t)hist_planes(p.nb) * (kFwdTX + 2) * (TY + 2);

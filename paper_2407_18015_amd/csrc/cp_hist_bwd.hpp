@@ -32,8 +32,10 @@ namespace cp {
 // entry of a neighbour bin is B + (1/Delta_n) int_{bin} (e_{j+1} - x)(lS + lF)
 // with B = QS' + QF' at the bin's lower edge; it is emitted when the sweep
 // leaves the bin, without the g_max QF_n(hv) term, which is known only at the
-// end: then the bins already emitted receive it (J.add), the open bin and the
-// bins above and below the sweep are emitted once.  The node weights carry
+// end and belongs to every bin of the neighbour at or below the open one: it
+// is stored once per neighbour (J.tail) and the gather adds it to all of the
+// neighbour's bins, so the bins above the open one are emitted as
+// QS_n(hv) - tail, those below the sweep as 0, and no entry is read back.  The node weights carry
 // the vertex pdf and the half-length of the sub-interval, so the
 // accumulators run over the whole sweep.
 //
@@ -41,7 +43,7 @@ namespace cp {
 // cp_hist.hpp); every sub-interval advances the cursors that end it with
 // selects rather than branches.
 //
-// J must provide set(slot, k, value) and add(slot, k, value); slot 0 is the
+// J must provide set(slot, k, value) and tail(i, value); slot 0 is the
 // vertex's own histogram, slot 1 + i neighbour i (e, n, w, s).
 // ---------------------------------------------------------------------------
 template <typename T, typename JOut>
@@ -146,31 +148,31 @@ __host__ __device__ void hist_jac_both(const HistSuf<T>& L, int ev, const int (&
   for (int i = 0; i < 4; ++i) {
     if (!pres[i]) continue;
     const int j = c[i].m - 1;  // open bin (-1: below the range, h: past it)
-    const T tf = -QF[i];            // g_max QF_n(hv)
+    const T tf = -QF[i];            // g_max QF_n(hv), added to every bin by the gather
+    J.tail(i, tf);
     // first bin the sweep entered (the cursor's start, found again)
     HistCursor<T> c0;
     hist_cursor_init(c0, base, E, h, en[i], lo[i], hi[i], true, big);
     const int first = c0.m < 1 ? 0 : c0.m - 1;
     for (int k = 0; k < h; ++k) {
       if (k < first) {
-        J.set(1 + i, k, tf);  // entirely below the sweep: dF/dm = 1 there
-      } else if (k < j) {
-        J.add(1 + i, k, tf);  // emitted when the sweep left it
+        J.set(1 + i, k, T(0));  // entirely below the sweep: dF/dm = 1 there (the tail)
       } else if (k == j) {
-        J.set(1 + i, k, cfma(c[i].id, Y[i], tf));  // k == j: inside the range
-      } else {
-        J.set(1 + i, k, QS[i]);  // entirely above the sweep: dS/dm = 1 there
-      }
+        J.set(1 + i, k, c[i].id * Y[i]);  // the open bin: inside the range
+      } else if (k > j) {
+        J.set(1 + i, k, QS[i] - tf);  // entirely above the sweep: dS/dm = 1 there
+      }  // first <= k < j: emitted when the sweep left the bin
     }
   }
   pmin = amin;
   pmax = amax;
 }
 
-// Entries of one stencil stored at J[(slot * h + k) * EJ + sj] (the layout
-// of a per-stencil Jacobian array, used by the host-side checks).
-// The plane size EJ (= H W) is below 2^30 (the descriptor check bounds the
-// grid), so the plane offset is one 32 x 32 -> 64-bit product.
+// Entries of one stencil stored at J[(slot * h + k) * EJ + sj], its four
+// tails at J[(5 h + i) * EJ + sj] (the workspace layout, [5 h + 4][H][W];
+// also used by the host-side checks).  The plane size EJ (= H W) is below
+// 2^30 (the descriptor check bounds the grid), so the plane offset is one
+// 32 x 32 -> 64-bit product.
 template <typename T>
 struct JPlanes {
   T* J;
@@ -179,8 +181,9 @@ struct JPlanes {
   int h;
   CP_HD int64_t at(int slot, int k) const { return (int64_t)((uint64_t)(uint32_t)(slot * h + k) * EJ) + sj; }
   CP_HD void set(int slot, int k, T v) const { J[at(slot, k)] = v; }
-  CP_HD void add(int slot, int k, T v) const { J[at(slot, k)] += v; }
+  CP_HD void tail(int i, T v) const { J[at(5, i)] = v; }  // plane 5 h + i
 };
+
 
 // Both sides of one stencil (centre e in the staged tile, grid position
 // (gy, gx)) into J; returns the probabilities; an invalid stencil emits NaN
@@ -199,8 +202,10 @@ __host__ __device__ void hist_stencil_jac(const HistLds<T>& L, const HistSuf<T>&
     for (int k = 0; k < h; ++k) J.set(0, k, qnan<T>());
 #pragma unroll
     for (int i = 0; i < 4; ++i)
-      if (pres[i])
+      if (pres[i]) {
         for (int k = 0; k < h; ++k) J.set(1 + i, k, qnan<T>());
+        J.tail(i, T(0));
+      }
     pmin = pmax = qnan<T>();
     return;
   }
@@ -216,9 +221,9 @@ __host__ __device__ void hist_stencil_jac(const HistLds<T>& L, const HistSuf<T>&
 
 // Sweep tile of the adjoint: 64 x TY stencils (params staged with a
 // one-vertex halo), entries written to the workspace J
-// ([5][h][H][W]: one plane per slot and bin, so the lanes of a wave that
-// emit the same entry write consecutive words); a gather kernel then adds the
-// five entries of every parameter.  If f.pmin is non-null the probabilities
+// ([5 h + 4][H][W]: one plane per slot and bin, then the four tails, so the
+// lanes of a wave that emit the same entry write consecutive words); a
+// gather kernel then adds the five entries of every parameter.  If f.pmin is non-null the probabilities
 // are written too (fused forward + adjoint).  NT threads; each takes the rows
 // ly, ly + NT/64, ... of its column.
 template <typename T, int TY, int NT = kFwdTX * TY>
@@ -265,12 +270,16 @@ __device__ __forceinline__ void hist_gather_vertex(const FieldPtrs<T>& f, const 
   f.grad[at] = T(0);
   f.grad[f.ps + at] = T(0);
   const auto e = [&](int64_t v, int slot, int k) { return J[(int64_t)(slot * h + k) * plane + v]; };
+  // tails of the four stencils: u is the west (east, south, north) neighbour
+  // of its east (west, north, south) neighbour
+  const T te = x + 1 < f.W ? e(id + 1, 5, 2) : T(0), tw = x > 0 ? e(id - 1, 5, 0) : T(0);
+  const T tn = y > 0 ? e(id - f.W, 5, 3) : T(0), ts = y + 1 < f.H ? e(id + f.W, 5, 1) : T(0);
   for (int k = 0; k < h; ++k) {
     T g = e(id, 0, k);
-    if (x + 1 < f.W) g += e(id + 1, 3, k);
-    if (x > 0) g += e(id - 1, 1, k);
-    if (y > 0) g += e(id - f.W, 4, k);
-    if (y + 1 < f.H) g += e(id + f.W, 2, k);
+    if (x + 1 < f.W) g += e(id + 1, 3, k) + te;
+    if (x > 0) g += e(id - 1, 1, k) + tw;
+    if (y > 0) g += e(id - f.W, 4, k) + tn;
+    if (y + 1 < f.H) g += e(id + f.W, 2, k) + ts;
     f.grad[(int64_t)(2 + k) * f.ps + at] = g;
   }
 }
@@ -280,10 +289,10 @@ __device__ __forceinline__ void hist_gather_vertex(const FieldPtrs<T>& f, const 
 // aligned): the own and north / south entries are aligned vector loads, the
 // east / west ones the same vectors shifted by one vertex (4-byte aligned
 // loads; at a row end the lane takes no entry, and every address stays
-// inside the workspace: the shifted rows of slots 1 and 3 and the rows above
-// / below of slots 4 and 2 lie between plane 1 and plane 5h - 1).  Terms
-// are added in the scalar gather's order and absent ones skipped, so the
-// sums are bit-identical to it.
+// inside the workspace: the shifted rows of slots 1 and 3, of the tail planes
+// and the rows above / below of slots 4 and 2 lie between plane 1 and the
+// last tail plane).  Terms are added in the scalar gather's order and absent
+// ones skipped, so the sums are bit-identical to it.
 template <typename T>
 __device__ __forceinline__ void hist_gather_vec(const FieldPtrs<T>& f, const T* __restrict__ J, int64_t q) {
   constexpr int V = 16 / sizeof(T);
@@ -303,6 +312,8 @@ __device__ __forceinline__ void hist_gather_vec(const FieldPtrs<T>& f, const T* 
     __builtin_memcpy(&r, J + (int64_t)(slot * h + k) * plane + v, sizeof(Vec));
     return r;
   };
+  const Vec te = ld(5, 2, id + 1), tw = ld(5, 0, id - 1);
+  const Vec tn = ld(5, 3, hasn ? id - f.W : id), ts = ld(5, 1, hass ? id + f.W : id);
   for (int k = 0; k < h; ++k) {
     Vec g = *reinterpret_cast<const Vec*>(J + (int64_t)k * plane + id);
     const Vec e = ld(3, k, id + 1), w = ld(1, k, id - 1);
@@ -310,10 +321,10 @@ __device__ __forceinline__ void hist_gather_vec(const FieldPtrs<T>& f, const T* 
 #pragma unroll
     for (int j = 0; j < V; ++j) {
       T t = g[j];
-      if (x + j + 1 < f.W) t += e[j];
-      if (x + j > 0) t += w[j];
-      if (hasn) t += n[j];
-      if (hass) t += s[j];
+      if (x + j + 1 < f.W) t += e[j] + te[j];
+      if (x + j > 0) t += w[j] + tw[j];
+      if (hasn) t += n[j] + tn[j];
+      if (hass) t += s[j] + ts[j];
       g[j] = t;
     }
     *reinterpret_cast<Vec*>(f.grad + (int64_t)(2 + k) * f.ps + at) = g;

@@ -13,6 +13,10 @@ namespace cp {
 
 constexpr int kMaxBins = 32;
 
+// planes of the histogram adjoint's workspace ([5 h + 4][H][W]): the
+// entries of the five stencil slots per bin, then one tail per neighbour
+__host__ __device__ constexpr int64_t hist_ws_planes(int h) { return 5 * (int64_t)h + 4; }
+
 // A validated field description (row_stride resolved).
 struct Field {
   int H = 0, W = 0;

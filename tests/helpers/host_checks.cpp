@@ -19,6 +19,7 @@
 #include <vector>
 
 #include "cp_hist_bwd.hpp"
+#include "cp_internal.hpp"
 #include "cp_tiles.hpp"
 #include "cp_workspace.hpp"
 
@@ -91,7 +92,7 @@ void run_hist(const std::vector<double>& p, const std::vector<double>& gmin, con
   std::vector<T> raw = g.par;  // validity-marked masses (for the Jacobian routine)
   cp::hist_stage_suffix<T, 1>(g.par.data(), g.E, h, 0);
   const size_t nv = (size_t)H * W;
-  std::vector<T> J((size_t)5 * h * nv, T(0));
+  std::vector<T> J((size_t)cp::hist_ws_planes(h) * nv, T(0));
   const cp::HistLds<T> L{g.par.data(), g.E, h, T(1) / T(h)};
   const cp::HistSuf<T> U{g.par.data(), g.E, h};
   for (int y = 0; y < H; ++y)
@@ -123,12 +124,15 @@ void run_hist(const std::vector<double>& p, const std::vector<double>& gmin, con
       const size_t v = (size_t)y * W + x;
       out[2 * nv + v] = 0.0;
       out[3 * nv + v] = 0.0;
+      // the tails of the four neighbours' stencils (u is the west neighbour
+      // of its east neighbour, and so on) apply to every bin
+      const auto tl = [&](int i, size_t w) { return J[(size_t)(5 * h + i) * nv + w]; };
       for (int k = 0; k < h; ++k) {
         T s = J[(size_t)(0 * h + k) * nv + v];
-        if (x + 1 < W) s += J[(size_t)(3 * h + k) * nv + v + 1];
-        if (x > 0) s += J[(size_t)(1 * h + k) * nv + v - 1];
-        if (y > 0) s += J[(size_t)(4 * h + k) * nv + v - W];
-        if (y + 1 < H) s += J[(size_t)(2 * h + k) * nv + v + W];
+        if (x + 1 < W) s += J[(size_t)(3 * h + k) * nv + v + 1] + tl(2, v + 1);
+        if (x > 0) s += J[(size_t)(1 * h + k) * nv + v - 1] + tl(0, v - 1);
+        if (y > 0) s += J[(size_t)(4 * h + k) * nv + v - W] + tl(3, v - W);
+        if (y + 1 < H) s += J[(size_t)(2 * h + k) * nv + v + W] + tl(1, v + W);
         out[(size_t)(4 + k) * nv + v] = (double)s;
       }
     }

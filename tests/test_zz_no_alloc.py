@@ -85,9 +85,10 @@ def test_noalloc_python_binding():
 
 
 def test_noalloc_rejects_fields_beyond_the_array():
-    # histogram FP32 with 32 bins: 5 * 32 * 4 bytes per vertex; no launch happens
+    # histogram FP32 with 32 bins: (5 * 32 + 4) * 4 bytes per vertex (the
+    # entries and the four tails); no launch happens
     H, W, nb = 512, 256, 32
-    need = 5 * nb * 4 * H * W
+    need = (5 * nb + 4) * 4 * H * W
     assert need > SCRATCH_BYTES
     p = torch.zeros((2 + nb, H, W), device="cuda")
     g = torch.zeros((H, W), device="cuda")
