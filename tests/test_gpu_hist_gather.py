@@ -72,3 +72,33 @@ def test_vector_gather_equals_scalar_gather_and_oracle(dtype, shape):
     print(f"[parity] histogram gather {dtype} {shape}: max |diff| {d.max():.3e}, worst |diff|/tolerance "
           f"{(d / t).max():.3g}", flush=True)
     assert np.all(d <= t)
+
+
+@pytest.mark.parametrize("nb", [1, 2, 32])
+@pytest.mark.parametrize("dtype", [torch.float32, torch.float64])
+def test_adjoint_bin_count_extremes(dtype, nb):
+    """One bin, two bins and the largest count (32: the FP64 sweep then
+    takes its two-row tiles): per-field (vector gather) against batched
+    (scalar gather) bit for bit, and the oracle within tolerance."""
+    H, W = 13, 24
+    note("histogram adjoint bins", dtype, nb)
+    p = workloads.random_params(HST, 300 + nb, H, W, nbins=nb, width=0.06)
+    pt = torch.as_tensor(p, dtype=dtype, device="cuda")
+    gmin, gmax = workloads.upstream(5, H, W, np.float64)
+    g1 = torch.as_tensor(gmin, dtype=dtype, device="cuda")
+    g2 = torch.as_tensor(gmax, dtype=dtype, device="cuda")
+    f = cp.field_of(pt, HST, nb)
+    got = cp.backward(pt, g1, g2, f)
+    ref_b = torch.empty_like(pt)
+    cp.batched([f], [pt], gmin=[g1], gmax=[g2], grad=[ref_b])
+    torch.cuda.synchronize()
+    assert torch.equal(got, ref_b), "per-field and batched adjoints differ"
+    gh = got.cpu().numpy().astype(np.float64)
+    args = (HST, pt.cpu().numpy().astype(np.float64), g1.cpu().numpy().astype(np.float64),
+            g2.cpu().numpy().astype(np.float64))
+    ref, S = oracle.grad(*args), oracle.grad(*args, absolute=True)
+    d = np.abs(gh - ref)
+    t = tol(ref, S, dtype)
+    print(f"[parity] histogram adjoint {dtype} {nb} bins: max |diff| {d.max():.3e}, worst |diff|/tolerance "
+          f"{(d / t).max():.3g}", flush=True)
+    assert np.all(d <= t)
