@@ -274,13 +274,14 @@ cp_status_t cp_prob_semianalytical(const cp_field_desc_t* desc, const void* para
 /* cp_prob_batched flags */
 #define CP_BATCH_FWD 1u       /* write p_min / p_max */
 #define CP_BATCH_BWD 2u       /* write grad_params (needs g_min / g_max) */
-#define CP_BATCH_GRAPH 4u     /* replay a cached HIP graph of the persistent launch */
+#define CP_BATCH_GRAPH 4u     /* replay a cached HIP graph of the plan's launches */
 #define CP_BATCH_PER_FIELD 8u /* reference mode: one forward / backward launch per field */
 #define CP_BATCH_TUNE 16u     /* autotune the plan's tile shapes and claim chunks (first call) */
 
 /*
  * Many independent fields (mixed sizes, closed-form models, one dtype) in one
- * persistent launch over a device-side table of field descriptors and tiles.
+ * launch per pass over a device-side table of field descriptors and tiles
+ * (one tile per block, or a persistent grid claiming tiles from a queue).
  * Arrays of n pointers index the fields; p_min/p_max may be NULL unless
  * CP_BATCH_FWD, g_min/g_max/grad_params unless CP_BATCH_BWD.  Results equal
  * those of cp_prob_forward / cp_prob_backward on each field.  The graph cache
@@ -298,11 +299,13 @@ cp_status_t cp_prob_semianalytical(const cp_field_desc_t* desc, const void* para
  * Epanechnikov forward: 64 x 4, 64 x 8 or 64 x 16 vertices; histogram
  * passes: 64 x 4 or 64 x 8; uniform / Epanechnikov adjoint: FP32 30x30,
  * 14x14 or 62x30 outputs, FP64 14x14, 30x14 or 30x30)
- * with each claim chunk (1, 2, 4, 8 tiles) on the caller's own buffers, and
- * keeps the fastest for every later call; the call then blocks until the
- * trials are done, and fails (CP_EINVAL) while the stream is being captured.
- * The trials write the outputs, with the same values: no tile shape changes
- * a result.  Without the flag a plan uses the first shape and a fixed chunk.
+ * with each claim chunk (1, 2, 4, 8 tiles) of the persistent launch and with
+ * one tile per block (a grid of all the pass's tiles, most expensive first),
+ * on the caller's own buffers, and keeps the fastest for every later call;
+ * the call then blocks until the trials are done, and fails (CP_EINVAL)
+ * while the stream is being captured.  The trials write the outputs, with
+ * the same values: no tile shape or launch form changes a result.  Without
+ * the flag a plan uses the first shape and one tile per block.
  * Tuning table: if the environment variable CPCRIT_TUNE_CACHE names a file,
  * every plan the tuner times appends its choices there (one text line keyed
  * by the GPU architecture, its CU count and the field shapes), and a later
@@ -328,9 +331,10 @@ typedef enum {
  * Fix the tile shape and claim chunk of each pass of the plan that
  * cp_prob_batched uses for these descriptors and flags (building the plan if
  * no call has yet): shape[p] indexes the shapes listed under CP_BATCH_TUNE
- * for pass p (0 = the default), chunk[p] >= 1 tiles per claim; entries < 0
- * (shape) or < 1 (chunk) keep the current choice, entries of passes the plan
- * lacks are ignored.  For callers that tuned offline and want the result
+ * for pass p (0 = the default), chunk[p] >= 1 tiles per claim of the
+ * persistent launch or -1 for one tile per block; entries < 0 (shape) or of
+ * any other value (chunk) keep the current choice, entries of passes the
+ * plan lacks are ignored.  For callers that tuned offline and want the result
  * without timing, or that want one shape.  A pinned plan is not re-tuned.
  * CP_EINVAL: a shape index out of range; CP_EUNSUPPORTED: the shape does not
  * fit a workgroup for these fields.
@@ -341,7 +345,8 @@ cp_status_t cp_batched_pin(int32_t n, const cp_field_desc_t* descs, uint32_t fla
 /*
  * The plan a cp_prob_batched call with these descriptors and flags uses, as
  * text: "tuned", "pinned" or "default", then per pass its shape index and
- * tile, claim chunk, tile count, resident grid and (tuned) launch time.  Returns NULL when no
+ * tile, claim chunk and resident grid (or "one tile per block"), tile count
+ * and (tuned) launch time.  Returns NULL when no
  * call has built that plan yet.  The string is thread-local, valid until
  * the next call of this function on the thread.
  */

@@ -1,19 +1,25 @@
 // cp_batched.hip -- many fields of uneven size and mixed closed-form models
-// in one persistent launch per pass.
+// in one launch per pass.
 //
 // Small fields under-fill 256 CUs when launched one by one (a 128^2 field is
 // 64 forward tiles); the batched form flattens every field into tiles, orders
 // them by a per-vertex cost model (most expensive first, then field and row
-// order) and lets a grid of resident blocks take them from a device-side
-// queue: block after block claims the next tile with one atomic, so blocks
-// that draw cheap tiles simply take more of them.  The last block to leave
+// order) and launches them as one grid per pass, one tile per block, which the
+// dispatcher hands out in that order as slots free up.  A persistent form is
+// the alternative the autotuner also times: a grid of resident blocks takes
+// the tiles from a device-side queue, block after block claiming the next
+// chunk with one atomic, so blocks that draw cheap tiles take more of them.  The last block to leave
 // resets the queue, so every launch (and every graph replay) starts from a
 // zeroed counter without a memset.  The tile lists depend only on the
 // shapes, so they are built and uploaded once per shape signature; the field
 // table (data pointers) is refreshed only when a pointer changes.  With CP_BATCH_GRAPH the launches are captured once per
 // signature into a HIP graph and replayed.
 //
-// Every pass is its own kernel instantiation and persistent launch: histogram
+// The one-tile-per-block form (`chunk` 0 in a plan) keeps the registers of
+// the per-field kernels (the histogram sweeps: 96 and 80 VGPRs against 109
+// and 94 inside the claim loop) and saves the claims.
+//
+// Every pass is its own kernel instantiation and launch: histogram
 // tiles and uniform / Epanechnikov tiles run in separate passes, so each
 // carries only the registers and LDS of its own tile routine (the latency-
 // bound histogram sweep keeps the occupancy of its per-field kernel).
@@ -89,6 +95,41 @@ constexpr int batched_min_waves() {
 // latency overlaps the tile's own loads.  Every block leaves once the counter
 // has passed the last chunk (the loop ends for all).
 template <typename T, int PASS, int V>
+__device__ __forceinline__ void batched_tile(const BatchField<T>* __restrict__ fields, const BatchTile tl, T* lds,
+                                             int tid) {
+  constexpr int TY = 4 << V;
+  constexpr int OX = bwd_ox(sizeof(T) == 4, V), OY = bwd_oy(sizeof(T) == 4, V);
+  const BatchField<T> F = fields[tl.field];
+  if constexpr (PASS == PASS_FWD_UE) {
+    if (F.model == CP_UNIFORM)
+      tile_fwd_ue<T, CP_UNIFORM, TY, kNT>(F.p, tl.ty0, tl.tx0, lds, tid);
+    else
+      tile_fwd_ue<T, CP_EPANECHNIKOV, TY, kNT>(F.p, tl.ty0, tl.tx0, lds, tid);
+  } else if constexpr (PASS == PASS_FWD_HIST) {
+    tile_fwd_hist<T, TY, kNT>(F.p, tl.ty0, tl.tx0, lds, tid);
+  } else if constexpr (PASS == PASS_BWD_UE) {
+    if (F.model == CP_UNIFORM)
+      tile_bwd_ue<T, CP_UNIFORM, OX, OY, kNT>(F.p, tl.ty0, tl.tx0, lds, tid);
+    else
+      tile_bwd_ue<T, CP_EPANECHNIKOV, OX, OY, kNT>(F.p, tl.ty0, tl.tx0, lds, tid);
+  } else if constexpr (PASS == PASS_BWD_HIST) {
+    tile_hist_sweep<T, TY, kNT>(F.p, tl.ty0, tl.tx0, lds, tid, F.J);
+  } else {
+    hist_gather_vertex<T>(F.p, F.J, (int64_t)tl.ty0 + tid);
+  }
+}
+
+// One tile per block, blocks in the table's order (the dispatcher hands them
+// out as slots free up, most expensive first): no claim loop around the tile,
+// so a pass keeps the registers of its per-field kernel.
+template <typename T, int PASS, int V>
+__global__ __launch_bounds__(kNT) void k_batched_flat(const BatchField<T>* __restrict__ fields,
+                                                      const BatchTile* __restrict__ tiles) {
+  extern __shared__ __align__(16) unsigned char smem[];
+  batched_tile<T, PASS, V>(fields, tiles[blockIdx.x], reinterpret_cast<T*>(smem), threadIdx.x);
+}
+
+template <typename T, int PASS, int V>
 __global__ __launch_bounds__(kNT, (batched_min_waves<T, PASS>())) void k_batched(
     const BatchField<T>* __restrict__ fields, const BatchTile* __restrict__ tiles, int ntiles, int chunk,
     int* queue) {
@@ -108,25 +149,7 @@ __global__ __launch_bounds__(kNT, (batched_min_waves<T, PASS>())) void k_batched
     if (tid == 0) ahead = atomicAdd(&queue[0], 1);
     const int t1 = min(ntiles, (c + 1) * chunk);
     for (int t = c * chunk; t < t1; ++t) {
-      const BatchTile tl = tiles[t];
-      const BatchField<T> F = fields[tl.field];
-      if constexpr (PASS == PASS_FWD_UE) {
-        if (F.model == CP_UNIFORM)
-          tile_fwd_ue<T, CP_UNIFORM, TY, kNT>(F.p, tl.ty0, tl.tx0, lds, tid);
-        else
-          tile_fwd_ue<T, CP_EPANECHNIKOV, TY, kNT>(F.p, tl.ty0, tl.tx0, lds, tid);
-      } else if constexpr (PASS == PASS_FWD_HIST) {
-        tile_fwd_hist<T, TY, kNT>(F.p, tl.ty0, tl.tx0, lds, tid);
-      } else if constexpr (PASS == PASS_BWD_UE) {
-        if (F.model == CP_UNIFORM)
-          tile_bwd_ue<T, CP_UNIFORM, OX, OY, kNT>(F.p, tl.ty0, tl.tx0, lds, tid);
-        else
-          tile_bwd_ue<T, CP_EPANECHNIKOV, OX, OY, kNT>(F.p, tl.ty0, tl.tx0, lds, tid);
-      } else if constexpr (PASS == PASS_BWD_HIST) {
-        tile_hist_sweep<T, TY, kNT>(F.p, tl.ty0, tl.tx0, lds, tid, F.J);
-      } else {
-        hist_gather_vertex<T>(F.p, F.J, (int64_t)tl.ty0 + tid);
-      }
+      batched_tile<T, PASS, V>(fields, tiles[t], lds, tid);
     }
     if (tid == 0) claimed = ahead;
     __syncthreads();
@@ -140,6 +163,23 @@ __global__ __launch_bounds__(kNT, (batched_min_waves<T, PASS>())) void k_batched
       atomicExch(&queue[0], 0);
       atomicExch(&queue[1], 0);
     }
+  }
+}
+
+template <typename T>
+const void* kernel_flat_of(int pass, int v) {
+  switch (pass * 4 + v) {
+    case PASS_FWD_UE * 4 + 0: return reinterpret_cast<const void*>(k_batched_flat<T, PASS_FWD_UE, 0>);
+    case PASS_FWD_UE * 4 + 1: return reinterpret_cast<const void*>(k_batched_flat<T, PASS_FWD_UE, 1>);
+    case PASS_FWD_UE * 4 + 2: return reinterpret_cast<const void*>(k_batched_flat<T, PASS_FWD_UE, 2>);
+    case PASS_FWD_HIST * 4 + 0: return reinterpret_cast<const void*>(k_batched_flat<T, PASS_FWD_HIST, 0>);
+    case PASS_FWD_HIST * 4 + 1: return reinterpret_cast<const void*>(k_batched_flat<T, PASS_FWD_HIST, 1>);
+    case PASS_BWD_UE * 4 + 0: return reinterpret_cast<const void*>(k_batched_flat<T, PASS_BWD_UE, 0>);
+    case PASS_BWD_UE * 4 + 1: return reinterpret_cast<const void*>(k_batched_flat<T, PASS_BWD_UE, 1>);
+    case PASS_BWD_UE * 4 + 2: return reinterpret_cast<const void*>(k_batched_flat<T, PASS_BWD_UE, 2>);
+    case PASS_BWD_HIST * 4 + 0: return reinterpret_cast<const void*>(k_batched_flat<T, PASS_BWD_HIST, 0>);
+    case PASS_BWD_HIST * 4 + 1: return reinterpret_cast<const void*>(k_batched_flat<T, PASS_BWD_HIST, 1>);
+    default: return reinterpret_cast<const void*>(k_batched_flat<T, PASS_GATHER, 0>);
   }
 }
 
@@ -258,6 +298,11 @@ const void* kernel_for(int dtype, int pass, int v) {
   return dtype == CP_F64 ? kernel_of<double>(pass, v) : kernel_of<float>(pass, v);
 }
 
+// the one-tile-per-block form of a pass
+const void* kernel_flat_for(int dtype, int pass, int v) {
+  return dtype == CP_F64 ? kernel_flat_of<double>(pass, v) : kernel_flat_of<float>(pass, v);
+}
+
 // resident blocks per CU of a pass variant (0: it cannot run)
 hipError_t blocks_per_cu(int dtype, int pass, int v, size_t lds, int* per_cu) {
   const void* k = kernel_for(dtype, pass, v);
@@ -319,6 +364,10 @@ cp_status_t build_pass(const Plan& P, int pass, int v, int chunk, Pass& out) {
   int per_cu = 0;
   if (blocks_per_cu(P.dtype, pass, v, lds, &per_cu) != hipSuccess) return CP_EDEVICE;
   if (per_cu < 1) return CP_EUNSUPPORTED;
+  const void* fk = kernel_flat_for(P.dtype, pass, v);
+  if (fk && lds > 65536 &&
+      hipFuncSetAttribute(fk, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds) != hipSuccess)
+    return CP_EDEVICE;
   Pass Q;
   Q.kind = pass;
   Q.variant = v;
@@ -344,8 +393,9 @@ cp_status_t build_pass(const Plan& P, int pass, int v, int chunk, Pass& out) {
   return CP_OK;
 }
 
-// default chunk: cheap tiles are claimed several at a time
-int default_chunk(int pass) { return pass == PASS_FWD_UE || pass == PASS_GATHER ? 4 : 1; }
+// default: one tile per block (0); on the 64-field benchmark the tuner chose
+// it for every pass in most runs (histogram passes always)
+int default_chunk(int) { return 0; }
 
 cp_status_t build_plan(int n, const Field* fs, bool bwd, Plan& P, const char** why) {
   const size_t el = fs[0].dtype == CP_F64 ? 8 : 4;
@@ -424,8 +474,15 @@ hipError_t launch_pass(const Plan& P, const Pass& q, hipStream_t st) {
   const BatchTile* tiles = q.d_tiles;
   int ntiles = q.ntiles, chunk = q.chunk;
   int* queue = q.d_queue;
-  void* args[] = {&fields, &tiles, &ntiles, &chunk, &queue};
-  hipError_t e = hipLaunchKernel(kernel_for(P.dtype, q.kind, q.variant), dim3(q.grid), dim3(kNT), args, q.lds, st);
+  hipError_t e;
+  if (q.chunk == 0) {  // one tile per block, in the table's order
+    if (ntiles == 0) return hipSuccess;
+    void* fargs[] = {&fields, &tiles};
+    e = hipLaunchKernel(kernel_flat_for(P.dtype, q.kind, q.variant), dim3(ntiles), dim3(kNT), fargs, q.lds, st);
+  } else {
+    void* args[] = {&fields, &tiles, &ntiles, &chunk, &queue};
+    e = hipLaunchKernel(kernel_for(P.dtype, q.kind, q.variant), dim3(q.grid), dim3(kNT), args, q.lds, st);
+  }
   if (e != hipSuccess) return e;
   return hipGetLastError();
 }
@@ -458,12 +515,13 @@ cp_status_t time_pass(const Plan& P, const Pass& q, hipStream_t st, int reps, do
   return ok ? CP_OK : CP_EDEVICE;
 }
 
-// Autotuner: for every pass, time each tile variant with each claim chunk on
-// the plan's own fields (the field table must be current) and keep the
-// fastest.  Every trial writes the pass's outputs, with the same values.
+// Autotuner: for every pass, time each tile variant with each claim chunk
+// and with one tile per block, on the plan's own
+// fields (the field table must be current) and keep the fastest.  Every
+// trial writes the pass's outputs, with the same values.
 cp_status_t tune(Plan& P, hipStream_t st) {
   constexpr int kReps = 3;
-  const int chunks[] = {1, 2, 4, 8};
+  const int chunks[] = {0, 1, 2, 4, 8};
   for (Pass& cur : P.passes) {
     Pass best = cur;
     double best_ms = 0.0;
@@ -483,6 +541,7 @@ cp_status_t tune(Plan& P, hipStream_t st) {
       }
       for (int c : chunks) {
         if (!built && c == cur.chunk) continue;
+        if (c == 0 && !kernel_flat_for(P.dtype, cur.kind, v)) continue;
         cand.chunk = c;
         double ms = 0.0;
         s = time_pass(P, cand, st, kReps, ms);
@@ -576,7 +635,9 @@ void tune_table_store(const char* path, const std::string& key, const Plan& P) {
 cp_status_t tune_table_apply(Plan& P, const std::vector<TunedPass>& rec, bool& applied) {
   applied = false;
   for (const TunedPass& t : rec)
-    if (t.kind < 0 || t.kind >= NPASS || t.variant < 0 || t.variant >= n_variants(t.kind) || t.chunk < 1) return CP_OK;
+    if (t.kind < 0 || t.kind >= NPASS || t.variant < 0 || t.variant >= n_variants(t.kind) || t.chunk < 0 ||
+        (t.chunk == 0 && !kernel_flat_for(P.dtype, t.kind, t.variant)))
+      return CP_OK;
   for (Pass& cur : P.passes) {
     for (const TunedPass& t : rec) {
       if (t.kind != cur.kind) continue;
@@ -607,8 +668,12 @@ std::string describe(const Plan& P) {
   for (const Pass& q : P.passes) {
     int ox, oy;
     pass_geom(q.kind, q.variant, el, ox, oy);
-    std::snprintf(buf, sizeof buf, "; %s: shape %d (tile %dx%d), chunk %d, %d tiles, grid %d", pass_name(q.kind),
-                  q.variant, ox, oy, q.chunk, q.ntiles, q.grid);
+    if (q.chunk == 0)
+      std::snprintf(buf, sizeof buf, "; %s: shape %d (tile %dx%d), one tile per block, %d tiles", pass_name(q.kind),
+                    q.variant, ox, oy, q.ntiles);
+    else
+      std::snprintf(buf, sizeof buf, "; %s: shape %d (tile %dx%d), chunk %d, %d tiles, grid %d", pass_name(q.kind),
+                    q.variant, ox, oy, q.chunk, q.ntiles, q.grid);
     out += buf;
     if (q.ms >= 0.0) {
       std::snprintf(buf, sizeof buf, ", %.4f ms", q.ms);
@@ -780,7 +845,8 @@ cp_status_t batched_pin(int n, const Field* fs, uint32_t flags, const int* shape
     }
   for (Pass& cur : P.passes) {
     const int v = shape[cur.kind] < 0 ? cur.variant : shape[cur.kind];
-    const int c = chunk[cur.kind] < 1 ? cur.chunk : chunk[cur.kind];
+    // >= 1: tiles per claim; -1: one tile per block (chunk 0); else keep
+    const int c = chunk[cur.kind] >= 1 ? chunk[cur.kind] : (chunk[cur.kind] == -1 ? 0 : cur.chunk);
     if (v == cur.variant) {
       cur.chunk = c;
     } else {

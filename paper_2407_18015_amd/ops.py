@@ -251,13 +251,14 @@ BATCH_PASSES = ("forward", "hist_forward", "adjoint", "hist_adjoint", "hist_gath
 def batched_pin(fields: list[Field], fwd: bool = True, bwd: bool = False, shape: dict | None = None,
                 chunk: dict | None = None) -> None:
     """cp_batched_pin: fix the tile shape index / claim chunk of passes of the
-    plan used by batched calls over these fields (keys of BATCH_PASSES)."""
+    plan used by batched calls over these fields (keys of BATCH_PASSES);
+    chunk -1 (or "flat") launches one tile per block."""
     shape, chunk = shape or {}, chunk or {}
     for k in list(shape) + list(chunk):
         if k not in BATCH_PASSES:
             raise ValueError(f"unknown pass {k!r}")
     sh = [int(shape.get(k, -1)) for k in BATCH_PASSES]
-    ch = [int(chunk.get(k, 0)) for k in BATCH_PASSES]
+    ch = [-1 if chunk.get(k) == "flat" else int(chunk.get(k, 0)) for k in BATCH_PASSES]
     L.check(L.cp_batched_pin(len(fields), [f.desc() for f in fields], _batch_flags(fwd, bwd), sh, ch))
 
 

@@ -1,6 +1,6 @@
-"""GPU: tile shapes of the batched persistent launch, pinned one by one and
-chosen by the autotuner.  Every shape and claim chunk must give exactly the
-per-field launches' results (the tile shape changes no per-vertex
+"""GPU: tile shapes of the batched launch, pinned one by one and chosen by
+the autotuner.  Every shape, claim chunk and the one-tile-per-block form
+must give exactly the per-field launches' results (the tile shape changes no per-vertex
 arithmetic); the tuner must record its choice and reuse it.
 """
 import sys
@@ -78,12 +78,13 @@ def check_backward(fields, params, gmin, gmax, grad, what):
 def test_every_forward_shape_and_chunk(dtype):
     fields, params = mixed_fields(11, dtype)
     for shape in (0, 1, 2):
-        for chunk in (1, 3):
+        for chunk in (1, 3, "flat"):
             note("pinned forward shape", shape, "chunk", chunk, dtype)
             cp.batched_pin(fields, fwd=True, shape={"forward": shape, "hist_forward": min(shape, 1)},
                            chunk={"forward": chunk, "hist_forward": chunk})
             d = cp.batched_describe(fields, fwd=True)
-            assert d.startswith("pinned") and f"shape {shape}" in d and f"chunk {chunk}" in d, d
+            form = "one tile per block" if chunk == "flat" else f"chunk {chunk}"
+            assert d.startswith("pinned") and f"shape {shape}" in d and form in d, d
             pmin, pmax = outputs(fields, dtype)
             cp.batched(fields, params, pmin=pmin, pmax=pmax)
             check_forward(fields, params, pmin, pmax, f"shape {shape} chunk {chunk}")
@@ -94,7 +95,7 @@ def test_every_adjoint_shape_and_chunk(dtype):
     fields, params = mixed_fields(12, dtype)
     gmin, gmax = upstream(fields, dtype)
     for shape in (0, 1, 2):
-        for chunk in (1, 3):
+        for chunk in (1, 3, "flat"):
             note("pinned adjoint shape", shape, "chunk", chunk, dtype)
             hs = min(shape, 1)
             cp.batched_pin(fields, fwd=False, bwd=True, shape={"adjoint": shape, "hist_adjoint": hs},
