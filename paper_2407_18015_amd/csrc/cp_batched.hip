@@ -201,15 +201,15 @@ const void* kernel_of(int pass, int v) {
 }
 
 // Relative cost per vertex (forward, adjoint), measured on MI355X with the
-// per-field kernels at 2048^2 (uniform forward = 1: 47 us; uniform adjoint
-// 80 us, Epanechnikov forward 81 us and adjoint 145 us, 10-bin histogram
-// forward 0.59 ms and adjoint 1.95 ms); histograms scale with the number of
+// per-field kernels at 2048^2 (uniform forward = 1: 40.6 us; uniform adjoint
+// 64.7 us, Epanechnikov forward 85 us and adjoint 147.5 us, 10-bin histogram
+// forward 0.545 ms and adjoint 1.41 ms); histograms scale with the number of
 // bin edges.  The costs only order the tiles of one pass (longest first), so
 // within a pass only the ratios between models matter.
 double vertex_cost(int model, int nb, bool bwd) {
-  if (model == CP_UNIFORM) return bwd ? 1.7 : 1.0;
-  if (model == CP_EPANECHNIKOV) return bwd ? 3.1 : 1.7;
-  return (bwd ? 3.8 : 1.15) * (nb + 1);
+  if (model == CP_UNIFORM) return bwd ? 1.6 : 1.0;
+  if (model == CP_EPANECHNIKOV) return bwd ? 3.6 : 2.1;
+  return (bwd ? 3.2 : 1.2) * (nb + 1);
 }
 
 const char* pass_name(int pass) {
