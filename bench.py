@@ -599,7 +599,7 @@ def more_detail(cp, workloads, torch, dev, S, reps, ceil):
 def batched_detail(cp, workloads, torch, dev):
     """64 fields, sides round(2^U[7,11]), models cycling uniform /
     Epanechnikov / histogram(10), each fitted from a 20-member ensemble:
-    forward + adjoint as one persistent launch, as a replayed graph, and as
+    forward + adjoint as one launch per pass, as a replayed graph, and as
     one forward and one adjoint launch per field."""
     t0 = time.time()
     fields, params, pmin, pmax, gmin, gmax, grad = [], [], [], [], [], [], []
@@ -626,7 +626,7 @@ def batched_detail(cp, workloads, torch, dev):
         fl_f += a
         fl_b += b
     out = {"fields": len(fields), "vertices": nv, "algorithmic_flops_fwd": fl_f, "algorithmic_flops_fwd_bwd": fl_f + fl_b}
-    for name, kw in (("per_field", dict(per_field=True)), ("persistent", dict()), ("graph", dict(graph=True))):
+    for name, kw in (("per_field", dict(per_field=True)), ("one_launch_per_pass", dict()), ("graph", dict(graph=True))):
         ms = _timed(torch, lambda: cp.batched(fields, params, pmin, pmax, gmin, gmax, grad, **kw), 5)
         out[name + "_fwd_bwd_ms"] = ms
         out[name + "_fwd_bwd_vertices_per_s"] = nv / (ms * 1e-3)
