@@ -308,12 +308,17 @@ __host__ __device__ void hist_vertex_sweep(const HistSuf<T>& L, int ev, const in
     T x1 = nv;
 #pragma unroll
     for (int i = 0; i < 4; ++i) x1 = fmin_nn(x1, c[i].nxt);  // sweep edges: finite
+    const T wgt = pv * (x1 - x0);
+#pragma unroll
+    for (int i = 0; i < 4; ++i) suf_cursor_step(c[i], L, en[i], x1, big);
+    // end values from the cursors after their steps (a cursor that crossed
+    // x1 gives S(x1) from its new bin): the state before the step is dead by
+    // now, so the steps update it in place
 #pragma unroll
     for (int i = 0; i < 4; ++i) {
       s1[i] = cfma(c[i].slope, c[i].nxt - x1, c[i].snx);
       f1[i] = c[i].tot - s1[i];
     }
-    const T wgt = pv * (x1 - x0);
     amin = cfma(wgt, bern4(s0, s1), amin);
     amax = cfma(wgt, bern4(f0, f1), amax);
     if constexpr (SAD) {
@@ -333,8 +338,6 @@ __host__ __device__ void hist_vertex_sweep(const HistSuf<T>& L, int ev, const in
       }
       nv = jv + 1 < h ? T(jv + 1) * dv : hv;
     }
-#pragma unroll
-    for (int i = 0; i < 4; ++i) suf_cursor_step(c[i], L, en[i], x1, big);
     x0 = x1;
   };
   const int maxit = 5 * (h + 1) + 2;  // every step crosses at least one edge
