@@ -289,8 +289,8 @@ __host__ __device__ void hist_vertex_sweep(const HistSuf<T>& L, int ev, const in
   const T dv = hv * (T(1) / T(h)), idv = T(h) * crcp(hv);
   int jv = 0;
   T nv = h > 1 ? dv : hv;
-  T uv = L.U(ev, 1);                // U_{jv+1} (carried by the saddle sweep only)
-  T pv = (L.U(ev, 0) - uv) * idv;   // density of the vertex's bin jv
+  T uv = L.U(ev, 1);               // U_{jv+1}
+  T pv = (L.U(ev, 0) - uv) * idv;  // density of the vertex's bin jv
   SufCursor<T> c[4];
 #pragma unroll
   for (int i = 0; i < 4; ++i) suf_cursor_init(c[i], L, en[i], lo[i], hi[i], pres[i], big);
@@ -330,12 +330,8 @@ __host__ __device__ void hist_vertex_sweep(const HistSuf<T>& L, int ev, const in
     if (nv == x1) {
       ++jv;
       const T un = L.U(ev, jv + 1 < h ? jv + 1 : h);
-      if constexpr (SAD) {
-        pv = (uv - un) * idv;
-        uv = un;
-      } else {  // read again: one register less, which gives P_min / P_max a sixth wave per SIMD
-        pv = (L.U(ev, jv) - un) * idv;
-      }
+      pv = (uv - un) * idv;
+      uv = un;
       nv = jv + 1 < h ? T(jv + 1) * dv : hv;
     }
     x0 = x1;
