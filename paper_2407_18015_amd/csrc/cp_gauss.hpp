@@ -192,10 +192,12 @@ CP_HD void gauss_vertex_jac(T mv, T sv, const T (&mn)[4], const T (&sn)[4], cons
   P x0 = -C;
   // panel sums in T (z_n keeps its sign on a panel: its mean is a cut), the
   // sums over panels in FP64: dP/dsigma_n cancels between the panels below
-  // and above the neighbour's mean
+  // and above the neighbour's mean.  The upstream weights enter at every
+  // node (g_min times the S integrand, -g_max times the F one, one sum per
+  // derivative): half the accumulators of separate P_min and P_max sums.
   P fS = P(0), fF = P(0);
-  P aS[4] = {P(0), P(0), P(0), P(0)}, bS[4] = {P(0), P(0), P(0), P(0)};
-  P aF[4] = {P(0), P(0), P(0), P(0)}, bF[4] = {P(0), P(0), P(0), P(0)};
+  P a[4] = {P(0), P(0), P(0), P(0)}, b[4] = {P(0), P(0), P(0), P(0)};
+  const T ngmax = -gmax;
   constexpr T rs2 = T(0.70710678118654752440);
   for (int it = 0; it < 5 * K; ++it) {
     if (!(x0 < C)) break;
@@ -204,9 +206,9 @@ CP_HD void gauss_vertex_jac(T mv, T sv, const T (&mn)[4], const T (&sn)[4], cons
     for (int n = 0; n < 4; ++n) x1 = tmin(x1, nx[n]);
     const P mid = (x0 + x1) * P(0.5), hlp = (x1 - x0) * P(0.5);
     const T hl = T(hlp);
-    T pS = T(0), pF = T(0), qaS[4], qbS[4], qaF[4], qbF[4];
+    T pS = T(0), pF = T(0), qa[4], qb[4];
 #pragma unroll
-    for (int n = 0; n < 4; ++n) qaS[n] = qbS[n] = qaF[n] = qbF[n] = T(0);
+    for (int n = 0; n < 4; ++n) qa[n] = qb[n] = T(0);
     // the node loop stays a loop (the rule's nodes and weights are read from
     // constant memory): unrolled, its live values do not fit the registers
 #pragma unroll 1
@@ -244,22 +246,17 @@ CP_HD void gauss_vertex_jac(T mv, T sv, const T (&mn)[4], const T (&sn)[4], cons
       pF += preF[4];
 #pragma unroll
       for (int n = 0; n < 4; ++n) {
-        const T ls = pz[n] * (preS[n] * sufS[n + 1]);
-        const T lf = pz[n] * (preF[n] * sufF[n + 1]);
-        qaS[n] += ls;
-        qbS[n] = cfma(ls, z[n], qbS[n]);
-        qaF[n] += lf;
-        qbF[n] = cfma(lf, z[n], qbF[n]);
+        const T l = pz[n] * cfma(gmin, preS[n] * sufS[n + 1], ngmax * (preF[n] * sufF[n + 1]));
+        qa[n] += l;
+        qb[n] = cfma(l, z[n], qb[n]);
       }
     }
     fS = cfma(P(pS), hlp, fS);
     fF = cfma(P(pF), hlp, fF);
 #pragma unroll
     for (int n = 0; n < 4; ++n) {
-      aS[n] = cfma(P(qaS[n]), hlp, aS[n]);
-      bS[n] = cfma(P(qbS[n]), hlp, bS[n]);
-      aF[n] = cfma(P(qaF[n]), hlp, aF[n]);
-      bF[n] = cfma(P(qbF[n]), hlp, bF[n]);
+      a[n] = cfma(P(qa[n]), hlp, a[n]);
+      b[n] = cfma(P(qb[n]), hlp, b[n]);
     }
     if (nv == x1) {
       kv += 1;
@@ -283,8 +280,8 @@ CP_HD void gauss_vertex_jac(T mv, T sv, const T (&mn)[4], const T (&sn)[4], cons
     jac[2 + 2 * n] = jac[3 + 2 * n] = T(0);
     if (!pres[n]) continue;
     const P c = P(inv_2pi) / P(sn[n]);
-    const P dmu = c * (P(gmin) * aS[n] - P(gmax) * aF[n]);  // g-weighted dP/dmu_n
-    const P dsg = c * (P(gmin) * bS[n] - P(gmax) * bF[n]);  // g-weighted dP/dsigma_n
+    const P dmu = c * a[n];  // g-weighted dP/dmu_n
+    const P dsg = c * b[n];  // g-weighted dP/dsigma_n
     jac[2 + 2 * n] = T(dmu);
     jac[3 + 2 * n] = T(dsg);
     smu += dmu;
