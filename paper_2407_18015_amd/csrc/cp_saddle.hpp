@@ -102,14 +102,25 @@ CP_HD T epa_saddle_term(int term, T wv, T iwv, const T (&d)[4], const T (&w)[4],
     }
     T sum = T(0);
 #pragma unroll
-    for (int j = 0; j < 8; ++j) {
-      const T x = T(GL<8>::x[j]);
+    for (int j = 0; j < 7; ++j) {
+      const T x = T(GL<7>::x[j]);
       const T t = cfma(bv, x, av);
       T prod = cfma(-t, t, T(1));
 #pragma unroll
       for (int i = 0; i < 4; ++i) prod *= epa_s4(tclamp(cfma(bu[i], x, au[i]), T(-1), T(1)));
-      sum = cfma(T(GL<8>::w[j]), prod, sum);
+      sum = cfma(T(GL<7>::w[j]), prod, sum);
     }
+    // The integrand has degree 14 when no factor is clamped on the piece
+    // (each unclamped factor a cubic in x with leading coefficient bu^3, the
+    // vertex kernel a quadratic with -bv^2), below that otherwise (a clamped
+    // factor is constant): the 7-point rule misses only the x^14 term, which
+    // is added in closed form.  A factor is clamped on the whole piece or
+    // nowhere inside it (its clamp point is a breakpoint), so the midpoint
+    // decides.
+    T lead = -bv * bv;
+#pragma unroll
+    for (int i = 0; i < 4; ++i) lead *= fabs(au[i]) < T(1) ? bu[i] * bu[i] * bu[i] : T(0);
+    sum = cfma(T(GLRem<7>::e), lead, sum);
     acc = cfma(sum, hl, acc);
   }
   return acc * T(0.75) * iwv * T(0.00390625);
