@@ -15,9 +15,10 @@
 // empty bin), x = lo + Delta (j + f): the inverse of the histogram CDF.
 //
 // Tiles of 64 x TY vertices stage lo, hi and the masses with a one-vertex
-// halo (as the closed-form forward does) and add h planes of cumulative
-// masses (FP64 running sums rounded once); one thread per vertex loops over
-// its samples.  Sample positions and neighbour tails are computed in FP64
+// halo (as the closed-form forward does) and replace the masses by the
+// cumulative masses in place (FP64 running sums rounded once); a bin's mass
+// is then the difference of its two cumulative values, which keeps the tile
+// at 2 + h planes of LDS.  One thread per vertex loops over its samples.  Sample positions and neighbour tails are computed in FP64
 // for both dtypes, in vertex-local coordinates: in FP32 a position carries
 // an error of one unit in the last place of the distribution width, which
 // is h units of a bin, and the neighbour's tail inherits it for every
@@ -60,12 +61,13 @@ __global__ __launch_bounds__(kFwdTX* TY) void k_semi(SemiArgs<T> a, int tiles_x,
   stage<T, EY, EX, NT>(lds, a.params, 2 + h, a.ps, a.rs, a.H, a.W, ty0 - 1, tx0 - 1, tid);
   __syncthreads();
   hist_stage_validity<T, NT>(lds, E, h, tid);
-  // cumulative masses: plane k - 1 of `cum` holds C_k, k = 1..h (C_h = T)
-  T* cum = lds + (size_t)(2 + h) * E;
+  // cumulative masses over the mass planes: plane k - 1 of `cum` holds C_k,
+  // k = 1..h (C_h = T); the thread that checked a vertex sums it
+  T* cum = lds + (size_t)2 * E;
   for (int e = tid; e < E; e += NT) {
     double c = 0.0;
     for (int k = 0; k < h; ++k) {
-      c += (double)lds[(2 + k) * E + e];
+      c += (double)cum[k * E + e];
       cum[k * E + e] = (T)c;
     }
   }
@@ -107,8 +109,8 @@ __global__ __launch_bounds__(kFwdTX* TY) void k_semi(SemiArgs<T> a, int tiles_x,
       const A r = u24_of<A>(w[i & 3]) * (A)Tv;
       int j = 0;
       for (int k = 1; k < h; ++k) j += (A)cum[(k - 1) * E + e] <= r ? 1 : 0;
-      const A mj = (A)lds[(2 + j) * E + e];
       const A cj = j > 0 ? (A)cum[(j - 1) * E + e] : A(0);
+      const A mj = (A)cum[j * E + e] - cj;
       const A f = mj > A(0) ? clamp01((r - cj) / mj) : A(0);
       const A xs = dv * (A(j) + f);
       A S[4], F[4];
@@ -127,7 +129,7 @@ __global__ __launch_bounds__(kFwdTX* TY) void k_semi(SemiArgs<T> a, int tiles_x,
         } else {
           const int k = min((int)z, h - 1);
           const A below = k > 0 ? (A)cum[(k - 1) * E + en[n]] : A(0);
-          F[n] = fma((A)lds[(2 + k) * E + en[n]], z - A(k), below);
+          F[n] = fma((A)cum[k * E + en[n]] - below, z - A(k), below);
           S[n] = tot[n] - F[n];
         }
       }
@@ -156,7 +158,7 @@ int cdiv_s(int p, int q) { return (p + q - 1) / q; }
 template <typename T, int TY>
 hipError_t launch_semi(const SemiArgs<T>& a, hipStream_t st) {
   const int tx = cdiv_s(a.W, kFwdTX), ty = cdiv_s(a.H, TY), n = tx * ty;
-  const size_t lds = sizeof(T) * (size_t)(2 + 2 * a.nb) * (kFwdTX + 2) * (TY + 2);
+  const size_t lds = sizeof(T) * (size_t)(2 + a.nb) * (kFwdTX + 2) * (TY + 2);
   if (lds > 65536) {
     hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(k_semi<T, TY>),
                                        hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
@@ -182,8 +184,9 @@ hipError_t semi_typed(const Field& f, const void* params, void* pmin, void* pmax
   a.k0 = (uint32_t)f.seed;
   a.k1 = (uint32_t)(f.seed >> 32);
   a.fid = f.fid;
-  // tile height: the staged and cumulative planes must fit the LDS
-  const size_t per_row = sizeof(T) * (size_t)(2 + 2 * f.nb) * (kFwdTX + 2);
+  // tile height: the staged planes (the masses overwritten by their
+  // cumulative sums) must fit the LDS
+  const size_t per_row = sizeof(T) * (size_t)(2 + f.nb) * (kFwdTX + 2);
   if (per_row * 6 <= 64 * 1024) return launch_semi<T, 4>(a, st);
   if (per_row * 4 <= 160 * 1024) return launch_semi<T, 2>(a, st);
   return launch_semi<T, 1>(a, st);
